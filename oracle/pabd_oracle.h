@@ -1,0 +1,108 @@
+/*
+ * pabd_oracle.h -- interface of the plain FP64 CPU oracle for projective affine
+ * body dynamics (PABD).
+ *
+ * TEST INFRASTRUCTURE ONLY.  The oracle exists to check the HIP library; it is
+ * called by the test suite, by the package smoke check and by the CPU-baseline
+ * leg of the benchmark, and by nothing else.  It shares no source, header,
+ * helper or table with the HIP library (include/pabd.h is a different header
+ * with different types), and it never calls the library.
+ *
+ * Everything is double precision, row-major, SI units.  All arrays passed in are
+ * owned by the caller and copied at create time.
+ */
+#ifndef PABD_ORACLE_H
+#define PABD_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* body shape ids */
+#define ORACLE_SHAPE_BOX 0    /* shape_param = half extents (3) */
+#define ORACLE_SHAPE_SPHERE 1 /* shape_param[0] = radius       */
+
+/* body flag bits */
+#define ORACLE_FLAG_PINNED 1u     /* kinematic: infinite mass, never updated */
+#define ORACLE_FLAG_NO_CONTACT 2u /* excluded from collision detection       */
+
+/* bond kinds */
+#define ORACLE_BOND_QUADRATIC 0 /* Psi = 1/2 kappa (d - l)^2 (l = 0: ball joint) */
+#define ORACLE_BOND_DRIVEN 1    /* ball joint whose j-side anchor follows a target angle */
+#define ORACLE_BOND_CONTACT 2   /* created per step by collision detection      */
+
+typedef struct {
+  int32_t n_bodies;
+  const int32_t *shape;        /* [N] */
+  const double *shape_param;   /* [N*3] */
+  const double *density;       /* [N] kg/m^3 */
+  const uint8_t *flags;        /* [N] */
+  const int32_t *group;        /* [N] bodies sharing a nonzero group never collide */
+  const double *c0, *A0;       /* [N*3], [N*9] */
+  const double *v0, *w0;       /* [N*3], [N*3] */
+  int32_t n_bonds;
+  const int32_t *bond_i, *bond_j; /* [B]; j = -1: world anchor */
+  const int32_t *bond_type;       /* [B] QUADRATIC or DRIVEN */
+  const double *x_i, *x_j;        /* [B*3] material anchors (world coords if j = -1) */
+  const double *kappa, *rest_len; /* [B] */
+  const double *drive;            /* [B*13]: axis(3) pivot(3) base(3) theta0 amp freq phase */
+  double gravity[3];
+  double h;
+  double t0; /* simulation time at the start of the first step */
+  int32_t iters;
+  int32_t contact_enable;
+  double mu;
+  double contact_kappa_scale; /* kappa_c = scale * m_max / h^2 (heavier free body) */
+  double contact_margin;      /* base detection margin (m) */
+  int32_t n_planes;
+  const double *planes; /* [P*4]: unit normal n, offset o; free side n.y >= o */
+} pabd_oracle_desc;
+
+typedef struct pabd_oracle pabd_oracle;
+
+/* create / destroy; create returns NULL on an invalid descriptor */
+pabd_oracle *pabd_oracle_create(const pabd_oracle_desc *d);
+void pabd_oracle_destroy(pabd_oracle *o);
+
+/* advance nsteps steps of Algorithm 1; returns 0, or -1 on non-finite state */
+int pabd_oracle_step(pabd_oracle *o, int32_t nsteps);
+
+/* state read-back (any pointer may be NULL) */
+void pabd_oracle_read_state(const pabd_oracle *o, double *c, double *A, double *v, double *w);
+
+/* convergence residual rho_k of every iteration of the last step; returns K */
+int pabd_oracle_residuals(const pabd_oracle *o, double *rho, int32_t cap);
+
+/* debug switches: bit0 = skip the local (rigidification) step */
+void pabd_oracle_set_debug(pabd_oracle *o, int32_t flags);
+
+/* iterates of the last step: q^{K-1} (after projection) and q^{K-1/2}
+ * (global result of the last iteration, before projection); [N*12] each */
+void pabd_oracle_last_iterates(const pabd_oracle *o, double *q_prev, double *q_half);
+
+/* mass and affine moment Pi0 (3x3) of one body shape at unit-free density */
+void pabd_oracle_body_mass(int32_t shape, const double *param, double density, double *m,
+                           double *Pi0);
+
+/* nearest rotation of A (polar factor with determinant fix), via an SVD */
+void pabd_oracle_polar(const double *A, double *R);
+
+/* dense 12x12 H_i^k of body i at the last iteration of the last step */
+void pabd_oracle_dense_H(const pabd_oracle *o, int32_t body, double *H);
+
+/* contact bonds built by the last step's collision detection.
+ * Returns their count; fills up to cap entries of each non-NULL array. */
+int pabd_oracle_contacts(const pabd_oracle *o, int32_t cap, int32_t *ci, int32_t *cj,
+                         int32_t *feature, double *xi, double *xj, double *normal,
+                         double *kappa);
+
+/* build the contact set of the current state without stepping (same rule) */
+int pabd_oracle_detect(pabd_oracle *o);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

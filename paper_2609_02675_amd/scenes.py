@@ -1,0 +1,356 @@
+"""Seeded synthetic scene generators.
+
+This module builds scene descriptions only: body shapes, densities, initial
+poses and velocities, bond anchors and stiffnesses, contact settings.  It holds
+none of the method's arithmetic (no mass or inertia, no dynamics); the HIP
+library and the test oracle each derive everything else from these inputs.
+
+The paper's own scenes (meshes, sand, water) are not available, so these
+synthetic workloads stand in for them.  All randomness is NumPy PCG64 with an
+explicit seed.
+
+Shapes: 0 = box (shape_param = half extents), 1 = sphere (shape_param[0] = radius).
+Body flags: bit0 = pinned (kinematic, infinite mass), bit1 = no contact.
+Bond types: 0 = quadratic (rest length l; l = 0 is a ball joint),
+            1 = driven ball joint (j-side anchor follows a target angle).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional
+
+import numpy as np
+
+SHAPE_BOX = 0
+SHAPE_SPHERE = 1
+FLAG_PINNED = 1
+FLAG_NO_CONTACT = 2
+BOND_QUADRATIC = 0
+BOND_DRIVEN = 1
+
+PREC_FP32 = 0
+PREC_FP64 = 1
+
+
+@dataclasses.dataclass
+class SceneDesc:
+    """Arrays are float64 / int32 / uint8 numpy arrays, row-major."""
+
+    shape: np.ndarray          # [N] int32
+    shape_param: np.ndarray    # [N,3]
+    density: np.ndarray        # [N]
+    flags: np.ndarray          # [N] uint8
+    group: np.ndarray          # [N] int32
+    c0: np.ndarray             # [N,3]
+    A0: np.ndarray             # [N,3,3]
+    v0: np.ndarray             # [N,3]
+    w0: np.ndarray             # [N,3]
+    bond_i: np.ndarray         # [B] int32
+    bond_j: np.ndarray         # [B] int32 (-1 = world)
+    bond_type: np.ndarray      # [B] int32
+    x_i: np.ndarray            # [B,3]
+    x_j: np.ndarray            # [B,3]
+    kappa: np.ndarray          # [B]
+    rest_len: np.ndarray       # [B]
+    drive: np.ndarray          # [B,13]
+    gravity: np.ndarray = dataclasses.field(default_factory=lambda: np.array([0.0, -9.81, 0.0]))
+    h: float = 1.0 / 60.0
+    t0: float = 0.0
+    iters: int = 20
+    contact_enable: int = 0
+    mu: float = 0.5
+    contact_kappa_scale: float = 0.3
+    contact_margin: float = 0.01
+    planes: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros((0, 4)))
+    precision: int = PREC_FP64
+    max_contacts_per_body: int = 64
+    name: str = ""
+
+    @property
+    def n_bodies(self) -> int:
+        return int(self.shape.shape[0])
+
+    @property
+    def n_bonds(self) -> int:
+        return int(self.bond_i.shape[0])
+
+    def copy(self, **changes) -> "SceneDesc":
+        d = {f.name: getattr(self, f.name) for f in dataclasses.fields(self)}
+        for k, v in d.items():
+            if isinstance(v, np.ndarray):
+                d[k] = v.copy()
+        d.update(changes)
+        return SceneDesc(**d)
+
+    def with_state(self, c, A, v, w, t0: Optional[float] = None) -> "SceneDesc":
+        """Same scene restarted from another state (e.g. a checkpoint)."""
+        out = self.copy(c0=np.array(c, dtype=np.float64).reshape(-1, 3),
+                        A0=np.array(A, dtype=np.float64).reshape(-1, 3, 3),
+                        v0=np.array(v, dtype=np.float64).reshape(-1, 3),
+                        w0=np.array(w, dtype=np.float64).reshape(-1, 3))
+        if t0 is not None:
+            out.t0 = float(t0)
+        return out
+
+    def normalized(self) -> "SceneDesc":
+        """Contiguous arrays of the dtypes the C interfaces expect."""
+        f64 = lambda a, shp: np.ascontiguousarray(np.asarray(a, dtype=np.float64).reshape(shp))
+        i32 = lambda a: np.ascontiguousarray(np.asarray(a, dtype=np.int32).reshape(-1))
+        n, b = self.n_bodies, self.n_bonds
+        return dataclasses.replace(
+            self,
+            shape=i32(self.shape), shape_param=f64(self.shape_param, (n, 3)),
+            density=f64(self.density, (n,)),
+            flags=np.ascontiguousarray(np.asarray(self.flags, dtype=np.uint8).reshape(-1)),
+            group=i32(self.group), c0=f64(self.c0, (n, 3)), A0=f64(self.A0, (n, 3, 3)),
+            v0=f64(self.v0, (n, 3)), w0=f64(self.w0, (n, 3)),
+            bond_i=i32(self.bond_i), bond_j=i32(self.bond_j), bond_type=i32(self.bond_type),
+            x_i=f64(self.x_i, (b, 3)), x_j=f64(self.x_j, (b, 3)), kappa=f64(self.kappa, (b,)),
+            rest_len=f64(self.rest_len, (b,)), drive=f64(self.drive, (b, 13)),
+            gravity=f64(self.gravity, (3,)), planes=f64(self.planes, (-1, 4)))
+
+
+def _empty_bonds(b: int):
+    return dict(bond_i=np.zeros(b, np.int32), bond_j=np.zeros(b, np.int32),
+                bond_type=np.zeros(b, np.int32), x_i=np.zeros((b, 3)), x_j=np.zeros((b, 3)),
+                kappa=np.zeros(b), rest_len=np.zeros(b), drive=np.zeros((b, 13)))
+
+
+def _bodies(n: int):
+    return dict(shape=np.zeros(n, np.int32), shape_param=np.zeros((n, 3)), density=np.ones(n),
+                flags=np.zeros(n, np.uint8), group=np.zeros(n, np.int32), c0=np.zeros((n, 3)),
+                A0=np.tile(np.eye(3), (n, 1, 1)), v0=np.zeros((n, 3)), w0=np.zeros((n, 3)))
+
+
+def rot_z(theta: float) -> np.ndarray:
+    c, s = math.cos(theta), math.sin(theta)
+    return np.array([[c, -s, 0.0], [s, c, 0.0], [0.0, 0.0, 1.0]])
+
+
+def rot_axis(axis, theta: float) -> np.ndarray:
+    u = np.asarray(axis, dtype=np.float64)
+    u = u / np.linalg.norm(u)
+    K = np.array([[0, -u[2], u[1]], [u[2], 0, -u[0]], [-u[1], u[0], 0]])
+    return np.eye(3) + math.sin(theta) * K + (1 - math.cos(theta)) * (K @ K)
+
+
+def random_rotations(rng: np.random.Generator, n: int) -> np.ndarray:
+    """Uniformly distributed rotations (normalised Gaussian quaternions)."""
+    q = rng.standard_normal((n, 4))
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    x, y, z, w = q.T
+    R = np.empty((n, 3, 3))
+    R[:, 0, 0] = 1 - 2 * (y * y + z * z); R[:, 0, 1] = 2 * (x * y - z * w); R[:, 0, 2] = 2 * (x * z + y * w)
+    R[:, 1, 0] = 2 * (x * y + z * w); R[:, 1, 1] = 1 - 2 * (x * x + z * z); R[:, 1, 2] = 2 * (y * z - x * w)
+    R[:, 2, 0] = 2 * (x * z - y * w); R[:, 2, 1] = 2 * (y * z + x * w); R[:, 2, 2] = 1 - 2 * (x * x + y * y)
+    return R
+
+
+# ---------------------------------------------------------------------------
+# joint chains (the 8-body chain and the batched chains)
+# ---------------------------------------------------------------------------
+
+def chain(n: int, *, tilt_deg: float = 45.0, joint_angles_deg=None, kappa: float = 1e5,
+          iters: int = 20, h: float = 1.0 / 60.0, origin=(0.0, 0.0, 0.0),
+          precision: int = PREC_FP64, pin_top: bool = True, name: str = "") -> SceneDesc:
+    """Chain of n unit cubes (1 kg: density 1) joined by ball joints at the face
+    centres (0, -0.5, 0) of body k and (0, +0.5, 0) of body k+1, body 0 pinned.
+
+    Body 0's axis is tilted by ``tilt_deg`` from the downward vertical in the x-y
+    plane; joint k additionally turns body k+1 by ``joint_angles_deg[k]`` about z.
+    """
+    bd = _bodies(n)
+    bd["shape_param"][:] = 0.5
+    if pin_top:
+        bd["flags"][0] = FLAG_PINNED
+    bd["flags"] |= FLAG_NO_CONTACT
+    ang = np.zeros(max(n - 1, 0)) if joint_angles_deg is None else np.asarray(joint_angles_deg, float)
+    R = rot_z(math.radians(tilt_deg))
+    c = np.asarray(origin, dtype=np.float64)
+    xa, xb = np.array([0.0, -0.5, 0.0]), np.array([0.0, 0.5, 0.0])
+    for k in range(n):
+        bd["c0"][k] = c
+        bd["A0"][k] = R
+        if k + 1 < n:
+            joint = c + R @ xa
+            R = R @ rot_z(math.radians(ang[k]))
+            c = joint - R @ xb
+    bonds = _empty_bonds(max(n - 1, 0))
+    for k in range(n - 1):
+        bonds["bond_i"][k], bonds["bond_j"][k] = k, k + 1
+        bonds["x_i"][k], bonds["x_j"][k] = xa, xb
+        bonds["kappa"][k] = kappa
+    return SceneDesc(**bd, **bonds, h=h, iters=iters, precision=precision, name=name or f"chain{n}")
+
+
+def chain8(precision: int = PREC_FP64, tilt_deg: float = 45.0) -> SceneDesc:
+    """8 unit cubes, 7 ball joints (kappa 1e5), body 0 pinned, g = 9.81, h = 1/60,
+    20 iterations per step.  ``tilt_deg=10`` is the gentle, non-chaotic variant."""
+    return chain(8, tilt_deg=tilt_deg, kappa=1e5, iters=20, precision=precision,
+                 name=f"chain8_tilt{tilt_deg:g}")
+
+
+def batched_chain_lengths(n_scenes: int, seed: int = 2, lo: int = 4, hi: int = 64) -> np.ndarray:
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.integers(lo, hi + 1, size=n_scenes)
+
+
+def batched_chains(n_scenes: int = 4096, seed: int = 2, iters: int = 20,
+                   precision: int = PREC_FP32, lo: int = 4, hi: int = 64,
+                   max_angle_deg: float = 30.0) -> List[SceneDesc]:
+    """Independent chains of U{lo..hi} unit cubes with ball joints at the face
+    centres; every joint turned by U[-30, 30] degrees about z; top body pinned."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    lengths = rng.integers(lo, hi + 1, size=n_scenes)
+    out = []
+    for s, n in enumerate(lengths):
+        ang = rng.uniform(-max_angle_deg, max_angle_deg, size=int(n) - 1)
+        out.append(chain(int(n), tilt_deg=0.0, joint_angles_deg=ang, kappa=1e5, iters=iters,
+                         precision=precision, name=f"chain{n}_s{s}"))
+    return out
+
+
+def merge(scenes: List[SceneDesc], name: str = "merged") -> SceneDesc:
+    """Concatenate independent scenes into one scene (same h, iters, gravity)."""
+    off = np.cumsum([0] + [s.n_bodies for s in scenes])
+    cat = lambda k: np.concatenate([getattr(s, k) for s in scenes], axis=0)
+    bi = np.concatenate([s.bond_i + off[i] for i, s in enumerate(scenes)])
+    bj = np.concatenate([np.where(s.bond_j >= 0, s.bond_j + off[i], -1) for i, s in enumerate(scenes)])
+    first = scenes[0]
+    return first.copy(
+        shape=cat("shape"), shape_param=cat("shape_param"), density=cat("density"),
+        flags=cat("flags"), group=cat("group"), c0=cat("c0"), A0=cat("A0"), v0=cat("v0"),
+        w0=cat("w0"), bond_i=bi.astype(np.int32), bond_j=bj.astype(np.int32),
+        bond_type=cat("bond_type"), x_i=cat("x_i"), x_j=cat("x_j"), kappa=cat("kappa"),
+        rest_len=cat("rest_len"), drive=cat("drive"), name=name)
+
+
+# ---------------------------------------------------------------------------
+# box piles with contact and friction
+# ---------------------------------------------------------------------------
+
+def box_drop(n_side: int = 10, layers: Optional[int] = None, seed: int = 0, mu: float = 0.5,
+             iters: int = 30, h: float = 1.0 / 60.0, spacing: float = 2.7,
+             base_height: float = 2.0, precision: int = PREC_FP32, jitter: float = 0.1,
+             name: str = "") -> SceneDesc:
+    """Boxes with side lengths U[0.5, 1.5] per axis, density 1000, on an
+    n_side x layers x n_side lattice at ``spacing`` with +-jitter, uniformly random
+    orientation, at rest, every box's lowest point at least ``base_height``
+    above the ground plane y = 0.  n_side = 10, layers = 10 is the 1,000-box drop."""
+    layers = n_side if layers is None else layers
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n = n_side * n_side * layers
+    bd = _bodies(n)
+    bd["shape"][:] = SHAPE_BOX
+    bd["shape_param"][:] = 0.5 * rng.uniform(0.5, 1.5, size=(n, 3))
+    bd["density"][:] = 1000.0
+    bd["A0"][:] = random_rotations(rng, n)
+    ix, iy, iz = np.meshgrid(np.arange(n_side), np.arange(layers), np.arange(n_side), indexing="ij")
+    grid = np.stack([ix.ravel(), iy.ravel(), iz.ravel()], axis=1).astype(np.float64)
+    lift = base_height + math.sqrt(3.0) * 0.75
+    centre = np.array([(n_side - 1) * spacing / 2, 0.0, (n_side - 1) * spacing / 2])
+    bd["c0"][:] = grid * spacing - centre + np.array([0.0, lift, 0.0])
+    bd["c0"][:] += rng.uniform(-jitter, jitter, size=(n, 3))
+    return SceneDesc(**bd, **_empty_bonds(0), h=h, iters=iters, contact_enable=1, mu=mu,
+                     contact_kappa_scale=0.3, contact_margin=0.01,
+                     planes=np.array([[0.0, 1.0, 0.0, 0.0]]), precision=precision,
+                     name=name or f"boxdrop{n}")
+
+
+def box_stack(n: int = 6, mass_ratio: float = 10.0, size: float = 1.0, gap: float = 0.0,
+              mu: float = 0.5, iters: int = 30, precision: int = PREC_FP64,
+              name: str = "") -> SceneDesc:
+    """Axis-aligned stack of n cubes resting on the ground plane y = 0, each box
+    ``mass_ratio`` times heavier than the one below it (bottom box density 100)."""
+    bd = _bodies(n)
+    bd["shape"][:] = SHAPE_BOX
+    bd["shape_param"][:] = size / 2
+    bd["density"][:] = 100.0 * mass_ratio ** np.arange(n)
+    bd["c0"][:, 1] = size / 2 + np.arange(n) * (size + gap)
+    return SceneDesc(**bd, **_empty_bonds(0), iters=iters, contact_enable=1, mu=mu,
+                     planes=np.array([[0.0, 1.0, 0.0, 0.0]]), precision=precision,
+                     name=name or f"stack{n}x{mass_ratio:g}")
+
+
+def single_body(shape: int = SHAPE_BOX, half=(0.5, 0.5, 0.5), density: float = 1.0,
+                c=(0.0, 0.0, 0.0), A=None, v=(0.0, 0.0, 0.0), w=(0.0, 0.0, 0.0),
+                gravity=(0.0, -9.81, 0.0), iters: int = 20, h: float = 1.0 / 60.0,
+                precision: int = PREC_FP64) -> SceneDesc:
+    bd = _bodies(1)
+    bd["shape"][0] = shape
+    bd["shape_param"][0] = half
+    bd["density"][0] = density
+    bd["c0"][0] = c
+    if A is not None:
+        bd["A0"][0] = A
+    bd["v0"][0] = v
+    bd["w0"][0] = w
+    return SceneDesc(**bd, **_empty_bonds(0), gravity=np.asarray(gravity, float), iters=iters, h=h,
+                     precision=precision, name="single")
+
+
+def world_pendulum(ell: float = 0.5, theta0_deg: float = 0.0, kappa: float = 1e5,
+                   h: float = 1.0 / 60.0, iters: int = 20, precision: int = PREC_FP64) -> SceneDesc:
+    """Unit cube hung from the world point (0, 0, 0) by a ball joint at the
+    material point (0, ell, 0), swung by theta0 about z."""
+    bd = _bodies(1)
+    bd["shape_param"][0] = 0.5
+    R = rot_z(math.radians(theta0_deg))
+    x = np.array([0.0, ell, 0.0])
+    bd["A0"][0] = R
+    bd["c0"][0] = -(R @ x)
+    bonds = _empty_bonds(1)
+    bonds["bond_i"][0], bonds["bond_j"][0] = 0, -1
+    bonds["x_i"][0] = x
+    bonds["kappa"][0] = kappa
+    return SceneDesc(**bd, **bonds, h=h, iters=iters, precision=precision, name="pendulum")
+
+
+# ---------------------------------------------------------------------------
+# serving requests (Poisson arrivals of chains and box piles)
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class Request:
+    arrival_s: float
+    scene: SceneDesc
+    steps: int
+
+
+def pile(n: int, seed: int, precision: int = PREC_FP32, iters: int = 30) -> SceneDesc:
+    """A box pile of about n boxes as in the box drop, on a near-square lattice."""
+    side = max(1, int(round(n ** (1.0 / 3.0))))
+    layers = max(1, int(math.ceil(n / (side * side))))
+    full = box_drop(n_side=side, layers=layers, seed=seed, iters=iters, precision=precision)
+    keep = np.arange(n)
+    return full.copy(shape=full.shape[keep], shape_param=full.shape_param[keep],
+                     density=full.density[keep], flags=full.flags[keep], group=full.group[keep],
+                     c0=full.c0[keep], A0=full.A0[keep], v0=full.v0[keep], w0=full.w0[keep],
+                     name=f"pile{n}_s{seed}")
+
+
+def serving_requests(rate_hz: float = 200.0, duration_s: float = 60.0, seed: int = 3,
+                     n_lo: int = 8, n_hi: int = 5000, steps_lo: int = 60, steps_hi: int = 600,
+                     precision: int = PREC_FP32, max_requests: Optional[int] = None) -> List[Request]:
+    """Poisson arrivals; body counts log-uniform in [n_lo, n_hi]; half random
+    chains (K = 20), half box piles (K = 30); U{steps_lo..steps_hi} steps each."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    t, out = 0.0, []
+    while True:
+        t += rng.exponential(1.0 / rate_hz)
+        if t >= duration_s or (max_requests is not None and len(out) >= max_requests):
+            break
+        n = int(round(math.exp(rng.uniform(math.log(n_lo), math.log(n_hi)))))
+        steps = int(rng.integers(steps_lo, steps_hi + 1))
+        sub = int(rng.integers(0, 2**31 - 1))
+        if rng.uniform() < 0.5:
+            r2 = np.random.Generator(np.random.PCG64(sub))
+            ang = r2.uniform(-30.0, 30.0, size=n - 1)
+            sc = chain(n, tilt_deg=0.0, joint_angles_deg=ang, iters=20, precision=precision,
+                       name=f"req{len(out)}_chain{n}")
+        else:
+            sc = pile(n, seed=sub, precision=precision)
+            sc.name = f"req{len(out)}_pile{n}"
+        out.append(Request(arrival_s=t, scene=sc, steps=steps))
+    return out

@@ -1,0 +1,115 @@
+"""Invariants of the oracle's contact bonds.  The paper's own contact and
+friction energies are in its (unavailable) supplement, so the contact model is a
+reading (contact bond with a stick anchor, normal gate and Coulomb clamp); these
+tests pin what that reading must satisfy geometrically and physically.  Parity
+with the paper's own contact model is unpinned."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2609_02675_amd import scenes as S
+
+
+def _verts(he):
+    return np.array([[sx, sy, sz] for sz in (-1, 1) for sy in (-1, 1) for sx in (-1, 1)]) * he
+
+
+def test_box_plane_contacts_are_the_vertices_within_the_margin():
+    rng = np.random.default_rng(1)
+    R = S.random_rotations(rng, 1)[0]
+    sc = S.box_stack(n=1).copy(A0=R[None], c0=np.array([[0.2, 0.62, -0.1]]))
+    o = oracle.Oracle(sc)
+    o.detect()
+    ct = o.contacts()
+    y = sc.c0[0] + _verts(sc.shape_param[0]) @ R.T
+    expect = sorted(np.nonzero(y[:, 1] < sc.contact_margin)[0].tolist())
+    assert sorted(ct["feature"].tolist()) == expect
+    assert np.all(ct["j"] == -1)
+    for k, f in enumerate(ct["feature"]):
+        np.testing.assert_allclose(ct["x_i"][k], _verts(sc.shape_param[0])[f], atol=1e-15)
+        np.testing.assert_allclose(ct["x_j"][k], [y[f, 0], 0.0, y[f, 2]], atol=1e-14)
+
+
+def test_sphere_sphere_contact_geometry():
+    sc = S.single_body(shape=S.SHAPE_SPHERE, half=(0.3, 0, 0), density=500.0)
+    sc = S.merge([sc, sc.copy(c0=np.array([[0.35, 0.4, 0.1]]), shape_param=np.array([[0.25, 0, 0]]))])
+    sc = sc.copy(contact_enable=1, A0=np.stack([S.rot_z(0.3), S.rot_axis((1, 2, 3), 1.0)]))
+    o = oracle.Oracle(sc)
+    o.detect()
+    ct = o.contacts()
+    assert len(ct["i"]) == 1 and ct["i"][0] == 0 and ct["j"][0] == 1
+    d = sc.c0[1] - sc.c0[0]
+    n = -d / np.linalg.norm(d)
+    np.testing.assert_allclose(ct["normal"][0], n, atol=1e-15)
+    yi = sc.c0[0] + sc.A0[0] @ ct["x_i"][0]
+    yj = sc.c0[1] + sc.A0[1] @ ct["x_j"][0]
+    np.testing.assert_allclose(yi, sc.c0[0] - 0.3 * n, atol=1e-15)
+    np.testing.assert_allclose(yj, sc.c0[1] + 0.25 * n, atol=1e-15)
+    assert n @ (yi - yj) == pytest.approx(np.linalg.norm(d) - 0.55, abs=1e-14)
+
+
+def test_aligned_box_stack_contacts_use_face_normals():
+    sc = S.box_stack(n=2, mass_ratio=1.0)
+    o = oracle.Oracle(sc)
+    o.detect()
+    ct = o.contacts()
+    pair = ct["j"] >= 0
+    assert pair.sum() == 4 and (~pair).sum() == 4
+    for k in np.nonzero(pair)[0]:
+        # vertex of the incident box on the reference face, normal along +-y
+        assert abs(abs(ct["normal"][k][1]) - 1.0) < 1e-15
+
+
+def test_box_at_rest_on_plane_stays_at_rest():
+    sc = S.box_stack(n=1)
+    o = oracle.Oracle(sc)
+    o.step(240)
+    c, A, v, w = o.state()
+    assert np.abs(v).max() < 1e-6 and np.abs(w).max() < 1e-6
+    np.testing.assert_allclose(A[0], np.eye(3), atol=1e-9)
+    # sinks by the contact compliance plus the projection offset (bounded, steady)
+    assert 0.45 < c[0, 1] < 0.5
+    o.step(60)
+    assert abs(o.state()[0][0, 1] - c[0, 1]) < 1e-7
+
+
+def _incline(theta_deg, mu):
+    th = math.radians(theta_deg)
+    n = np.array([-math.sin(th), math.cos(th), 0.0])
+    R = S.rot_z(th)
+    sc = S.box_stack(n=1, mu=mu).copy(planes=np.array([[n[0], n[1], n[2], 0.0]]),
+                                      A0=R[None], c0=(R @ np.array([0, 0.5, 0]))[None])
+    t_dir = np.array([math.cos(th), math.sin(th), 0.0])
+    o = oracle.Oracle(sc)
+    o.step(60)
+    v1 = o.state()[2][0] @ t_dir
+    o.step(60)
+    v2 = o.state()[2][0] @ t_dir
+    return (v2 - v1) / 1.0, v2
+
+
+def test_incline_slip_accelerates_at_coulomb_rate():
+    acc, _ = _incline(35.0, 0.5)
+    th = math.radians(35.0)
+    assert -acc == pytest.approx(9.81 * (math.sin(th) - 0.5 * math.cos(th)), rel=0.1)
+
+
+def test_incline_below_friction_angle_does_not_accelerate():
+    acc, v = _incline(20.0, 0.5)
+    assert abs(acc) < 0.02 * 9.81 * math.sin(math.radians(20.0))
+    assert abs(v) < 0.5  # bounded creep from the per-step anchor reset
+
+
+def test_mass_ratio_stack_is_stable():
+    """Six boxes, each ten times heavier than the one below (the paper's mass-ratio
+    stack): it stays upright and settles."""
+    sc = S.box_stack(n=6, mass_ratio=10.0)
+    o = oracle.Oracle(sc)
+    o.step(180)
+    c, A, v, w = o.state()
+    assert np.abs(v).max() < 0.2
+    assert np.all(np.diff(c[:, 1]) > 0.8)
+    assert np.abs(c[:, [0, 2]]).max() < 1e-6
+    assert c[0, 1] > 0.4
