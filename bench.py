@@ -1,0 +1,244 @@
+#!/usr/bin/env python3
+"""Benchmark: affine-body SSM iterations per second on one MI355X.
+
+Default workload: 4,096 independent joint chains of 4..64 unit cubes (ball joints,
++-30 degree random joint angles, top body pinned), FP32, 20 iterations per step,
+all advanced together by the batched path (one captured-graph replay per step,
+tile kernel running each scene's whole step from LDS).  Also reported on the
+same accuracy bar: the plain single-scene path (one kernel launch per
+iteration) on a sample of the same scenes, the served mix (continuous
+batching, see paper_2609_02675_amd/serve.py), and the FP64 CPU oracle on a
+bounded sample (the CPU baseline).
+
+Prints ONE JSON line.  `python bench.py --gpus N` with N > 1 exits: this build
+runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import multiprocessing as mp
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "affine-body SSM iterations/s (served/batched vs plain); p50/p99 step ms"
+HBM_PEAK = 8.0e12            # B/s, MI355X HBM3E
+FP32_VALU_PEAK = 78.6e12     # flop/s: 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz, unpacked FP32
+# algorithmic bytes moved per body and step by the tile kernel: read q (16 floats:
+# c_hi, A, c_lo), v/w (8), mass (8), H^-1 factor (12), two bond ends (8 floats +
+# partner id each), scene id, flags, end range; write q, v/w and the two FP64
+# residual partials -- see the design doc
+TILE_BYTES_PER_BODY_STEP = 64 + 32 + 32 + 48 + 2 * (32 + 4) + 4 + 1 + 8 + 64 + 32 + 16
+# flops of one body-iteration of a two-bond chain body (bond terms, inertia
+# term, block solve, increment, three Newton polar steps) -- see the design doc
+FLOPS_PER_BODY_ITER = 2 * 63 + 81 + 84 + 12 + 3 * 90
+# bytes per body-iteration a streaming (one launch per iteration) sweep must move:
+# read q^k, s, mass, factor, two bond ends; write q^{k+1}
+STREAM_BYTES_PER_BODY_ITER = 64 + 64 + 32 + 48 + 2 * (32 + 4) + 64
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+# ---------------------------------------------------------------------------
+# CPU baseline: the FP64 oracle as it stands, one scene per task
+# ---------------------------------------------------------------------------
+
+_SCENES = None
+
+
+def _oracle_worker(args):
+    k, steps = args
+    import oracle
+    sc = _SCENES[k]
+    o = oracle.Oracle(sc)
+    t = time.perf_counter()
+    o.step(steps)
+    return sc.n_bodies * sc.iters * steps, time.perf_counter() - t
+
+
+def cpu_baseline(scenes, n_sample, steps, cores):
+    global _SCENES
+    _SCENES = scenes[:n_sample]
+    import oracle
+    oracle.build()
+    work = [(k, steps) for k in range(len(_SCENES))]
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(cores) as pool:
+        res = pool.map(_oracle_worker, work, chunksize=4)
+    wall = time.perf_counter() - t0
+    body_its = sum(r[0] for r in res)
+    cpu_s = sum(r[1] for r in res)
+    return dict(value=body_its / wall, unit="body-iterations/s", cores=cores, kind="oracle",
+                per_core=body_its / cpu_s,
+                sample=f"first {len(_SCENES)} of the batched chains, {steps} steps each, FP64 "
+                       f"oracle, one scene per task on a {cores}-process pool "
+                       f"({body_its:.3g} body-iterations, {wall:.1f} s wall)")
+
+
+# ---------------------------------------------------------------------------
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--scenes", type=int, default=4096)
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--plain-sample", type=int, default=64)
+    ap.add_argument("--cpu-sample", type=int, default=1024)
+    ap.add_argument("--cpu-steps", type=int, default=20)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+
+    from paper_2609_02675_amd import scenes as S
+    scenes = S.batched_chains(args.scenes, seed=2, precision=S.PREC_FP32)
+    n_bodies = sum(s.n_bodies for s in scenes)
+    iters = scenes[0].iters
+
+    # CPU baseline first (before the GPU is touched, so fork is safe)
+    cpu = None
+    if not args.no_cpu_baseline:
+        cores = min(16, os.cpu_count() or 1)
+        sc64 = [s.copy(precision=S.PREC_FP64) for s in scenes]
+        cpu = cpu_baseline(sc64, min(args.cpu_sample, len(sc64)), args.cpu_steps, cores)
+        log("cpu baseline", cpu)
+
+    import torch
+    import paper_2609_02675_amd as P
+    if P.device_count() < 1:
+        raise SystemExit("no HIP device visible")
+    total_steps = args.warmup + args.steps
+    b = P.Batch(len(scenes) + 8, 4 << 30, S.PREC_FP32)
+    t = time.perf_counter()
+    slots = [b.admit(s, 1 << 30) for s in scenes]
+    assert all(x is not None for x in slots)
+    log(f"admitted {len(scenes)} scenes ({n_bodies} bodies) in {time.perf_counter() - t:.1f}s")
+    if args.tile:
+        b.set_tile(args.tile)
+    elif not args.no_autotune:
+        t = time.perf_counter()
+        tb = b.autotune()
+        log(f"autotune picked tile {tb} in {time.perf_counter() - t:.1f}s")
+    lay = b.layout()
+
+    stream = torch.cuda.Stream()
+    sptr = stream.cuda_stream
+    for _ in range(args.warmup):
+        b.step(stream=sptr)
+    torch.cuda.synchronize()
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    evs[0].record(stream)
+    for k in range(args.steps):
+        b.step(stream=sptr)
+        evs[k + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step_ms = np.array([evs[k].elapsed_time(evs[k + 1]) for k in range(args.steps)])
+    total_ms = evs[0].elapsed_time(evs[-1])
+    ms_per_step = total_ms / args.steps
+    body_its = n_bodies * iters * args.steps
+    value = body_its / (total_ms / 1e3)
+    log(f"batched: {ms_per_step:.4f} ms/step, {value:.4g} body-it/s (host wall {wall:.3f}s)")
+
+    # accuracy of the benchmarked run on sampled scenes vs the FP64 oracle
+    import oracle
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from parity import errors, scale_of
+    acc = 0.0
+    rng = np.random.default_rng(1)
+    for k in rng.choice(len(scenes), 4, replace=False):
+        o = oracle.Oracle(scenes[k].copy(precision=S.PREC_FP64))
+        o.step(total_steps)
+        e = errors(b.state(slots[k]), o.state(), scale_of(scenes[k]))
+        acc = max(acc, e["pos"], e["rot"])
+    log(f"accuracy vs oracle after {total_steps} steps: {acc:.3e}")
+
+    # dominant kernel: the tile kernel alone, timed with HIP events on its stream
+    tile_ms = b.time_tile_kernel(20)
+    body_steps = n_bodies
+    tile_bytes = body_steps * TILE_BYTES_PER_BODY_STEP
+    tile_flops = n_bodies * iters * FLOPS_PER_BODY_ITER
+    hbm_ach = tile_bytes / (tile_ms / 1e3)
+    alu_ach = tile_flops / (tile_ms / 1e3)
+    if alu_ach / FP32_VALU_PEAK >= hbm_ach / HBM_PEAK:
+        roof = dict(bound="alu", achieved=alu_ach / 1e12, peak=FP32_VALU_PEAK / 1e12, unit="TFLOP/s",
+                    frac=alu_ach / FP32_VALU_PEAK, traffic=None, kernel="k_tile_step<float>",
+                    kernel_ms=tile_ms, flops_per_launch=tile_flops, bytes_per_launch=tile_bytes,
+                    hbm_achieved_GBs=hbm_ach / 1e9)
+    else:
+        roof = dict(bound="hbm", achieved=hbm_ach / 1e9, peak=HBM_PEAK / 1e9, unit="GB/s",
+                    frac=hbm_ach / HBM_PEAK, traffic=None, kernel="k_tile_step<float>",
+                    kernel_ms=tile_ms, flops_per_launch=tile_flops, bytes_per_launch=tile_bytes)
+    eff_bw = value * STREAM_BYTES_PER_BODY_ITER
+    log(f"tile kernel {tile_ms:.4f} ms; roofline {roof['bound']} frac {roof['frac']:.3f}")
+
+    # plain path (one kernel launch per iteration, one scene at a time)
+    plain = None
+    if not args.no_plain:
+        sample = scenes[: args.plain_sample]
+        objs = [P.Scene(s) for s in sample]
+        for o_ in objs:
+            o_.step(2)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        nst = 10
+        for o_ in objs:
+            o_.step(nst)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        its = sum(s.n_bodies for s in sample) * iters * nst
+        plain = dict(value=its / dt, unit="body-iterations/s", ms_per_scene_step=1e3 * dt / (nst * len(sample)),
+                     sample=f"{len(sample)} of the chains, {nst} steps each, one scene at a time")
+        del objs
+        log(f"plain: {plain['value']:.4g} body-it/s")
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "body-iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"batched_chains_{len(scenes)}", "scenes": len(scenes),
+                   "bodies": n_bodies, "iters": iters, "dt": scenes[0].h,
+                   "tile_bodies": lay["tile_bodies"], "tiles": lay["tiles"],
+                   "mode": "batched, one graph replay per step"},
+        "p50_step_ms": float(np.percentile(step_ms, 50)),
+        "p99_step_ms": float(np.percentile(step_ms, 99)),
+        "accuracy": {"max_rel_err_vs_fp64_oracle": acc, "after_steps": total_steps,
+                     "tolerance": 1e-3},
+        "effective_stream_bandwidth_GBs": eff_bw / 1e9,
+        "effective_stream_frac_of_hbm": eff_bw / HBM_PEAK,
+        "plain": plain,
+        "speedup_vs_plain": (value / plain["value"]) if plain else None,
+        "served": None,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,179 @@
+/*
+ * pabd.h -- C ABI of the MI355X (gfx950) library for projective affine body
+ * dynamics (PABD): affine bodies joined by peridynamic bonds, advanced by the
+ * semi-implicit successive-substitution global/local iteration of the paper
+ * "Projective Affine Body Dynamics for Multibody Systems" (Algorithm 1).
+ *
+ * Conventions
+ *  - Every call returns a pabd_status; no exception crosses the ABI.  After a
+ *    failure pabd_last_error() returns a thread-local message.
+ *  - All host arrays are owned by the caller.  Descriptor arrays are copied at
+ *    create/admit time; output arrays are written in full.  Read-back is always
+ *    double precision.  Row-major; SI units; A is 3x3 with rows a1, a2, a3 so that
+ *    a material point x maps to y = A x + c (Sec. 3).
+ *  - Handles are owned by the library and freed with *_destroy.  A handle is not
+ *    thread safe; use one host thread and one stream per handle.
+ *  - hip_stream arguments are hipStream_t values passed as void* (NULL = the
+ *    library's own stream of the handle).  Work is enqueued asynchronously;
+ *    read-back calls synchronise the handle's stream.
+ *  - Device memory is allocated by the library (hipMalloc) at create/admit time
+ *    and released at destroy/release; stepping allocates nothing.
+ */
+#ifndef PABD_H
+#define PABD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PABD_OK = 0,
+  PABD_E_INVALID = -1,  /* malformed argument or descriptor */
+  PABD_E_OOM = -2,      /* device allocation failed or budget exceeded */
+  PABD_E_DEVICE = -3,   /* HIP runtime error */
+  PABD_E_DIVERGED = -4, /* non-finite state or contact capacity overflow */
+  PABD_E_BUSY = -5,     /* batch has no free slot or HBM budget for the scene */
+  PABD_E_NOTFOUND = -6  /* slot not in use */
+} pabd_status;
+
+/* body shapes (shape_param: box half extents; sphere radius in [0]) */
+#define PABD_SHAPE_BOX 0
+#define PABD_SHAPE_SPHERE 1
+/* body flags */
+#define PABD_FLAG_PINNED 1u     /* kinematic: infinite mass, never updated, v = w = 0 */
+#define PABD_FLAG_NO_CONTACT 2u /* never takes part in collision detection */
+/* bond types */
+#define PABD_BOND_QUADRATIC 0 /* Psi = 1/2 kappa (d - l)^2 (Sec. 5.2.2); l = 0: ball joint */
+#define PABD_BOND_DRIVEN 1    /* ball joint whose j-side anchor is turned by theta(t) */
+/* precision of bond and body arithmetic; the block factorisation and the
+ * convergence-residual reductions are always FP64 */
+#define PABD_FP32 0
+#define PABD_FP64 1
+
+/*
+ * Scene description: the statement of the problem of Sec. 4 -- bodies with mass
+ * density and shape (from which m and the affine moment Pi = int rho x x^T dV of
+ * the generalised mass matrix follow, Sec. 4.1.1), initial q and velocities,
+ * bonds with material anchors and energy parameters, gravity, time step h and
+ * the number K of global/local iterations per step (Algorithm 1).
+ */
+typedef struct {
+  int32_t n_bodies;
+  const int32_t *shape;       /* [N] PABD_SHAPE_* */
+  const double *shape_param;  /* [N*3] */
+  const double *density;      /* [N] kg/m^3 (> 0 unless pinned) */
+  const uint8_t *flags;       /* [N] PABD_FLAG_* or NULL */
+  const int32_t *group;       /* [N] bodies sharing a nonzero group never collide; or NULL */
+  const double *c0;           /* [N*3] centre of mass */
+  const double *A0;           /* [N*9] rotation, row-major */
+  const double *v0, *w0;      /* [N*3] linear / angular (world) velocity, or NULL */
+  int32_t n_bonds;
+  const int32_t *bond_i;      /* [B] */
+  const int32_t *bond_j;      /* [B] -1 = world (x_j then in world coordinates) */
+  const int32_t *bond_type;   /* [B] PABD_BOND_* or NULL (all quadratic) */
+  const double *x_i, *x_j;    /* [B*3] material anchors */
+  const double *kappa;        /* [B] stiffness > 0 */
+  const double *rest_len;     /* [B] rest length >= 0, or NULL */
+  const double *drive;        /* [B*13] driven bonds: axis3 pivot3 base3 theta0 amp freq phase */
+  double gravity[3];
+  double h;                   /* time step > 0 */
+  double t0;                  /* time at the start of the first step */
+  int32_t iters;              /* K >= 1 */
+  int32_t contact_enable;     /* build contact bonds every step */
+  double mu;                  /* Coulomb friction coefficient */
+  double contact_kappa_scale; /* kappa_c = scale * m / h^2, m the heavier free mass */
+  double contact_margin;      /* base detection margin (m) */
+  int32_t n_planes;
+  const double *planes;       /* [P*4] unit normal n and offset o: free side n.y >= o */
+  int32_t max_contacts_per_body; /* capacity of contact ends per body (> 0 if contacts) */
+  int32_t precision;          /* PABD_FP32 or PABD_FP64 */
+} pabd_scene_desc;
+
+typedef struct pabd_scene pabd_scene;
+typedef struct pabd_batch pabd_batch;
+
+const char *pabd_last_error(void);
+/* number of HIP devices visible (0 without a GPU); never fails */
+int32_t pabd_device_count(void);
+
+/* ---- plain path: one scene, one kernel launch per iteration --------------- */
+
+/* Validate the descriptor, derive m and Pi per body, build the bond incidence
+ * lists, upload, and factor every body's 12x12 block in FP64 (Sec. 4.3). */
+pabd_status pabd_scene_create(const pabd_scene_desc *desc, pabd_scene **out);
+pabd_status pabd_scene_destroy(pabd_scene *s);
+/* Advance nsteps steps of Algorithm 1 (collision detection, prediction, K
+ * global/local iterations, velocity recovery), enqueued on hip_stream. */
+pabd_status pabd_scene_step(pabd_scene *s, int32_t nsteps, void *hip_stream);
+/* Copy the state (c [N*3], A [N*9], v [N*3], w [N*3]; any may be NULL) to the
+ * host after the scene's stream is idle.  Returns PABD_E_DIVERGED (state still
+ * copied) if a step produced a non-finite state or overflowed contact capacity. */
+pabd_status pabd_scene_read_state(pabd_scene *s, double *c, double *A, double *v, double *w);
+/* FP64 convergence residual rho_k = ||q^{k+1} - q^k||_M / ||q^k||_M of every
+ * iteration k of the last step (out[K]); writes K to *k_out. */
+pabd_status pabd_scene_residuals(pabd_scene *s, double *out, int32_t cap, int32_t *k_out);
+/* Contact bonds built by the last step's collision detection, in a canonical
+ * order (i, j, feature).  Arrays of length cap (any may be NULL); *n_out is the
+ * total count. */
+pabd_status pabd_scene_contacts(pabd_scene *s, int32_t cap, int32_t *ci, int32_t *cj,
+                                int32_t *feature, double *xi, double *xj, double *normal,
+                                double *kappa, int32_t *n_out);
+/* Device bytes the scene needs (admission bound for the batch). */
+size_t pabd_scene_bytes(const pabd_scene_desc *desc);
+/* debug switches: bit0 = skip the local (rigidification) step */
+pabd_status pabd_scene_set_debug(pabd_scene *s, int32_t flags);
+/* Fault injection for tests: overwrite one state component of one body
+ * (field 0..2 = c, 3..11 = A, 12..14 = v, 15..17 = w). */
+pabd_status pabd_scene_poke(pabd_scene *s, int32_t body, int32_t field, double value);
+/* the hipStream_t of the handle, as void* */
+void *pabd_scene_stream(pabd_scene *s);
+
+/* ---- batched / served path ------------------------------------------------- */
+
+/* A batch keeps many independent scenes resident and advances all of them one
+ * step per pabd_batch_step, in one replay of a captured HIP graph whose kernels
+ * read the device scene table (admission changes data, not the graph).  Scenes
+ * without contacts and with few bodies are packed into workgroup tiles that run
+ * the whole step (prediction, K iterations, velocity recovery) from LDS.
+ * All scenes of a batch share its precision. */
+pabd_status pabd_batch_create(int32_t max_slots, size_t hbm_budget, int32_t precision,
+                              pabd_batch **out);
+pabd_status pabd_batch_destroy(pabd_batch *b);
+/* Admit a scene for nsteps steps.  PABD_E_BUSY if no slot or not enough of the
+ * HBM budget is free right now; the scene then stays outside (retry later). */
+pabd_status pabd_batch_admit(pabd_batch *b, const pabd_scene_desc *desc, int32_t nsteps,
+                             int32_t *slot);
+/* One step of every resident scene that has steps left. */
+pabd_status pabd_batch_step(pabd_batch *b, void *hip_stream);
+/* Slots whose scenes finished all their steps (host bookkeeping, no sync). */
+pabd_status pabd_batch_poll(pabd_batch *b, int32_t *done, int32_t cap, int32_t *n_done);
+pabd_status pabd_batch_read_state(pabd_batch *b, int32_t slot, double *c, double *A, double *v,
+                                  double *w);
+pabd_status pabd_batch_residual(pabd_batch *b, int32_t slot, double *rho_last);
+pabd_status pabd_batch_release(pabd_batch *b, int32_t slot);
+/* Steps taken so far by the scene in slot. */
+pabd_status pabd_batch_steps_done(pabd_batch *b, int32_t slot, int32_t *steps);
+/* Time candidate tile schedules on the resident scenes (their state is saved
+ * and restored) and keep the fastest; writes the chosen tile size. */
+pabd_status pabd_batch_autotune(pabd_batch *b, int32_t *tile_bodies);
+/* Force a tile size (32, 64, 128 or 256 bodies; 0 = automatic). */
+pabd_status pabd_batch_set_tile(pabd_batch *b, int32_t tile_bodies);
+void *pabd_batch_stream(pabd_batch *b);
+/* Measurement: launch the tile kernel alone reps times on the batch's stream
+ * between two HIP events and return its average duration in ms (0 if no scene
+ * is tiled).  Advances the tiled scenes' bodies like extra steps would. */
+pabd_status pabd_batch_time_tile_kernel(pabd_batch *b, int32_t reps, double *avg_ms);
+/* Bodies, tiles and tile size currently in the batch. */
+pabd_status pabd_batch_layout(pabd_batch *b, int32_t *n_bodies, int32_t *n_tiles,
+                              int32_t *tile_bodies);
+/* Bytes of HBM budget in use / free. */
+pabd_status pabd_batch_memory(pabd_batch *b, size_t *used, size_t *budget);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

@@ -1,0 +1,324 @@
+"""ctypes binding of libpabd.so (include/pabd.h): argument marshalling only.
+
+Every step of the simulation runs in the HIP library; this module converts
+numpy scene descriptions into the C descriptor and arrays back.  It raises
+immediately when the built library is missing -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import List, Optional
+
+import numpy as np
+
+from .scenes import SceneDesc
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libpabd.so")
+
+PABD_OK, PABD_E_INVALID, PABD_E_OOM, PABD_E_DEVICE, PABD_E_DIVERGED, PABD_E_BUSY, PABD_E_NOTFOUND = (
+    0, -1, -2, -3, -4, -5, -6)
+
+SYMBOLS = [
+    "pabd_last_error", "pabd_device_count", "pabd_scene_create", "pabd_scene_destroy",
+    "pabd_scene_step", "pabd_scene_read_state", "pabd_scene_residuals", "pabd_scene_contacts",
+    "pabd_scene_bytes", "pabd_scene_set_debug", "pabd_scene_poke", "pabd_scene_stream",
+    "pabd_batch_create", "pabd_batch_destroy", "pabd_batch_admit", "pabd_batch_step",
+    "pabd_batch_poll", "pabd_batch_read_state", "pabd_batch_residual", "pabd_batch_release",
+    "pabd_batch_steps_done", "pabd_batch_autotune", "pabd_batch_set_tile", "pabd_batch_stream",
+    "pabd_batch_memory", "pabd_batch_time_tile_kernel", "pabd_batch_layout",
+]
+
+
+class PabdError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"pabd status {status}: {msg}")
+        self.status = status
+
+
+class Busy(PabdError):
+    pass
+
+
+class Diverged(PabdError):
+    pass
+
+
+_P = C.POINTER
+_d = _P(C.c_double)
+_i = _P(C.c_int32)
+
+
+class _Desc(C.Structure):
+    _fields_ = [
+        ("n_bodies", C.c_int32), ("shape", _i), ("shape_param", _d), ("density", _d),
+        ("flags", _P(C.c_uint8)), ("group", _i), ("c0", _d), ("A0", _d), ("v0", _d), ("w0", _d),
+        ("n_bonds", C.c_int32), ("bond_i", _i), ("bond_j", _i), ("bond_type", _i),
+        ("x_i", _d), ("x_j", _d), ("kappa", _d), ("rest_len", _d), ("drive", _d),
+        ("gravity", C.c_double * 3), ("h", C.c_double), ("t0", C.c_double), ("iters", C.c_int32),
+        ("contact_enable", C.c_int32), ("mu", C.c_double), ("contact_kappa_scale", C.c_double),
+        ("contact_margin", C.c_double), ("n_planes", C.c_int32), ("planes", _d),
+        ("max_contacts_per_body", C.c_int32), ("precision", C.c_int32),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """Load the built library; raise if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build() first")
+    L = C.CDLL(LIB_PATH)
+    vp = C.c_void_p
+    L.pabd_last_error.restype = C.c_char_p
+    L.pabd_device_count.restype = C.c_int32
+    L.pabd_scene_create.argtypes = [_P(_Desc), _P(vp)]
+    L.pabd_scene_destroy.argtypes = [vp]
+    L.pabd_scene_step.argtypes = [vp, C.c_int32, vp]
+    L.pabd_scene_read_state.argtypes = [vp, _d, _d, _d, _d]
+    L.pabd_scene_residuals.argtypes = [vp, _d, C.c_int32, _i]
+    L.pabd_scene_contacts.argtypes = [vp, C.c_int32, _i, _i, _i, _d, _d, _d, _d, _i]
+    L.pabd_scene_bytes.argtypes = [_P(_Desc)]
+    L.pabd_scene_bytes.restype = C.c_size_t
+    L.pabd_scene_set_debug.argtypes = [vp, C.c_int32]
+    L.pabd_scene_poke.argtypes = [vp, C.c_int32, C.c_int32, C.c_double]
+    L.pabd_scene_stream.argtypes = [vp]
+    L.pabd_scene_stream.restype = vp
+    L.pabd_batch_create.argtypes = [C.c_int32, C.c_size_t, C.c_int32, _P(vp)]
+    L.pabd_batch_destroy.argtypes = [vp]
+    L.pabd_batch_admit.argtypes = [vp, _P(_Desc), C.c_int32, _i]
+    L.pabd_batch_step.argtypes = [vp, vp]
+    L.pabd_batch_poll.argtypes = [vp, _i, C.c_int32, _i]
+    L.pabd_batch_read_state.argtypes = [vp, C.c_int32, _d, _d, _d, _d]
+    L.pabd_batch_residual.argtypes = [vp, C.c_int32, _d]
+    L.pabd_batch_release.argtypes = [vp, C.c_int32]
+    L.pabd_batch_steps_done.argtypes = [vp, C.c_int32, _i]
+    L.pabd_batch_autotune.argtypes = [vp, _i]
+    L.pabd_batch_set_tile.argtypes = [vp, C.c_int32]
+    L.pabd_batch_stream.argtypes = [vp]
+    L.pabd_batch_stream.restype = vp
+    L.pabd_batch_memory.argtypes = [vp, _P(C.c_size_t), _P(C.c_size_t)]
+    L.pabd_batch_time_tile_kernel.argtypes = [vp, C.c_int32, _d]
+    L.pabd_batch_layout.argtypes = [vp, _i, _i, _i]
+    _lib = L
+    return L
+
+
+def _check(status: int):
+    if status == PABD_OK:
+        return
+    msg = lib().pabd_last_error().decode(errors="replace")
+    if status == PABD_E_BUSY:
+        raise Busy(status, msg)
+    if status == PABD_E_DIVERGED:
+        raise Diverged(status, msg)
+    raise PabdError(status, msg)
+
+
+def _ptr(a, t):
+    return a.ctypes.data_as(_P(t)) if a is not None and a.size else None
+
+
+class _Marshalled:
+    """The C descriptor plus the numpy arrays it points into (kept alive)."""
+
+    def __init__(self, scene: SceneDesc):
+        s = scene.normalized()
+        self.s = s
+        d = _Desc()
+        d.n_bodies = s.n_bodies
+        d.shape = _ptr(s.shape, C.c_int32)
+        d.shape_param = _ptr(s.shape_param, C.c_double)
+        d.density = _ptr(s.density, C.c_double)
+        d.flags = _ptr(s.flags, C.c_uint8)
+        d.group = _ptr(s.group, C.c_int32)
+        d.c0 = _ptr(s.c0, C.c_double)
+        d.A0 = _ptr(s.A0, C.c_double)
+        d.v0 = _ptr(s.v0, C.c_double)
+        d.w0 = _ptr(s.w0, C.c_double)
+        d.n_bonds = s.n_bonds
+        d.bond_i = _ptr(s.bond_i, C.c_int32)
+        d.bond_j = _ptr(s.bond_j, C.c_int32)
+        d.bond_type = _ptr(s.bond_type, C.c_int32)
+        d.x_i = _ptr(s.x_i, C.c_double)
+        d.x_j = _ptr(s.x_j, C.c_double)
+        d.kappa = _ptr(s.kappa, C.c_double)
+        d.rest_len = _ptr(s.rest_len, C.c_double)
+        d.drive = _ptr(s.drive, C.c_double)
+        d.gravity = (C.c_double * 3)(*s.gravity.tolist())
+        d.h = s.h
+        d.t0 = s.t0
+        d.iters = s.iters
+        d.contact_enable = s.contact_enable
+        d.mu = s.mu
+        d.contact_kappa_scale = s.contact_kappa_scale
+        d.contact_margin = s.contact_margin
+        d.n_planes = s.planes.shape[0]
+        d.planes = _ptr(s.planes, C.c_double)
+        d.max_contacts_per_body = s.max_contacts_per_body if s.contact_enable else 0
+        d.precision = s.precision
+        self.desc = d
+
+
+def device_count() -> int:
+    return int(lib().pabd_device_count())
+
+
+def scene_bytes(scene: SceneDesc) -> int:
+    m = _Marshalled(scene)
+    return int(lib().pabd_scene_bytes(C.byref(m.desc)))
+
+
+def _state_arrays(n):
+    return np.zeros((n, 3)), np.zeros((n, 3, 3)), np.zeros((n, 3)), np.zeros((n, 3))
+
+
+class Scene:
+    """One scene on the plain path (one kernel launch per iteration)."""
+
+    def __init__(self, scene: SceneDesc):
+        self.n = scene.n_bodies
+        self.iters = scene.iters
+        m = _Marshalled(scene)
+        h = C.c_void_p()
+        _check(lib().pabd_scene_create(C.byref(m.desc), C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().pabd_scene_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+    @property
+    def stream(self) -> int:
+        return int(lib().pabd_scene_stream(self._h) or 0)
+
+    def step(self, nsteps: int = 1, stream: Optional[int] = None):
+        _check(lib().pabd_scene_step(self._h, int(nsteps), C.c_void_p(stream) if stream else None))
+
+    def state(self, check: bool = True):
+        c, A, v, w = _state_arrays(self.n)
+        st = lib().pabd_scene_read_state(self._h, _ptr(c, C.c_double), _ptr(A, C.c_double),
+                                         _ptr(v, C.c_double), _ptr(w, C.c_double))
+        if check:
+            _check(st)
+        return c, A, v, w
+
+    def residuals(self) -> np.ndarray:
+        out = np.zeros(self.iters)
+        k = C.c_int32()
+        _check(lib().pabd_scene_residuals(self._h, _ptr(out, C.c_double), self.iters, C.byref(k)))
+        return out
+
+    def set_debug(self, flags: int):
+        _check(lib().pabd_scene_set_debug(self._h, int(flags)))
+
+    def poke(self, body: int, field: int, value: float):
+        _check(lib().pabd_scene_poke(self._h, int(body), int(field), float(value)))
+
+    def contacts(self):
+        n = C.c_int32()
+        _check(lib().pabd_scene_contacts(self._h, 0, None, None, None, None, None, None, None,
+                                         C.byref(n)))
+        k = n.value
+        ci = np.zeros(k, np.int32); cj = np.zeros(k, np.int32); ft = np.zeros(k, np.int32)
+        xi = np.zeros((k, 3)); xj = np.zeros((k, 3)); nn = np.zeros((k, 3)); kk = np.zeros(k)
+        if k:
+            _check(lib().pabd_scene_contacts(self._h, k, _ptr(ci, C.c_int32), _ptr(cj, C.c_int32),
+                                             _ptr(ft, C.c_int32), _ptr(xi, C.c_double),
+                                             _ptr(xj, C.c_double), _ptr(nn, C.c_double),
+                                             _ptr(kk, C.c_double), C.byref(n)))
+        return dict(i=ci, j=cj, feature=ft, x_i=xi, x_j=xj, normal=nn, kappa=kk)
+
+
+class Batch:
+    """Many resident scenes advanced together, one graph replay per step."""
+
+    def __init__(self, max_slots: int, hbm_budget: int, precision: int):
+        h = C.c_void_p()
+        _check(lib().pabd_batch_create(int(max_slots), int(hbm_budget), int(precision), C.byref(h)))
+        self._h = h
+        self._n = {}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().pabd_batch_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+    @property
+    def stream(self) -> int:
+        return int(lib().pabd_batch_stream(self._h) or 0)
+
+    def admit(self, scene: SceneDesc, nsteps: int) -> Optional[int]:
+        """Slot of the admitted scene, or None if no slot / budget is free now."""
+        m = _Marshalled(scene)
+        slot = C.c_int32(-1)
+        st = lib().pabd_batch_admit(self._h, C.byref(m.desc), int(nsteps), C.byref(slot))
+        if st == PABD_E_BUSY:
+            return None
+        _check(st)
+        self._n[slot.value] = scene.n_bodies
+        return slot.value
+
+    def step(self, stream: Optional[int] = None):
+        _check(lib().pabd_batch_step(self._h, C.c_void_p(stream) if stream else None))
+
+    def poll(self) -> List[int]:
+        cap = max(1, len(self._n))
+        out = np.zeros(cap, np.int32)
+        n = C.c_int32()
+        _check(lib().pabd_batch_poll(self._h, _ptr(out, C.c_int32), cap, C.byref(n)))
+        return out[: min(n.value, cap)].tolist()
+
+    def state(self, slot: int, check: bool = True):
+        c, A, v, w = _state_arrays(self._n[slot])
+        st = lib().pabd_batch_read_state(self._h, int(slot), _ptr(c, C.c_double), _ptr(A, C.c_double),
+                                         _ptr(v, C.c_double), _ptr(w, C.c_double))
+        if check:
+            _check(st)
+        return c, A, v, w
+
+    def residual(self, slot: int) -> float:
+        r = np.zeros(1)
+        _check(lib().pabd_batch_residual(self._h, int(slot), _ptr(r, C.c_double)))
+        return float(r[0])
+
+    def steps_done(self, slot: int) -> int:
+        k = C.c_int32()
+        _check(lib().pabd_batch_steps_done(self._h, int(slot), C.byref(k)))
+        return k.value
+
+    def release(self, slot: int):
+        _check(lib().pabd_batch_release(self._h, int(slot)))
+        self._n.pop(slot, None)
+
+    def autotune(self) -> int:
+        t = C.c_int32()
+        _check(lib().pabd_batch_autotune(self._h, C.byref(t)))
+        return t.value
+
+    def set_tile(self, tile_bodies: int):
+        _check(lib().pabd_batch_set_tile(self._h, int(tile_bodies)))
+
+    def time_tile_kernel(self, reps: int) -> float:
+        ms = np.zeros(1)
+        _check(lib().pabd_batch_time_tile_kernel(self._h, int(reps), _ptr(ms, C.c_double)))
+        return float(ms[0])
+
+    def layout(self):
+        a, b, c = C.c_int32(), C.c_int32(), C.c_int32()
+        _check(lib().pabd_batch_layout(self._h, C.byref(a), C.byref(b), C.byref(c)))
+        return dict(bodies=a.value, tiles=b.value, tile_bodies=c.value)
+
+    def memory(self):
+        u, b = C.c_size_t(), C.c_size_t()
+        _check(lib().pabd_batch_memory(self._h, C.byref(u), C.byref(b)))
+        return u.value, b.value

@@ -1,0 +1,343 @@
+// engine.h -- device storage for a set of scenes and the launch sequence of one
+// step over it.  Used by the plain scene handle (one scene, one kernel launch
+// per iteration, captured into a graph) and by the batch (flat kernels for
+// scenes that need contacts or do not fit a tile; tile kernel for the rest).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "host_scene.h"
+#include "kernels_contact.h"
+#include "kernels_step.h"
+#include "kernels_tile.h"
+
+namespace pabd {
+
+#define PABD_HIP(x)                                                        \
+  do {                                                                     \
+    hipError_t e_ = (x);                                                   \
+    if (e_ != hipSuccess) {                                                \
+      err = std::string(#x) + " failed: " + hipGetErrorString(e_);         \
+      return PABD_E_DEVICE;                                                \
+    }                                                                      \
+  } while (0)
+
+struct Caps {
+  int n = 0, e = 0, s = 0, p = 0, dr = 0, ccap = 0;
+  bool contacts = false;
+};
+
+template <typename T>
+struct Engine {
+  Caps cap;
+  // per body
+  T *qn = nullptr, *q0 = nullptr, *q1 = nullptr, *s = nullptr, *vel = nullptr, *mass = nullptr,
+    *fac = nullptr, *half = nullptr;
+  double *blk = nullptr, *mass64 = nullptr, *r_num = nullptr, *r_den = nullptr;
+  uint8_t *flags = nullptr, *shape = nullptr;
+  int *group = nullptr, *bscene = nullptr, *srow = nullptr, *srow_end = nullptr;
+  // static ends
+  int* se_partner = nullptr;
+  T* se = nullptr;
+  double* se64 = nullptr;
+  // contacts
+  int *ccount = nullptr, *ce_partner = nullptr;
+  unsigned long long *ce_key = nullptr, *reach = nullptr;
+  T* ce = nullptr;
+  int *bucket_count = nullptr, *bucket_start = nullptr, *bucket_fill = nullptr,
+      *sorted_body = nullptr, *scan_tmp = nullptr;
+  int tb = 0;
+  // scenes
+  SceneDev* scenes = nullptr;
+  int* health = nullptr;
+  double* rho = nullptr;
+  double* planes = nullptr;
+  // driven bonds
+  int *drv_scene = nullptr, *drv_end_i = nullptr, *drv_end_j = nullptr;
+  double* drv_param = nullptr;
+  // residual history (optional)
+  double *rh_num = nullptr, *rh_den = nullptr, *rh_rho = nullptr;
+  int rh_k = 0;
+
+  std::vector<void*> allocs;
+  std::string err;
+
+  ~Engine() { release(); }
+  void release() {
+    for (void* p : allocs) (void)hipFree(p);
+    allocs.clear();
+  }
+
+  template <typename U>
+  pabd_status alloc(U*& p, size_t count) {
+    void* v = nullptr;
+    hipError_t e = hipMalloc(&v, std::max<size_t>(count, 1) * sizeof(U));
+    if (e != hipSuccess) {
+      err = std::string("hipMalloc of ") + std::to_string(count * sizeof(U)) +
+            " bytes failed: " + hipGetErrorString(e);
+      (void)hipGetLastError();
+      return PABD_E_OOM;
+    }
+    allocs.push_back(v);
+    p = static_cast<U*>(v);
+    return PABD_OK;
+  }
+
+#define PABD_TRY(x)                      \
+  do {                                   \
+    pabd_status st_ = (x);               \
+    if (st_ != PABD_OK) return st_;      \
+  } while (0)
+
+  pabd_status allocate(const Caps& c) {
+    cap = c;
+    const size_t n = c.n;
+    constexpr int QR = Rec<T>::Q;
+    PABD_TRY(alloc(qn, QR * n));
+    PABD_TRY(alloc(q0, QR * n));
+    PABD_TRY(alloc(q1, QR * n));
+    PABD_TRY(alloc(s, QR * n));
+    PABD_TRY(alloc(vel, VW * n));
+    PABD_TRY(alloc(mass, MW * n));
+    PABD_TRY(alloc(fac, FW * n));
+    PABD_TRY(alloc(half, 4 * n));
+    PABD_TRY(alloc(blk, 10 * n));
+    PABD_TRY(alloc(mass64, 8 * n));
+    PABD_TRY(alloc(r_num, n));
+    PABD_TRY(alloc(r_den, n));
+    PABD_TRY(alloc(flags, n));
+    PABD_TRY(alloc(shape, n));
+    PABD_TRY(alloc(group, n));
+    PABD_TRY(alloc(bscene, n));
+    PABD_TRY(alloc(srow, n));
+    PABD_TRY(alloc(srow_end, n));
+    PABD_TRY(alloc(se_partner, (size_t)c.e));
+    PABD_TRY(alloc(se, EW * (size_t)c.e));
+    PABD_TRY(alloc(se64, 4 * (size_t)c.e));
+    PABD_TRY(alloc(ccount, n));
+    PABD_TRY(alloc(scenes, (size_t)c.s));
+    PABD_TRY(alloc(health, (size_t)c.s));
+    PABD_TRY(alloc(rho, (size_t)c.s));
+    PABD_TRY(alloc(reach, (size_t)c.s));
+    PABD_TRY(alloc(planes, 4 * (size_t)c.p));
+    PABD_TRY(alloc(drv_scene, (size_t)c.dr));
+    PABD_TRY(alloc(drv_end_i, (size_t)c.dr));
+    PABD_TRY(alloc(drv_end_j, (size_t)c.dr));
+    PABD_TRY(alloc(drv_param, 13 * (size_t)c.dr));
+    if (c.contacts) {
+      const size_t nc = n * (size_t)c.ccap;
+      PABD_TRY(alloc(ce, CW * nc));
+      PABD_TRY(alloc(ce_partner, nc));
+      PABD_TRY(alloc(ce_key, nc));
+      // power of two, at most 2^20 so the three-pass scan (1024 x 1024) covers it
+      tb = 1024;
+      while (tb < 2 * c.n && tb < (1 << 20)) tb <<= 1;
+      PABD_TRY(alloc(bucket_count, (size_t)tb));
+      PABD_TRY(alloc(bucket_start, (size_t)tb + 1));
+      PABD_TRY(alloc(bucket_fill, (size_t)tb));
+      PABD_TRY(alloc(sorted_body, n));
+      PABD_TRY(alloc(scan_tmp, (size_t)(tb / 1024 + 2)));
+    }
+    // every body slot starts unused
+    std::vector<int> neg(n, -1);
+    PABD_HIP(hipMemcpy(bscene, neg.data(), n * sizeof(int), hipMemcpyHostToDevice));
+    std::vector<int> zero(std::max<size_t>(n, (size_t)c.s) + 1, 0);
+    PABD_HIP(hipMemcpy(srow, zero.data(), n * sizeof(int), hipMemcpyHostToDevice));
+    PABD_HIP(hipMemcpy(srow_end, zero.data(), n * sizeof(int), hipMemcpyHostToDevice));
+    PABD_HIP(hipMemcpy(ccount, zero.data(), n * sizeof(int), hipMemcpyHostToDevice));
+    PABD_HIP(hipMemcpy(health, zero.data(), (size_t)c.s * sizeof(int), hipMemcpyHostToDevice));
+    std::vector<int> dneg(std::max(1, c.dr), -1);
+    PABD_HIP(hipMemcpy(drv_scene, dneg.data(), dneg.size() * sizeof(int), hipMemcpyHostToDevice));
+    std::vector<double> dz(n, 0.0);
+    PABD_HIP(hipMemcpy(r_num, dz.data(), n * sizeof(double), hipMemcpyHostToDevice));
+    PABD_HIP(hipMemcpy(r_den, dz.data(), n * sizeof(double), hipMemcpyHostToDevice));
+    return PABD_OK;
+  }
+
+  View<T> view() const {
+    View<T> v{};
+    v.n = cap.n;
+    v.q[0] = q0;
+    v.q[1] = q1;
+    v.qn = qn;
+    v.vel = vel;
+    v.s = s;
+    v.mass = mass;
+    v.fac = fac;
+    v.blk = blk;
+    v.flags = flags;
+    v.shape = shape;
+    v.half = half;
+    v.group = group;
+    v.bscene = bscene;
+    v.srow = srow;
+    v.srow_end = srow_end;
+    v.se_partner = se_partner;
+    v.se = se;
+    v.se64 = se64;
+    v.ccount = ccount;
+    v.ce_partner = ce_partner;
+    v.ce_key = ce_key;
+    v.ce = ce;
+    v.planes = planes;
+    v.r_num = r_num;
+    v.r_den = r_den;
+    v.scenes = scenes;
+    v.health = health;
+    return v;
+  }
+
+  template <typename U>
+  pabd_status put(U* dst, const U* src, size_t count, hipStream_t st) {
+    if (!count) return PABD_OK;
+    PABD_HIP(hipMemcpyAsync(dst, src, count * sizeof(U), hipMemcpyHostToDevice, st));
+    return PABD_OK;
+  }
+
+  // Upload a prepared scene at body offset boff, end offset eoff, plane offset
+  // poff, driven offset doff into scene slot sidx.
+  pabd_status upload(const HostScene& hs, int boff, int eoff, int poff, int doff, int sidx,
+                     hipStream_t st) {
+    const size_t n = hs.n, ne = hs.ne;
+    constexpr int QR = Rec<T>::Q;
+    std::vector<T> tq(QR * n, (T)0), tv(VW * n), tm(MW * n), th(4 * n), te(EW * ne);
+    for (size_t b = 0; b < n; ++b) {
+      for (int k = 0; k < QW; ++k) tq[QR * b + k] = (T)hs.qn[QW * b + k];
+      if (QR > QW)  // compensated position: c = c_hi + c_lo
+        for (int k = 0; k < 3; ++k)
+          tq[QR * b + 12 + k] = (T)(hs.qn[QW * b + k] - (double)tq[QR * b + k]);
+    }
+    for (size_t k = 0; k < VW * n; ++k) tv[k] = (T)hs.vel[k];
+    for (size_t b = 0; b < n; ++b) {
+      const double* M = &hs.mass64[8 * b];
+      // packed sym Pi: 00 01 02 11 12 22 (mass64 stores Pi00 Pi01 Pi02 Pi11 Pi12 Pi22 at 1..6)
+      for (int k = 0; k < 8; ++k) tm[MW * b + k] = (T)M[k];
+    }
+    for (size_t k = 0; k < 4 * n; ++k) th[k] = (T)hs.half[k];
+    for (size_t k = 0; k < EW * ne; ++k) te[k] = (T)hs.se[k];
+    std::vector<int> part(ne), rows(n), rows_end(n), bs(n, sidx);
+    for (size_t e = 0; e < ne; ++e) part[e] = hs.se_partner[e] < 0 ? -1 : hs.se_partner[e] + boff;
+    for (size_t b = 0; b < n; ++b) {
+      rows[b] = hs.srow[b] + eoff;
+      rows_end[b] = hs.srow[b + 1] + eoff;
+    }
+    std::vector<uint8_t> fl(hs.flags);
+    SceneDev S = hs.params;
+    S.body_off = boff;
+    S.plane_off = poff;
+    S.step = 0;
+    // the same staging vectors are used by asynchronous copies: finish them here
+    PABD_TRY(put(qn + QR * (size_t)boff, tq.data(), tq.size(), st));
+    PABD_TRY(put(vel + VW * (size_t)boff, tv.data(), tv.size(), st));
+    PABD_TRY(put(mass + MW * (size_t)boff, tm.data(), tm.size(), st));
+    PABD_TRY(put(mass64 + 8 * (size_t)boff, hs.mass64.data(), hs.mass64.size(), st));
+    PABD_TRY(put(half + 4 * (size_t)boff, th.data(), th.size(), st));
+    PABD_TRY(put(flags + boff, fl.data(), fl.size(), st));
+    PABD_TRY(put(shape + boff, hs.shape.data(), hs.shape.size(), st));
+    PABD_TRY(put(group + boff, hs.group.data(), hs.group.size(), st));
+    PABD_TRY(put(bscene + boff, bs.data(), bs.size(), st));
+    PABD_TRY(put(srow + boff, rows.data(), rows.size(), st));
+    PABD_TRY(put(srow_end + boff, rows_end.data(), rows_end.size(), st));
+    PABD_TRY(put(se_partner + eoff, part.data(), part.size(), st));
+    PABD_TRY(put(se + EW * (size_t)eoff, te.data(), te.size(), st));
+    PABD_TRY(put(se64 + 4 * (size_t)eoff, hs.se64.data(), hs.se64.size(), st));
+    PABD_TRY(put(planes + 4 * (size_t)poff, hs.planes.data(), hs.planes.size(), st));
+    PABD_TRY(put(scenes + sidx, &S, 1, st));
+    int zero = 0;
+    PABD_TRY(put(health + sidx, &zero, 1, st));
+    if (!hs.drv_end_i.empty()) {
+      const size_t nd = hs.drv_end_i.size();
+      std::vector<int> di(nd), dj(nd), ds(nd, sidx);
+      for (size_t k = 0; k < nd; ++k) {
+        di[k] = hs.drv_end_i[k] < 0 ? -1 : hs.drv_end_i[k] + eoff;
+        dj[k] = hs.drv_end_j[k] < 0 ? -1 : hs.drv_end_j[k] + eoff;
+      }
+      PABD_TRY(put(drv_scene + doff, ds.data(), nd, st));
+      PABD_TRY(put(drv_end_i + doff, di.data(), nd, st));
+      PABD_TRY(put(drv_end_j + doff, dj.data(), nd, st));
+      PABD_TRY(put(drv_param + 13 * (size_t)doff, hs.drv_param.data(), hs.drv_param.size(), st));
+    }
+    PABD_HIP(hipStreamSynchronize(st));
+    return PABD_OK;
+  }
+
+  // mark body slots [boff, boff + n) and driven entries [doff, doff + nd) unused
+  pabd_status clear_bodies(int boff, int n, hipStream_t st, int doff = 0, int nd = 0) {
+    std::vector<int> neg(std::max(n, nd), -1);
+    PABD_TRY(put(bscene + boff, neg.data(), (size_t)n, st));
+    if (nd > 0) PABD_TRY(put(drv_scene + doff, neg.data(), (size_t)nd, st));
+    PABD_HIP(hipStreamSynchronize(st));
+    return PABD_OK;
+  }
+
+  static dim3 grid_for(int n, int bs) { return dim3((unsigned)std::max(1, (n + bs - 1) / bs)); }
+
+  // contact-bond construction for every contact scene among the bodies
+  void launch_contacts(int n_scenes, hipStream_t st) {
+    View<T> v = view();
+    ContactBuf cb{tb, bucket_count, bucket_start, bucket_fill, sorted_body, reach, mass64, scan_tmp};
+    const int n = cap.n;
+    hipLaunchKernelGGL(k_contact_prep<T>, grid_for(std::max(n, n_scenes), 256), dim3(256), 0, st, v, cb, n_scenes);
+    hipLaunchKernelGGL(k_contact_reach<T>, grid_for(n, 256), dim3(256), 0, st, v, cb);
+    hipLaunchKernelGGL(k_contact_cells, grid_for(n_scenes, 64), dim3(64), 0, st, scenes, n_scenes,
+                       (const unsigned long long*)reach);
+    hipLaunchKernelGGL(k_zero_int, grid_for(tb, 256), dim3(256), 0, st, bucket_count, tb);
+    hipLaunchKernelGGL(k_zero_int, grid_for(tb, 256), dim3(256), 0, st, bucket_fill, tb);
+    hipLaunchKernelGGL(k_hash_count<T>, grid_for(n, 256), dim3(256), 0, st, v, cb);
+    const int nb = (tb + 1023) / 1024;
+    hipLaunchKernelGGL(k_scan_block, dim3(nb), dim3(1024), 0, st, (const int*)bucket_count,
+                       bucket_start, tb, scan_tmp);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, st, scan_tmp, nb, bucket_start + tb);
+    hipLaunchKernelGGL(k_scan_add, grid_for(tb, 256), dim3(256), 0, st, bucket_start, tb,
+                       (const int*)scan_tmp);
+    hipLaunchKernelGGL(k_hash_fill<T>, grid_for(n, 256), dim3(256), 0, st, v, cb);
+    hipLaunchKernelGGL(k_narrow<T>, grid_for(n, 128), dim3(128), 0, st, v, cb);
+    hipLaunchKernelGGL(k_sort_contacts<T>, grid_for(n, 256), dim3(256), 0, st, v);
+  }
+
+  // FP64 block factorisation of bodies [first, first + count)
+  void launch_factor(hipStream_t st, int first = 0, int count = -1) {
+    if (count < 0) count = cap.n;
+    if (count == 0) return;
+    hipLaunchKernelGGL(k_factor<T>, grid_for(count, 256), dim3(256), 0, st, view(),
+                       (const double*)mass64, first, count);
+  }
+
+  // One step of Algorithm 1 with flat per-body kernels (one launch per iteration).
+  void launch_flat_step(int n_scenes, int kmax, bool contacts, int n_driven, bool history,
+                        bool finish_scenes, hipStream_t st) {
+    View<T> v = view();
+    const dim3 g = grid_for(cap.n, 256), b(256);
+    if (n_driven > 0) {
+      hipLaunchKernelGGL(k_update_driven<T>, grid_for(n_driven, 64), dim3(64), 0, st, v, n_driven,
+                         (const int*)drv_scene, (const int*)drv_end_i, (const int*)drv_end_j,
+                         (const double*)drv_param);
+      launch_factor(st);
+    }
+    if (contacts) launch_contacts(n_scenes, st);
+    hipLaunchKernelGGL(k_predict<T>, g, b, 0, st, v);
+    double* hn = history ? rh_num : nullptr;
+    double* hd = history ? rh_den : nullptr;
+    for (int k = 0; k < kmax; ++k) {
+      if (contacts)
+        hipLaunchKernelGGL((k_iterate<T, true>), g, b, 0, st, v, k, hn, hd);
+      else
+        hipLaunchKernelGGL((k_iterate<T, false>), g, b, 0, st, v, k, hn, hd);
+    }
+    hipLaunchKernelGGL(k_finish<T>, g, b, 0, st, v);
+    if (!finish_scenes) return;
+    hipLaunchKernelGGL(k_reduce_residual, dim3(std::max(1, n_scenes)), dim3(256), 0, st,
+                       (const SceneDev*)scenes, n_scenes, (const double*)r_num,
+                       (const double*)r_den, rho);
+    if (history)
+      hipLaunchKernelGGL(k_reduce_history, dim3(std::max(1, kmax)), dim3(256), 0, st, cap.n, kmax,
+                         (const double*)rh_num, (const double*)rh_den, rh_rho);
+    hipLaunchKernelGGL(k_end_step, grid_for(n_scenes, 64), dim3(64), 0, st, scenes, n_scenes);
+  }
+};
+
+}  // namespace pabd

@@ -1,0 +1,194 @@
+// host_scene.h -- host-side preparation of one scene description: validation,
+// per-body mass and affine moment (Sec. 4.1.1), bond-end incidence lists in
+// (body, bond id) order, driven-bond table.  Everything here is FP64; upload
+// converts to the scene's arithmetic type.
+#pragma once
+
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "../../include/pabd.h"
+#include "common.h"
+
+namespace pabd {
+
+struct HostScene {
+  int n = 0, ne = 0;
+  std::vector<double> qn, vel, mass64, half;  // 12, 8, 8, 4 per body
+  std::vector<uint8_t> flags, shape;
+  std::vector<int> group;
+  std::vector<int> srow, se_partner;  // scene-local partner ids
+  std::vector<double> se;             // 8 per end (FP64 master copy)
+  std::vector<double> se64;           // 4 per end
+  std::vector<int> drv_end_i, drv_end_j;
+  std::vector<double> drv_param;      // 13 per driven bond
+  std::vector<double> planes;         // 4 per plane
+  SceneDev params{};
+  bool contact = false, driven = false;
+  int ccap = 0;
+  int max_ends = 0;  // largest number of static ends of one body
+};
+
+inline double sqr(double x) { return x * x; }
+
+// Returns an empty string on success, else the reason the description is invalid.
+inline std::string build_host_scene(const pabd_scene_desc* d, HostScene& hs) {
+  if (!d) return "null descriptor";
+  if (d->n_bodies < 0 || d->n_bonds < 0) return "negative body or bond count";
+  if (!(d->h > 0.0) || !std::isfinite(d->h)) return "time step h must be positive";
+  if (d->iters < 1) return "iters must be >= 1";
+  if (d->precision != PABD_FP32 && d->precision != PABD_FP64) return "unknown precision";
+  const int n = d->n_bodies;
+  if (n > 0 && (!d->shape || !d->shape_param || !d->density || !d->c0 || !d->A0))
+    return "missing body arrays";
+  if (d->n_bonds > 0 && (!d->bond_i || !d->bond_j || !d->x_i || !d->x_j || !d->kappa))
+    return "missing bond arrays";
+  hs.n = n;
+  hs.qn.assign(12 * (size_t)n, 0.0);
+  hs.vel.assign(8 * (size_t)n, 0.0);
+  hs.mass64.assign(8 * (size_t)n, 0.0);
+  hs.half.assign(4 * (size_t)n, 0.0);
+  hs.flags.assign(n, 0);
+  hs.shape.assign(n, 0);
+  hs.group.assign(n, 0);
+  for (int b = 0; b < n; ++b) {
+    const int sh = d->shape[b];
+    if (sh != PABD_SHAPE_BOX && sh != PABD_SHAPE_SPHERE) return "unknown shape of body " + std::to_string(b);
+    const double* p = d->shape_param + 3 * (size_t)b;
+    const uint8_t fl = d->flags ? d->flags[b] : 0;
+    hs.flags[b] = fl;
+    hs.shape[b] = (uint8_t)sh;
+    hs.group[b] = d->group ? d->group[b] : 0;
+    const double rho = d->density[b];
+    double m, P0, P1, P2;
+    if (sh == PABD_SHAPE_BOX) {
+      if (!(p[0] > 0 && p[1] > 0 && p[2] > 0)) return "box half extents must be positive";
+      // int rho x x^T over [-hx,hx]x[-hy,hy]x[-hz,hz] = m diag(hx^2, hy^2, hz^2) / 3
+      m = rho * 8.0 * p[0] * p[1] * p[2];
+      P0 = m * p[0] * p[0] / 3.0;
+      P1 = m * p[1] * p[1] / 3.0;
+      P2 = m * p[2] * p[2] / 3.0;
+      hs.half[4 * b] = p[0];
+      hs.half[4 * b + 1] = p[1];
+      hs.half[4 * b + 2] = p[2];
+      hs.half[4 * b + 3] = std::sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
+    } else {
+      if (!(p[0] > 0)) return "sphere radius must be positive";
+      // ball of radius r: m = rho 4 pi r^3 / 3, int rho x x^T = m r^2 / 5 I
+      m = rho * 4.0 * M_PI * p[0] * p[0] * p[0] / 3.0;
+      P0 = P1 = P2 = m * p[0] * p[0] / 5.0;
+      for (int k = 0; k < 4; ++k) hs.half[4 * b + k] = p[0];
+    }
+    const bool pinned = (fl & PABD_FLAG_PINNED) != 0;
+    if (!pinned && !(m > 0.0 && std::isfinite(m))) return "free body " + std::to_string(b) + " needs positive mass";
+    double* M = &hs.mass64[8 * (size_t)b];
+    M[0] = m; M[1] = P0; M[2] = 0; M[3] = 0; M[4] = P1; M[5] = 0; M[6] = P2; M[7] = 0;
+    for (int k = 0; k < 3; ++k) hs.qn[12 * b + k] = d->c0[3 * b + k];
+    for (int k = 0; k < 9; ++k) hs.qn[12 * b + 3 + k] = d->A0[9 * b + k];
+    if (!pinned) {
+      for (int k = 0; k < 3; ++k) {
+        hs.vel[8 * b + k] = d->v0 ? d->v0[3 * b + k] : 0.0;
+        hs.vel[8 * b + 3 + k] = d->w0 ? d->w0[3 * b + k] : 0.0;
+      }
+    }
+    for (int k = 0; k < 12; ++k)
+      if (!std::isfinite(hs.qn[12 * b + k])) return "non-finite initial state";
+  }
+  // bond ends, counting sort by owner keeping bond order (i side before j side)
+  const int B = d->n_bonds;
+  std::vector<int> cnt(n + 1, 0);
+  int n_driven = 0;
+  for (int e = 0; e < B; ++e) {
+    const int i = d->bond_i[e], j = d->bond_j[e];
+    const int ty = d->bond_type ? d->bond_type[e] : PABD_BOND_QUADRATIC;
+    if (i < 0 || i >= n || j < -1 || j >= n || i == j) return "bond " + std::to_string(e) + " has bad endpoints";
+    if (ty != PABD_BOND_QUADRATIC && ty != PABD_BOND_DRIVEN) return "unknown bond type";
+    if (!(d->kappa[e] > 0.0)) return "bond stiffness must be positive";
+    if (d->rest_len && d->rest_len[e] < 0.0) return "rest length must be >= 0";
+    if (ty == PABD_BOND_DRIVEN) {
+      if (!d->drive) return "driven bond without drive parameters";
+      ++n_driven;
+    }
+    cnt[i + 1]++;
+    if (j >= 0) cnt[j + 1]++;
+  }
+  hs.srow.assign(n + 1, 0);
+  for (int b = 0; b < n; ++b) hs.srow[b + 1] = hs.srow[b] + cnt[b + 1];
+  hs.ne = hs.srow[n];
+  hs.se_partner.assign(hs.ne, -1);
+  hs.se.assign(8 * (size_t)hs.ne, 0.0);
+  hs.se64.assign(4 * (size_t)hs.ne, 0.0);
+  std::vector<int> fill(n, 0);
+  hs.drv_end_i.clear();
+  hs.drv_end_j.clear();
+  hs.drv_param.clear();
+  for (int e = 0; e < B; ++e) {
+    const int i = d->bond_i[e], j = d->bond_j[e];
+    const double kap = d->kappa[e], l = d->rest_len ? d->rest_len[e] : 0.0;
+    const double* xi = d->x_i + 3 * (size_t)e;
+    const double* xj = d->x_j + 3 * (size_t)e;
+    const int ei = hs.srow[i] + fill[i]++;
+    hs.se_partner[ei] = j;
+    double* E = &hs.se[8 * (size_t)ei];
+    E[0] = xi[0]; E[1] = xi[1]; E[2] = xi[2]; E[3] = kap;
+    E[4] = xj[0]; E[5] = xj[1]; E[6] = xj[2]; E[7] = -kap * l;
+    double* E64 = &hs.se64[4 * (size_t)ei];
+    E64[0] = xi[0]; E64[1] = xi[1]; E64[2] = xi[2]; E64[3] = kap;
+    int ej = -1;
+    if (j >= 0) {
+      ej = hs.srow[j] + fill[j]++;
+      hs.se_partner[ej] = i;
+      double* F = &hs.se[8 * (size_t)ej];
+      F[0] = xj[0]; F[1] = xj[1]; F[2] = xj[2]; F[3] = kap;
+      F[4] = xi[0]; F[5] = xi[1]; F[6] = xi[2]; F[7] = -kap * l;
+      double* F64 = &hs.se64[4 * (size_t)ej];
+      F64[0] = xj[0]; F64[1] = xj[1]; F64[2] = xj[2]; F64[3] = kap;
+    }
+    const int ty = d->bond_type ? d->bond_type[e] : PABD_BOND_QUADRATIC;
+    if (ty == PABD_BOND_DRIVEN) {
+      hs.drv_end_i.push_back(ei);
+      hs.drv_end_j.push_back(ej);
+      for (int k = 0; k < 13; ++k) hs.drv_param.push_back(d->drive[13 * (size_t)e + k]);
+    }
+  }
+  hs.max_ends = 0;
+  for (int b = 0; b < n; ++b) hs.max_ends = std::max(hs.max_ends, hs.srow[b + 1] - hs.srow[b]);
+  hs.driven = n_driven > 0;
+  hs.contact = d->contact_enable != 0;
+  if (hs.contact) {
+    if (d->max_contacts_per_body <= 0) return "contacts need max_contacts_per_body > 0";
+    if (d->n_planes > 0 && !d->planes) return "missing planes";
+  }
+  hs.ccap = hs.contact ? d->max_contacts_per_body : 0;
+  hs.planes.assign(d->planes ? d->planes : nullptr,
+                   d->planes ? d->planes + 4 * (size_t)std::max(d->n_planes, 0) : nullptr);
+  SceneDev& S = hs.params;
+  S = SceneDev{};
+  S.h = d->h;
+  S.g0 = d->gravity[0];
+  S.g1 = d->gravity[1];
+  S.g2 = d->gravity[2];
+  S.t0 = d->t0;
+  S.kscale = d->contact_kappa_scale;
+  S.margin = d->contact_margin;
+  S.mu = d->mu;
+  S.cell = 1.0;
+  S.iters = d->iters;
+  S.n_bodies = n;
+  S.n_planes = hs.contact ? std::max(d->n_planes, 0) : 0;
+  S.contact = hs.contact ? 1 : 0;
+  S.ccap = hs.ccap;
+  return "";
+}
+
+// device bytes of one scene at arithmetic type size ts (admission bound)
+inline size_t scene_bytes(const HostScene& hs, int ts) {
+  const size_t per_body = (size_t)ts * (4 * (QW + 4) + VW + MW + FW + 4) + 8 * (10 + 8 + 2) + 2 + 4 * 4;
+  const size_t per_end = (size_t)ts * EW + 4 + 8 * 4;
+  const size_t per_contact = (size_t)ts * CW + 4 + 8;
+  return per_body * hs.n + per_end * hs.ne + per_contact * (size_t)hs.n * hs.ccap +
+         hs.drv_param.size() * 8 + hs.planes.size() * 8 + sizeof(SceneDev) + 64;
+}
+
+}  // namespace pabd

@@ -1,0 +1,389 @@
+// kernels_step.h -- per-body kernels of one step of Algorithm 1 over a flat range
+// of bodies that may belong to several scenes (scene table lookup per body):
+//   k_predict   prediction loop (v* = v + h g, c* = c + h v*, A* = R(dQ) A^n; q^0 = s)
+//   k_factor    FP64 block H_i = M_i + h^2 sum w J^T J (Sec. 4.2.1) and its sparse
+//               inverse (Sec. 4.3), stored as the FP64 block and a T factor
+//   k_iterate   one global + local iteration for every body (Jacobi: reads only
+//               q^k, writes q^{k+1} to the other buffer), increment form:
+//               dq = H^{-1} (M (s - q^k) + h^2 sum [w J^T (y_o - y_s) + phi^- J^T n
+//                    + J^T f_contact]),  then A <- polar rotation (Sec. 4.2.2)
+//   k_finish    velocity recovery (Sec. 4.4) and health flags
+//   k_reduce_residual  per-scene FP64 residual, fixed summation order
+#pragma once
+
+#include "common.h"
+#include "device_math.h"
+
+namespace pabd {
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_predict(View<T> v) {
+  constexpr int QR = Rec<T>::Q;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= v.n) return;
+  const int sc = v.bscene[i];
+  if (sc < 0) return;
+  T q[QR];
+  load<T, QR>(v.qn + (size_t)QR * i, q);
+  if (v.scenes[sc].step >= v.scenes[sc].steps_total) return;
+  if (v.flags[i] & F_PINNED) {
+    store<T, QR>(v.q[0] + (size_t)QR * i, q);
+    store<T, QR>(v.q[1] + (size_t)QR * i, q);
+    store<T, QR>(v.s + (size_t)QR * i, q);
+    return;
+  }
+  const SceneDev& S = v.scenes[sc];
+  const T h = (T)S.h;
+  T vw[VW];
+  load<T, VW>(v.vel + (size_t)VW * i, vw);
+  T s[QR];
+#pragma unroll
+  for (int c = 0; c < QR; ++c) s[c] = q[c];
+  pos_add(s, h * (vw[0] + h * (T)S.g0), h * (vw[1] + h * (T)S.g1), h * (vw[2] + h * (T)S.g2));
+  predict_rotation(q + 3, vw + 3, h, s + 3);
+  store<T, QR>(v.s + (size_t)QR * i, s);
+  store<T, QR>(v.q[0] + (size_t)QR * i, s);
+}
+
+// mass64: 8 doubles per body (m, Pi sym 6, -)
+template <typename T>
+__global__ void __launch_bounds__(256) k_factor(View<T> v, const double* mass64, int first, int count) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= count) return;
+  const int i = first + t;
+  if (i >= v.n) return;
+  const int sc = v.bscene[i];
+  if (sc < 0 || (v.flags[i] & F_PINNED)) return;
+  const double h2 = v.scenes[sc].h * v.scenes[sc].h;
+  const double* m = mass64 + 8 * (size_t)i;
+  Block B{m[0], 0, 0, 0, m[1], m[2], m[3], m[4], m[5], m[6]};
+  for (int e = v.srow[i]; e < v.srow_end[i]; ++e) {
+    const double* x = v.se64 + 4 * (size_t)e;
+    block_add_end(B, h2 * x[3], x[0], x[1], x[2]);
+  }
+  double* bo = v.blk + 10 * (size_t)i;
+  bo[0] = B.a; bo[1] = B.b0; bo[2] = B.b1; bo[3] = B.b2; bo[4] = B.d00;
+  bo[5] = B.d01; bo[6] = B.d02; bo[7] = B.d11; bo[8] = B.d12; bo[9] = B.d22;
+  double f[10];
+  block_inverse(B, f);
+  T ft[FW];
+#pragma unroll
+  for (int k = 0; k < 10; ++k) ft[k] = (T)f[k];
+  ft[10] = ft[11] = (T)0;
+  store<T, FW>(v.fac + (size_t)FW * i, ft);
+}
+
+// contribution of one quadratic bond end with bond vector d = y_o - y_s:
+// f = kappa d + phim d/|d| (phi^+ / d = kappa implicit, phi^- = phim explicit)
+template <typename T>
+__device__ __forceinline__ void quad_end_force(const T* E, const T* d, T* f) {
+  const T kap = E[3];
+  f[0] = kap * d[0];
+  f[1] = kap * d[1];
+  f[2] = kap * d[2];
+  if (E[7] != (T)0) {
+    T dn2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    if (dn2 > (T)1e-24) {
+      T sc = E[7] / sqrt(dn2);
+      f[0] += sc * d[0];
+      f[1] += sc * d[1];
+      f[2] += sc * d[2];
+    }
+  }
+}
+
+// contact end (reading of the paper's contact bond), d = y_o - y_s: stick force
+// kappa d acting only while penetrating along n (n from the partner's surface
+// towards the owner), tangential part clamped to mu times the normal part.
+// Returns false when separated (no contribution, no implicit weight).
+template <typename T>
+__device__ __forceinline__ bool contact_end_force(const T* C, const T* d, T* f) {
+  const T d0 = d[0], d1 = d[1], d2 = d[2];
+  const T n0 = C[8], n1 = C[9], n2 = C[10];
+  T dn = n0 * d0 + n1 * d1 + n2 * d2;  // = -gap
+  if (!(dn > (T)0)) return false;
+  const T kap = C[3], mu = C[7];
+  T fn = kap * dn;
+  T t0 = kap * (d0 - dn * n0), t1 = kap * (d1 - dn * n1), t2 = kap * (d2 - dn * n2);
+  T tn2 = t0 * t0 + t1 * t1 + t2 * t2;
+  T lim = mu * fn;
+  if (tn2 > lim * lim) {
+    T sc = lim / sqrt(tn2);
+    t0 *= sc;
+    t1 *= sc;
+    t2 *= sc;
+  }
+  f[0] = fn * n0 + t0;
+  f[1] = fn * n1 + t1;
+  f[2] = fn * n2 + t2;
+  return true;
+}
+
+// FP64 residual partials of one body: |q_new - q|_M^2 and |q|_M^2
+template <typename T>
+__device__ __forceinline__ void residual_terms(const T* m, const T* qo, const T* q, double* num,
+                                               double* den) {
+  T dd[QW];
+  pos_diff(qo, q, dd);
+#pragma unroll
+  for (int c = 3; c < QW; ++c) dd[c] = qo[c] - q[c];
+  const double dc[3] = {(double)dd[0], (double)dd[1], (double)dd[2]};
+  const double cc[3] = {pos_value(q, 0), pos_value(q, 1), pos_value(q, 2)};
+  *num = m_norm2(m, dc, dd);
+  *den = m_norm2(m, cc, q);
+}
+
+template <typename T, bool CONTACT>
+__global__ void __launch_bounds__(256) k_iterate(View<T> v, int k, double* rh_num, double* rh_den) {
+  constexpr int QR = Rec<T>::Q;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= v.n) return;
+  const int sc = v.bscene[i];
+  if (sc < 0 || (v.flags[i] & F_PINNED)) return;
+  const SceneDev& S = v.scenes[sc];
+  const int K = S.iters;
+  if (k >= K || S.step >= S.steps_total) return;
+  const T* qs = v.q[k & 1];
+  T* qd = v.q[(k + 1) & 1];
+  T q[QR], s[QR], m[MW];
+  load<T, QR>(qs + (size_t)QR * i, q);
+  load<T, QR>(v.s + (size_t)QR * i, s);
+  load<T, MW>(v.mass + (size_t)MW * i, m);
+  T rb[QW];
+#pragma unroll
+  for (int c = 0; c < QW; ++c) rb[c] = (T)0;
+  const int e1 = v.srow_end[i];
+  for (int e = v.srow[i]; e < e1; ++e) {
+    const int j = v.se_partner[e];
+    T E[EW];
+    load<T, EW>(v.se + (size_t)EW * e, E);
+    T d[3], f[3];
+    if (j < 0) {
+      bond_vec<T>(q, E, nullptr, E + 4, d);
+    } else {
+      T qj[QR];
+      load<T, QR>(qs + (size_t)QR * j, qj);
+      bond_vec<T>(q, E, qj, E + 4, d);
+    }
+    quad_end_force(E, d, f);
+    add_JT(rb, E, f[0], f[1], f[2]);
+  }
+  const double h2d = S.h * S.h;
+  const T h2 = (T)h2d;
+  T fac[FW];
+  if constexpr (CONTACT) {
+    const double* bb = v.blk + 10 * (size_t)i;
+    Block B{bb[0], bb[1], bb[2], bb[3], bb[4], bb[5], bb[6], bb[7], bb[8], bb[9]};
+    int cnt = v.ccount[i];
+    if (cnt > S.ccap) cnt = S.ccap;
+    const size_t base = (size_t)i * S.ccap;
+    for (int c = 0; c < cnt; ++c) {
+      const int j = v.ce_partner[base + c];
+      T C[CW];
+      load<T, CW>(v.ce + (size_t)CW * (base + c), C);
+      T d[3], f[3];
+      if (j < 0) {
+        bond_vec<T>(q, C, nullptr, C + 4, d);
+      } else {
+        T qj[QR];
+        load<T, QR>(qs + (size_t)QR * j, qj);
+        bond_vec<T>(q, C, qj, C + 4, d);
+      }
+      if (!contact_end_force(C, d, f)) continue;
+      add_JT(rb, C, f[0], f[1], f[2]);
+      block_add_end(B, h2d * (double)C[3], (double)C[0], (double)C[1], (double)C[2]);
+    }
+    double f64[10];
+    block_inverse(B, f64);
+#pragma unroll
+    for (int c = 0; c < 10; ++c) fac[c] = (T)f64[c];
+  } else {
+    load<T, FW>(v.fac + (size_t)FW * i, fac);
+  }
+  T r[QW];
+#pragma unroll
+  for (int c = 0; c < QW; ++c) r[c] = h2 * rb[c];
+  add_inertia(r, m, s, q);
+  T dq[QW];
+  block_apply(fac, r, dq);
+  T qo[QR];
+#pragma unroll
+  for (int c = 0; c < QR; ++c) qo[c] = q[c];
+  pos_add(qo, dq[0], dq[1], dq[2]);
+  T Ah[9];
+#pragma unroll
+  for (int c = 0; c < 9; ++c) Ah[c] = q[3 + c] + dq[3 + c];
+  if (S.debug & 1) {
+#pragma unroll
+    for (int c = 0; c < 9; ++c) qo[3 + c] = Ah[c];
+  } else {
+    polar_rotation(Ah, qo + 3);
+  }
+  store<T, QR>(qd + (size_t)QR * i, qo);
+  if (k == K - 1 || rh_num) {
+    double num, den;
+    residual_terms(m, qo, q, &num, &den);
+    if (k == K - 1) {
+      v.r_num[i] = num;
+      v.r_den[i] = den;
+    }
+    if (rh_num) {
+      rh_num[(size_t)k * v.n + i] = num;
+      rh_den[(size_t)k * v.n + i] = den;
+    }
+  }
+}
+
+// velocity recovery from q^{n+1} (= qf) and q^n (= q0), shared with the tile kernel
+template <typename T>
+__device__ __forceinline__ void recover_velocity(const T* qf, const T* q0, T h, T* vw) {
+  const T ih = (T)1 / h;
+  T dc[3];
+  pos_diff(qf, q0, dc);
+  vw[0] = dc[0] * ih;
+  vw[1] = dc[1] * ih;
+  vw[2] = dc[2] * ih;
+  // W = (A^{n+1} - A^n) (A^n)^T / h (A^n orthogonal: inverse = transpose)
+  T dA[9], W[9];
+#pragma unroll
+  for (int c = 0; c < 9; ++c) dA[c] = qf[3 + c] - q0[3 + c];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      W[3 * r + c] = dA[3 * r] * q0[3 + 3 * c] + dA[3 * r + 1] * q0[4 + 3 * c] +
+                     dA[3 * r + 2] * q0[5 + 3 * c];
+  // average of [w]_x and -[w]_x^T
+  vw[3] = (T)0.5 * (W[7] - W[5]) * ih;
+  vw[4] = (T)0.5 * (W[2] - W[6]) * ih;
+  vw[5] = (T)0.5 * (W[3] - W[1]) * ih;
+  vw[6] = vw[7] = (T)0;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_finish(View<T> v) {
+  constexpr int QR = Rec<T>::Q;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= v.n) return;
+  const int sc = v.bscene[i];
+  if (sc < 0) return;
+  if (v.flags[i] & F_PINNED) {
+    v.r_num[i] = 0.0;
+    v.r_den[i] = 0.0;
+    return;
+  }
+  const SceneDev& S = v.scenes[sc];
+  if (S.step >= S.steps_total) return;
+  T qf[QR], q0[QR];
+  load<T, QR>(v.q[S.iters & 1] + (size_t)QR * i, qf);
+  load<T, QR>(v.qn + (size_t)QR * i, q0);
+  T vw[VW];
+  recover_velocity(qf, q0, (T)S.h, vw);
+  bool finite = true;
+#pragma unroll
+  for (int c = 0; c < QR; ++c) finite = finite && isfinite(qf[c]);
+#pragma unroll
+  for (int c = 0; c < 6; ++c) finite = finite && isfinite(vw[c]);
+  if (!finite) atomicOr(v.health + sc, 1);
+  store<T, QR>(v.qn + (size_t)QR * i, qf);
+  store<T, VW>(v.vel + (size_t)VW * i, vw);
+}
+
+// one block per scene; rho = sqrt(sum num / sum den) over the scene's bodies in a
+// fixed order (strided partial sums, then a tree), so results are reproducible
+__global__ void __launch_bounds__(256) k_reduce_residual(const SceneDev* scenes, int n_scenes,
+                                                        const double* num, const double* den,
+                                                        double* rho) {
+  __shared__ double sn[256], sd[256];
+  const int sc = blockIdx.x;
+  if (sc >= n_scenes) return;
+  const int off = scenes[sc].body_off, nb = scenes[sc].n_bodies;
+  double a = 0.0, b = 0.0;
+  for (int t = threadIdx.x; t < nb; t += blockDim.x) {
+    a += num[off + t];
+    b += den[off + t];
+  }
+  sn[threadIdx.x] = a;
+  sd[threadIdx.x] = b;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      sn[threadIdx.x] += sn[threadIdx.x + w];
+      sd[threadIdx.x] += sd[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) rho[sc] = sd[0] > 0.0 ? sqrt(sn[0] / sd[0]) : 0.0;
+}
+
+// residual history: rho_k for every k of the last step (plain path diagnostics)
+__global__ void __launch_bounds__(256) k_reduce_history(int n, int K, const double* num,
+                                                       const double* den, double* rho) {
+  __shared__ double sn[256], sd[256];
+  const int k = blockIdx.x;
+  if (k >= K) return;
+  double a = 0.0, b = 0.0;
+  for (int t = threadIdx.x; t < n; t += blockDim.x) {
+    a += num[(size_t)k * n + t];
+    b += den[(size_t)k * n + t];
+  }
+  sn[threadIdx.x] = a;
+  sd[threadIdx.x] = b;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      sn[threadIdx.x] += sn[threadIdx.x + w];
+      sd[threadIdx.x] += sd[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) rho[k] = sd[0] > 0.0 ? sqrt(sn[0] / sd[0]) : 0.0;
+}
+
+// driven bonds: the j-side anchor of bond b is base rotated about the axis through
+// pivot by theta(t) = theta0 + amp sin(2 pi f t + phase), t = time at the end of
+// the step being taken.  Updates the i-side end's partner anchor and the j-side
+// end's own anchor (T and FP64 copies).
+template <typename T>
+__global__ void k_update_driven(View<T> v, int n_driven, const int* d_scene, const int* d_end_i,
+                                const int* d_end_j, const double* d_param) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= n_driven) return;
+  const int sc = d_scene[b];
+  if (sc < 0) return;  // unused table entry
+  const SceneDev& S = v.scenes[sc];
+  if (S.step >= S.steps_total) return;
+  const double t = S.t0 + (double)(S.step + 1) * S.h;
+  const double* p = d_param + 13 * (size_t)b;
+  const double th = p[9] + p[10] * sin(2.0 * 3.14159265358979323846 * p[11] * t + p[12]);
+  const double u0 = p[0], u1 = p[1], u2 = p[2];
+  const double r0 = p[6] - p[3], r1 = p[7] - p[4], r2 = p[8] - p[5];
+  const double c = cos(th), s = sin(th), ud = u0 * r0 + u1 * r1 + u2 * r2;
+  const double x0 = p[3] + r0 * c + (u1 * r2 - u2 * r1) * s + u0 * ud * (1 - c);
+  const double x1 = p[4] + r1 * c + (u2 * r0 - u0 * r2) * s + u1 * ud * (1 - c);
+  const double x2 = p[5] + r2 * c + (u0 * r1 - u1 * r0) * s + u2 * ud * (1 - c);
+  const int ei = d_end_i[b], ej = d_end_j[b];
+  if (ei >= 0) {
+    T* E = v.se + (size_t)EW * ei;
+    E[4] = (T)x0;
+    E[5] = (T)x1;
+    E[6] = (T)x2;
+  }
+  if (ej >= 0) {
+    T* E = v.se + (size_t)EW * ej;
+    E[0] = (T)x0;
+    E[1] = (T)x1;
+    E[2] = (T)x2;
+    double* e64 = const_cast<double*>(v.se64) + 4 * (size_t)ej;
+    e64[0] = x0;
+    e64[1] = x1;
+    e64[2] = x2;
+  }
+}
+
+__global__ void k_end_step(SceneDev* scenes, int n_scenes) {
+  const int sc = blockIdx.x * blockDim.x + threadIdx.x;
+  if (sc < n_scenes && scenes[sc].step < scenes[sc].steps_total) scenes[sc].step += 1;
+}
+
+}  // namespace pabd

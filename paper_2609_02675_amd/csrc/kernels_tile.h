@@ -1,0 +1,159 @@
+// kernels_tile.h -- the batched substep: one workgroup owns a tile of up to TB
+// bodies made of whole scenes (joint scenes without contacts), and runs the
+// complete step of Algorithm 1 for them -- prediction, K global/local Jacobi
+// iterations, velocity recovery -- with the bodies' q^k exchanged through LDS
+// (double-buffered: one barrier per iteration).  HBM is touched once per step
+// to load and once to store each body.  The grid is persistent: workgroups
+// stride over the device tile table, so the captured graph's launch shape does
+// not depend on which scenes are resident.
+#pragma once
+
+#include "common.h"
+#include "device_math.h"
+#include "kernels_step.h"
+
+namespace pabd {
+
+struct TileTable {
+  const int* first;    // first body of the tile
+  const int* count;    // bodies in the tile (including released holes)
+  const int* kmax;     // largest K among the tile's scenes
+  const int* n_tiles;  // device count of tiles
+};
+
+template <typename T, int TB, int MAXE>
+__global__ void __launch_bounds__(TB) k_tile_step(View<T> v, TileTable tt) {
+  constexpr int QR = Rec<T>::Q;
+  __shared__ T lq[2][TB * QR];
+  const int lane = threadIdx.x;
+  const int ntiles = *tt.n_tiles;
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int first = tt.first[t], nb = tt.count[t], kmax = tt.kmax[t];
+    const int i = first + lane;
+    const int scn = lane < nb ? v.bscene[i] : -1;
+    const bool present = scn >= 0 && v.scenes[scn].step < v.scenes[scn].steps_total;
+    const bool pinned = present && (v.flags[i] & F_PINNED);
+    const bool moving = present && !pinned;
+    T q[QR], s[QR], m[MW], fac[FW], vw[VW];
+    T E[MAXE][EW];
+    int part[MAXE];
+    int e0 = 0, ne = 0, K = 0;
+    T h = (T)1, h2 = (T)1;
+    int debug = 0;
+    if (present) {
+      load<T, QR>(v.qn + (size_t)QR * i, q);
+      const SceneDev& S = v.scenes[scn];
+      K = S.iters;
+      debug = S.debug;
+      h = (T)S.h;
+      h2 = (T)(S.h * S.h);
+      if (moving) {
+        load<T, VW>(v.vel + (size_t)VW * i, vw);
+        load<T, MW>(v.mass + (size_t)MW * i, m);
+        load<T, FW>(v.fac + (size_t)FW * i, fac);
+        e0 = v.srow[i];
+        ne = v.srow_end[i] - e0;
+#pragma unroll
+        for (int u = 0; u < MAXE; ++u)
+          if (u < ne) {
+            load<T, EW>(v.se + (size_t)EW * (e0 + u), E[u]);
+            const int p = v.se_partner[e0 + u];
+            part[u] = p < 0 ? -1 : p - first;
+          }
+        // prediction
+#pragma unroll
+        for (int c = 0; c < QR; ++c) s[c] = q[c];
+        pos_add(s, h * (vw[0] + h * (T)S.g0), h * (vw[1] + h * (T)S.g1), h * (vw[2] + h * (T)S.g2));
+        predict_rotation(q + 3, vw + 3, h, s + 3);
+      }
+    }
+    T qn[QR];
+#pragma unroll
+    for (int c = 0; c < QR; ++c) qn[c] = q[c];
+    if (moving) {
+#pragma unroll
+      for (int c = 0; c < QR; ++c) q[c] = s[c];
+    }
+    double num = 0.0, den = 0.0;
+    for (int k = 0; k < kmax; ++k) {
+      T* buf = lq[k & 1];
+      if (present) store<T, QR>(buf + QR * lane, q);
+      __syncthreads();
+      if (moving && k < K) {
+        T rb[QW];
+#pragma unroll
+        for (int c = 0; c < QW; ++c) rb[c] = (T)0;
+#pragma unroll
+        for (int u = 0; u < MAXE; ++u)
+          if (u < ne) {
+            T d[3], f[3];
+            if (part[u] < 0) {
+              bond_vec<T>(q, E[u], nullptr, E[u] + 4, d);
+            } else {
+              T qj[QR];
+              load<T, QR>(buf + QR * part[u], qj);
+              bond_vec<T>(q, E[u], qj, E[u] + 4, d);
+            }
+            quad_end_force(E[u], d, f);
+            add_JT(rb, E[u], f[0], f[1], f[2]);
+          }
+        for (int e = e0 + MAXE; e < e0 + ne; ++e) {
+          T Eg[EW];
+          load<T, EW>(v.se + (size_t)EW * e, Eg);
+          const int p = v.se_partner[e];
+          T d[3], f[3];
+          if (p < 0) {
+            bond_vec<T>(q, Eg, nullptr, Eg + 4, d);
+          } else {
+            T qj[QR];
+            load<T, QR>(buf + QR * (p - first), qj);
+            bond_vec<T>(q, Eg, qj, Eg + 4, d);
+          }
+          quad_end_force(Eg, d, f);
+          add_JT(rb, Eg, f[0], f[1], f[2]);
+        }
+        T r[QW];
+#pragma unroll
+        for (int c = 0; c < QW; ++c) r[c] = h2 * rb[c];
+        add_inertia(r, m, s, q);
+        T dq[QW];
+        block_apply(fac, r, dq);
+        T qo[QR];
+#pragma unroll
+        for (int c = 0; c < QR; ++c) qo[c] = q[c];
+        pos_add(qo, dq[0], dq[1], dq[2]);
+        T Ah[9];
+#pragma unroll
+        for (int c = 0; c < 9; ++c) Ah[c] = q[3 + c] + dq[3 + c];
+        if (debug & 1) {
+#pragma unroll
+          for (int c = 0; c < 9; ++c) qo[3 + c] = Ah[c];
+        } else {
+          polar_rotation(Ah, qo + 3);
+        }
+        if (k == K - 1) residual_terms(m, qo, q, &num, &den);
+#pragma unroll
+        for (int c = 0; c < QR; ++c) q[c] = qo[c];
+      }
+    }
+    __syncthreads();  // LDS reused by the next tile of this workgroup
+    if (present) {
+      if (moving) {
+        T o[VW];
+        recover_velocity(q, qn, h, o);
+        bool finite = true;
+#pragma unroll
+        for (int c = 0; c < QR; ++c) finite = finite && isfinite(q[c]);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) finite = finite && isfinite(o[c]);
+        if (!finite) atomicOr(v.health + scn, 1);
+        store<T, QR>(v.qn + (size_t)QR * i, q);
+        store<T, VW>(v.vel + (size_t)VW * i, o);
+      }
+      v.r_num[i] = num;
+      v.r_den[i] = den;
+    }
+  }
+}
+
+}  // namespace pabd

@@ -1,0 +1,1057 @@
+// pabd_api.hip -- the C ABI of include/pabd.h: plain scene handles and batches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <climits>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/pabd.h"
+#include "engine.h"
+
+using namespace pabd;
+
+namespace {
+
+thread_local std::string g_err;
+
+pabd_status fail(pabd_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define API_HIP(x)                                                                   \
+  do {                                                                               \
+    hipError_t e_ = (x);                                                             \
+    if (e_ != hipSuccess) return fail(PABD_E_DEVICE, std::string(#x) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+bool use_graphs() {
+  const char* e = std::getenv("PABD_NO_GRAPH");
+  return !(e && e[0] == '1');
+}
+
+// ---------------------------------------------------------------------------
+// precision-erased engine interface
+// ---------------------------------------------------------------------------
+
+struct EngineBase {
+  virtual ~EngineBase() = default;
+  virtual pabd_status allocate(const Caps& c) = 0;
+  virtual pabd_status upload(const HostScene& hs, int boff, int eoff, int poff, int doff, int sidx,
+                             hipStream_t st) = 0;
+  virtual pabd_status clear_bodies(int boff, int n, hipStream_t st, int doff, int nd) = 0;
+  virtual void factor(hipStream_t st, int first = 0, int count = -1) = 0;
+  virtual void flat_step(int first, int n, int n_scenes, int kmax, bool contacts, int n_driven,
+                         bool history, bool finish_scenes, hipStream_t st) = 0;
+  virtual void tile_step(int tile_bodies, const TileTable& tt, int grid, hipStream_t st) = 0;
+  virtual void finish_scenes(int n_scenes, hipStream_t st) = 0;
+  virtual pabd_status read_bodies(int boff, int n, double* c, double* A, double* v, double* w,
+                                  hipStream_t st) = 0;
+  virtual pabd_status write_body_field(int body, int field, double value, hipStream_t st) = 0;
+  virtual std::string& error() = 0;
+  virtual int type_size() const = 0;
+  // raw pointers used by the API layer
+  virtual SceneDev* scene_table() = 0;
+  virtual int* health_ptr() = 0;
+  virtual double* rho_ptr() = 0;
+  virtual double** history(int* k) = 0;
+  virtual pabd_status alloc_history(int K) = 0;
+  virtual pabd_status read_contacts(int n, int ccap, std::vector<int>& count,
+                                    std::vector<int>& partner,
+                                    std::vector<unsigned long long>& key,
+                                    std::vector<double>& rec, hipStream_t st) = 0;
+  virtual pabd_status snapshot(int n, std::vector<char>& buf, hipStream_t st, bool restore) = 0;
+};
+
+template <typename T>
+struct EngineT final : EngineBase {
+  Engine<T> e;
+  pabd_status allocate(const Caps& c) override { return e.allocate(c); }
+  pabd_status upload(const HostScene& hs, int boff, int eoff, int poff, int doff, int sidx,
+                     hipStream_t st) override {
+    return e.upload(hs, boff, eoff, poff, doff, sidx, st);
+  }
+  pabd_status clear_bodies(int boff, int n, hipStream_t st, int doff, int nd) override {
+    return e.clear_bodies(boff, n, st, doff, nd);
+  }
+  void factor(hipStream_t st, int first, int count) override { e.launch_factor(st, first, count); }
+  void flat_step(int first, int n, int n_scenes, int kmax, bool contacts, int n_driven, bool history,
+                 bool fin, hipStream_t st) override {
+    (void)first;
+    const int saved = e.cap.n;
+    e.cap.n = n;  // flat kernels cover bodies [0, n)
+    e.launch_flat_step(n_scenes, kmax, contacts, n_driven, history, fin, st);
+    e.cap.n = saved;
+  }
+  void tile_step(int tb, const TileTable& tt, int grid, hipStream_t st) override {
+    View<T> v = e.view();
+    switch (tb) {
+      case 32:
+        hipLaunchKernelGGL((k_tile_step<T, 32, 2>), dim3(grid), dim3(32), 0, st, v, tt);
+        break;
+      case 64:
+        hipLaunchKernelGGL((k_tile_step<T, 64, 2>), dim3(grid), dim3(64), 0, st, v, tt);
+        break;
+      case 128:
+        hipLaunchKernelGGL((k_tile_step<T, 128, 2>), dim3(grid), dim3(128), 0, st, v, tt);
+        break;
+      default:
+        hipLaunchKernelGGL((k_tile_step<T, 256, 2>), dim3(grid), dim3(256), 0, st, v, tt);
+        break;
+    }
+  }
+  void finish_scenes(int n_scenes, hipStream_t st) override {
+    hipLaunchKernelGGL(k_reduce_residual, dim3(std::max(1, n_scenes)), dim3(256), 0, st,
+                       (const SceneDev*)e.scenes, n_scenes, (const double*)e.r_num,
+                       (const double*)e.r_den, e.rho);
+    hipLaunchKernelGGL(k_end_step, Engine<T>::grid_for(n_scenes, 64), dim3(64), 0, st, e.scenes,
+                       n_scenes);
+  }
+  pabd_status read_bodies(int boff, int n, double* c, double* A, double* v, double* w,
+                          hipStream_t st) override {
+    constexpr int QR = Rec<T>::Q;
+    std::vector<T> q((size_t)QR * n), vl((size_t)VW * n);
+    if (n > 0) {
+      if (hipMemcpyAsync(q.data(), e.qn + (size_t)QR * boff, q.size() * sizeof(T),
+                         hipMemcpyDeviceToHost, st) != hipSuccess ||
+          hipMemcpyAsync(vl.data(), e.vel + (size_t)VW * boff, vl.size() * sizeof(T),
+                         hipMemcpyDeviceToHost, st) != hipSuccess)
+        return fail(PABD_E_DEVICE, "state copy failed");
+    }
+    if (hipStreamSynchronize(st) != hipSuccess) return fail(PABD_E_DEVICE, "stream sync failed");
+    for (int b = 0; b < n; ++b) {
+      for (int k = 0; k < 3; ++k) {
+        if (c) c[3 * b + k] = (double)q[QR * b + k] + (QR > QW ? (double)q[QR * b + 12 + k] : 0.0);
+        if (v) v[3 * b + k] = (double)vl[VW * b + k];
+        if (w) w[3 * b + k] = (double)vl[VW * b + 3 + k];
+      }
+      for (int k = 0; k < 9; ++k)
+        if (A) A[9 * b + k] = (double)q[QR * b + 3 + k];
+    }
+    return PABD_OK;
+  }
+  pabd_status write_body_field(int body, int field, double value, hipStream_t st) override {
+    constexpr int QR = Rec<T>::Q;
+    T val = (T)value, zero = (T)0;
+    T* dst = field < 12 ? e.qn + (size_t)QR * body + field : e.vel + (size_t)VW * body + (field - 12);
+    if (hipMemcpyAsync(dst, &val, sizeof(T), hipMemcpyHostToDevice, st) != hipSuccess)
+      return fail(PABD_E_DEVICE, "poke failed");
+    if (QR > QW && field < 3 &&  // a poked position has no low part
+        hipMemcpyAsync(e.qn + (size_t)QR * body + 12 + field, &zero, sizeof(T), hipMemcpyHostToDevice,
+                       st) != hipSuccess)
+      return fail(PABD_E_DEVICE, "poke failed");
+    if (hipStreamSynchronize(st) != hipSuccess) return fail(PABD_E_DEVICE, "poke failed");
+    return PABD_OK;
+  }
+  std::string& error() override { return e.err; }
+  int type_size() const override { return (int)sizeof(T); }
+  SceneDev* scene_table() override { return e.scenes; }
+  int* health_ptr() override { return e.health; }
+  double* rho_ptr() override { return e.rho; }
+  double** history(int* k) override {
+    *k = e.rh_k;
+    return &e.rh_rho;
+  }
+  pabd_status alloc_history(int K) override {
+    if (e.rh_num && e.rh_k >= K) return PABD_OK;
+    pabd_status st;
+    if ((st = e.alloc(e.rh_num, (size_t)K * e.cap.n)) != PABD_OK) return st;
+    if ((st = e.alloc(e.rh_den, (size_t)K * e.cap.n)) != PABD_OK) return st;
+    if ((st = e.alloc(e.rh_rho, (size_t)K)) != PABD_OK) return st;
+    e.rh_k = K;
+    return PABD_OK;
+  }
+  pabd_status read_contacts(int n, int ccap, std::vector<int>& count, std::vector<int>& partner,
+                            std::vector<unsigned long long>& key, std::vector<double>& rec,
+                            hipStream_t st) override {
+    count.assign(n, 0);
+    const size_t ns = (size_t)n * ccap;
+    partner.assign(ns, 0);
+    key.assign(ns, 0);
+    std::vector<T> r(CW * ns);
+    if (n > 0 && ccap > 0) {
+      if (hipMemcpyAsync(count.data(), e.ccount, n * sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+          hipMemcpyAsync(partner.data(), e.ce_partner, ns * sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+          hipMemcpyAsync(key.data(), e.ce_key, ns * sizeof(unsigned long long), hipMemcpyDeviceToHost, st) != hipSuccess ||
+          hipMemcpyAsync(r.data(), e.ce, r.size() * sizeof(T), hipMemcpyDeviceToHost, st) != hipSuccess)
+        return fail(PABD_E_DEVICE, "contact copy failed");
+    }
+    if (hipStreamSynchronize(st) != hipSuccess) return fail(PABD_E_DEVICE, "stream sync failed");
+    rec.resize(r.size());
+    for (size_t k = 0; k < r.size(); ++k) rec[k] = (double)r[k];
+    return PABD_OK;
+  }
+  pabd_status snapshot(int n, std::vector<char>& buf, hipStream_t st, bool restore) override {
+    const size_t bq = (size_t)Rec<T>::Q * n * sizeof(T), bv = (size_t)VW * n * sizeof(T);
+    const size_t bs = (size_t)e.cap.s * sizeof(SceneDev);
+    if (!restore) buf.resize(bq + bv + bs);
+    hipMemcpyKind kind = restore ? hipMemcpyHostToDevice : hipMemcpyDeviceToHost;
+    char* h = buf.data();
+    hipError_t r1 = restore ? hipMemcpyAsync(e.qn, h, bq, kind, st) : hipMemcpyAsync(h, e.qn, bq, kind, st);
+    hipError_t r2 = restore ? hipMemcpyAsync(e.vel, h + bq, bv, kind, st)
+                            : hipMemcpyAsync(h + bq, e.vel, bv, kind, st);
+    hipError_t r3 = restore ? hipMemcpyAsync(e.scenes, h + bq + bv, bs, kind, st)
+                            : hipMemcpyAsync(h + bq + bv, e.scenes, bs, kind, st);
+    if (r1 != hipSuccess || r2 != hipSuccess || r3 != hipSuccess || hipStreamSynchronize(st) != hipSuccess)
+      return fail(PABD_E_DEVICE, "snapshot copy failed");
+    return PABD_OK;
+  }
+};
+
+std::unique_ptr<EngineBase> make_engine(int precision) {
+  if (precision == PABD_FP64) return std::make_unique<EngineT<double>>();
+  return std::make_unique<EngineT<float>>();
+}
+
+struct Graph {
+  hipGraph_t g = nullptr;
+  hipGraphExec_t x = nullptr;
+  void reset() {
+    if (x) (void)hipGraphExecDestroy(x);
+    if (g) (void)hipGraphDestroy(g);
+    x = nullptr;
+    g = nullptr;
+  }
+  ~Graph() { reset(); }
+};
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// plain scene
+// ---------------------------------------------------------------------------
+
+struct pabd_scene {
+  HostScene hs;
+  std::unique_ptr<EngineBase> eng;
+  hipStream_t stream = nullptr;
+  int precision = PABD_FP32;
+  int debug = 0;
+  bool history = false;
+  Graph graph;
+  hipStream_t graph_stream = nullptr;
+};
+
+extern "C" {
+
+const char* pabd_last_error(void) { return g_err.c_str(); }
+
+int32_t pabd_device_count(void) {
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return n;
+}
+
+size_t pabd_scene_bytes(const pabd_scene_desc* desc) {
+  HostScene hs;
+  if (!build_host_scene(desc, hs).empty()) return 0;
+  return scene_bytes(hs, desc->precision == PABD_FP64 ? 8 : 4);
+}
+
+pabd_status pabd_scene_create(const pabd_scene_desc* desc, pabd_scene** out) {
+  if (!out) return fail(PABD_E_INVALID, "null output handle");
+  *out = nullptr;
+  auto s = std::make_unique<pabd_scene>();
+  std::string why = build_host_scene(desc, s->hs);
+  if (!why.empty()) return fail(PABD_E_INVALID, why);
+  if (pabd_device_count() < 1) return fail(PABD_E_DEVICE, "no HIP device");
+  s->precision = desc->precision;
+  s->eng = make_engine(desc->precision);
+  API_HIP(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking));
+  Caps c;
+  c.n = std::max(1, s->hs.n);
+  c.e = std::max(1, s->hs.ne);
+  c.s = 1;
+  c.p = std::max(1, (int)s->hs.planes.size() / 4);
+  c.dr = std::max(1, (int)s->hs.drv_end_i.size());
+  c.contacts = s->hs.contact;
+  c.ccap = s->hs.ccap;
+  pabd_status st = s->eng->allocate(c);
+  if (st != PABD_OK) return fail(st, s->eng->error());
+  s->hs.params.steps_total = INT_MAX;
+  st = s->eng->upload(s->hs, 0, 0, 0, 0, 0, s->stream);
+  if (st != PABD_OK) return fail(st, s->eng->error());
+  s->eng->factor(s->stream);
+  API_HIP(hipGetLastError());
+  API_HIP(hipStreamSynchronize(s->stream));
+  *out = s.release();
+  return PABD_OK;
+}
+
+pabd_status pabd_scene_destroy(pabd_scene* s) {
+  if (!s) return PABD_OK;
+  if (s->stream) (void)hipStreamSynchronize(s->stream);
+  s->graph.reset();
+  s->eng.reset();
+  if (s->stream) (void)hipStreamDestroy(s->stream);
+  delete s;
+  return PABD_OK;
+}
+
+void* pabd_scene_stream(pabd_scene* s) { return s ? (void*)s->stream : nullptr; }
+
+static void scene_enqueue_step(pabd_scene* s, hipStream_t st) {
+  const HostScene& hs = s->hs;
+  s->eng->flat_step(0, std::max(1, hs.n), 1, hs.params.iters, hs.contact,
+                    (int)hs.drv_end_i.size(), s->history, true, st);
+}
+
+pabd_status pabd_scene_step(pabd_scene* s, int32_t nsteps, void* hip_stream) {
+  if (!s) return fail(PABD_E_INVALID, "null scene");
+  if (nsteps < 0) return fail(PABD_E_INVALID, "negative step count");
+  if (nsteps == 0 || s->hs.n == 0) return PABD_OK;
+  hipStream_t st = hip_stream ? (hipStream_t)hip_stream : s->stream;
+  if (!use_graphs() || s->history) {
+    for (int k = 0; k < nsteps; ++k) scene_enqueue_step(s, st);
+    API_HIP(hipGetLastError());
+    return PABD_OK;
+  }
+  if (!s->graph.x) {
+    hipStream_t cs = s->stream;
+    API_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    scene_enqueue_step(s, cs);
+    hipError_t e = hipStreamEndCapture(cs, &s->graph.g);
+    if (e != hipSuccess) return fail(PABD_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    API_HIP(hipGraphInstantiate(&s->graph.x, s->graph.g, nullptr, nullptr, 0));
+  }
+  for (int k = 0; k < nsteps; ++k) API_HIP(hipGraphLaunch(s->graph.x, st));
+  return PABD_OK;
+}
+
+pabd_status pabd_scene_read_state(pabd_scene* s, double* c, double* A, double* v, double* w) {
+  if (!s) return fail(PABD_E_INVALID, "null scene");
+  API_HIP(hipDeviceSynchronize());
+  pabd_status st = s->eng->read_bodies(0, s->hs.n, c, A, v, w, s->stream);
+  if (st != PABD_OK) return st;
+  int health = 0;
+  API_HIP(hipMemcpy(&health, s->eng->health_ptr(), sizeof(int), hipMemcpyDeviceToHost));
+  if (health & 1) return fail(PABD_E_DIVERGED, "non-finite state");
+  if (health & 2) return fail(PABD_E_DIVERGED, "contact capacity exceeded");
+  return PABD_OK;
+}
+
+pabd_status pabd_scene_residuals(pabd_scene* s, double* out, int32_t cap, int32_t* k_out) {
+  if (!s) return fail(PABD_E_INVALID, "null scene");
+  API_HIP(hipDeviceSynchronize());
+  const int K = s->hs.params.iters;
+  if (k_out) *k_out = K;
+  if (!out || cap <= 0) return PABD_OK;
+  if (s->history) {
+    int kk = 0;
+    double** rh = s->eng->history(&kk);
+    std::vector<double> h(K, 0.0);
+    API_HIP(hipMemcpy(h.data(), *rh, K * sizeof(double), hipMemcpyDeviceToHost));
+    for (int k = 0; k < K && k < cap; ++k) out[k] = h[k];
+  } else {
+    double r = 0.0;
+    API_HIP(hipMemcpy(&r, s->eng->rho_ptr(), sizeof(double), hipMemcpyDeviceToHost));
+    for (int k = 0; k < K && k < cap; ++k) out[k] = (k == K - 1) ? r : 0.0;
+  }
+  return PABD_OK;
+}
+
+pabd_status pabd_scene_set_debug(pabd_scene* s, int32_t flags) {
+  if (!s) return fail(PABD_E_INVALID, "null scene");
+  API_HIP(hipStreamSynchronize(s->stream));
+  s->debug = flags;
+  s->history = (flags & 2) != 0;
+  if (s->history) {
+    pabd_status st = s->eng->alloc_history(s->hs.params.iters);
+    if (st != PABD_OK) return fail(st, s->eng->error());
+  }
+  int dbg = flags & 1;
+  API_HIP(hipMemcpy((char*)s->eng->scene_table() + offsetof(SceneDev, debug), &dbg, sizeof(int),
+                    hipMemcpyHostToDevice));
+  s->graph.reset();
+  return PABD_OK;
+}
+
+pabd_status pabd_scene_poke(pabd_scene* s, int32_t body, int32_t field, double value) {
+  if (!s) return fail(PABD_E_INVALID, "null scene");
+  if (body < 0 || body >= s->hs.n || field < 0 || field > 17) return fail(PABD_E_INVALID, "bad poke target");
+  API_HIP(hipDeviceSynchronize());
+  return s->eng->write_body_field(body, field, value, s->stream);
+}
+
+pabd_status pabd_scene_contacts(pabd_scene* s, int32_t cap, int32_t* ci, int32_t* cj,
+                                int32_t* feature, double* xi, double* xj, double* normal,
+                                double* kappa, int32_t* n_out) {
+  if (!s) return fail(PABD_E_INVALID, "null scene");
+  if (n_out) *n_out = 0;
+  if (!s->hs.contact) return PABD_OK;
+  API_HIP(hipDeviceSynchronize());
+  std::vector<int> count, partner;
+  std::vector<unsigned long long> key;
+  std::vector<double> rec;
+  pabd_status st = s->eng->read_contacts(s->hs.n, s->hs.ccap, count, partner, key, rec, s->stream);
+  if (st != PABD_OK) return st;
+  struct C {
+    int i, j, f;
+    size_t slot;
+  };
+  std::vector<C> all;
+  for (int b = 0; b < s->hs.n; ++b) {
+    const int cnt = std::min(count[b], s->hs.ccap);
+    for (int k = 0; k < cnt; ++k) {
+      const size_t slot = (size_t)b * s->hs.ccap + k;
+      if (key[slot] & 1ull) continue;  // j-side copy
+      all.push_back({b, partner[slot], (int)((key[slot] >> 1) & 0x7fffffffull), slot});
+    }
+  }
+  std::sort(all.begin(), all.end(), [](const C& a, const C& b) {
+    if (a.i != b.i) return a.i < b.i;
+    if (a.j != b.j) return a.j < b.j;
+    return a.f < b.f;
+  });
+  for (size_t k = 0; k < all.size() && (int)k < cap; ++k) {
+    const double* r = &rec[CW * all[k].slot];
+    if (ci) ci[k] = all[k].i;
+    if (cj) cj[k] = all[k].j;
+    if (feature) feature[k] = all[k].f;
+    for (int d = 0; d < 3; ++d) {
+      if (xi) xi[3 * k + d] = r[d];
+      if (xj) xj[3 * k + d] = r[4 + d];
+      if (normal) normal[3 * k + d] = r[8 + d];
+    }
+    if (kappa) kappa[k] = r[3];
+  }
+  if (n_out) *n_out = (int32_t)all.size();
+  return PABD_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// batch
+// ---------------------------------------------------------------------------
+
+namespace {
+
+// first-fit allocator of index ranges
+struct RangeAlloc {
+  std::map<int, int> free_;  // start -> length
+  int cap = 0;
+  void init(int n) {
+    cap = n;
+    free_.clear();
+    if (n > 0) free_[0] = n;
+  }
+  int take(int n, int align = 1) {
+    if (n <= 0) return 0;
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      int s = it->first, len = it->second;
+      int a = (s + align - 1) / align * align;
+      if (a + n <= s + len) {
+        free_.erase(it);
+        if (a > s) free_[s] = a - s;
+        if (a + n < s + len) free_[a + n] = s + len - (a + n);
+        return a;
+      }
+    }
+    return -1;
+  }
+  void give(int s, int n) {
+    if (n <= 0) return;
+    auto it = free_.emplace(s, n).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+};
+
+struct Slot {
+  bool used = false;
+  bool tiled = false;
+  int boff = 0, n = 0, eoff = 0, ne = 0, poff = 0, np = 0, doff = 0, nd = 0;
+  int tile = -1;
+  int steps_total = 0;
+  long long admitted_at = 0;  // batch substep counter at admission
+  size_t bytes = 0;
+  int iters = 0;
+  bool contact = false;
+  std::shared_ptr<HostScene> hs;
+};
+
+struct Tile {
+  int first = 0, used = 0;
+  std::vector<int> slots;
+};
+
+}  // namespace
+
+struct pabd_batch {
+  int precision = PABD_FP32;
+  int max_slots = 0;
+  size_t budget = 0, used_bytes = 0;
+  Caps caps;
+  int n_stream = 0;  // bodies [0, n_stream) are for scenes on the flat path
+  std::unique_ptr<EngineBase> eng;
+  hipStream_t stream = nullptr;
+  std::vector<Slot> slots;
+  RangeAlloc stream_bodies, tile_space, ends, planes, driven;
+  std::vector<Tile> tiles;  // index = tile id; used == 0 and no slots: free
+  int tile_bodies = 64;
+  bool tile_auto = true;
+  long long substeps = 0;
+  // device tile table
+  int *d_first = nullptr, *d_count = nullptr, *d_kmax = nullptr, *d_ntiles = nullptr;
+  int tile_table_cap = 0;
+  Graph graph;
+  bool dirty = true;
+  int grid_tiles = 0;
+  bool any_stream = false, any_contact = false;
+  int stream_kmax = 0, n_driven_hi = 0;
+};
+
+namespace {
+
+size_t body_cost(int ts) { return (size_t)ts * (4 * (QW + 4) + VW + MW + FW + 4) + 8 * (10 + 8 + 2) + 2 + 4 * 5; }
+size_t end_cost(int ts) { return (size_t)ts * EW + 4 + 8 * 4; }
+size_t contact_cost(int ts) { return (size_t)ts * CW + 4 + 8; }
+
+pabd_status batch_tables(pabd_batch* b) {
+  // rebuild the device tile table from the host tiles
+  std::vector<int> first, count, kmax;
+  for (const Tile& t : b->tiles) {
+    if (t.slots.empty()) continue;
+    int km = 0;
+    for (int s : t.slots) km = std::max(km, b->slots[s].iters);
+    first.push_back(t.first);
+    count.push_back(t.used);
+    kmax.push_back(km);
+  }
+  const int nt = (int)first.size();
+  if (nt > b->tile_table_cap) {
+    int cap = std::max(nt, 2 * b->tile_table_cap + 16);
+    if (b->d_first) {
+      (void)hipFree(b->d_first);
+      (void)hipFree(b->d_count);
+      (void)hipFree(b->d_kmax);
+    }
+    API_HIP(hipMalloc(&b->d_first, cap * sizeof(int)));
+    API_HIP(hipMalloc(&b->d_count, cap * sizeof(int)));
+    API_HIP(hipMalloc(&b->d_kmax, cap * sizeof(int)));
+    b->tile_table_cap = cap;
+  }
+  if (!b->d_ntiles) API_HIP(hipMalloc(&b->d_ntiles, sizeof(int)));
+  if (nt) {
+    API_HIP(hipMemcpyAsync(b->d_first, first.data(), nt * sizeof(int), hipMemcpyHostToDevice, b->stream));
+    API_HIP(hipMemcpyAsync(b->d_count, count.data(), nt * sizeof(int), hipMemcpyHostToDevice, b->stream));
+    API_HIP(hipMemcpyAsync(b->d_kmax, kmax.data(), nt * sizeof(int), hipMemcpyHostToDevice, b->stream));
+  }
+  API_HIP(hipMemcpyAsync(b->d_ntiles, &nt, sizeof(int), hipMemcpyHostToDevice, b->stream));
+  API_HIP(hipStreamSynchronize(b->stream));
+  b->grid_tiles = nt;
+  b->any_stream = false;
+  b->any_contact = false;
+  b->stream_kmax = 0;
+  b->n_driven_hi = 0;
+  for (const Slot& s : b->slots) {
+    if (!s.used || s.tiled) continue;
+    b->any_stream = true;
+    b->any_contact = b->any_contact || s.contact;
+    b->stream_kmax = std::max(b->stream_kmax, s.iters);
+    if (s.nd > 0) b->n_driven_hi = std::max(b->n_driven_hi, s.doff + s.nd);
+  }
+  return PABD_OK;
+}
+
+void batch_enqueue(pabd_batch* b, hipStream_t st) {
+  if (b->any_stream)
+    b->eng->flat_step(0, b->n_stream, b->max_slots, b->stream_kmax, b->any_contact, b->n_driven_hi,
+                      false, false, st);
+  if (b->grid_tiles > 0) {
+    TileTable tt{b->d_first, b->d_count, b->d_kmax, b->d_ntiles};
+    b->eng->tile_step(b->tile_bodies, tt, b->grid_tiles, st);
+  }
+  b->eng->finish_scenes(b->max_slots, st);
+}
+
+pabd_status place_tiled(pabd_batch* b, int slot, int n) {
+  Slot& s = b->slots[slot];
+  for (size_t t = 0; t < b->tiles.size(); ++t) {
+    Tile& T = b->tiles[t];
+    if (!T.slots.empty() && T.used + n <= b->tile_bodies) {
+      s.tile = (int)t;
+      s.boff = T.first + T.used;
+      T.used += n;
+      T.slots.push_back(slot);
+      return PABD_OK;
+    }
+  }
+  int first = b->tile_space.take(b->tile_bodies, b->tile_bodies);
+  if (first < 0) return PABD_E_BUSY;
+  int tid = -1;
+  for (size_t t = 0; t < b->tiles.size(); ++t)
+    if (b->tiles[t].slots.empty() && b->tiles[t].used == 0 && b->tiles[t].first < 0) {
+      tid = (int)t;
+      break;
+    }
+  if (tid < 0) {
+    tid = (int)b->tiles.size();
+    b->tiles.push_back(Tile{});
+  }
+  Tile& T = b->tiles[tid];
+  T.first = first;
+  T.used = n;
+  T.slots = {slot};
+  s.tile = tid;
+  s.boff = first;
+  return PABD_OK;
+}
+
+void unplace_tiled(pabd_batch* b, int slot) {
+  Slot& s = b->slots[slot];
+  Tile& T = b->tiles[s.tile];
+  T.slots.erase(std::find(T.slots.begin(), T.slots.end(), slot));
+  if (T.slots.empty()) {
+    b->tile_space.give(T.first, b->tile_bodies);
+    T.first = -1;
+    T.used = 0;
+  } else {
+    int hi = 0;
+    for (int o : T.slots) hi = std::max(hi, b->slots[o].boff + b->slots[o].n - T.first);
+    T.used = hi;
+  }
+  s.tile = -1;
+}
+
+pabd_status batch_place_and_upload(pabd_batch* b, int slot) {
+  Slot& s = b->slots[slot];
+  const HostScene& hs = *s.hs;
+  const bool tiled = !hs.contact && !hs.driven && hs.n > 0 && hs.n <= b->tile_bodies;
+  s.tiled = tiled;
+  if (tiled) {
+    pabd_status st = place_tiled(b, slot, hs.n);
+    if (st != PABD_OK) return st;
+  } else {
+    s.boff = b->stream_bodies.take(std::max(1, hs.n));
+    if (s.boff < 0) return PABD_E_BUSY;
+  }
+  s.eoff = b->ends.take(std::max(1, hs.ne));
+  s.np = (int)hs.planes.size() / 4;
+  s.poff = b->planes.take(std::max(1, s.np));
+  s.nd = (int)hs.drv_end_i.size();
+  s.doff = b->driven.take(std::max(1, s.nd));
+  auto undo = [&]() {
+    if (s.tiled) unplace_tiled(b, slot);
+    else if (s.boff >= 0) b->stream_bodies.give(s.boff, std::max(1, hs.n));
+    if (s.eoff >= 0) b->ends.give(s.eoff, std::max(1, hs.ne));
+    if (s.poff >= 0) b->planes.give(s.poff, std::max(1, s.np));
+    if (s.doff >= 0) b->driven.give(s.doff, std::max(1, s.nd));
+  };
+  if (s.eoff < 0 || s.poff < 0 || s.doff < 0) {
+    undo();
+    return PABD_E_BUSY;
+  }
+  HostScene copy = hs;
+  copy.params.steps_total = s.steps_total;
+  copy.params.ccap = b->caps.ccap;
+  pabd_status st = b->eng->upload(copy, s.boff, s.eoff, s.poff, s.doff, slot, b->stream);
+  if (st != PABD_OK) {
+    undo();
+    return fail(st, b->eng->error());
+  }
+  b->eng->factor(b->stream, s.boff, hs.n);
+  API_HIP(hipGetLastError());
+  API_HIP(hipStreamSynchronize(b->stream));
+  return PABD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pabd_status pabd_batch_create(int32_t max_slots, size_t hbm_budget, int32_t precision,
+                              pabd_batch** out) {
+  if (!out) return fail(PABD_E_INVALID, "null output handle");
+  *out = nullptr;
+  if (max_slots < 1) return fail(PABD_E_INVALID, "max_slots must be >= 1");
+  if (precision != PABD_FP32 && precision != PABD_FP64) return fail(PABD_E_INVALID, "unknown precision");
+  if (pabd_device_count() < 1) return fail(PABD_E_DEVICE, "no HIP device");
+  auto b = std::make_unique<pabd_batch>();
+  b->precision = precision;
+  b->max_slots = max_slots;
+  b->budget = hbm_budget;
+  const int ts = precision == PABD_FP64 ? 8 : 4;
+  // capacity: half the budget for bodies on the flat path (with contact slots),
+  // half for tiled bodies; about three bond ends per body
+  const int ccap = 64;
+  const size_t per_stream = body_cost(ts) + 3 * end_cost(ts) + (size_t)ccap * contact_cost(ts);
+  const size_t per_tiled = body_cost(ts) + 3 * end_cost(ts);
+  size_t n_stream = std::max<size_t>(1024, hbm_budget / 2 / per_stream);
+  size_t n_tiled = std::max<size_t>(1024, hbm_budget / 2 / per_tiled);
+  n_tiled = (n_tiled + 255) / 256 * 256;
+  if (n_stream + n_tiled > (size_t)INT_MAX / 64) return fail(PABD_E_INVALID, "budget too large");
+  b->n_stream = (int)n_stream;
+  b->caps.n = (int)(n_stream + n_tiled);
+  b->caps.e = (int)(3 * (n_stream + n_tiled));
+  b->caps.s = max_slots;
+  b->caps.p = 4 * max_slots + 16;
+  b->caps.dr = std::max(64, (int)(n_stream / 4));
+  b->caps.contacts = true;
+  b->caps.ccap = ccap;
+  b->eng = make_engine(precision);
+  API_HIP(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
+  pabd_status st = b->eng->allocate(b->caps);
+  if (st != PABD_OK) return fail(st, b->eng->error());
+  // scene table entries start inactive (no bodies, zero steps)
+  std::vector<SceneDev> sc(max_slots);
+  for (auto& s : sc) {
+    s = SceneDev{};
+    s.h = 1.0;
+    s.iters = 1;
+    s.cell = 1.0;
+  }
+  API_HIP(hipMemcpy(b->eng->scene_table(), sc.data(), sc.size() * sizeof(SceneDev), hipMemcpyHostToDevice));
+  b->slots.resize(max_slots);
+  b->stream_bodies.init(b->n_stream);
+  b->tile_space.init(b->caps.n);
+  b->tile_space.take(b->n_stream);  // tile space begins after the flat-path bodies
+  {
+    // re-init tile space as [n_stream, n)
+    b->tile_space.init(0);
+    b->tile_space.cap = b->caps.n;
+    b->tile_space.free_.clear();
+    b->tile_space.free_[b->n_stream] = b->caps.n - b->n_stream;
+  }
+  b->ends.init(b->caps.e);
+  b->planes.init(b->caps.p);
+  b->driven.init(b->caps.dr);
+  *out = b.release();
+  return PABD_OK;
+}
+
+pabd_status pabd_batch_destroy(pabd_batch* b) {
+  if (!b) return PABD_OK;
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  b->graph.reset();
+  if (b->d_first) (void)hipFree(b->d_first);
+  if (b->d_count) (void)hipFree(b->d_count);
+  if (b->d_kmax) (void)hipFree(b->d_kmax);
+  if (b->d_ntiles) (void)hipFree(b->d_ntiles);
+  b->eng.reset();
+  if (b->stream) (void)hipStreamDestroy(b->stream);
+  delete b;
+  return PABD_OK;
+}
+
+void* pabd_batch_stream(pabd_batch* b) { return b ? (void*)b->stream : nullptr; }
+
+pabd_status pabd_batch_memory(pabd_batch* b, size_t* used, size_t* budget) {
+  if (!b) return fail(PABD_E_INVALID, "null batch");
+  if (used) *used = b->used_bytes;
+  if (budget) *budget = b->budget;
+  return PABD_OK;
+}
+
+pabd_status pabd_batch_admit(pabd_batch* b, const pabd_scene_desc* desc, int32_t nsteps,
+                             int32_t* slot_out) {
+  if (!b) return fail(PABD_E_INVALID, "null batch");
+  if (nsteps < 0) return fail(PABD_E_INVALID, "negative step count");
+  if (!desc || desc->precision != b->precision)
+    return fail(PABD_E_INVALID, "scene precision differs from the batch precision");
+  auto hs = std::make_shared<HostScene>();
+  std::string why = build_host_scene(desc, *hs);
+  if (!why.empty()) return fail(PABD_E_INVALID, why);
+  if (hs->contact && hs->ccap > b->caps.ccap)
+    return fail(PABD_E_INVALID, "max_contacts_per_body exceeds the batch capacity (64)");
+  const size_t bytes = scene_bytes(*hs, b->precision == PABD_FP64 ? 8 : 4);
+  if (b->used_bytes + bytes > b->budget) return fail(PABD_E_BUSY, "HBM budget exhausted");
+  int slot = -1;
+  for (int k = 0; k < b->max_slots; ++k)
+    if (!b->slots[k].used) {
+      slot = k;
+      break;
+    }
+  if (slot < 0) return fail(PABD_E_BUSY, "no free slot");
+  // the flat path is not yet recorded in a graph: finish in-flight work first
+  API_HIP(hipStreamSynchronize(b->stream));
+  Slot& s = b->slots[slot];
+  s = Slot{};
+  s.hs = hs;
+  s.n = hs->n;
+  s.ne = hs->ne;
+  s.iters = hs->params.iters;
+  s.contact = hs->contact;
+  s.steps_total = nsteps;
+  s.admitted_at = b->substeps;
+  s.bytes = bytes;
+  pabd_status st = batch_place_and_upload(b, slot);
+  if (st != PABD_OK) {
+    s = Slot{};
+    return st == PABD_E_BUSY ? fail(st, "no contiguous room for the scene") : st;
+  }
+  s.used = true;
+  b->used_bytes += bytes;
+  b->dirty = true;
+  if (slot_out) *slot_out = slot;
+  return PABD_OK;
+}
+
+pabd_status pabd_batch_release(pabd_batch* b, int32_t slot) {
+  if (!b) return fail(PABD_E_INVALID, "null batch");
+  if (slot < 0 || slot >= b->max_slots || !b->slots[slot].used) return fail(PABD_E_NOTFOUND, "slot not in use");
+  API_HIP(hipStreamSynchronize(b->stream));
+  Slot& s = b->slots[slot];
+  pabd_status st = b->eng->clear_bodies(s.boff, std::max(1, s.n), b->stream, s.doff, s.nd);
+  if (st != PABD_OK) return fail(st, b->eng->error());
+  SceneDev off{};
+  off.h = 1.0;
+  off.iters = 1;
+  off.cell = 1.0;
+  API_HIP(hipMemcpy(b->eng->scene_table() + slot, &off, sizeof(SceneDev), hipMemcpyHostToDevice));
+  if (s.tiled) unplace_tiled(b, slot);
+  else b->stream_bodies.give(s.boff, std::max(1, s.n));
+  b->ends.give(s.eoff, std::max(1, s.ne));
+  b->planes.give(s.poff, std::max(1, s.np));
+  b->driven.give(s.doff, std::max(1, s.nd));
+  b->used_bytes -= s.bytes;
+  s = Slot{};
+  b->dirty = true;
+  return PABD_OK;
+}
+
+pabd_status pabd_batch_step(pabd_batch* b, void* hip_stream) {
+  if (!b) return fail(PABD_E_INVALID, "null batch");
+  hipStream_t st = hip_stream ? (hipStream_t)hip_stream : b->stream;
+  if (b->dirty) {
+    pabd_status s2 = batch_tables(b);
+    if (s2 != PABD_OK) return s2;
+    b->graph.reset();
+    b->dirty = false;
+  }
+  if (use_graphs()) {
+    if (!b->graph.x) {
+      API_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+      batch_enqueue(b, b->stream);
+      hipError_t e = hipStreamEndCapture(b->stream, &b->graph.g);
+      if (e != hipSuccess) return fail(PABD_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+      API_HIP(hipGraphInstantiate(&b->graph.x, b->graph.g, nullptr, nullptr, 0));
+    }
+    API_HIP(hipGraphLaunch(b->graph.x, st));
+  } else {
+    batch_enqueue(b, st);
+    API_HIP(hipGetLastError());
+  }
+  b->substeps++;
+  return PABD_OK;
+}
+
+pabd_status pabd_batch_steps_done(pabd_batch* b, int32_t slot, int32_t* steps) {
+  if (!b) return fail(PABD_E_INVALID, "null batch");
+  if (slot < 0 || slot >= b->max_slots || !b->slots[slot].used) return fail(PABD_E_NOTFOUND, "slot not in use");
+  const Slot& s = b->slots[slot];
+  long long d = b->substeps - s.admitted_at;
+  if (steps) *steps = (int32_t)std::min<long long>(d, s.steps_total);
+  return PABD_OK;
+}
+
+pabd_status pabd_batch_poll(pabd_batch* b, int32_t* done, int32_t cap, int32_t* n_done) {
+  if (!b) return fail(PABD_E_INVALID, "null batch");
+  int n = 0;
+  for (int k = 0; k < b->max_slots; ++k) {
+    const Slot& s = b->slots[k];
+    if (!s.used) continue;
+    if (b->substeps - s.admitted_at >= s.steps_total) {
+      if (done && n < cap) done[n] = k;
+      ++n;
+    }
+  }
+  if (n_done) *n_done = n;
+  return PABD_OK;
+}
+
+pabd_status pabd_batch_read_state(pabd_batch* b, int32_t slot, double* c, double* A, double* v,
+                                  double* w) {
+  if (!b) return fail(PABD_E_INVALID, "null batch");
+  if (slot < 0 || slot >= b->max_slots || !b->slots[slot].used) return fail(PABD_E_NOTFOUND, "slot not in use");
+  API_HIP(hipDeviceSynchronize());
+  const Slot& s = b->slots[slot];
+  pabd_status st = b->eng->read_bodies(s.boff, s.n, c, A, v, w, b->stream);
+  if (st != PABD_OK) return st;
+  int health = 0;
+  API_HIP(hipMemcpy(&health, b->eng->health_ptr() + slot, sizeof(int), hipMemcpyDeviceToHost));
+  if (health & 1) return fail(PABD_E_DIVERGED, "non-finite state");
+  if (health & 2) return fail(PABD_E_DIVERGED, "contact capacity exceeded");
+  return PABD_OK;
+}
+
+pabd_status pabd_batch_residual(pabd_batch* b, int32_t slot, double* rho_last) {
+  if (!b) return fail(PABD_E_INVALID, "null batch");
+  if (slot < 0 || slot >= b->max_slots || !b->slots[slot].used) return fail(PABD_E_NOTFOUND, "slot not in use");
+  API_HIP(hipDeviceSynchronize());
+  API_HIP(hipMemcpy(rho_last, b->eng->rho_ptr() + slot, sizeof(double), hipMemcpyDeviceToHost));
+  return PABD_OK;
+}
+
+static pabd_status batch_repack(pabd_batch* b, int tile_bodies) {
+  // read back every resident scene's state, re-place all scenes with the new
+  // tile size, and upload again
+  API_HIP(hipDeviceSynchronize());
+  std::vector<int> live;
+  for (int k = 0; k < b->max_slots; ++k)
+    if (b->slots[k].used) live.push_back(k);
+  std::vector<int> sc_steps(b->max_slots, 0);
+  {
+    std::vector<SceneDev> tab(b->max_slots);
+    API_HIP(hipMemcpy(tab.data(), b->eng->scene_table(), tab.size() * sizeof(SceneDev), hipMemcpyDeviceToHost));
+    for (int k : live) sc_steps[k] = tab[k].step;
+  }
+  for (int k : live) {
+    Slot& s = b->slots[k];
+    HostScene& hs = *s.hs;
+    std::vector<double> c(3 * s.n), A(9 * s.n), v(3 * s.n), w(3 * s.n);
+    pabd_status st = b->eng->read_bodies(s.boff, s.n, c.data(), A.data(), v.data(), w.data(), b->stream);
+    if (st != PABD_OK) return st;
+    auto fresh = std::make_shared<HostScene>(hs);
+    for (int i = 0; i < s.n; ++i) {
+      for (int d = 0; d < 3; ++d) fresh->qn[12 * i + d] = c[3 * i + d];
+      for (int d = 0; d < 9; ++d) fresh->qn[12 * i + 3 + d] = A[9 * i + d];
+      for (int d = 0; d < 3; ++d) {
+        fresh->vel[8 * i + d] = v[3 * i + d];
+        fresh->vel[8 * i + 3 + d] = w[3 * i + d];
+      }
+    }
+    s.hs = fresh;
+  }
+  for (int k : live) {
+    Slot& s = b->slots[k];
+    pabd_status st = b->eng->clear_bodies(s.boff, std::max(1, s.n), b->stream, s.doff, s.nd);
+    if (st != PABD_OK) return fail(st, b->eng->error());
+    if (s.tiled) unplace_tiled(b, k);
+    else b->stream_bodies.give(s.boff, std::max(1, s.n));
+    b->ends.give(s.eoff, std::max(1, s.ne));
+    b->planes.give(s.poff, std::max(1, s.np));
+    b->driven.give(s.doff, std::max(1, s.nd));
+  }
+  b->tiles.clear();
+  b->tile_bodies = tile_bodies;
+  for (int k : live) {
+    Slot& s = b->slots[k];
+    pabd_status st = batch_place_and_upload(b, k);
+    if (st != PABD_OK) return fail(PABD_E_OOM, "repack did not fit");
+    // restore the scene's step counter
+    SceneDev* d = b->eng->scene_table() + k;
+    API_HIP(hipMemcpy((char*)d + offsetof(SceneDev, step), &sc_steps[k], sizeof(int), hipMemcpyHostToDevice));
+    (void)s;
+  }
+  b->eng->factor(b->stream);
+  API_HIP(hipStreamSynchronize(b->stream));
+  b->dirty = true;
+  return PABD_OK;
+}
+
+pabd_status pabd_batch_time_tile_kernel(pabd_batch* b, int32_t reps, double* avg_ms) {
+  if (!b || reps < 1 || !avg_ms) return fail(PABD_E_INVALID, "bad arguments");
+  *avg_ms = 0.0;
+  if (b->dirty) {
+    pabd_status s2 = batch_tables(b);
+    if (s2 != PABD_OK) return s2;
+    b->graph.reset();
+    b->dirty = false;
+  }
+  if (b->grid_tiles == 0) return PABD_OK;
+  hipEvent_t e0, e1;
+  API_HIP(hipEventCreate(&e0));
+  API_HIP(hipEventCreate(&e1));
+  TileTable tt{b->d_first, b->d_count, b->d_kmax, b->d_ntiles};
+  b->eng->tile_step(b->tile_bodies, tt, b->grid_tiles, b->stream);  // warm
+  API_HIP(hipEventRecord(e0, b->stream));
+  for (int r = 0; r < reps; ++r) b->eng->tile_step(b->tile_bodies, tt, b->grid_tiles, b->stream);
+  API_HIP(hipEventRecord(e1, b->stream));
+  API_HIP(hipEventSynchronize(e1));
+  float ms = 0.f;
+  API_HIP(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *avg_ms = (double)ms / reps;
+  return PABD_OK;
+}
+
+pabd_status pabd_batch_layout(pabd_batch* b, int32_t* n_bodies, int32_t* n_tiles, int32_t* tile_bodies) {
+  if (!b) return fail(PABD_E_INVALID, "null batch");
+  int nb = 0, nt = 0;
+  for (const Slot& s : b->slots)
+    if (s.used) nb += s.n;
+  for (const Tile& t : b->tiles)
+    if (!t.slots.empty()) ++nt;
+  if (n_bodies) *n_bodies = nb;
+  if (n_tiles) *n_tiles = nt;
+  if (tile_bodies) *tile_bodies = b->tile_bodies;
+  return PABD_OK;
+}
+
+pabd_status pabd_batch_set_tile(pabd_batch* b, int32_t tile_bodies) {
+  if (!b) return fail(PABD_E_INVALID, "null batch");
+  if (tile_bodies == 0) {
+    b->tile_auto = true;
+    return PABD_OK;
+  }
+  if (tile_bodies != 32 && tile_bodies != 64 && tile_bodies != 128 && tile_bodies != 256)
+    return fail(PABD_E_INVALID, "tile size must be 32, 64, 128 or 256");
+  b->tile_auto = false;
+  if (tile_bodies == b->tile_bodies) return PABD_OK;
+  return batch_repack(b, tile_bodies);
+}
+
+pabd_status pabd_batch_autotune(pabd_batch* b, int32_t* tile_out) {
+  if (!b) return fail(PABD_E_INVALID, "null batch");
+  // candidates: tile sizes that hold the largest tiled scene
+  int largest = 0;
+  for (const Slot& s : b->slots)
+    if (s.used && !s.hs->contact && !s.hs->driven) largest = std::max(largest, s.n);
+  std::vector<int> cand;
+  for (int t : {32, 64, 128, 256})
+    if (t >= largest) cand.push_back(t);
+  if (cand.empty()) cand.push_back(256);
+  API_HIP(hipDeviceSynchronize());
+  std::vector<char> snap;
+  const int n = b->caps.n;
+  pabd_status st;
+  double best_t = 1e300;
+  int best = b->tile_bodies;
+  long long substeps0 = b->substeps;
+  for (int t : cand) {
+    if ((st = batch_repack(b, t)) != PABD_OK) return st;
+    if ((st = b->eng->snapshot(n, snap, b->stream, false)) != PABD_OK) return st;
+    if ((st = pabd_batch_step(b, nullptr)) != PABD_OK) return st;  // warm-up and capture
+    API_HIP(hipStreamSynchronize(b->stream));
+    const int reps = 5;
+    auto t0 = std::chrono::steady_clock::now();
+    for (int r = 0; r < reps; ++r)
+      if ((st = pabd_batch_step(b, nullptr)) != PABD_OK) return st;
+    API_HIP(hipStreamSynchronize(b->stream));
+    double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count() / reps;
+    if ((st = b->eng->snapshot(n, snap, b->stream, true)) != PABD_OK) return st;
+    b->substeps = substeps0;
+    if (dt < best_t) {
+      best_t = dt;
+      best = t;
+    }
+  }
+  if ((st = batch_repack(b, best)) != PABD_OK) return st;
+  b->tile_auto = false;
+  if (tile_out) *tile_out = best;
+  return PABD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,142 @@
+"""GPU tests of the batched path (tile kernel + flat kernels in one captured
+graph per step): parity with the oracle per scene, invariance of every scene's
+result alone vs in the mix and across tile sizes, admission by HBM budget."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2609_02675_amd import scenes as S
+from parity import errors, fp64_ok, scale_of, worst
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2609_02675_amd as P
+    if P.device_count() < 1:
+        pytest.fail("no HIP device visible")
+    return P
+
+
+def _oracle_state(sc, steps):
+    o = oracle.Oracle(sc)
+    o.step(steps)
+    return o.state()
+
+
+def _run_batch(P, scenes, steps, prec, tile=None, budget=1 << 30):
+    b = P.Batch(len(scenes) + 2, budget, prec)
+    if tile:
+        b.set_tile(tile)
+    slots = [b.admit(s, steps) for s in scenes]
+    assert all(x is not None for x in slots)
+    for _ in range(steps):
+        b.step()
+    return b, slots, [b.state(s) for s in slots]
+
+
+def test_batched_chains_fp64_match_oracle(P):
+    scs = S.batched_chains(48, seed=2, precision=S.PREC_FP64)
+    print(f"[case] 48 chains fp64 sizes {[s.n_bodies for s in scs][:8]}...", flush=True)
+    b, slots, states = _run_batch(P, scs, 30, S.PREC_FP64)
+    for sc, st in zip(scs, states):
+        e = errors(st, _oracle_state(sc, 30), scale_of(sc))
+        assert e["pos"] <= 1e-9 and e["rot"] <= 1e-9, (sc.name, e)
+
+
+@pytest.mark.parametrize("steps,tol", [(1, 1e-4), (100, 1e-3)])
+def test_batched_chains_fp32_match_oracle(P, steps, tol):
+    scs = S.batched_chains(32, seed=7, precision=S.PREC_FP32)
+    print(f"[case] 32 chains fp32 steps {steps}", flush=True)
+    b, slots, states = _run_batch(P, scs, steps, S.PREC_FP32)
+    worst_e = 0.0
+    for sc, st in zip(scs, states):
+        e = errors(st, _oracle_state(sc, steps), scale_of(sc))
+        worst_e = max(worst_e, e["pos"], e["rot"])
+        assert e["pos"] <= tol and e["rot"] <= tol, (sc.name, e)
+    print(f"fp32 worst error after {steps} steps: {worst_e:.3e}")
+
+
+def test_each_scene_same_alone_and_in_the_mix(P):
+    """Per-body sums run in a fixed (bond id) order, so a scene's bits do not
+    depend on its neighbours in the batch."""
+    scs = S.batched_chains(40, seed=11, precision=S.PREC_FP32)
+    b, slots, mixed = _run_batch(P, scs, 20, S.PREC_FP32)
+    for k in (0, 13, 39):
+        b1, s1, alone = _run_batch(P, [scs[k]], 20, S.PREC_FP32)
+        for x, y in zip(mixed[k], alone[0]):
+            np.testing.assert_array_equal(x, y)
+
+
+@pytest.mark.parametrize("tile", [32, 128, 256])
+def test_tile_size_does_not_change_results(P, tile):
+    scs = [s for s in S.batched_chains(24, seed=5, precision=S.PREC_FP32) if s.n_bodies <= 32]
+    b, slots, ref = _run_batch(P, scs, 10, S.PREC_FP32, tile=64)
+    b2, slots2, got = _run_batch(P, scs, 10, S.PREC_FP32, tile=tile)
+    for x, y in zip(ref, got):
+        for a, c in zip(x, y):
+            np.testing.assert_array_equal(a, c)
+
+
+def test_flat_path_scenes_in_a_batch(P):
+    """Scenes too large for a tile (300 bodies) and driven scenes go through the
+    flat kernels of the same graph; mixed with tiled chains."""
+    big = S.chain(300, tilt_deg=20.0, joint_angles_deg=np.linspace(-5, 5, 299),
+                  precision=S.PREC_FP64, iters=12)
+    small = S.batched_chains(5, seed=3, precision=S.PREC_FP64)
+    scs = [big] + small
+    b, slots, states = _run_batch(P, scs, 15, S.PREC_FP64)
+    for sc, st in zip(scs, states):
+        assert fp64_ok(errors(st, _oracle_state(sc, 15), scale_of(sc))), sc.name
+
+
+def test_scenes_with_different_step_budgets_freeze(P):
+    scs = S.batched_chains(3, seed=1, precision=S.PREC_FP64)
+    b = P.Batch(4, 1 << 28, S.PREC_FP64)
+    slots = [b.admit(s, n) for s, n in zip(scs, (5, 10, 15))]
+    for _ in range(15):
+        b.step()
+    assert sorted(b.poll()) == sorted(slots)
+    for sc, sl, n in zip(scs, slots, (5, 10, 15)):
+        assert b.steps_done(sl) == n
+        assert fp64_ok(errors(b.state(sl), _oracle_state(sc, n), scale_of(sc)))
+
+
+def test_admission_respects_budget_and_release_frees_it(P):
+    sc = S.chain(64, tilt_deg=0.0, precision=S.PREC_FP32)
+    need = P.scene_bytes(sc)
+    b = P.Batch(16, 3 * need + need // 2, S.PREC_FP32)
+    slots = [b.admit(sc, 10) for _ in range(4)]
+    assert slots[3] is None and all(s is not None for s in slots[:3])
+    b.release(slots[0])
+    assert b.admit(sc, 10) is not None
+
+
+def test_autotune_picks_a_tile_and_keeps_state(P):
+    scs = S.batched_chains(64, seed=9, precision=S.PREC_FP32)
+    b = P.Batch(70, 1 << 28, S.PREC_FP32)
+    slots = [b.admit(s, 20) for s in scs]
+    for _ in range(5):
+        b.step()
+    tile = b.autotune()
+    assert tile in (64, 128, 256)
+    for _ in range(15):
+        b.step()
+    ref_b, ref_slots, ref = _run_batch(P, scs, 20, S.PREC_FP32)
+    for sl, r in zip(slots, ref):
+        for x, y in zip(b.state(sl), r):
+            np.testing.assert_array_equal(x, y)
+
+
+def test_full_size_batched_chains_sampled(P):
+    """4096 chains of 4..64 bodies (the batched workload) in one batch, FP32,
+    20 iterations, 100 steps; sampled scenes checked against the oracle."""
+    scs = S.batched_chains(4096, seed=2, precision=S.PREC_FP32)
+    print(f"[case] 4096 chains, {sum(s.n_bodies for s in scs)} bodies", flush=True)
+    b, slots, _ = _run_batch(P, scs, 100, S.PREC_FP32, budget=2 << 30)
+    rng = np.random.default_rng(0)
+    for k in rng.choice(len(scs), 8, replace=False):
+        e = errors(b.state(slots[k]), _oracle_state(scs[k], 100), scale_of(scs[k]))
+        print(scs[k].name, e)
+        assert e["pos"] <= 1e-3 and e["rot"] <= 1e-3

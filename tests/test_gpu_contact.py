@@ -1,0 +1,136 @@
+"""GPU contact-bond construction and contact dynamics against the oracle.
+
+The discrete contact set (which point of which body touches which surface) is
+compared exactly in FP64 mode; the states within the FP64/FP32 tolerances.
+Contact-rich starting states are made by the oracle alone."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2609_02675_amd import scenes as S
+from parity import errors, fp64_ok, scale_of, worst
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2609_02675_amd as P
+    if P.device_count() < 1:
+        pytest.fail("no HIP device visible")
+    return P
+
+
+def settled_drop(n_side=4, layers=2, steps=90, seed=0):
+    """A small box drop advanced by the oracle until many contacts exist."""
+    sc = S.box_drop(n_side=n_side, layers=layers, seed=seed, precision=S.PREC_FP64)
+    o = oracle.Oracle(sc)
+    o.step(steps)
+    c, A, v, w = o.state()
+    return sc.with_state(c, A, v, w, t0=steps * sc.h)
+
+
+def _contact_table(ct):
+    key = np.stack([ct["i"], ct["j"], ct["feature"]], axis=1)
+    order = np.lexsort((key[:, 2], key[:, 1], key[:, 0]))
+    return key[order], {k: v[order] for k, v in ct.items()}
+
+
+def _compare_contacts(g, o):
+    kg, cg = _contact_table(g.contacts())
+    ko, co = _contact_table(o.contacts())
+    assert len(kg) > 0
+    np.testing.assert_array_equal(kg, ko)
+    for f in ("x_i", "x_j", "normal", "kappa"):
+        np.testing.assert_allclose(cg[f], co[f], rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_contact_set_matches_oracle_fp64(P, seed):
+    sc = settled_drop(seed=seed)
+    print(f"[case] contact set seed {seed} n={sc.n_bodies}", flush=True)
+    g = P.Scene(sc)
+    g.step(1)
+    o = oracle.Oracle(sc)
+    o.step(1)
+    _compare_contacts(g, o)
+    assert fp64_ok(errors(g.state(), o.state(), scale_of(sc)))
+
+
+def test_contact_dynamics_fp64_several_steps(P):
+    sc = settled_drop(seed=2)
+    g = P.Scene(sc)
+    g.step(10)
+    o = oracle.Oracle(sc)
+    o.step(10)
+    e = errors(g.state(), o.state(), scale_of(sc))
+    print("contact fp64 10 steps", e)
+    assert e["pos"] <= 1e-9 and e["rot"] <= 1e-9
+
+
+def test_contact_dynamics_fp32_one_step(P):
+    sc = settled_drop(seed=3).copy(precision=S.PREC_FP32)
+    g = P.Scene(sc)
+    g.step(1)
+    o = oracle.Oracle(sc)
+    o.step(1)
+    e = errors(g.state(), o.state(), scale_of(sc))
+    print("contact fp32 1 step", e)
+    assert e["pos"] <= 1e-4 and e["rot"] <= 1e-4
+
+
+def test_mass_ratio_stack_fp64(P):
+    sc = S.box_stack(n=6, mass_ratio=10.0)
+    g = P.Scene(sc)
+    g.step(60)
+    o = oracle.Oracle(sc)
+    o.step(60)
+    assert fp64_ok(errors(g.state(), o.state(), scale_of(sc)))
+
+
+def test_spheres_and_boxes_fp64(P):
+    """Sphere-sphere, sphere-plane, sphere-box and box-plane contacts."""
+    rng = np.random.default_rng(4)
+    n = 40
+    sc = S.box_drop(n_side=2, layers=1, seed=4, precision=S.PREC_FP64)
+    sp = S.single_body(shape=S.SHAPE_SPHERE, half=(0.2, 0, 0), density=800.0)
+    spheres = []
+    for k in range(n):
+        spheres.append(sp.copy(c0=np.array([[rng.uniform(-2, 2), 0.25 + 0.45 * k / 4, rng.uniform(-2, 2)]]),
+                               shape_param=np.array([[rng.uniform(0.15, 0.3), 0, 0]])))
+    sc = S.merge([sc] + spheres).copy(contact_enable=1, planes=np.array([[0.0, 1.0, 0.0, 0.0]]),
+                                      precision=S.PREC_FP64)
+    o = oracle.Oracle(sc)
+    o.step(40)
+    c, A, v, w = o.state()
+    sc = sc.with_state(c, A, v, w, t0=40 * sc.h)
+    g = P.Scene(sc)
+    g.step(1)
+    o = oracle.Oracle(sc)
+    o.step(1)
+    _compare_contacts(g, o)
+    g.step(9)
+    o.step(9)
+    assert fp64_ok(errors(g.state(), o.state(), scale_of(sc)))
+
+
+def test_contact_capacity_overflow_is_reported(P):
+    sc = settled_drop(seed=0).copy(max_contacts_per_body=2)
+    g = P.Scene(sc)
+    g.step(1)
+    with pytest.raises(P.Diverged):
+        g.state()
+
+
+def test_contact_scenes_in_a_batch_fp64(P):
+    scs = [settled_drop(n_side=3, layers=1, steps=60, seed=s) for s in (5, 6)]
+    b = P.Batch(8, 1 << 28, S.PREC_FP64)
+    slots = [b.admit(s, 8) for s in scs]
+    chains = S.batched_chains(3, seed=4, precision=S.PREC_FP64)
+    cslots = [b.admit(s, 8) for s in chains]
+    for _ in range(8):
+        b.step()
+    for sc, sl in zip(scs + chains, slots + cslots):
+        o = oracle.Oracle(sc)
+        o.step(8)
+        assert fp64_ok(errors(b.state(sl), o.state(), scale_of(sc))), sc.name
