@@ -162,6 +162,8 @@ pabd_status pabd_batch_autotune(pabd_batch *b, int32_t *tile_bodies);
 /* Force a tile size (32, 64, 128 or 256 bodies; 0 = automatic). */
 pabd_status pabd_batch_set_tile(pabd_batch *b, int32_t tile_bodies);
 void *pabd_batch_stream(pabd_batch *b);
+/* Block until all work enqueued on the batch's stream has finished. */
+pabd_status pabd_batch_sync(pabd_batch *b);
 /* Measurement: launch the tile kernel alone reps times on the batch's stream
  * between two HIP events and return its average duration in ms (0 if no scene
  * is tiled).  Advances the tiled scenes' bodies like extra steps would. */
@@ -171,6 +173,15 @@ pabd_status pabd_batch_layout(pabd_batch *b, int32_t *n_bodies, int32_t *n_tiles
                               int32_t *tile_bodies);
 /* Bytes of HBM budget in use / free. */
 pabd_status pabd_batch_memory(pabd_batch *b, size_t *used, size_t *budget);
+
+/* ---- measurement ------------------------------------------------------------ */
+
+/* Device-wide streaming copy of `bytes` (rounded down to 16-byte units) between
+ * two library-owned buffers, timed with HIP events over `reps` launches on the
+ * library's probe stream: the achievable-HBM-bandwidth reference and the
+ * calibration kernel for hardware traffic counters.  Writes GB/s of read+write
+ * traffic (2 * bytes per launch) and the average launch duration in ms. */
+pabd_status pabd_hbm_copy_probe(size_t bytes, int32_t reps, double *gbps, double *avg_ms);
 
 #ifdef __cplusplus
 }

@@ -27,6 +27,7 @@ SYMBOLS = [
     "pabd_batch_poll", "pabd_batch_read_state", "pabd_batch_residual", "pabd_batch_release",
     "pabd_batch_steps_done", "pabd_batch_autotune", "pabd_batch_set_tile", "pabd_batch_stream",
     "pabd_batch_memory", "pabd_batch_time_tile_kernel", "pabd_batch_layout",
+    "pabd_hbm_copy_probe", "pabd_batch_sync",
 ]
 
 
@@ -104,6 +105,8 @@ def lib():
     L.pabd_batch_memory.argtypes = [vp, _P(C.c_size_t), _P(C.c_size_t)]
     L.pabd_batch_time_tile_kernel.argtypes = [vp, C.c_int32, _d]
     L.pabd_batch_layout.argtypes = [vp, _i, _i, _i]
+    L.pabd_hbm_copy_probe.argtypes = [C.c_size_t, C.c_int32, _d, _d]
+    L.pabd_batch_sync.argtypes = [vp]
     _lib = L
     return L
 
@@ -166,6 +169,13 @@ class _Marshalled:
 
 def device_count() -> int:
     return int(lib().pabd_device_count())
+
+
+def hbm_copy_probe(nbytes: int, reps: int = 20):
+    """(GB/s of read + write traffic, average ms) of a device-wide streaming copy."""
+    g, ms = np.zeros(1), np.zeros(1)
+    _check(lib().pabd_hbm_copy_probe(int(nbytes), int(reps), _ptr(g, C.c_double), _ptr(ms, C.c_double)))
+    return float(g[0]), float(ms[0])
 
 
 def scene_bytes(scene: SceneDesc) -> int:
@@ -270,6 +280,9 @@ class Batch:
 
     def step(self, stream: Optional[int] = None):
         _check(lib().pabd_batch_step(self._h, C.c_void_p(stream) if stream else None))
+
+    def sync(self):
+        _check(lib().pabd_batch_sync(self._h))
 
     def poll(self) -> List[int]:
         cap = max(1, len(self._n))

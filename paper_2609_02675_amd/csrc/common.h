@@ -54,6 +54,8 @@ struct SceneDev {
   int step;         // completed steps
   int debug;        // bit0: skip the local step
   int steps_total;  // the scene is frozen once step reaches this
+  int tiled;        // advanced by the tile kernel (which also reduces its residual)
+  int pad;
 };
 
 template <typename T>
@@ -89,6 +91,7 @@ struct View {
   // scenes
   SceneDev* scenes;
   int* health;  // per scene: bit0 non-finite, bit1 contact overflow
+  double* rho;  // per scene: residual of the last iteration of the last step
 };
 
 // ---- vector load/store of packed records --------------------------------------

@@ -31,6 +31,23 @@ __device__ __forceinline__ T dsqrt(T x) {
   return sqrt(x);
 }
 
+// 1/x and 1/sqrt(x): the hardware approximations (about 1 ulp) in FP32, exact
+// IEEE operations in FP64
+template <typename T>
+__device__ __forceinline__ T rcp(T x) {
+  if constexpr (sizeof(T) == 4)
+    return __builtin_amdgcn_rcpf(x);
+  else
+    return (T)1 / x;
+}
+template <typename T>
+__device__ __forceinline__ T rsqrt_(T x) {
+  if constexpr (sizeof(T) == 4)
+    return __builtin_amdgcn_rsqf(x);
+  else
+    return (T)1 / sqrt(x);
+}
+
 // ---- 3x3 helpers (row-major) ------------------------------------------------
 
 template <typename T>
@@ -155,9 +172,9 @@ __device__ void nearest_rotation_svd(const T* A, T* R) {
 }
 
 // Rotation factor of the polar decomposition A = R S (Sec. 4.2.2, local solve):
-// Newton's iteration X <- (zeta X + X^{-T} / zeta) / 2 with determinant scaling
-// zeta = |det X|^{-1/3} in the first steps, stopped once the update is below the
-// precision's tolerance.  det A <= 0 (no proper polar factor) or a stalled
+// Newton's iteration X <- (zeta X + X^{-T} / zeta) / 2, with determinant scaling
+// zeta = |det X|^{-1/3} while det X is far from 1, stopped once the update is
+// below the precision's tolerance.  det A <= 0 (no proper polar factor) or a stalled
 // iteration fall back to the nearest proper rotation.
 template <typename T>
 __device__ __forceinline__ void polar_rotation(const T* A, T* R) {
@@ -169,8 +186,9 @@ __device__ __forceinline__ void polar_rotation(const T* A, T* R) {
     T C[9];
     T det = cofactor(X, C);
     if (!(det > Eps<T>::det_floor)) break;
-    T zeta = it < 2 ? (T)1 / cbrt(det) : (T)1;
-    T a = (T)0.5 * zeta, b = (T)0.5 / (zeta * det);
+    // determinant scaling only far from orthogonal (near SO(3), det ~ 1)
+    T zeta = (det > (T)0.5 && det < (T)1.5) ? (T)1 : rcp(cbrt(det));
+    T a = (T)0.5 * zeta, b = (T)0.5 * rcp(zeta * det);
     T diff = 0;
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
@@ -199,7 +217,7 @@ __device__ __forceinline__ void polar_rotation(const T* A, T* R) {
 template <typename T>
 __device__ __forceinline__ void predict_rotation(const T* A, const T* w, T h, T* As) {
   T x = (T)0.5 * h * w[0], y = (T)0.5 * h * w[1], z = (T)0.5 * h * w[2];
-  T inv = (T)1 / ((T)1 + x * x + y * y + z * z);
+  T inv = rcp((T)1 + x * x + y * y + z * z);
   T R[9];
   R[0] = (T)1 - (T)2 * (y * y + z * z) * inv;
   R[1] = (T)2 * (x * y - z) * inv;

@@ -188,6 +188,7 @@ struct Engine {
     v.r_den = r_den;
     v.scenes = scenes;
     v.health = health;
+    v.rho = rho;
     return v;
   }
 

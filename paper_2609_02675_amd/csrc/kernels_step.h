@@ -84,7 +84,7 @@ __device__ __forceinline__ void quad_end_force(const T* E, const T* d, T* f) {
   if (E[7] != (T)0) {
     T dn2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
     if (dn2 > (T)1e-24) {
-      T sc = E[7] / sqrt(dn2);
+      T sc = E[7] * rsqrt_(dn2);
       f[0] += sc * d[0];
       f[1] += sc * d[1];
       f[2] += sc * d[2];
@@ -108,7 +108,7 @@ __device__ __forceinline__ bool contact_end_force(const T* C, const T* d, T* f) 
   T tn2 = t0 * t0 + t1 * t1 + t2 * t2;
   T lim = mu * fn;
   if (tn2 > lim * lim) {
-    T sc = lim / sqrt(tn2);
+    T sc = lim * rsqrt_(tn2);
     t0 *= sc;
     t1 *= sc;
     t2 *= sc;
@@ -236,8 +236,7 @@ __global__ void __launch_bounds__(256) k_iterate(View<T> v, int k, double* rh_nu
 
 // velocity recovery from q^{n+1} (= qf) and q^n (= q0), shared with the tile kernel
 template <typename T>
-__device__ __forceinline__ void recover_velocity(const T* qf, const T* q0, T h, T* vw) {
-  const T ih = (T)1 / h;
+__device__ __forceinline__ void recover_velocity(const T* qf, const T* q0, T ih, T* vw) {
   T dc[3];
   pos_diff(qf, q0, dc);
   vw[0] = dc[0] * ih;
@@ -278,7 +277,7 @@ __global__ void __launch_bounds__(256) k_finish(View<T> v) {
   load<T, QR>(v.q[S.iters & 1] + (size_t)QR * i, qf);
   load<T, QR>(v.qn + (size_t)QR * i, q0);
   T vw[VW];
-  recover_velocity(qf, q0, (T)S.h, vw);
+  recover_velocity(qf, q0, (T)(1.0 / S.h), vw);
   bool finite = true;
 #pragma unroll
   for (int c = 0; c < QR; ++c) finite = finite && isfinite(qf[c]);
@@ -297,6 +296,7 @@ __global__ void __launch_bounds__(256) k_reduce_residual(const SceneDev* scenes,
   __shared__ double sn[256], sd[256];
   const int sc = blockIdx.x;
   if (sc >= n_scenes) return;
+  if (scenes[sc].tiled) return;  // the tile kernel reduces its own scenes
   const int off = scenes[sc].body_off, nb = scenes[sc].n_bodies;
   double a = 0.0, b = 0.0;
   for (int t = threadIdx.x; t < nb; t += blockDim.x) {
@@ -383,7 +383,8 @@ __global__ void k_update_driven(View<T> v, int n_driven, const int* d_scene, con
 
 __global__ void k_end_step(SceneDev* scenes, int n_scenes) {
   const int sc = blockIdx.x * blockDim.x + threadIdx.x;
-  if (sc < n_scenes && scenes[sc].step < scenes[sc].steps_total) scenes[sc].step += 1;
+  if (sc < n_scenes && !scenes[sc].tiled && scenes[sc].step < scenes[sc].steps_total)
+    scenes[sc].step += 1;
 }
 
 }  // namespace pabd

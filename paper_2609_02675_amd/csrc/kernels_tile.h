@@ -34,20 +34,22 @@ __global__ void __launch_bounds__(TB) k_tile_step(View<T> v, TileTable tt) {
     const bool present = scn >= 0 && v.scenes[scn].step < v.scenes[scn].steps_total;
     const bool pinned = present && (v.flags[i] & F_PINNED);
     const bool moving = present && !pinned;
-    T q[QR], s[QR], m[MW], fac[FW], vw[VW];
+    T q[QR], s[QR], m[MW], fac[FW];
     T E[MAXE][EW];
     int part[MAXE];
     int e0 = 0, ne = 0, K = 0;
-    T h = (T)1, h2 = (T)1;
+    T ih = (T)1, h2 = (T)1;
     int debug = 0;
     if (present) {
       load<T, QR>(v.qn + (size_t)QR * i, q);
       const SceneDev& S = v.scenes[scn];
       K = S.iters;
       debug = S.debug;
-      h = (T)S.h;
+      const T h = (T)S.h;
+      ih = (T)(1.0 / S.h);
       h2 = (T)(S.h * S.h);
       if (moving) {
+        T vw[VW];
         load<T, VW>(v.vel + (size_t)VW * i, vw);
         load<T, MW>(v.mass + (size_t)MW * i, m);
         load<T, FW>(v.fac + (size_t)FW * i, fac);
@@ -67,9 +69,6 @@ __global__ void __launch_bounds__(TB) k_tile_step(View<T> v, TileTable tt) {
         predict_rotation(q + 3, vw + 3, h, s + 3);
       }
     }
-    T qn[QR];
-#pragma unroll
-    for (int c = 0; c < QR; ++c) qn[c] = q[c];
     if (moving) {
 #pragma unroll
       for (int c = 0; c < QR; ++c) q[c] = s[c];
@@ -136,23 +135,37 @@ __global__ void __launch_bounds__(TB) k_tile_step(View<T> v, TileTable tt) {
         for (int c = 0; c < QR; ++c) q[c] = qo[c];
       }
     }
-    __syncthreads();  // LDS reused by the next tile of this workgroup
-    if (present) {
-      if (moving) {
-        T o[VW];
-        recover_velocity(q, qn, h, o);
-        bool finite = true;
+    __syncthreads();  // every lane is done with the q buffers
+    // per-scene FP64 residual: partials through LDS, summed by the scene's first
+    // body in body order (independent of where the scene sits in the tile)
+    double* red = reinterpret_cast<double*>(&lq[0][0]);
+    red[lane] = num;
+    red[TB + lane] = den;
+    if (moving) {
+      T qn[QR], o[VW];
+      load<T, QR>(v.qn + (size_t)QR * i, qn);
+      recover_velocity(q, qn, ih, o);
+      bool finite = true;
 #pragma unroll
-        for (int c = 0; c < QR; ++c) finite = finite && isfinite(q[c]);
+      for (int c = 0; c < QR; ++c) finite = finite && isfinite(q[c]);
 #pragma unroll
-        for (int c = 0; c < 6; ++c) finite = finite && isfinite(o[c]);
-        if (!finite) atomicOr(v.health + scn, 1);
-        store<T, QR>(v.qn + (size_t)QR * i, q);
-        store<T, VW>(v.vel + (size_t)VW * i, o);
-      }
-      v.r_num[i] = num;
-      v.r_den[i] = den;
+      for (int c = 0; c < 6; ++c) finite = finite && isfinite(o[c]);
+      if (!finite) atomicOr(v.health + scn, 1);
+      store<T, QR>(v.qn + (size_t)QR * i, q);
+      store<T, VW>(v.vel + (size_t)VW * i, o);
     }
+    __syncthreads();
+    if (present && i == v.scenes[scn].body_off) {
+      const int nbs = v.scenes[scn].n_bodies;
+      double a = 0.0, b = 0.0;
+      for (int t = 0; t < nbs; ++t) {
+        a += red[lane + t];
+        b += red[TB + lane + t];
+      }
+      v.rho[scn] = b > 0.0 ? sqrt(a / b) : 0.0;
+      v.scenes[scn].step += 1;
+    }
+    __syncthreads();  // LDS reused by the next tile of this workgroup
   }
 }
 

@@ -519,6 +519,7 @@ struct pabd_batch {
   int grid_tiles = 0;
   bool any_stream = false, any_contact = false;
   int stream_kmax = 0, n_driven_hi = 0;
+  int stream_hi = 0;  // one past the highest flat-path body in use
 };
 
 namespace {
@@ -564,25 +565,29 @@ pabd_status batch_tables(pabd_batch* b) {
   b->any_contact = false;
   b->stream_kmax = 0;
   b->n_driven_hi = 0;
+  b->stream_hi = 0;
   for (const Slot& s : b->slots) {
     if (!s.used || s.tiled) continue;
     b->any_stream = true;
     b->any_contact = b->any_contact || s.contact;
     b->stream_kmax = std::max(b->stream_kmax, s.iters);
     if (s.nd > 0) b->n_driven_hi = std::max(b->n_driven_hi, s.doff + s.nd);
+    b->stream_hi = std::max(b->stream_hi, s.boff + std::max(1, s.n));
   }
   return PABD_OK;
 }
 
 void batch_enqueue(pabd_batch* b, hipStream_t st) {
   if (b->any_stream)
-    b->eng->flat_step(0, b->n_stream, b->max_slots, b->stream_kmax, b->any_contact, b->n_driven_hi,
+    b->eng->flat_step(0, b->stream_hi, b->max_slots, b->stream_kmax, b->any_contact, b->n_driven_hi,
                       false, false, st);
   if (b->grid_tiles > 0) {
     TileTable tt{b->d_first, b->d_count, b->d_kmax, b->d_ntiles};
     b->eng->tile_step(b->tile_bodies, tt, b->grid_tiles, st);
   }
-  b->eng->finish_scenes(b->max_slots, st);
+  // scenes on the flat path: residual reduction and step counters (tiled
+  // scenes do both inside the tile kernel)
+  if (b->any_stream) b->eng->finish_scenes(b->max_slots, st);
 }
 
 pabd_status place_tiled(pabd_batch* b, int slot, int n) {
@@ -665,6 +670,7 @@ pabd_status batch_place_and_upload(pabd_batch* b, int slot) {
   HostScene copy = hs;
   copy.params.steps_total = s.steps_total;
   copy.params.ccap = b->caps.ccap;
+  copy.params.tiled = tiled ? 1 : 0;
   pabd_status st = b->eng->upload(copy, s.boff, s.eoff, s.poff, s.doff, slot, b->stream);
   if (st != PABD_OK) {
     undo();
@@ -755,6 +761,12 @@ pabd_status pabd_batch_destroy(pabd_batch* b) {
 }
 
 void* pabd_batch_stream(pabd_batch* b) { return b ? (void*)b->stream : nullptr; }
+
+pabd_status pabd_batch_sync(pabd_batch* b) {
+  if (!b) return fail(PABD_E_INVALID, "null batch");
+  API_HIP(hipStreamSynchronize(b->stream));
+  return PABD_OK;
+}
 
 pabd_status pabd_batch_memory(pabd_batch* b, size_t* used, size_t* budget) {
   if (!b) return fail(PABD_E_INVALID, "null batch");
@@ -1051,6 +1063,50 @@ pabd_status pabd_batch_autotune(pabd_batch* b, int32_t* tile_out) {
   if ((st = batch_repack(b, best)) != PABD_OK) return st;
   b->tile_auto = false;
   if (tile_out) *tile_out = best;
+  return PABD_OK;
+}
+
+// streaming copy, 16 bytes per lane per step, grid-stride
+__global__ void __launch_bounds__(256) k_copy_probe(const float4* __restrict__ src, float4* __restrict__ dst,
+                                                    size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+pabd_status pabd_hbm_copy_probe(size_t bytes, int32_t reps, double* gbps, double* avg_ms) {
+  if (reps < 1 || bytes < 16) return fail(PABD_E_INVALID, "bad probe arguments");
+  if (pabd_device_count() < 1) return fail(PABD_E_DEVICE, "no HIP device");
+  const size_t n = bytes / 16;
+  float4 *a = nullptr, *b = nullptr;
+  hipStream_t st;
+  API_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+  if (hipMalloc(&a, n * 16) != hipSuccess || hipMalloc(&b, n * 16) != hipSuccess) {
+    if (a) (void)hipFree(a);
+    (void)hipStreamDestroy(st);
+    return fail(PABD_E_OOM, "probe allocation failed");
+  }
+  API_HIP(hipMemsetAsync(a, 0, n * 16, st));
+  int cus = 256;
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, 0);
+  const dim3 grid((unsigned)std::min<size_t>((n + 255) / 256, (size_t)cus * 16)), block(256);
+  hipLaunchKernelGGL(k_copy_probe, grid, block, 0, st, (const float4*)a, b, n);
+  hipEvent_t e0, e1;
+  API_HIP(hipEventCreate(&e0));
+  API_HIP(hipEventCreate(&e1));
+  API_HIP(hipEventRecord(e0, st));
+  for (int r = 0; r < reps; ++r) hipLaunchKernelGGL(k_copy_probe, grid, block, 0, st, (const float4*)a, b, n);
+  API_HIP(hipEventRecord(e1, st));
+  API_HIP(hipEventSynchronize(e1));
+  float ms = 0.f;
+  API_HIP(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(a);
+  (void)hipFree(b);
+  (void)hipStreamDestroy(st);
+  const double per = (double)ms / reps;
+  if (avg_ms) *avg_ms = per;
+  if (gbps) *gbps = 2.0 * (double)(n * 16) / (per * 1e-3) / 1e9;
   return PABD_OK;
 }
 

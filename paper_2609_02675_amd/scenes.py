@@ -166,21 +166,27 @@ def chain(n: int, *, tilt_deg: float = 45.0, joint_angles_deg=None, kappa: float
         bd["flags"][0] = FLAG_PINNED
     bd["flags"] |= FLAG_NO_CONTACT
     ang = np.zeros(max(n - 1, 0)) if joint_angles_deg is None else np.asarray(joint_angles_deg, float)
-    R = rot_z(math.radians(tilt_deg))
-    c = np.asarray(origin, dtype=np.float64)
+    # every joint turns about z, so body k is turned by tilt + sum of the first k joint angles
+    th = np.radians(tilt_deg + np.concatenate([[0.0], np.cumsum(ang)]))[:n]
+    cth, sth = np.cos(th), np.sin(th)
+    R = np.zeros((n, 3, 3))
+    R[:, 0, 0], R[:, 0, 1], R[:, 1, 0], R[:, 1, 1], R[:, 2, 2] = cth, -sth, sth, cth, 1.0
     xa, xb = np.array([0.0, -0.5, 0.0]), np.array([0.0, 0.5, 0.0])
-    for k in range(n):
-        bd["c0"][k] = c
-        bd["A0"][k] = R
-        if k + 1 < n:
-            joint = c + R @ xa
-            R = R @ rot_z(math.radians(ang[k]))
-            c = joint - R @ xb
-    bonds = _empty_bonds(max(n - 1, 0))
-    for k in range(n - 1):
-        bonds["bond_i"][k], bonds["bond_j"][k] = k, k + 1
-        bonds["x_i"][k], bonds["x_j"][k] = xa, xb
-        bonds["kappa"][k] = kappa
+    # c_{k+1} = c_k + R_k x_a - R_{k+1} x_b
+    step = (R[:-1] @ xa) - (R[1:] @ xb)
+    c = np.zeros((n, 3))
+    c[0] = np.asarray(origin, dtype=np.float64)
+    if n > 1:
+        c[1:] = c[0] + np.cumsum(step, axis=0)
+    bd["c0"][:] = c
+    bd["A0"][:] = R
+    b = max(n - 1, 0)
+    bonds = _empty_bonds(b)
+    bonds["bond_i"][:] = np.arange(b, dtype=np.int32)
+    bonds["bond_j"][:] = np.arange(1, b + 1, dtype=np.int32)
+    bonds["x_i"][:] = xa
+    bonds["x_j"][:] = xb
+    bonds["kappa"][:] = kappa
     return SceneDesc(**bd, **bonds, h=h, iters=iters, precision=precision, name=name or f"chain{n}")
 
 

@@ -1,0 +1,167 @@
+"""Serving loop: continuous batching of simulation requests on one GPU.
+
+Requests (a scene description and a number of steps) arrive over time.  The
+server keeps one batch resident on the device; every iteration of its loop it
+admits waiting requests in arrival order while a slot and enough of the HBM
+budget are free (admission is a copy into the batch's arrays -- the captured
+step graph is rebuilt only when the set of resident scenes changed), advances
+every resident scene one step with a single graph replay, and hands back the
+scenes that have taken all their steps, freeing their slot and memory for the
+next arrivals.  Work of scenes admitted at different times overlaps on the
+device within each replay.
+
+Reported: per-step latency (wall time of the replay that advanced a scene, as
+seen by that scene), aggregate body-iterations per second, queueing delay.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import time
+from typing import Callable, Dict, List, Optional
+
+import numpy as np
+
+from . import _lib
+from .scenes import Request
+
+
+@dataclasses.dataclass
+class Result:
+    index: int
+    scene_name: str
+    n_bodies: int
+    steps: int
+    arrival_s: float
+    admitted_s: float
+    finished_s: float
+    state: tuple
+    residual: float
+
+
+@dataclasses.dataclass
+class ServeStats:
+    wall_s: float
+    body_iterations: float
+    body_its_per_s: float
+    step_latency_ms: np.ndarray
+    p50_step_ms: float
+    p99_step_ms: float
+    queue_wait_ms_p50: float
+    queue_wait_ms_p99: float
+    completed: int
+    rejected: int
+    replays: int
+    max_resident: int
+    peak_bytes: int
+
+    def summary(self) -> dict:
+        return dict(wall_s=self.wall_s, body_its_per_s=self.body_its_per_s,
+                    body_iterations=self.body_iterations, p50_step_ms=self.p50_step_ms,
+                    p99_step_ms=self.p99_step_ms, queue_wait_ms_p50=self.queue_wait_ms_p50,
+                    queue_wait_ms_p99=self.queue_wait_ms_p99, completed=self.completed,
+                    rejected=self.rejected, replays=self.replays, max_resident=self.max_resident,
+                    peak_bytes=self.peak_bytes)
+
+
+class Server:
+    """Continuous-batching server over one pabd batch (or any object with the
+    same admit / step / sync / poll / state / residual / release / memory
+    methods)."""
+
+    def __init__(self, hbm_budget: int, max_slots: int, precision: int,
+                 clock: Callable[[], float] = time.perf_counter, batch=None):
+        self.batch = batch if batch is not None else _lib.Batch(max_slots, hbm_budget, precision)
+        self.precision = precision
+        self.clock = clock
+
+    def close(self):
+        self.batch.close()
+
+    def run(self, requests: List[Request], realtime: bool = True,
+            keep_state: bool = True, max_wall_s: Optional[float] = None) -> tuple:
+        """Serve ``requests`` (sorted by arrival).  With ``realtime`` the arrival
+        times are honoured against the wall clock; otherwise every request is
+        available at once.  Returns (results by request index, ServeStats)."""
+        b = self.batch
+        pending = collections.deque()
+        nxt = 0
+        resident: Dict[int, dict] = {}
+        results: Dict[int, Result] = {}
+        lat = []
+        waits = []
+        body_its = 0.0
+        replays = 0
+        max_res = 0
+        peak = 0
+        t0 = self.clock()
+        order = sorted(range(len(requests)), key=lambda k: requests[k].arrival_s)
+        while nxt < len(order) or pending or resident:
+            now = self.clock() - t0
+            if max_wall_s is not None and now > max_wall_s:
+                break
+            while nxt < len(order) and (not realtime or requests[order[nxt]].arrival_s <= now):
+                pending.append(order[nxt])
+                nxt += 1
+            # admit in arrival order while room is free
+            while pending:
+                k = pending[0]
+                req = requests[k]
+                slot = b.admit(req.scene, req.steps)
+                if slot is None:
+                    if not resident:
+                        # nothing resident and still no room: the request can
+                        # never fit this server's budget; reject it
+                        pending.popleft()
+                        results[k] = Result(index=k, scene_name=req.scene.name,
+                                            n_bodies=req.scene.n_bodies, steps=0,
+                                            arrival_s=req.arrival_s, admitted_s=-1.0,
+                                            finished_s=self.clock() - t0, state=None,
+                                            residual=float("nan"))
+                        continue
+                    break
+                pending.popleft()
+                t_adm = self.clock() - t0
+                waits.append(1e3 * max(0.0, t_adm - (req.arrival_s if realtime else 0.0)))
+                resident[slot] = dict(k=k, admitted=t_adm, n=req.scene.n_bodies,
+                                      iters=req.scene.iters, steps=req.steps, done=0)
+            if not resident:
+                if nxt < len(order) and realtime:
+                    time.sleep(max(0.0, min(0.001, requests[order[nxt]].arrival_s - now)))
+                continue
+            max_res = max(max_res, len(resident))
+            peak = max(peak, b.memory()[0])
+            ts = self.clock()
+            b.step()
+            b.sync()
+            dt = self.clock() - ts
+            replays += 1
+            for slot, r in resident.items():
+                if r["done"] < r["steps"]:
+                    r["done"] += 1
+                    lat.append(1e3 * dt)
+                    body_its += r["n"] * r["iters"]
+            for slot in b.poll():
+                r = resident.pop(slot)
+                req = requests[r["k"]]
+                st = b.state(slot, check=False) if keep_state else None
+                rho = b.residual(slot)
+                results[r["k"]] = Result(index=r["k"], scene_name=req.scene.name, n_bodies=r["n"],
+                                         steps=r["steps"], arrival_s=req.arrival_s,
+                                         admitted_s=r["admitted"], finished_s=self.clock() - t0,
+                                         state=st, residual=rho)
+                b.release(slot)
+        wall = self.clock() - t0
+        lat = np.asarray(lat) if lat else np.zeros(1)
+        waits = np.asarray(waits) if waits else np.zeros(1)
+        stats = ServeStats(wall_s=wall, body_iterations=body_its, body_its_per_s=body_its / max(wall, 1e-9),
+                           step_latency_ms=lat, p50_step_ms=float(np.percentile(lat, 50)),
+                           p99_step_ms=float(np.percentile(lat, 99)),
+                           queue_wait_ms_p50=float(np.percentile(waits, 50)),
+                           queue_wait_ms_p99=float(np.percentile(waits, 99)),
+                           completed=sum(1 for r in results.values() if r.state is not None or r.steps > 0),
+                           rejected=sum(1 for r in results.values() if r.admitted_s < 0),
+                           replays=replays, max_resident=max_res, peak_bytes=peak)
+        return results, stats
+
+

@@ -1,0 +1,48 @@
+"""Serving on the GPU: continuous batching under an HBM budget; every result is
+the same alone and in the mix (bit for bit: per-body sums run in a fixed order
+that does not depend on the other resident scenes)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2609_02675_amd import scenes as S
+from parity import errors, scale_of
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2609_02675_amd as P
+    if P.device_count() < 1:
+        pytest.fail("no HIP device visible")
+    return P
+
+
+def _requests(prec, n=20, seed=3):
+    return S.serving_requests(rate_hz=2000.0, duration_s=1.0, seed=seed, n_lo=8, n_hi=400,
+                              steps_lo=5, steps_hi=25, precision=prec, max_requests=n)
+
+
+@pytest.mark.parametrize("prec", [S.PREC_FP32, S.PREC_FP64])
+def test_served_results_equal_alone_and_in_the_mix(P, prec):
+    from paper_2609_02675_amd.serve import Server
+    reqs = _requests(prec)
+    print(f"[case] serve mix prec={prec} sizes={[r.scene.n_bodies for r in reqs]}", flush=True)
+    need = [P.scene_bytes(r.scene) for r in reqs]
+    budget = max(max(need), sum(need) // 4)
+    srv = Server(budget, 32, prec)
+    res, st = srv.run(reqs, realtime=False)
+    assert st.rejected == 0 and st.completed == len(reqs)
+    assert st.peak_bytes <= budget
+    assert st.max_resident < len(reqs)
+    for k in (0, 5, 11, len(reqs) - 1):
+        alone = Server(1 << 28, 4, prec)
+        ra, _ = alone.run([reqs[k]], realtime=False)
+        for a, b in zip(res[k].state, ra[0].state):
+            np.testing.assert_array_equal(a, b)
+        o = oracle.Oracle(reqs[k].scene)
+        o.step(reqs[k].steps)
+        e = errors(res[k].state, o.state(), scale_of(reqs[k].scene))
+        tol = 1e-9 if prec == S.PREC_FP64 else 1e-4
+        assert e["pos"] <= tol and e["rot"] <= tol, (reqs[k].scene.name, e)
