@@ -48,6 +48,30 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+TILE_SOURCES = ["common.h", "device_math.h", "kernels_step.h", "kernels_tile.h"]
+TILE_PROFILE = os.path.join(ROOT, "profiles", "k_tile_step_batched_chains_4096.md")
+
+
+def tile_traffic():
+    """HBM bytes per tile-kernel launch from the committed counter profile, if the
+    kernel sources still hash to what was profiled; else None."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in TILE_SOURCES:
+        with open(os.path.join(ROOT, "paper_2609_02675_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    try:
+        text = open(TILE_PROFILE).read()
+    except OSError:
+        return None
+    import re
+    m = re.search(r"kernel-source-sha256-16:\s*([0-9a-f]{16})", text)
+    t = re.search(r"traffic_bytes_per_launch:\s*(\d+)", text)
+    if not m or not t or m.group(1) != h.hexdigest()[:16]:
+        return None
+    return float(t.group(1))
+
+
 # ---------------------------------------------------------------------------
 # CPU baseline: the FP64 oracle as it stands, one scene per task
 # ---------------------------------------------------------------------------
@@ -187,14 +211,15 @@ def main():
     tile_flops = n_bodies * iters * FLOPS_PER_BODY_ITER
     hbm_ach = tile_bytes / (tile_ms / 1e3)
     alu_ach = tile_flops / (tile_ms / 1e3)
+    traffic = tile_traffic()
     if alu_ach / FP32_VALU_PEAK >= hbm_ach / HBM_PEAK:
         roof = dict(bound="alu", achieved=alu_ach / 1e12, peak=FP32_VALU_PEAK / 1e12, unit="TFLOP/s",
-                    frac=alu_ach / FP32_VALU_PEAK, traffic=None, kernel="k_tile_step<float>",
+                    frac=alu_ach / FP32_VALU_PEAK, traffic=traffic, traffic_unit="bytes/launch", kernel="k_tile_step<float>",
                     kernel_ms=tile_ms, flops_per_launch=tile_flops, bytes_per_launch=tile_bytes,
                     hbm_achieved_GBs=hbm_ach / 1e9)
     else:
         roof = dict(bound="hbm", achieved=hbm_ach / 1e9, peak=HBM_PEAK / 1e9, unit="GB/s",
-                    frac=hbm_ach / HBM_PEAK, traffic=None, kernel="k_tile_step<float>",
+                    frac=hbm_ach / HBM_PEAK, traffic=traffic, traffic_unit="bytes/launch", kernel="k_tile_step<float>",
                     kernel_ms=tile_ms, flops_per_launch=tile_flops, bytes_per_launch=tile_bytes)
     eff_bw = value * STREAM_BYTES_PER_BODY_ITER
     log(f"tile kernel {tile_ms:.4f} ms; roofline {roof['bound']} frac {roof['frac']:.3f}")

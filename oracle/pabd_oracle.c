@@ -574,8 +574,12 @@ static void driven_anchor(const double *dr, double t, double *xj) {
  * f = kappa_c (y_j - y_i); it acts only while n.(y_i - y_j) < 0, and its
  * tangential part is clamped to mu times its normal part. */
 
+/* speculative detection margin of a body: its surface can move by about
+ * h (|v| + |w| R) within the step; a sphere's distance to anything does not
+ * change when it spins about its centre, so spheres omit the |w| R term */
 static double body_margin(const pabd_oracle *o, int b) {
-  return o->margin + o->h * (v3_norm(o->v + 3 * b) + v3_norm(o->w + 3 * b) * o->radius[b]);
+  double spin = o->shape[b] == ORACLE_SHAPE_BOX ? v3_norm(o->w + 3 * b) * o->radius[b] : 0.0;
+  return o->margin + o->h * (v3_norm(o->v + 3 * b) + spin);
 }
 
 static double contact_kappa(const pabd_oracle *o, int i, int j) {

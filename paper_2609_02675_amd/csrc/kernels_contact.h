@@ -7,7 +7,8 @@
 // of j, or world coordinates for a plane), with a unit normal n fixed for the
 // step (outward from j, towards i) and stiffness kappa_c = scale * m / h^2, m the
 // heavier free mass of the pair.  Detection uses a speculative margin
-// pm = margin + h (|v| + |w| R) per body (R: bounding radius).
+// pm = margin + h (|v| + |w| R) per body (R: bounding radius; spheres omit
+// the spin term).
 //
 // Pipeline: k_contact_prep (margins, per-scene max reach, clear counters) ->
 // k_hash_count / scan / k_hash_fill (uniform grid of cell 2 max(R + pm), spatial
@@ -32,10 +33,12 @@ struct ContactBuf {
   int* scan_tmp;         // block sums
 };
 
-__device__ __forceinline__ double body_pm(const SceneDev& S, const double* vw, double R) {
+// speculative margin: the body's surface moves by about h (|v| + |w| R) in a
+// step; spheres omit the spin term (spinning does not move their surface)
+__device__ __forceinline__ double body_pm(const SceneDev& S, const double* vw, double R, int shape) {
   double vn = sqrt(vw[0] * vw[0] + vw[1] * vw[1] + vw[2] * vw[2]);
-  double wn = sqrt(vw[3] * vw[3] + vw[4] * vw[4] + vw[5] * vw[5]);
-  return S.margin + S.h * (vn + wn * R);
+  double wn = shape == 0 ? sqrt(vw[3] * vw[3] + vw[4] * vw[4] + vw[5] * vw[5]) * R : 0.0;
+  return S.margin + S.h * (vn + wn);
 }
 
 template <typename T>
@@ -64,7 +67,7 @@ __global__ void k_contact_reach(View<T> v, ContactBuf cb) {
   load<T, VW>(v.vel + (size_t)VW * i, vw);
   double vd[6] = {(double)vw[0], (double)vw[1], (double)vw[2], (double)vw[3], (double)vw[4], (double)vw[5]};
   double R = (double)v.half[4 * i + 3];
-  double reach = R + body_pm(v.scenes[sc], vd, R);
+  double reach = R + body_pm(v.scenes[sc], vd, R, v.shape[i]);
   atomicMax(cb.reach + sc, (unsigned long long)__double_as_longlong(reach));
 }
 
@@ -333,7 +336,7 @@ __device__ void narrow_pair(const View<T>& v, const ContactBuf& cb, int sc, int 
   T vw[VW];
   load<T, VW>(v.vel + (size_t)VW * j, vw);
   const double vd[6] = {(double)vw[0], (double)vw[1], (double)vw[2], (double)vw[3], (double)vw[4], (double)vw[5]};
-  const double pm = pmi + body_pm(v.scenes[sc], vd, gj.R);
+  const double pm = pmi + body_pm(v.scenes[sc], vd, gj.R, gj.shape);
   const double dc[3] = {gj.c[0] - gi.c[0], gj.c[1] - gi.c[1], gj.c[2] - gi.c[2]};
   const double dist = sqrt(dc[0] * dc[0] + dc[1] * dc[1] + dc[2] * dc[2]);
   if (!(dist < gi.R + gj.R + pm)) return;
@@ -370,7 +373,7 @@ __global__ void __launch_bounds__(128) k_narrow(View<T> v, ContactBuf cb) {
   T vw[VW];
   load<T, VW>(v.vel + (size_t)VW * i, vw);
   const double vd[6] = {(double)vw[0], (double)vw[1], (double)vw[2], (double)vw[3], (double)vw[4], (double)vw[5]};
-  const double pmi = body_pm(S, vd, gi.R);
+  const double pmi = body_pm(S, vd, gi.R, gi.shape);
   const bool pin_i = (v.flags[i] & F_PINNED) != 0;
   // planes
   if (!pin_i) {

@@ -171,11 +171,15 @@ __global__ void __launch_bounds__(256) k_iterate(View<T> v, int k, double* rh_nu
   const double h2d = S.h * S.h;
   const T h2 = (T)h2d;
   T fac[FW];
+  bool refactor = false;
   if constexpr (CONTACT) {
-    const double* bb = v.blk + 10 * (size_t)i;
-    Block B{bb[0], bb[1], bb[2], bb[3], bb[4], bb[5], bb[6], bb[7], bb[8], bb[9]};
     int cnt = v.ccount[i];
     if (cnt > S.ccap) cnt = S.ccap;
+    Block B{};
+    if (cnt > 0) {
+      const double* bb = v.blk + 10 * (size_t)i;
+      B = Block{bb[0], bb[1], bb[2], bb[3], bb[4], bb[5], bb[6], bb[7], bb[8], bb[9]};
+    }
     const size_t base = (size_t)i * S.ccap;
     for (int c = 0; c < cnt; ++c) {
       const int j = v.ce_partner[base + c];
@@ -192,14 +196,16 @@ __global__ void __launch_bounds__(256) k_iterate(View<T> v, int k, double* rh_nu
       if (!contact_end_force(C, d, f)) continue;
       add_JT(rb, C, f[0], f[1], f[2]);
       block_add_end(B, h2d * (double)C[3], (double)C[0], (double)C[1], (double)C[2]);
+      refactor = true;
     }
-    double f64[10];
-    block_inverse(B, f64);
+    if (refactor) {  // H^k changed: some contact penetrates at this iterate
+      double f64[10];
+      block_inverse(B, f64);
 #pragma unroll
-    for (int c = 0; c < 10; ++c) fac[c] = (T)f64[c];
-  } else {
-    load<T, FW>(v.fac + (size_t)FW * i, fac);
+      for (int c = 0; c < 10; ++c) fac[c] = (T)f64[c];
+    }
   }
+  if (!refactor) load<T, FW>(v.fac + (size_t)FW * i, fac);
   T r[QW];
 #pragma unroll
   for (int c = 0; c < QW; ++c) r[c] = h2 * rb[c];

@@ -360,3 +360,92 @@ def serving_requests(rate_hz: float = 200.0, duration_s: float = 60.0, seed: int
             sc.name = f"req{len(out)}_pile{n}"
         out.append(Request(arrival_s=t, scene=sc, steps=steps))
     return out
+
+
+# ---------------------------------------------------------------------------
+# legged robot on a granular bed
+# ---------------------------------------------------------------------------
+
+def granular_bed_quadruped(nx: int = 50, nz: int = 50, ny: int = 20, r: float = 0.01,
+                           seed: int = 1, mu: float = 0.6, iters: int = 20,
+                           precision: int = PREC_FP32, with_robot: bool = True,
+                           gait_amp_deg: float = 20.0, gait_hz: float = 1.0,
+                           joint_kappa: float = 2e4, drive_kappa: float = 5e3,
+                           name: str = "") -> SceneDesc:
+    """Spheres of radius r (density 1000) on an nx x ny x nz lattice at spacing
+    2r(1 + 1e-3) with 1e-4 m jitter, inside a box of walls around the nx x nz
+    footprint (1 x 1 m for 50 x 50 at r = 0.01) on the floor y = 0, plus a 13-body
+    quadruped: torso box 0.6 x 0.15 x 0.3 m and four legs of three 0.05 x 0.15 x
+    0.05 m links.  Each of the 12 revolute joints is two ball bonds at +-0.025 m on
+    its hinge axis (z) plus a driven bond that pulls the child's centre to the
+    parent point turned by theta(t) = amp sin(2 pi f t + phase) (trot phases)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    sp = 2 * r * (1 + 1e-3)
+    ix, iy, iz = np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij")
+    grid = np.stack([ix.ravel(), iy.ravel(), iz.ravel()], axis=1).astype(np.float64)
+    ns = grid.shape[0]
+    half_x, half_z = nx * sp / 2, nz * sp / 2
+    cs = np.empty((ns, 3))
+    cs[:, 0] = -half_x + sp / 2 + grid[:, 0] * sp
+    cs[:, 1] = sp / 2 + grid[:, 1] * sp
+    cs[:, 2] = -half_z + sp / 2 + grid[:, 2] * sp
+    cs += rng.uniform(-1e-4, 1e-4, size=cs.shape)
+    bodies = _bodies(ns)
+    bodies["shape"][:] = SHAPE_SPHERE
+    bodies["shape_param"][:, 0] = r
+    bodies["density"][:] = 1000.0
+    bodies["c0"][:] = cs
+    bond_rows = []
+    if with_robot:
+        top = ny * sp
+        th_, tw, td = 0.15, 0.6, 0.3
+        link = np.array([0.025, 0.075, 0.025])
+        leg_len = 3 * 0.15
+        y_torso = top + leg_len + th_ / 2 + 0.01
+        rb = _bodies(13)
+        rb["shape"][:] = SHAPE_BOX
+        rb["group"][:] = 1
+        rb["density"][:] = 1000.0
+        rb["shape_param"][0] = (tw / 2, th_ / 2, td / 2)
+        rb["c0"][0] = (0.0, y_torso, 0.0)
+        corners = [(0.25, 0.12), (0.25, -0.12), (-0.25, 0.12), (-0.25, -0.12)]  # FL FR BL BR
+        phases = [0.0, math.pi, math.pi, 0.0]
+        b = 1
+        for leg, ((cx, cz), ph) in enumerate(zip(corners, phases)):
+            parent, p_joint_local = 0, np.array([cx, -th_ / 2, cz])
+            p_center = np.array([0.0, y_torso, 0.0])
+            for seg in range(3):
+                joint_world = p_center + p_joint_local
+                child_center = joint_world - np.array([0.0, 0.075, 0.0])
+                rb["shape_param"][b] = link
+                rb["c0"][b] = child_center
+                child_joint_local = np.array([0.0, 0.075, 0.0])
+                for dz in (-0.025, 0.025):
+                    bond_rows.append(dict(i=ns + b, j=ns + parent, type=BOND_QUADRATIC,
+                                          xi=child_joint_local + [0, 0, dz],
+                                          xj=p_joint_local + [0, 0, dz], kappa=joint_kappa))
+                # driven bond: child centre to the parent point turned about z through the joint
+                base = (child_center - p_center)
+                drive = np.concatenate([[0.0, 0.0, 1.0], p_joint_local, base,
+                                        [0.0, math.radians(gait_amp_deg) * (1.0 if seg < 2 else 0.5),
+                                         gait_hz, ph + (math.pi / 2 if seg == 1 else 0.0)]])
+                bond_rows.append(dict(i=ns + b, j=ns + parent, type=BOND_DRIVEN, xi=np.zeros(3),
+                                      xj=base, kappa=drive_kappa, drive=drive))
+                parent, p_center, p_joint_local = b, child_center, np.array([0.0, -0.075, 0.0])
+                b += 1
+        for k in bodies:
+            bodies[k] = np.concatenate([bodies[k], rb[k]], axis=0)
+    nb = len(bond_rows)
+    bonds = _empty_bonds(nb)
+    for e, row in enumerate(bond_rows):
+        bonds["bond_i"][e], bonds["bond_j"][e], bonds["bond_type"][e] = row["i"], row["j"], row["type"]
+        bonds["x_i"][e], bonds["x_j"][e], bonds["kappa"][e] = row["xi"], row["xj"], row["kappa"]
+        if "drive" in row:
+            bonds["drive"][e] = row["drive"]
+    planes = np.array([[0.0, 1.0, 0.0, 0.0],
+                       [1.0, 0.0, 0.0, -half_x], [-1.0, 0.0, 0.0, -half_x],
+                       [0.0, 0.0, 1.0, -half_z], [0.0, 0.0, -1.0, -half_z]])
+    return SceneDesc(**bodies, **bonds, iters=iters, contact_enable=1, mu=mu,
+                     contact_kappa_scale=0.3, contact_margin=0.2 * r, planes=planes,
+                     precision=precision, max_contacts_per_body=64,
+                     name=name or f"bed{ns}{'_quadruped' if with_robot else ''}")
