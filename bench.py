@@ -126,6 +126,8 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=6.0,
                     help="seconds of Poisson arrivals (200 req/s) in the served leg; 0 = skip")
     ap.add_argument("--serve-budget-gib", type=float, default=8.0)
+    ap.add_argument("--no-scenes", action="store_true",
+                    help="skip the single-scene legs (1,000-box drop, granular bed)")
     ap.add_argument("--probe-only", action="store_true",
                     help="run only the 1 GiB HBM copy probe (counter calibration)")
     args = ap.parse_args()
@@ -285,6 +287,50 @@ def main():
         srv.close()
         log("served (saturated)", served_sat)
 
+    # single-scene legs on the plain path: the 1,000-box drop (contact and
+    # friction; FP32 and FP64) and the legged robot on a 50,000-sphere bed
+    scene_legs = None
+    if not args.no_scenes:
+        scene_legs = {}
+
+        def time_scene(sc, warm, steps):
+            g = P.Scene(sc)
+            g.step(warm)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            g.step(steps)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t
+            return g, sc.n_bodies * sc.iters * steps / dt, 1e3 * dt / steps
+
+        drop_oracle = S.box_drop(precision=S.PREC_FP64)
+        o = oracle.Oracle(drop_oracle)
+        o.step(60)
+        c, A, v, w = o.state()
+        for prec, tag in ((S.PREC_FP32, "fp32"), (S.PREC_FP64, "fp64")):
+            sc = S.box_drop(precision=prec)
+            g, rate, ms = time_scene(sc, 40, 60)
+            # accuracy: one step from the oracle's state after 60 steps (contacts active)
+            mid = drop_oracle.with_state(c, A, v, w, t0=60 * sc.h).copy(precision=prec)
+            gm = P.Scene(mid)
+            gm.step(1)
+            om = oracle.Oracle(mid.copy(precision=S.PREC_FP64))
+            om.step(1)
+            e = errors(gm.state(check=False), om.state(), scale_of(mid))
+            scene_legs[f"box_drop_1000_{tag}"] = dict(
+                body_its_per_s=rate, ms_per_step=ms, steps_timed="40..100 (falling, then landing)",
+                one_step_err_vs_oracle=max(e["pos"], e["rot"]), iters=sc.iters)
+            log(f"box drop {tag}: {rate:.3g} body-it/s, {ms:.3f} ms/step, 1-step err {max(e['pos'], e['rot']):.2e}")
+        bed = S.granular_bed_quadruped(precision=S.PREC_FP32)
+        # the bed churns as it sinks (a property of the method as read for 1 cm
+        # spheres at h = 1/60), so the timed window is its first steps
+        g, rate, ms = time_scene(bed, 1, 5)
+        ct = g.contacts()
+        scene_legs["granular_bed_quadruped_fp32"] = dict(
+            body_its_per_s=rate, ms_per_step=ms, bodies=bed.n_bodies, iters=bed.iters,
+            steps_timed="2..6", contacts_after=int(len(ct["i"])))
+        log(f"granular bed: {rate:.3g} body-it/s, {ms:.3f} ms/step")
+
     out = {
         "metric": METRIC,
         "value": value,
@@ -314,6 +360,7 @@ def main():
         "served": served,
         "served_saturated": served_sat,
         "roofline": roof,
+        "single_scene": scene_legs,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

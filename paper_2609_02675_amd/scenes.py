@@ -378,7 +378,15 @@ def granular_bed_quadruped(nx: int = 50, nz: int = 50, ny: int = 20, r: float = 
     quadruped: torso box 0.6 x 0.15 x 0.3 m and four legs of three 0.05 x 0.15 x
     0.05 m links.  Each of the 12 revolute joints is two ball bonds at +-0.025 m on
     its hinge axis (z) plus a driven bond that pulls the child's centre to the
-    parent point turned by theta(t) = amp sin(2 pi f t + phase) (trot phases)."""
+    parent point turned by theta(t) = amp sin(2 pi f t + phase) (trot phases).
+
+    Under the method as read this bed does not stand: a body resting on a contact
+    settles a gap of g h^2 (1/scale + m l^2/Pi) below it (the local step keeps the
+    centre solved together with the stretched A), which for a sphere (l = r,
+    Pi = m r^2/5) is g h^2 (1/scale + 5) = 22.7 mm at h = 1/60 and scale 0.3 --
+    more than the radius.  The spheres sink through the floor and each other and
+    the bed churns, so contact counts grow with time; the capacity is sized for
+    the first tens of steps, which is the horizon it serves (parity and timing)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     sp = 2 * r * (1 + 1e-3)
     ix, iy, iz = np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij")
@@ -447,5 +455,5 @@ def granular_bed_quadruped(nx: int = 50, nz: int = 50, ny: int = 20, r: float = 
                        [0.0, 0.0, 1.0, -half_z], [0.0, 0.0, -1.0, -half_z]])
     return SceneDesc(**bodies, **bonds, iters=iters, contact_enable=1, mu=mu,
                      contact_kappa_scale=0.3, contact_margin=0.2 * r, planes=planes,
-                     precision=precision, max_contacts_per_body=64,
+                     precision=precision, max_contacts_per_body=256,
                      name=name or f"bed{ns}{'_quadruped' if with_robot else ''}")
