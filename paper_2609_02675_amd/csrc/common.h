@@ -84,6 +84,10 @@ struct View {
   int* ce_partner;
   unsigned long long* ce_key;
   T* ce;
+  // narrow-phase output before the canonical sort
+  int* ce_st_partner;
+  unsigned long long* ce_st_key;
+  T* ce_st;
   const double* planes;
   // residual partials
   double* r_num;

@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <string>
 #include <vector>
 
@@ -28,8 +29,12 @@ namespace pabd {
 
 struct Caps {
   int n = 0, e = 0, s = 0, p = 0, dr = 0, ccap = 0;
+  int nc = -1;  // bodies [0, nc) may have contacts (-1: all n)
   bool contacts = false;
 };
+
+// candidate pairs provisioned per contact body
+inline int pairs_per_body(int ccap) { return std::max(16, ccap / 2); }
 
 template <typename T>
 struct Engine {
@@ -45,12 +50,15 @@ struct Engine {
   T* se = nullptr;
   double* se64 = nullptr;
   // contacts
-  int *ccount = nullptr, *ce_partner = nullptr;
-  unsigned long long *ce_key = nullptr, *reach = nullptr;
-  T* ce = nullptr;
-  int *bucket_count = nullptr, *bucket_start = nullptr, *bucket_fill = nullptr,
-      *sorted_body = nullptr, *scan_tmp = nullptr;
-  int tb = 0;
+  int *ccount = nullptr, *ce_partner = nullptr, *ce_st_partner = nullptr;
+  unsigned long long *ce_key = nullptr, *ce_st_key = nullptr, *reach = nullptr;
+  T *ce = nullptr, *ce_st = nullptr;
+  int *bucket_count = nullptr, *bucket_start = nullptr, *bucket_fill = nullptr, *scan_tmp = nullptr;
+  int *hist = nullptr, *large = nullptr, *counters = nullptr;
+  double* breach = nullptr;
+  BroadRec* brec = nullptr;
+  int2* pairs = nullptr;
+  int tb = 0, pcap = 0, ncb = 0;
   // scenes
   SceneDev* scenes = nullptr;
   int* health = nullptr;
@@ -129,18 +137,33 @@ struct Engine {
     PABD_TRY(alloc(drv_end_j, (size_t)c.dr));
     PABD_TRY(alloc(drv_param, 13 * (size_t)c.dr));
     if (c.contacts) {
-      const size_t nc = n * (size_t)c.ccap;
+      ncb = c.nc < 0 ? c.n : std::min(c.nc, c.n);
+      const size_t nb = (size_t)ncb, nc = nb * (size_t)c.ccap;
       PABD_TRY(alloc(ce, CW * nc));
       PABD_TRY(alloc(ce_partner, nc));
       PABD_TRY(alloc(ce_key, nc));
+      PABD_TRY(alloc(ce_st, CW * nc));
+      PABD_TRY(alloc(ce_st_partner, nc));
+      PABD_TRY(alloc(ce_st_key, nc));
       // power of two, at most 2^20 so the three-pass scan (1024 x 1024) covers it
       tb = 1024;
-      while (tb < 2 * c.n && tb < (1 << 20)) tb <<= 1;
+      while (tb < 2 * ncb && tb < (1 << 20)) tb <<= 1;
       PABD_TRY(alloc(bucket_count, (size_t)tb));
       PABD_TRY(alloc(bucket_start, (size_t)tb + 1));
       PABD_TRY(alloc(bucket_fill, (size_t)tb));
-      PABD_TRY(alloc(sorted_body, n));
       PABD_TRY(alloc(scan_tmp, (size_t)(tb / 1024 + 2)));
+      PABD_TRY(alloc(brec, nb));
+      PABD_TRY(alloc(breach, nb));
+      PABD_TRY(alloc(large, nb));
+      PABD_TRY(alloc(counters, 2));
+      PABD_TRY(alloc(hist, (size_t)REACH_BINS * c.s));
+      const size_t pc = nb * (size_t)pairs_per_body(c.ccap);
+      if (pc > (size_t)INT_MAX) {
+        err = "candidate pair capacity exceeds 2^31";
+        return PABD_E_INVALID;
+      }
+      pcap = (int)pc;
+      PABD_TRY(alloc(pairs, pc));
     }
     // every body slot starts unused
     std::vector<int> neg(n, -1);
@@ -183,6 +206,9 @@ struct Engine {
     v.ce_partner = ce_partner;
     v.ce_key = ce_key;
     v.ce = ce;
+    v.ce_st_partner = ce_st_partner;
+    v.ce_st_key = ce_st_key;
+    v.ce_st = ce_st;
     v.planes = planes;
     v.r_num = r_num;
     v.r_den = r_den;
@@ -278,14 +304,18 @@ struct Engine {
   static dim3 grid_for(int n, int bs) { return dim3((unsigned)std::max(1, (n + bs - 1) / bs)); }
 
   // contact-bond construction for every contact scene among the bodies
+  // [0, min(cap.n, contact bodies))
   void launch_contacts(int n_scenes, hipStream_t st) {
     View<T> v = view();
-    ContactBuf cb{tb, bucket_count, bucket_start, bucket_fill, sorted_body, reach, mass64, scan_tmp};
-    const int n = cap.n;
-    hipLaunchKernelGGL(k_contact_prep<T>, grid_for(std::max(n, n_scenes), 256), dim3(256), 0, st, v, cb, n_scenes);
+    v.n = std::min(cap.n, ncb);
+    ContactBuf cb{tb,    bucket_count, bucket_start, bucket_fill, brec,  reach,   hist,
+                  breach, large,       counters,     pairs,       pcap,  mass64,  scan_tmp};
+    const int n = v.n;
+    hipLaunchKernelGGL(k_contact_prep<T>, grid_for(std::max(n, REACH_BINS * n_scenes), 256), dim3(256), 0,
+                       st, v, cb, n_scenes);
     hipLaunchKernelGGL(k_contact_reach<T>, grid_for(n, 256), dim3(256), 0, st, v, cb);
     hipLaunchKernelGGL(k_contact_cells, grid_for(n_scenes, 64), dim3(64), 0, st, scenes, n_scenes,
-                       (const unsigned long long*)reach);
+                       (const unsigned long long*)reach, (const int*)hist);
     hipLaunchKernelGGL(k_zero_int, grid_for(tb, 256), dim3(256), 0, st, bucket_count, tb);
     hipLaunchKernelGGL(k_zero_int, grid_for(tb, 256), dim3(256), 0, st, bucket_fill, tb);
     hipLaunchKernelGGL(k_hash_count<T>, grid_for(n, 256), dim3(256), 0, st, v, cb);
@@ -296,8 +326,13 @@ struct Engine {
     hipLaunchKernelGGL(k_scan_add, grid_for(tb, 256), dim3(256), 0, st, bucket_start, tb,
                        (const int*)scan_tmp);
     hipLaunchKernelGGL(k_hash_fill<T>, grid_for(n, 256), dim3(256), 0, st, v, cb);
-    hipLaunchKernelGGL(k_narrow<T>, grid_for(n, 128), dim3(128), 0, st, v, cb);
-    hipLaunchKernelGGL(k_sort_contacts<T>, grid_for(n, 256), dim3(256), 0, st, v);
+    hipLaunchKernelGGL(k_broad_small<T>, grid_for(n, 256), dim3(256), 0, st, v, cb);
+    hipLaunchKernelGGL(k_broad_large<T>, dim3(256), dim3(256), 0, st, v, cb);
+    const int ng = std::min(8192, std::max(1, (pcap + 255) / 256));
+    hipLaunchKernelGGL(k_narrow_pairs<T>, dim3(ng), dim3(256), 0, st, v, cb);
+    const long long ns = (long long)n * cap.ccap;
+    hipLaunchKernelGGL(k_sort_contacts<T>, dim3((unsigned)std::max(1LL, (ns + 255) / 256)), dim3(256), 0, st,
+                       v, cap.ccap);
   }
 
   // FP64 block factorisation of bodies [first, first + count)
@@ -323,11 +358,13 @@ struct Engine {
     hipLaunchKernelGGL(k_predict<T>, g, b, 0, st, v);
     double* hn = history ? rh_num : nullptr;
     double* hd = history ? rh_den : nullptr;
+    constexpr int LPB = 4;  // lanes per body when contacts are present
+    const dim3 gc = grid_for((int)std::min<long long>((long long)cap.n * LPB, INT_MAX), 256);
     for (int k = 0; k < kmax; ++k) {
       if (contacts)
-        hipLaunchKernelGGL((k_iterate<T, true>), g, b, 0, st, v, k, hn, hd);
+        hipLaunchKernelGGL((k_iterate<T, true, LPB>), gc, b, 0, st, v, k, hn, hd);
       else
-        hipLaunchKernelGGL((k_iterate<T, false>), g, b, 0, st, v, k, hn, hd);
+        hipLaunchKernelGGL((k_iterate<T, false, 1>), g, b, 0, st, v, k, hn, hd);
     }
     hipLaunchKernelGGL(k_finish<T>, g, b, 0, st, v);
     if (!finish_scenes) return;

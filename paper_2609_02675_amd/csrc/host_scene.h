@@ -4,6 +4,7 @@
 // converts to the scene's arithmetic type.
 #pragma once
 
+#include <algorithm>
 #include <cmath>
 #include <string>
 #include <vector>
@@ -186,8 +187,12 @@ inline std::string build_host_scene(const pabd_scene_desc* d, HostScene& hs) {
 inline size_t scene_bytes(const HostScene& hs, int ts) {
   const size_t per_body = (size_t)ts * (4 * (QW + 4) + VW + MW + FW + 4) + 8 * (10 + 8 + 2) + 2 + 4 * 4;
   const size_t per_end = (size_t)ts * EW + 4 + 8 * 4;
-  const size_t per_contact = (size_t)ts * CW + 4 + 8;
+  // contact slots (final and staging) and the broad phase: record, reach,
+  // large-list entry and max(16, ccap / 2) candidate pairs per body
+  const size_t per_contact = 2 * ((size_t)ts * CW + 4 + 8);
+  const size_t per_contact_body = hs.ccap > 0 ? 64 + 8 + 4 + 8 * (size_t)std::max(16, hs.ccap / 2) : 0;
   return per_body * hs.n + per_end * hs.ne + per_contact * (size_t)hs.n * hs.ccap +
+         per_contact_body * hs.n +
          hs.drv_param.size() * 8 + hs.planes.size() * 8 + sizeof(SceneDev) + 64;
 }
 

@@ -10,11 +10,30 @@
 // pm = margin + h (|v| + |w| R) per body (R: bounding radius; spheres omit
 // the spin term).
 //
-// Pipeline: k_contact_prep (margins, per-scene max reach, clear counters) ->
-// k_hash_count / scan / k_hash_fill (uniform grid of cell 2 max(R + pm), spatial
-// hash with scene id) -> k_narrow (27 neighbour cells, each pair once by its
-// lower index, plus planes) -> k_sort_contacts (per-body canonical order, so the
-// iteration sums in a fixed order whatever order the atomics produced).
+// Pipeline (one launch each):
+//   k_contact_prep   clear per-body and per-scene counters
+//   k_contact_reach  reach = R + pm per body; per-scene maximum and a log-scale
+//                    histogram of reach (four bins per octave)
+//   k_contact_cells  per scene: cell = 2 cut, cut = the smaller of the maximum
+//                    reach and the upper edge of the bin holding the 98th
+//                    percentile; bodies with reach > cut are "large"
+//   k_hash_count / scan / k_hash_fill   uniform-grid spatial hash of the small
+//                    bodies (scene id in the hash), each bucket a run of 64-byte
+//                    records holding the body's centre, reach, cell and filters;
+//                    large bodies go to a list instead
+//   k_broad_small    one thread per body: planes; then the 27 neighbour cells of
+//                    a small body, pairs with small bodies of higher index
+//   k_broad_large    one workgroup per large body: small partners over the cells
+//                    its reach spans (or over the scene's bodies when that is
+//                    fewer), large partners of higher index over the scene
+//   k_narrow_pairs   one thread per candidate pair: narrow phase, bond ends into
+//                    the owners' staging slots
+//   k_sort_contacts  per body, ends copied in canonical key order to their final
+//                    slots, so the iteration sums in a fixed order whatever order
+//                    the atomics produced
+// Candidate tests are conservative (a relative slack of 1e-12 on the sum of
+// reaches); the narrow phase repeats the exact bounding test, so the contact
+// set does not depend on the broad phase.
 #pragma once
 
 #include "common.h"
@@ -22,13 +41,40 @@
 
 namespace pabd {
 
+// broad-phase record of a small body, in bucket order (32 bytes): centre and
+// reach rounded to float (tests against them carry a slack that covers the
+// rounding), body and scene, and the cell packed as three 21-bit fields
+struct BroadRec {
+  float c[3];
+  float reach;
+  int body, scene;
+  unsigned long long cell;
+};
+
+__device__ __forceinline__ unsigned long long pack_cell(int x, int y, int z) {
+  auto f = [](int a) {
+    a = a < -(1 << 20) ? -(1 << 20) : (a > (1 << 20) - 1 ? (1 << 20) - 1 : a);
+    return (unsigned long long)(unsigned)(a + (1 << 20));
+  };
+  return (f(x) << 42) | (f(y) << 21) | f(z);
+}
+
+constexpr int REACH_BINS = 64;
+constexpr int REACH_BIN_BASE = 468;  // float bits >> 21 of 2^-10: bins span 2^-10 .. 2^6
+
 struct ContactBuf {
   int tb;                // hash buckets (power of two)
   int* bucket_count;     // [tb]
   int* bucket_start;     // [tb + 1]
   int* bucket_fill;      // [tb]
-  int* sorted_body;      // [n]
+  BroadRec* rec;         // [nc] small bodies in bucket order
   unsigned long long* reach;  // per scene: max(R + pm) as double bits
+  int* hist;             // per scene: REACH_BINS counts
+  double* breach;        // per body: R + pm
+  int* large;            // [nc] large bodies
+  int* counters;         // [0] large bodies, [1] candidate pairs
+  int2* pairs;           // [pcap]
+  int pcap;
   const double* mass64;  // 8 per body
   int* scan_tmp;         // block sums
 };
@@ -51,31 +97,91 @@ template <typename T>
 __global__ void k_contact_prep(View<T> v, ContactBuf cb, int n_scenes) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n_scenes) cb.reach[i] = 0ull;
+  if (i < n_scenes * REACH_BINS) cb.hist[i] = 0;
+  if (i < 2) cb.counters[i] = 0;
   if (i >= v.n) return;
   v.ccount[i] = 0;
   v.r_num[i] = 0.0;
   v.r_den[i] = 0.0;
 }
 
-template <typename T>
-__global__ void k_contact_reach(View<T> v, ContactBuf cb) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= v.n) return;
-  const int sc = v.bscene[i];
-  if (!contact_body(v, i, sc)) return;
-  T vw[VW];
-  load<T, VW>(v.vel + (size_t)VW * i, vw);
-  double vd[6] = {(double)vw[0], (double)vw[1], (double)vw[2], (double)vw[3], (double)vw[4], (double)vw[5]};
-  double R = (double)v.half[4 * i + 3];
-  double reach = R + body_pm(v.scenes[sc], vd, R, v.shape[i]);
-  atomicMax(cb.reach + sc, (unsigned long long)__double_as_longlong(reach));
+__device__ __forceinline__ int reach_bin(double r) {
+  const int b = (int)(__float_as_uint((float)r) >> 21) - REACH_BIN_BASE;
+  return b < 0 ? 0 : (b >= REACH_BINS ? REACH_BINS - 1 : b);
 }
 
-__global__ void k_contact_cells(SceneDev* scenes, int n_scenes, const unsigned long long* reach) {
+// upper edge of a reach bin (every reach in bin b is below it, up to float rounding)
+__device__ __forceinline__ double reach_bin_edge(int b) {
+  return (double)__uint_as_float((unsigned)(b + REACH_BIN_BASE + 1) << 21);
+}
+
+// per-scene maximum reach and reach histogram; lanes of a wavefront that share a
+// scene (or a scene and bin) combine before one atomic
+template <typename T>
+__global__ void __launch_bounds__(256) k_contact_reach(View<T> v, ContactBuf cb) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int sc = i < v.n ? v.bscene[i] : -1;
+  double reach = 0.0;
+  if (i < v.n && contact_body(v, i, sc)) {
+    T vw[VW];
+    load<T, VW>(v.vel + (size_t)VW * i, vw);
+    double vd[6] = {(double)vw[0], (double)vw[1], (double)vw[2], (double)vw[3], (double)vw[4], (double)vw[5]};
+    double R = (double)v.half[4 * i + 3];
+    reach = R + body_pm(v.scenes[sc], vd, R, v.shape[i]);
+    cb.breach[i] = reach;
+  } else {
+    sc = -1;
+  }
+  const int lane = __lane_id();
+  // maximum, one scene at a time
+  bool todo = sc >= 0;
+  while (__ballot(todo)) {
+    const int leader = __ffsll((long long)__ballot(todo)) - 1;
+    const int s0 = __shfl(sc, leader);
+    const bool mine = todo && sc == s0;
+    double r = mine ? reach : 0.0;
+    for (int o = 32; o > 0; o >>= 1) r = fmax(r, __shfl_xor(r, o));
+    if (lane == leader) atomicMax(cb.reach + s0, (unsigned long long)__double_as_longlong(r));
+    todo = todo && !mine;
+  }
+  // histogram, one (scene, bin) at a time
+  const int key = sc >= 0 ? REACH_BINS * sc + reach_bin(reach) : -1;
+  todo = key >= 0;
+  while (__ballot(todo)) {
+    const unsigned long long act = __ballot(todo);
+    const int leader = __ffsll((long long)act) - 1;
+    const int k0 = __shfl(key, leader);
+    const unsigned long long same = __ballot(todo && key == k0);
+    if (lane == leader) atomicAdd(cb.hist + k0, __popcll(same));
+    todo = todo && key != k0;
+  }
+}
+
+// cell = 2 cut: cut covers at least 98 % of the scene's bodies (the bin edge
+// above the percentile, rounded up by a factor 1 + 1e-6 against float rounding
+// of the binning) and never exceeds the largest reach
+__global__ void k_contact_cells(SceneDev* scenes, int n_scenes, const unsigned long long* reach,
+                                const int* hist) {
   const int sc = blockIdx.x * blockDim.x + threadIdx.x;
   if (sc >= n_scenes) return;
-  double r = __longlong_as_double((long long)reach[sc]);
-  scenes[sc].cell = r > 0.0 ? 2.0 * r : 1.0;
+  const double rmax = __longlong_as_double((long long)reach[sc]);
+  if (!(rmax > 0.0)) {
+    scenes[sc].cell = 1.0;
+    return;
+  }
+  int total = 0;
+  for (int b = 0; b < REACH_BINS; ++b) total += hist[REACH_BINS * sc + b];
+  const int need = total - total / 50;
+  int cum = 0, pb = REACH_BINS - 1;
+  for (int b = 0; b < REACH_BINS; ++b) {
+    cum += hist[REACH_BINS * sc + b];
+    if (cum >= need) {
+      pb = b;
+      break;
+    }
+  }
+  const double cut = fmin(rmax, reach_bin_edge(pb) * (1.0 + 1e-6));
+  scenes[sc].cell = 2.0 * cut;
 }
 
 __device__ __forceinline__ unsigned bucket_of(int sc, int cx, int cy, int cz, int tb) {
@@ -87,12 +193,18 @@ __device__ __forceinline__ unsigned bucket_of(int sc, int cx, int cy, int cz, in
   return h & (unsigned)(tb - 1);
 }
 
+__device__ __forceinline__ void cell_of_pos(const double* c, double cell, int* cc) {
+  cc[0] = (int)floor(c[0] / cell);
+  cc[1] = (int)floor(c[1] / cell);
+  cc[2] = (int)floor(c[2] / cell);
+}
+
 template <typename T>
-__device__ __forceinline__ void cell_of(const View<T>& v, int i, double cell, int* cc) {
+__device__ __forceinline__ void centre_of(const View<T>& v, int i, double* c) {
   const T* q = v.qn + (size_t)Rec<T>::Q * i;
-  cc[0] = (int)floor(pos_value(q, 0) / cell);
-  cc[1] = (int)floor(pos_value(q, 1) / cell);
-  cc[2] = (int)floor(pos_value(q, 2) / cell);
+  c[0] = pos_value(q, 0);
+  c[1] = pos_value(q, 1);
+  c[2] = pos_value(q, 2);
 }
 
 __global__ void k_zero_int(int* p, int n) {
@@ -101,13 +213,24 @@ __global__ void k_zero_int(int* p, int n) {
 }
 
 template <typename T>
+__device__ __forceinline__ bool is_large(const View<T>& v, const ContactBuf& cb, int i, int sc) {
+  return cb.breach[i] > 0.5 * v.scenes[sc].cell;
+}
+
+template <typename T>
 __global__ void k_hash_count(View<T> v, ContactBuf cb) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= v.n) return;
   const int sc = v.bscene[i];
   if (!contact_body(v, i, sc)) return;
+  if (is_large(v, cb, i, sc)) {
+    cb.large[atomicAdd(cb.counters, 1)] = i;
+    return;
+  }
+  double c[3];
   int cc[3];
-  cell_of(v, i, v.scenes[sc].cell, cc);
+  centre_of(v, i, c);
+  cell_of_pos(c, v.scenes[sc].cell, cc);
   atomicAdd(cb.bucket_count + bucket_of(sc, cc[0], cc[1], cc[2], cb.tb), 1);
 }
 
@@ -116,12 +239,22 @@ __global__ void k_hash_fill(View<T> v, ContactBuf cb) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= v.n) return;
   const int sc = v.bscene[i];
-  if (!contact_body(v, i, sc)) return;
+  if (!contact_body(v, i, sc) || is_large(v, cb, i, sc)) return;
+  double c[3];
   int cc[3];
-  cell_of(v, i, v.scenes[sc].cell, cc);
-  unsigned b = bucket_of(sc, cc[0], cc[1], cc[2], cb.tb);
-  int pos = atomicAdd(cb.bucket_fill + b, 1);
-  cb.sorted_body[cb.bucket_start[b] + pos] = i;
+  centre_of(v, i, c);
+  cell_of_pos(c, v.scenes[sc].cell, cc);
+  BroadRec r;
+  r.c[0] = (float)c[0];
+  r.c[1] = (float)c[1];
+  r.c[2] = (float)c[2];
+  r.reach = (float)cb.breach[i];
+  r.body = i;
+  r.scene = sc;
+  r.cell = pack_cell(cc[0], cc[1], cc[2]);
+  const unsigned b = bucket_of(sc, cc[0], cc[1], cc[2], cb.tb);
+  const int pos = atomicAdd(cb.bucket_fill + b, 1);
+  cb.rec[cb.bucket_start[b] + pos] = r;
 }
 
 // ---- exclusive scan of int counts (three passes, 1024 per block) ---------------
@@ -192,10 +325,10 @@ __device__ __forceinline__ void push_end(const View<T>& v, int owner, int sc, in
   const size_t e = (size_t)owner * cap + slot;
   T C[CW] = {(T)xs[0], (T)xs[1], (T)xs[2], (T)kap, (T)xo[0], (T)xo[1], (T)xo[2], (T)mu,
              (T)n[0], (T)n[1], (T)n[2], (T)0};
-  store<T, CW>(v.ce + CW * e, C);
-  v.ce_partner[e] = partner;
-  v.ce_key[e] = ((unsigned long long)(unsigned)(partner + 1) << 32) |
-                ((unsigned long long)(unsigned)feature << 1) | (unsigned)side;
+  store<T, CW>(v.ce_st + CW * e, C);
+  v.ce_st_partner[e] = partner;
+  v.ce_st_key[e] = ((unsigned long long)(unsigned)(partner + 1) << 32) |
+                   ((unsigned long long)(unsigned)feature << 1) | (unsigned)side;
 }
 
 template <typename T>
@@ -361,107 +494,220 @@ __device__ void narrow_pair(const View<T>& v, const ContactBuf& cb, int sc, int 
   }
 }
 
+// ---- broad phase ---------------------------------------------------------------
+
+// Append candidate pair (i, j), i < j, to the pair list.  Called by any subset of
+// a wavefront's lanes: one atomic per wavefront and call site.
+__device__ __forceinline__ void append_pair(const ContactBuf& cb, int* health, int sc, int i, int j) {
+  const unsigned long long m = __ballot(1);
+  const int lane = __lane_id();
+  const int leader = __ffsll((long long)m) - 1;
+  const int rank = __popcll(m & ((1ull << lane) - 1ull));
+  int base = 0;
+  if (lane == leader) base = atomicAdd(cb.counters + 1, __popcll(m));
+  base = __shfl(base, leader);
+  const int slot = base + rank;
+  if (slot < cb.pcap) cb.pairs[slot] = make_int2(i, j);
+  else atomicOr(health + sc, 2);
+}
+
+// conservative bounding-sphere test (the narrow phase repeats it exactly)
+__device__ __forceinline__ bool spheres_near(const double* a, double ra, const double* b, double rb) {
+  const double d0 = b[0] - a[0], d1 = b[1] - a[1], d2 = b[2] - a[2];
+  const double r = (ra + rb) * (1.0 + 1e-12);
+  return d0 * d0 + d1 * d1 + d2 * d2 < r * r;
+}
+
+// the same against a float record: the slack covers float rounding of the
+// record's centre (2^-24 relative per coordinate) and reach
+__device__ __forceinline__ bool near_rec(const double* a, double ra, const BroadRec& r) {
+  const double b0 = r.c[0], b1 = r.c[1], b2 = r.c[2], rb = r.reach;
+  const double d0 = b0 - a[0], d1 = b1 - a[1], d2 = b2 - a[2];
+  const double mag = fmax(fabs(b0), fmax(fabs(b1), fabs(b2)));
+  const double rr = (ra + rb) * (1.0 + 1e-6) + 1e-6 * mag;
+  return d0 * d0 + d1 * d1 + d2 * d2 < rr * rr;
+}
+
+// pair filters shared by both broad kernels
+__device__ __forceinline__ bool pair_allowed(bool pin_i, int group_i, unsigned flags_j, int group_j) {
+  if (flags_j & F_NOCONTACT) return false;
+  if (pin_i && (flags_j & F_PINNED)) return false;
+  if (group_i != 0 && group_j == group_i) return false;
+  return true;
+}
+
 template <typename T>
-__global__ void __launch_bounds__(128) k_narrow(View<T> v, ContactBuf cb) {
+__device__ void plane_contacts(const View<T>& v, const ContactBuf& cb, int sc, int i,
+                               const BodyGeo<T>& gi, double pmi) {
+  const SceneDev& S = v.scenes[sc];
+  for (int p = 0; p < S.n_planes; ++p) {
+    const double* pl = v.planes + 4 * (size_t)(S.plane_off + p);
+    const double n[3] = {pl[0], pl[1], pl[2]};
+    if (gi.shape == 0) {
+      for (int k = 0; k < 8; ++k) {
+        double x[3], y[3];
+        vertex_of(k, gi.he, x);
+        mat_vec(gi.A, x, y);
+        for (int r = 0; r < 3; ++r) y[r] += gi.c[r];
+        const double gap = n[0] * y[0] + n[1] * y[1] + n[2] * y[2] - pl[3];
+        if (gap < pmi) {
+          const double xw[3] = {y[0] - gap * n[0], y[1] - gap * n[1], y[2] - gap * n[2]};
+          emit_contact(v, cb, sc, i, -1, 16 * p + k, x, xw, n);
+        }
+      }
+    } else {
+      const double r = gi.he[0];
+      const double gap = n[0] * gi.c[0] + n[1] * gi.c[1] + n[2] * gi.c[2] - r - pl[3];
+      if (gap < pmi) {
+        const double pw[3] = {-r * n[0], -r * n[1], -r * n[2]};
+        double x[3];
+        mat_tvec(gi.A, pw, x);
+        const double xw[3] = {gi.c[0] - (r + gap) * n[0], gi.c[1] - (r + gap) * n[1],
+                              gi.c[2] - (r + gap) * n[2]};
+        emit_contact(v, cb, sc, i, -1, 16 * p + 8, x, xw, n);
+      }
+    }
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ double own_pm(const View<T>& v, int i, int sc, const BodyGeo<T>& g) {
+  T vw[VW];
+  load<T, VW>(v.vel + (size_t)VW * i, vw);
+  const double vd[6] = {(double)vw[0], (double)vw[1], (double)vw[2], (double)vw[3], (double)vw[4], (double)vw[5]};
+  return body_pm(v.scenes[sc], vd, g.R, g.shape);
+}
+
+// one thread per body: plane contacts, then (small bodies) pairs with the small
+// bodies of its own cell (higher index) and of the 13 cells of the forward half
+// of its neighbourhood, so each pair of neighbouring cells is searched from one
+// side only
+template <typename T>
+__global__ void __launch_bounds__(256) k_broad_small(View<T> v, ContactBuf cb) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= v.n) return;
   const int sc = v.bscene[i];
   if (!contact_body(v, i, sc)) return;
   const SceneDev& S = v.scenes[sc];
-  BodyGeo<T> gi;
-  body_geo(v, i, gi);
-  T vw[VW];
-  load<T, VW>(v.vel + (size_t)VW * i, vw);
-  const double vd[6] = {(double)vw[0], (double)vw[1], (double)vw[2], (double)vw[3], (double)vw[4], (double)vw[5]};
-  const double pmi = body_pm(S, vd, gi.R, gi.shape);
   const bool pin_i = (v.flags[i] & F_PINNED) != 0;
-  // planes
-  if (!pin_i) {
-    for (int p = 0; p < S.n_planes; ++p) {
-      const double* pl = v.planes + 4 * (size_t)(S.plane_off + p);
-      const double n[3] = {pl[0], pl[1], pl[2]};
-      if (gi.shape == 0) {
-        for (int k = 0; k < 8; ++k) {
-          double x[3], y[3];
-          vertex_of(k, gi.he, x);
-          mat_vec(gi.A, x, y);
-          for (int r = 0; r < 3; ++r) y[r] += gi.c[r];
-          const double gap = n[0] * y[0] + n[1] * y[1] + n[2] * y[2] - pl[3];
-          if (gap < pmi) {
-            const double xw[3] = {y[0] - gap * n[0], y[1] - gap * n[1], y[2] - gap * n[2]};
-            emit_contact(v, cb, sc, i, -1, 16 * p + k, x, xw, n);
-          }
-        }
-      } else {
-        const double r = gi.he[0];
-        const double gap = n[0] * gi.c[0] + n[1] * gi.c[1] + n[2] * gi.c[2] - r - pl[3];
-        if (gap < pmi) {
-          const double pw[3] = {-r * n[0], -r * n[1], -r * n[2]};
-          double x[3];
-          mat_tvec(gi.A, pw, x);
-          const double xw[3] = {gi.c[0] - (r + gap) * n[0], gi.c[1] - (r + gap) * n[1],
-                                gi.c[2] - (r + gap) * n[2]};
-          emit_contact(v, cb, sc, i, -1, 16 * p + 8, x, xw, n);
+  if (!pin_i && S.n_planes > 0) {
+    BodyGeo<T> gi;
+    body_geo(v, i, gi);
+    plane_contacts(v, cb, sc, i, gi, own_pm(v, i, sc, gi));
+  }
+  if (is_large(v, cb, i, sc)) return;
+  double c[3];
+  int cc[3];
+  centre_of(v, i, c);
+  cell_of_pos(c, S.cell, cc);
+  const double ri = cb.breach[i];
+  const int group_i = v.group[i];
+  for (int t = 13; t < 27; ++t) {  // offsets t - 13 in 0..13: own cell, then forward half
+    const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = t / 9 - 1;
+    const int tx = cc[0] + dx, ty = cc[1] + dy, tz = cc[2] + dz;
+    const unsigned long long key = pack_cell(tx, ty, tz);
+    const unsigned b = bucket_of(sc, tx, ty, tz, cb.tb);
+    const int e1 = cb.bucket_start[b + 1];
+    for (int e = cb.bucket_start[b]; e < e1; ++e) {
+      const BroadRec r = cb.rec[e];
+      if (r.cell != key || r.scene != sc || (t == 13 && r.body <= i)) continue;
+      if (!near_rec(c, ri, r)) continue;
+      const int j = r.body;
+      if (!pair_allowed(pin_i, group_i, v.flags[j], v.group[j])) continue;
+      append_pair(cb, v.health, sc, min(i, j), max(i, j));
+    }
+  }
+}
+
+// one workgroup per large body (grid-stride over the large list)
+template <typename T>
+__global__ void __launch_bounds__(256) k_broad_large(View<T> v, ContactBuf cb) {
+  const int nl = cb.counters[0];
+  for (int l = blockIdx.x; l < nl; l += gridDim.x) {
+    const int L = cb.large[l];
+    const int sc = v.bscene[L];
+    const SceneDev& S = v.scenes[sc];
+    const double cell = S.cell, cut = 0.5 * cell;
+    double c[3];
+    centre_of(v, L, c);
+    const double rL = cb.breach[L];
+    const bool pin_L = (v.flags[L] & F_PINNED) != 0;
+    const int group_L = v.group[L];
+    const int off = S.body_off, ns = S.n_bodies;
+    // small partners lie within rL + cut of the centre: cells within m of its own
+    const double md = ceil((rL + cut) / cell);
+    const double span = 2.0 * md + 1.0;
+    const bool by_cells = span * span * span <= (double)ns;
+    if (by_cells) {
+      const int m = (int)md, w = 2 * m + 1;
+      int cc[3];
+      cell_of_pos(c, cell, cc);
+      const int ncell = w * w * w;
+      for (int t = threadIdx.x; t < ncell; t += blockDim.x) {
+        const int tx = cc[0] + t % w - m, ty = cc[1] + (t / w) % w - m, tz = cc[2] + t / (w * w) - m;
+        const unsigned long long key = pack_cell(tx, ty, tz);
+        const unsigned b = bucket_of(sc, tx, ty, tz, cb.tb);
+        const int e1 = cb.bucket_start[b + 1];
+        for (int e = cb.bucket_start[b]; e < e1; ++e) {
+          const BroadRec r = cb.rec[e];
+          if (r.cell != key || r.scene != sc) continue;
+          if (!near_rec(c, rL, r)) continue;
+          if (!pair_allowed(pin_L, group_L, v.flags[r.body], v.group[r.body])) continue;
+          append_pair(cb, v.health, sc, min(L, r.body), max(L, r.body));
         }
       }
     }
+    // over the scene's bodies: large partners of higher index, and small ones
+    // when the cells were not used
+    for (int j = off + threadIdx.x; j < off + ns; j += blockDim.x) {
+      if (j == L || !contact_body(v, j, sc)) continue;
+      const bool lj = is_large(v, cb, j, sc);
+      if (lj ? j < L : by_cells) continue;
+      if (!pair_allowed(pin_L, group_L, v.flags[j], v.group[j])) continue;
+      double cj[3];
+      centre_of(v, j, cj);
+      if (spheres_near(c, rL, cj, cb.breach[j])) append_pair(cb, v.health, sc, min(L, j), max(L, j));
+    }
   }
-  // neighbour cells (each distinct bucket once)
-  int cc[3];
-  cell_of(v, i, S.cell, cc);
-  unsigned seen[27];
-  int nseen = 0;
-  const int gi_group = v.group[i];
-  for (int dz = -1; dz <= 1; ++dz)
-    for (int dy = -1; dy <= 1; ++dy)
-      for (int dx = -1; dx <= 1; ++dx) {
-        const unsigned b = bucket_of(sc, cc[0] + dx, cc[1] + dy, cc[2] + dz, cb.tb);
-        bool dup = false;
-        for (int t = 0; t < nseen; ++t) dup = dup || seen[t] == b;
-        if (dup) continue;
-        seen[nseen++] = b;
-        const int e1 = cb.bucket_start[b + 1];
-        for (int e = cb.bucket_start[b]; e < e1; ++e) {
-          const int j = cb.sorted_body[e];
-          if (j <= i || v.bscene[j] != sc) continue;
-          if (v.flags[j] & F_NOCONTACT) continue;
-          if (pin_i && (v.flags[j] & F_PINNED)) continue;
-          if (gi_group != 0 && v.group[j] == gi_group) continue;
-          narrow_pair(v, cb, sc, i, j, gi, pmi);
-        }
-      }
 }
 
-// insertion sort of each body's contact ends by key
+// one thread per candidate pair (grid-stride)
 template <typename T>
-__global__ void k_sort_contacts(View<T> v) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(256) k_narrow_pairs(View<T> v, ContactBuf cb) {
+  const int np = min(cb.counters[1], cb.pcap);
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < np; p += gridDim.x * blockDim.x) {
+    const int2 pr = cb.pairs[p];
+    const int i = pr.x, j = pr.y;
+    const int sc = v.bscene[i];
+    BodyGeo<T> gi;
+    body_geo(v, i, gi);
+    narrow_pair(v, cb, sc, i, j, gi, own_pm(v, i, sc, gi));
+  }
+}
+
+// each body's ends from the staging slots to their final slots in key order
+// (keys of one body are distinct: partner, feature, side).  One lane per slot:
+// the lanes of a body read the same keys, which the hardware broadcasts.
+template <typename T>
+__global__ void __launch_bounds__(256) k_sort_contacts(View<T> v, int cap) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = (int)(t / cap), a = (int)(t % cap);
   if (i >= v.n) return;
   const int sc = v.bscene[i];
   if (!contact_body(v, i, sc)) return;
-  const int cap = v.scenes[sc].ccap;
   int cnt = v.ccount[i];
   if (cnt > cap) cnt = cap;
+  if (a >= cnt) return;
   const size_t base = (size_t)i * cap;
-  for (int a = 1; a < cnt; ++a) {
-    unsigned long long key = v.ce_key[base + a];
-    int b = a - 1;
-    if (v.ce_key[base + b] <= key) continue;
-    T C[CW];
-    load<T, CW>(v.ce + CW * (base + a), C);
-    const int part = v.ce_partner[base + a];
-    while (b >= 0 && v.ce_key[base + b] > key) {
-      v.ce_key[base + b + 1] = v.ce_key[base + b];
-      v.ce_partner[base + b + 1] = v.ce_partner[base + b];
-      T D[CW];
-      load<T, CW>(v.ce + CW * (base + b), D);
-      store<T, CW>(v.ce + CW * (base + b + 1), D);
-      --b;
-    }
-    v.ce_key[base + b + 1] = key;
-    v.ce_partner[base + b + 1] = part;
-    store<T, CW>(v.ce + CW * (base + b + 1), C);
-  }
+  const unsigned long long* keys = v.ce_st_key + base;
+  const unsigned long long key = keys[a];
+  int r = 0;
+  for (int b = 0; b < cnt; ++b) r += keys[b] < key ? 1 : 0;
+  T C[CW];
+  load<T, CW>(v.ce_st + CW * (base + a), C);
+  store<T, CW>(v.ce + CW * (base + r), C);
+  v.ce_partner[base + r] = v.ce_st_partner[base + a];
+  v.ce_key[base + r] = key;
 }
 
 }  // namespace pabd

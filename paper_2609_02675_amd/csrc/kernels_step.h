@@ -133,10 +133,24 @@ __device__ __forceinline__ void residual_terms(const T* m, const T* qo, const T*
   *den = m_norm2(m, cc, q);
 }
 
-template <typename T, bool CONTACT>
+// sum over the LPB consecutive lanes of a body (xor butterfly: every lane gets
+// the same bits, since each partial sum is formed from the same two operands)
+template <int LPB, typename U>
+__device__ __forceinline__ U lane_sum(U x) {
+#pragma unroll
+  for (int o = 1; o < LPB; o <<= 1) x += __shfl_xor(x, o);
+  return x;
+}
+
+// One Jacobi iteration.  LPB consecutive lanes share a body: they split its
+// static bond ends and contact ends (lane l takes ends l, l + LPB, ...), sum the
+// force terms and the contact change of the FP64 block across the lanes, and the
+// first lane solves, projects and stores.
+template <typename T, bool CONTACT, int LPB>
 __global__ void __launch_bounds__(256) k_iterate(View<T> v, int k, double* rh_num, double* rh_den) {
   constexpr int QR = Rec<T>::Q;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = (int)(t / LPB), sub = (int)(t % LPB);
   if (i >= v.n) return;
   const int sc = v.bscene[i];
   if (sc < 0 || (v.flags[i] & F_PINNED)) return;
@@ -145,15 +159,13 @@ __global__ void __launch_bounds__(256) k_iterate(View<T> v, int k, double* rh_nu
   if (k >= K || S.step >= S.steps_total) return;
   const T* qs = v.q[k & 1];
   T* qd = v.q[(k + 1) & 1];
-  T q[QR], s[QR], m[MW];
+  T q[QR];
   load<T, QR>(qs + (size_t)QR * i, q);
-  load<T, QR>(v.s + (size_t)QR * i, s);
-  load<T, MW>(v.mass + (size_t)MW * i, m);
   T rb[QW];
 #pragma unroll
   for (int c = 0; c < QW; ++c) rb[c] = (T)0;
   const int e1 = v.srow_end[i];
-  for (int e = v.srow[i]; e < e1; ++e) {
+  for (int e = v.srow[i] + sub; e < e1; e += LPB) {
     const int j = v.se_partner[e];
     T E[EW];
     load<T, EW>(v.se + (size_t)EW * e, E);
@@ -172,16 +184,12 @@ __global__ void __launch_bounds__(256) k_iterate(View<T> v, int k, double* rh_nu
   const T h2 = (T)h2d;
   T fac[FW];
   bool refactor = false;
+  Block dB{};  // contact part of H^k - H (this lane's ends)
   if constexpr (CONTACT) {
     int cnt = v.ccount[i];
     if (cnt > S.ccap) cnt = S.ccap;
-    Block B{};
-    if (cnt > 0) {
-      const double* bb = v.blk + 10 * (size_t)i;
-      B = Block{bb[0], bb[1], bb[2], bb[3], bb[4], bb[5], bb[6], bb[7], bb[8], bb[9]};
-    }
     const size_t base = (size_t)i * S.ccap;
-    for (int c = 0; c < cnt; ++c) {
+    for (int c = sub; c < cnt; c += LPB) {
       const int j = v.ce_partner[base + c];
       T C[CW];
       load<T, CW>(v.ce + (size_t)CW * (base + c), C);
@@ -195,17 +203,44 @@ __global__ void __launch_bounds__(256) k_iterate(View<T> v, int k, double* rh_nu
       }
       if (!contact_end_force(C, d, f)) continue;
       add_JT(rb, C, f[0], f[1], f[2]);
-      block_add_end(B, h2d * (double)C[3], (double)C[0], (double)C[1], (double)C[2]);
+      block_add_end(dB, h2d * (double)C[3], (double)C[0], (double)C[1], (double)C[2]);
       refactor = true;
     }
-    if (refactor) {  // H^k changed: some contact penetrates at this iterate
-      double f64[10];
-      block_inverse(B, f64);
-#pragma unroll
-      for (int c = 0; c < 10; ++c) fac[c] = (T)f64[c];
-    }
   }
-  if (!refactor) load<T, FW>(v.fac + (size_t)FW * i, fac);
+  if constexpr (LPB > 1) {
+#pragma unroll
+    for (int c = 0; c < QW; ++c) rb[c] = lane_sum<LPB>(rb[c]);
+    if constexpr (CONTACT) {
+      refactor = lane_sum<LPB>(refactor ? 1 : 0) > 0;
+      if (refactor) {  // uniform across the body's lanes
+        dB.a = lane_sum<LPB>(dB.a);
+        dB.b0 = lane_sum<LPB>(dB.b0);
+        dB.b1 = lane_sum<LPB>(dB.b1);
+        dB.b2 = lane_sum<LPB>(dB.b2);
+        dB.d00 = lane_sum<LPB>(dB.d00);
+        dB.d01 = lane_sum<LPB>(dB.d01);
+        dB.d02 = lane_sum<LPB>(dB.d02);
+        dB.d11 = lane_sum<LPB>(dB.d11);
+        dB.d12 = lane_sum<LPB>(dB.d12);
+        dB.d22 = lane_sum<LPB>(dB.d22);
+      }
+    }
+    if (sub != 0) return;
+  }
+  if (refactor) {  // H^k changed: some contact penetrates at this iterate
+    const double* bb = v.blk + 10 * (size_t)i;
+    const Block B{bb[0] + dB.a,   bb[1] + dB.b0,  bb[2] + dB.b1,  bb[3] + dB.b2,  bb[4] + dB.d00,
+                  bb[5] + dB.d01, bb[6] + dB.d02, bb[7] + dB.d11, bb[8] + dB.d12, bb[9] + dB.d22};
+    double f64[10];
+    block_inverse(B, f64);
+#pragma unroll
+    for (int c = 0; c < 10; ++c) fac[c] = (T)f64[c];
+  } else {
+    load<T, FW>(v.fac + (size_t)FW * i, fac);
+  }
+  T s[QR], m[MW];
+  load<T, QR>(v.s + (size_t)QR * i, s);
+  load<T, MW>(v.mass + (size_t)MW * i, m);
   T r[QW];
 #pragma unroll
   for (int c = 0; c < QW; ++c) r[c] = h2 * rb[c];

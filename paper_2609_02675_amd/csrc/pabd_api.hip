@@ -526,7 +526,10 @@ namespace {
 
 size_t body_cost(int ts) { return (size_t)ts * (4 * (QW + 4) + VW + MW + FW + 4) + 8 * (10 + 8 + 2) + 2 + 4 * 5; }
 size_t end_cost(int ts) { return (size_t)ts * EW + 4 + 8 * 4; }
-size_t contact_cost(int ts) { return (size_t)ts * CW + 4 + 8; }
+// one contact slot: final and staging copies of the record, partner and key
+size_t contact_cost(int ts) { return 2 * ((size_t)ts * CW + 4 + 8); }
+// per contact body: broad-phase record, reach, large-list entry, candidate pairs
+size_t contact_body_cost(int ccap) { return sizeof(BroadRec) + 8 + 4 + 8 * (size_t)pairs_per_body(ccap); }
 
 pabd_status batch_tables(pabd_batch* b) {
   // rebuild the device tile table from the host tiles
@@ -701,7 +704,8 @@ pabd_status pabd_batch_create(int32_t max_slots, size_t hbm_budget, int32_t prec
   // capacity: half the budget for bodies on the flat path (with contact slots),
   // half for tiled bodies; about three bond ends per body
   const int ccap = 64;
-  const size_t per_stream = body_cost(ts) + 3 * end_cost(ts) + (size_t)ccap * contact_cost(ts);
+  const size_t per_stream =
+      body_cost(ts) + 3 * end_cost(ts) + (size_t)ccap * contact_cost(ts) + contact_body_cost(ccap);
   const size_t per_tiled = body_cost(ts) + 3 * end_cost(ts);
   size_t n_stream = std::max<size_t>(1024, hbm_budget / 2 / per_stream);
   size_t n_tiled = std::max<size_t>(1024, hbm_budget / 2 / per_tiled);
@@ -715,6 +719,7 @@ pabd_status pabd_batch_create(int32_t max_slots, size_t hbm_budget, int32_t prec
   b->caps.dr = std::max(64, (int)(n_stream / 4));
   b->caps.contacts = true;
   b->caps.ccap = ccap;
+  b->caps.nc = (int)n_stream;  // contacts only on the flat path
   b->eng = make_engine(precision);
   API_HIP(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
   pabd_status st = b->eng->allocate(b->caps);
