@@ -171,33 +171,48 @@ __device__ void nearest_rotation_svd(const T* A, T* R) {
     for (int c = 0; c < 3; ++c) R[3 * r + c] = u1[r] * v1[c] + u2[r] * v2[c] + u3[r] * v3[c];
 }
 
-// Rotation factor of the polar decomposition A = R S (Sec. 4.2.2, local solve):
-// Newton's iteration X <- (zeta X + X^{-T} / zeta) / 2, with determinant scaling
-// zeta = |det X|^{-1/3} while det X is far from 1, stopped once the update is
-// below the precision's tolerance.  det A <= 0 (no proper polar factor) or a stalled
-// iteration fall back to the nearest proper rotation.
+// One Newton step X <- (zeta X + X^{-T} / zeta) / 2 for the orthogonal polar factor,
+// with determinant scaling zeta = det^{-1/3} only far from orthogonal (near
+// SO(3), det ~ 1).  Returns false when det X is not safely positive.
+template <typename T>
+__device__ __forceinline__ bool polar_newton_step(T* X, T* step2) {
+  T C[9];
+  const T det = cofactor(X, C);
+  if (!(det > Eps<T>::det_floor)) return false;
+  const T zeta = (det > (T)0.5 && det < (T)1.5) ? (T)1 : rcp(cbrt(det));
+  const T a = (T)0.5 * zeta, b = (T)0.5 * rcp(zeta * det);
+  if (step2) {
+    T diff = 0;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      const T xn = a * X[k] + b * C[k];
+      const T dk = xn - X[k];
+      diff += dk * dk;
+      X[k] = xn;
+    }
+    *step2 = diff;
+  } else {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) X[k] = a * X[k] + b * C[k];
+  }
+  return true;
+}
+
+// Rotation factor of the polar decomposition of A (local step, Sec. 4.2.2):
+// Newton steps in pairs, the size of the second step of each pair ending the
+// iteration (near SO(3) the first pair converges); if det A is not safely
+// positive or Newton stalls, the nearest proper rotation from the SVD.
 template <typename T>
 __device__ __forceinline__ void polar_rotation(const T* A, T* R) {
   T X[9];
 #pragma unroll
   for (int k = 0; k < 9; ++k) X[k] = A[k];
   bool ok = false;
-  for (int it = 0; it < 16; ++it) {
-    T C[9];
-    T det = cofactor(X, C);
-    if (!(det > Eps<T>::det_floor)) break;
-    // determinant scaling only far from orthogonal (near SO(3), det ~ 1)
-    T zeta = (det > (T)0.5 && det < (T)1.5) ? (T)1 : rcp(cbrt(det));
-    T a = (T)0.5 * zeta, b = (T)0.5 * rcp(zeta * det);
-    T diff = 0;
-#pragma unroll
-    for (int k = 0; k < 9; ++k) {
-      T xn = a * X[k] + b * C[k];
-      T dk = xn - X[k];
-      diff += dk * dk;
-      X[k] = xn;
-    }
-    if (diff < Eps<T>::polar_tol2) {
+#pragma unroll 1
+  for (int it = 0; it < 8; ++it) {
+    T d2;
+    if (!polar_newton_step<T>(X, nullptr) || !polar_newton_step<T>(X, &d2)) break;
+    if (d2 < Eps<T>::polar_tol2) {
       ok = true;
       break;
     }
@@ -341,27 +356,33 @@ __device__ __forceinline__ void point_minus_pos(const T* p, const T* q, T* d) {
   }
 }
 
-// c += dc (two-sum renormalisation of the pair in FP32)
+// c += dc within a step: in FP32 the increment goes to the low word only, so the
+// high word stays the step's starting position and the low word carries the
+// displacement (small, hence exact to a few 1e-9 m); pos_renorm folds it back
+// at the end of the step
 template <typename T>
-__device__ __forceinline__ void pos_add(T* q, T d0, T d1, T d2) {
-  const T dc[3] = {d0, d1, d2};
+__device__ __forceinline__ void pos_add_lo(T* q, T d0, T d1, T d2) {
+  constexpr int L = sizeof(T) == 4 ? 12 : 0;
+  q[L] += d0;
+  q[L + 1] += d1;
+  q[L + 2] += d2;
+}
+
+// (hi, lo) <- two-sum of hi + lo (FP32); nothing to do in FP64
+template <typename T>
+__device__ __forceinline__ void pos_renorm(T* q) {
+  if constexpr (sizeof(T) == 4) {
 #pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    if constexpr (sizeof(T) == 4) {
-      const T s = q[k] + dc[k];
-      const T bv = s - q[k];
-      const T err = (q[k] - (s - bv)) + (dc[k] - bv);
-      const T lo = q[12 + k] + err;
-      const T hi = s + lo;
-      q[12 + k] = lo - (hi - s);
-      q[k] = hi;
-    } else {
-      q[k] += dc[k];
+    for (int k = 0; k < 3; ++k) {
+      const T hi = q[k], lo = q[12 + k];
+      const T s = hi + lo;
+      const T bv = s - hi;
+      q[12 + k] = (hi - (s - bv)) + (lo - bv);
+      q[k] = s;
     }
   }
 }
 
-// position as a double (hi + lo in FP32)
 template <typename T>
 __device__ __forceinline__ double pos_value(const T* q, int k) {
   if constexpr (sizeof(T) == 4)

@@ -245,7 +245,9 @@ struct Engine {
       for (int k = 0; k < 8; ++k) tm[MW * b + k] = (T)M[k];
     }
     for (size_t k = 0; k < 4 * n; ++k) th[k] = (T)hs.half[k];
-    for (size_t k = 0; k < EW * ne; ++k) te[k] = (T)hs.se[k];
+    // bond records carry h^2 kappa and h^2 phi^- (the iteration sums h^2-scaled forces)
+    const double h2 = hs.params.h * hs.params.h;
+    for (size_t k = 0; k < EW * ne; ++k) te[k] = (T)((k % EW == 3 || k % EW == 7) ? h2 * hs.se[k] : hs.se[k]);
     std::vector<int> part(ne), rows(n), rows_end(n), bs(n, sidx);
     for (size_t e = 0; e < ne; ++e) part[e] = hs.se_partner[e] < 0 ? -1 : hs.se_partner[e] + boff;
     for (size_t b = 0; b < n; ++b) {
@@ -326,7 +328,8 @@ struct Engine {
     hipLaunchKernelGGL(k_scan_add, grid_for(tb, 256), dim3(256), 0, st, bucket_start, tb,
                        (const int*)scan_tmp);
     hipLaunchKernelGGL(k_hash_fill<T>, grid_for(n, 256), dim3(256), 0, st, v, cb);
-    hipLaunchKernelGGL(k_broad_small<T>, grid_for(n, 256), dim3(256), 0, st, v, cb);
+    hipLaunchKernelGGL(k_broad_small<T>, grid_for((int)std::min<long long>((long long)n * BLPB, INT_MAX), 256),
+                       dim3(256), 0, st, v, cb);
     hipLaunchKernelGGL(k_broad_large<T>, dim3(256), dim3(256), 0, st, v, cb);
     const int ng = std::min(8192, std::max(1, (pcap + 255) / 256));
     hipLaunchKernelGGL(k_narrow_pairs<T>, dim3(ng), dim3(256), 0, st, v, cb);

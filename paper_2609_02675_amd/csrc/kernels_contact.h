@@ -310,7 +310,7 @@ __device__ __forceinline__ double free_mass(const View<T>& v, const ContactBuf& 
   return cb.mass64[8 * (size_t)b];
 }
 
-// write one bond end into the owner's slot list
+// write one bond end into the owner's slot list (stiffness as h^2 kappa_c)
 template <typename T>
 __device__ __forceinline__ void push_end(const View<T>& v, int owner, int sc, int partner,
                                          int feature, int side, const double* xs,
@@ -337,7 +337,7 @@ __device__ __forceinline__ void emit_contact(const View<T>& v, const ContactBuf&
                                              const double* xj, const double* n) {
   const SceneDev& S = v.scenes[sc];
   double m = fmax(free_mass(v, cb, i), free_mass(v, cb, j));
-  double kap = S.kscale * m / (S.h * S.h);
+  double kap = S.kscale * m;  // h^2 kappa_c, kappa_c = scale m / h^2
   push_end(v, i, sc, j, feature, 0, xi, xj, n, kap, S.mu);
   if (j >= 0) {
     double nn[3] = {-n[0], -n[1], -n[2]};
@@ -578,19 +578,22 @@ __device__ __forceinline__ double own_pm(const View<T>& v, int i, int sc, const 
   return body_pm(v.scenes[sc], vd, g.R, g.shape);
 }
 
-// one thread per body: plane contacts, then (small bodies) pairs with the small
-// bodies of its own cell (higher index) and of the 13 cells of the forward half
-// of its neighbourhood, so each pair of neighbouring cells is searched from one
-// side only
+// BLPB lanes per body: the first lane does the plane contacts; then, for a
+// small body, the lanes split the 14 cells made of its own cell (partners of
+// higher index) and the 13 cells of the forward half of its neighbourhood, so
+// each pair of neighbouring cells is searched from one side only
+constexpr int BLPB = 1;
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_broad_small(View<T> v, ContactBuf cb) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const long long gt = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = (int)(gt / BLPB), sub = (int)(gt % BLPB);
   if (i >= v.n) return;
   const int sc = v.bscene[i];
   if (!contact_body(v, i, sc)) return;
   const SceneDev& S = v.scenes[sc];
   const bool pin_i = (v.flags[i] & F_PINNED) != 0;
-  if (!pin_i && S.n_planes > 0) {
+  if (sub == 0 && !pin_i && S.n_planes > 0) {
     BodyGeo<T> gi;
     body_geo(v, i, gi);
     plane_contacts(v, cb, sc, i, gi, own_pm(v, i, sc, gi));
@@ -602,7 +605,7 @@ __global__ void __launch_bounds__(256) k_broad_small(View<T> v, ContactBuf cb) {
   cell_of_pos(c, S.cell, cc);
   const double ri = cb.breach[i];
   const int group_i = v.group[i];
-  for (int t = 13; t < 27; ++t) {  // offsets t - 13 in 0..13: own cell, then forward half
+  for (int t = 13 + sub; t < 27; t += BLPB) {  // offset t: own cell (13), then forward half
     const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = t / 9 - 1;
     const int tx = cc[0] + dx, ty = cc[1] + dy, tz = cc[2] + dz;
     const unsigned long long key = pack_cell(tx, ty, tz);

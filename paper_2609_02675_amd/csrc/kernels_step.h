@@ -39,7 +39,7 @@ __global__ void __launch_bounds__(256) k_predict(View<T> v) {
   T s[QR];
 #pragma unroll
   for (int c = 0; c < QR; ++c) s[c] = q[c];
-  pos_add(s, h * (vw[0] + h * (T)S.g0), h * (vw[1] + h * (T)S.g1), h * (vw[2] + h * (T)S.g2));
+  pos_add_lo(s, h * (vw[0] + h * (T)S.g0), h * (vw[1] + h * (T)S.g1), h * (vw[2] + h * (T)S.g2));
   predict_rotation(q + 3, vw + 3, h, s + 3);
   store<T, QR>(v.s + (size_t)QR * i, s);
   store<T, QR>(v.q[0] + (size_t)QR * i, s);
@@ -73,8 +73,9 @@ __global__ void __launch_bounds__(256) k_factor(View<T> v, const double* mass64,
   store<T, FW>(v.fac + (size_t)FW * i, ft);
 }
 
-// contribution of one quadratic bond end with bond vector d = y_o - y_s:
-// f = kappa d + phim d/|d| (phi^+ / d = kappa implicit, phi^- = phim explicit)
+// contribution of one quadratic bond end with bond vector d = y_o - y_s, scaled
+// by h^2 (the record holds h^2 kappa and h^2 phi^-):
+// h^2 f = h^2 kappa d + h^2 phim d/|d| (phi^+ / d = kappa implicit, phi^- explicit)
 template <typename T>
 __device__ __forceinline__ void quad_end_force(const T* E, const T* d, T* f) {
   const T kap = E[3];
@@ -94,7 +95,8 @@ __device__ __forceinline__ void quad_end_force(const T* E, const T* d, T* f) {
 
 // contact end (reading of the paper's contact bond), d = y_o - y_s: stick force
 // kappa d acting only while penetrating along n (n from the partner's surface
-// towards the owner), tangential part clamped to mu times the normal part.
+// towards the owner), tangential part clamped to mu times the normal part; the
+// record holds h^2 kappa, so the force comes out scaled by h^2 like the bonds'.
 // Returns false when separated (no contribution, no implicit weight).
 template <typename T>
 __device__ __forceinline__ bool contact_end_force(const T* C, const T* d, T* f) {
@@ -180,8 +182,6 @@ __global__ void __launch_bounds__(256) k_iterate(View<T> v, int k, double* rh_nu
     quad_end_force(E, d, f);
     add_JT(rb, E, f[0], f[1], f[2]);
   }
-  const double h2d = S.h * S.h;
-  const T h2 = (T)h2d;
   T fac[FW];
   bool refactor = false;
   Block dB{};  // contact part of H^k - H (this lane's ends)
@@ -203,7 +203,7 @@ __global__ void __launch_bounds__(256) k_iterate(View<T> v, int k, double* rh_nu
       }
       if (!contact_end_force(C, d, f)) continue;
       add_JT(rb, C, f[0], f[1], f[2]);
-      block_add_end(dB, h2d * (double)C[3], (double)C[0], (double)C[1], (double)C[2]);
+      block_add_end(dB, (double)C[3], (double)C[0], (double)C[1], (double)C[2]);
       refactor = true;
     }
   }
@@ -241,16 +241,16 @@ __global__ void __launch_bounds__(256) k_iterate(View<T> v, int k, double* rh_nu
   T s[QR], m[MW];
   load<T, QR>(v.s + (size_t)QR * i, s);
   load<T, MW>(v.mass + (size_t)MW * i, m);
-  T r[QW];
+  T r[QW];  // M (s - q^k) + h^2 sum (...): the forces are already scaled by h^2
 #pragma unroll
-  for (int c = 0; c < QW; ++c) r[c] = h2 * rb[c];
+  for (int c = 0; c < QW; ++c) r[c] = rb[c];
   add_inertia(r, m, s, q);
   T dq[QW];
   block_apply(fac, r, dq);
   T qo[QR];
 #pragma unroll
   for (int c = 0; c < QR; ++c) qo[c] = q[c];
-  pos_add(qo, dq[0], dq[1], dq[2]);
+  pos_add_lo(qo, dq[0], dq[1], dq[2]);
   T Ah[9];
 #pragma unroll
   for (int c = 0; c < 9; ++c) Ah[c] = q[3 + c] + dq[3 + c];
@@ -325,6 +325,7 @@ __global__ void __launch_bounds__(256) k_finish(View<T> v) {
 #pragma unroll
   for (int c = 0; c < 6; ++c) finite = finite && isfinite(vw[c]);
   if (!finite) atomicOr(v.health + sc, 1);
+  pos_renorm(qf);
   store<T, QR>(v.qn + (size_t)QR * i, qf);
   store<T, VW>(v.vel + (size_t)VW * i, vw);
 }

@@ -38,7 +38,7 @@ __global__ void __launch_bounds__(TB) k_tile_step(View<T> v, TileTable tt) {
     T E[MAXE][EW];
     int part[MAXE];
     int e0 = 0, ne = 0, K = 0;
-    T ih = (T)1, h2 = (T)1;
+    T ih = (T)1;
     int debug = 0;
     if (present) {
       load<T, QR>(v.qn + (size_t)QR * i, q);
@@ -47,7 +47,6 @@ __global__ void __launch_bounds__(TB) k_tile_step(View<T> v, TileTable tt) {
       debug = S.debug;
       const T h = (T)S.h;
       ih = (T)(1.0 / S.h);
-      h2 = (T)(S.h * S.h);
       if (moving) {
         T vw[VW];
         load<T, VW>(v.vel + (size_t)VW * i, vw);
@@ -65,7 +64,7 @@ __global__ void __launch_bounds__(TB) k_tile_step(View<T> v, TileTable tt) {
         // prediction
 #pragma unroll
         for (int c = 0; c < QR; ++c) s[c] = q[c];
-        pos_add(s, h * (vw[0] + h * (T)S.g0), h * (vw[1] + h * (T)S.g1), h * (vw[2] + h * (T)S.g2));
+        pos_add_lo(s, h * (vw[0] + h * (T)S.g0), h * (vw[1] + h * (T)S.g1), h * (vw[2] + h * (T)S.g2));
         predict_rotation(q + 3, vw + 3, h, s + 3);
       }
     }
@@ -111,16 +110,16 @@ __global__ void __launch_bounds__(TB) k_tile_step(View<T> v, TileTable tt) {
           quad_end_force(Eg, d, f);
           add_JT(rb, Eg, f[0], f[1], f[2]);
         }
-        T r[QW];
+        T r[QW];  // the forces carry h^2 already
 #pragma unroll
-        for (int c = 0; c < QW; ++c) r[c] = h2 * rb[c];
+        for (int c = 0; c < QW; ++c) r[c] = rb[c];
         add_inertia(r, m, s, q);
         T dq[QW];
         block_apply(fac, r, dq);
         T qo[QR];
 #pragma unroll
         for (int c = 0; c < QR; ++c) qo[c] = q[c];
-        pos_add(qo, dq[0], dq[1], dq[2]);
+        pos_add_lo(qo, dq[0], dq[1], dq[2]);
         T Ah[9];
 #pragma unroll
         for (int c = 0; c < 9; ++c) Ah[c] = q[3 + c] + dq[3 + c];
@@ -151,6 +150,7 @@ __global__ void __launch_bounds__(TB) k_tile_step(View<T> v, TileTable tt) {
 #pragma unroll
       for (int c = 0; c < 6; ++c) finite = finite && isfinite(o[c]);
       if (!finite) atomicOr(v.health + scn, 1);
+      pos_renorm(q);
       store<T, QR>(v.qn + (size_t)QR * i, q);
       store<T, VW>(v.vel + (size_t)VW * i, o);
     }

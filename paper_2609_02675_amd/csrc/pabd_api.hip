@@ -67,6 +67,8 @@ struct EngineBase {
                                     std::vector<unsigned long long>& key,
                                     std::vector<double>& rec, hipStream_t st) = 0;
   virtual pabd_status snapshot(int n, std::vector<char>& buf, hipStream_t st, bool restore) = 0;
+  // raw q^n and velocity records of bodies [boff, boff + n) (read, or write back)
+  virtual pabd_status raw_bodies(int boff, int n, std::vector<char>& buf, hipStream_t st, bool write) = 0;
 };
 
 template <typename T>
@@ -185,6 +187,20 @@ struct EngineT final : EngineBase {
     if (hipStreamSynchronize(st) != hipSuccess) return fail(PABD_E_DEVICE, "stream sync failed");
     rec.resize(r.size());
     for (size_t k = 0; k < r.size(); ++k) rec[k] = (double)r[k];
+    return PABD_OK;
+  }
+  pabd_status raw_bodies(int boff, int n, std::vector<char>& buf, hipStream_t st, bool write) override {
+    const size_t bq = (size_t)Rec<T>::Q * n * sizeof(T), bv = (size_t)VW * n * sizeof(T);
+    T* dq = e.qn + (size_t)Rec<T>::Q * boff;
+    T* dv = e.vel + (size_t)VW * boff;
+    if (!write) buf.resize(bq + bv);
+    if (n <= 0) return PABD_OK;
+    hipError_t r1 = write ? hipMemcpyAsync(dq, buf.data(), bq, hipMemcpyHostToDevice, st)
+                          : hipMemcpyAsync(buf.data(), dq, bq, hipMemcpyDeviceToHost, st);
+    hipError_t r2 = write ? hipMemcpyAsync(dv, buf.data() + bq, bv, hipMemcpyHostToDevice, st)
+                          : hipMemcpyAsync(buf.data() + bq, dv, bv, hipMemcpyDeviceToHost, st);
+    if (r1 != hipSuccess || r2 != hipSuccess || hipStreamSynchronize(st) != hipSuccess)
+      return fail(PABD_E_DEVICE, "body record copy failed");
     return PABD_OK;
   }
   pabd_status snapshot(int n, std::vector<char>& buf, hipStream_t st, bool restore) override {
@@ -422,7 +438,7 @@ pabd_status pabd_scene_contacts(pabd_scene* s, int32_t cap, int32_t* ci, int32_t
       if (xj) xj[3 * k + d] = r[4 + d];
       if (normal) normal[3 * k + d] = r[8 + d];
     }
-    if (kappa) kappa[k] = r[3];
+    if (kappa) kappa[k] = r[3] / (s->hs.params.h * s->hs.params.h);  // records hold h^2 kappa_c
   }
   if (n_out) *n_out = (int32_t)all.size();
   return PABD_OK;
@@ -933,6 +949,14 @@ static pabd_status batch_repack(pabd_batch* b, int tile_bodies) {
     API_HIP(hipMemcpy(tab.data(), b->eng->scene_table(), tab.size() * sizeof(SceneDev), hipMemcpyDeviceToHost));
     for (int k : live) sc_steps[k] = tab[k].step;
   }
+  // the device records move bit for bit (an FP32 position is a (hi, lo) pair that
+  // a round trip through FP64 need not reproduce)
+  std::vector<std::vector<char>> raw(b->max_slots);
+  for (int k : live) {
+    Slot& s = b->slots[k];
+    pabd_status st = b->eng->raw_bodies(s.boff, s.n, raw[k], b->stream, false);
+    if (st != PABD_OK) return st;
+  }
   for (int k : live) {
     Slot& s = b->slots[k];
     HostScene& hs = *s.hs;
@@ -966,10 +990,11 @@ static pabd_status batch_repack(pabd_batch* b, int tile_bodies) {
     Slot& s = b->slots[k];
     pabd_status st = batch_place_and_upload(b, k);
     if (st != PABD_OK) return fail(PABD_E_OOM, "repack did not fit");
-    // restore the scene's step counter
+    // restore the scene's records and step counter
+    st = b->eng->raw_bodies(s.boff, s.n, raw[k], b->stream, true);
+    if (st != PABD_OK) return st;
     SceneDev* d = b->eng->scene_table() + k;
     API_HIP(hipMemcpy((char*)d + offsetof(SceneDev, step), &sc_steps[k], sizeof(int), hipMemcpyHostToDevice));
-    (void)s;
   }
   b->eng->factor(b->stream);
   API_HIP(hipStreamSynchronize(b->stream));
