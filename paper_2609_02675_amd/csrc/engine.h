@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <cstring>
 #include <string>
 #include <vector>
 
@@ -26,6 +27,28 @@ namespace pabd {
       return PABD_E_DEVICE;                                                \
     }                                                                      \
   } while (0)
+
+// one segment of a staged upload: bytes at src_off of the staging buffer go to dst
+struct Seg {
+  char* dst;
+  unsigned long long src_off, bytes;
+};
+
+// copy every segment of a staged upload to its destination (segment = blockIdx.y);
+// words where both ends are 4-byte aligned, bytes otherwise
+__global__ void __launch_bounds__(256) k_scatter(const char* src, const Seg* segs) {
+  const Seg sg = segs[blockIdx.y];
+  const char* s = src + sg.src_off;
+  const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
+  const unsigned long long t0 = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if ((((unsigned long long)sg.dst | sg.src_off | sg.bytes) & 3ull) == 0) {
+    const unsigned* w = reinterpret_cast<const unsigned*>(s);
+    unsigned* d = reinterpret_cast<unsigned*>(sg.dst);
+    for (unsigned long long k = t0; k < sg.bytes / 4; k += stride) d[k] = w[k];
+  } else {
+    for (unsigned long long k = t0; k < sg.bytes; k += stride) sg.dst[k] = s[k];
+  }
+}
 
 struct Caps {
   int n = 0, e = 0, s = 0, p = 0, dr = 0, ccap = 0;
@@ -73,11 +96,64 @@ struct Engine {
 
   std::vector<void*> allocs;
   std::string err;
+  // staged uploads: one pinned host buffer, one device buffer, grown on demand
+  char* h_stage = nullptr;
+  char* d_stage = nullptr;
+  size_t stage_cap = 0;
 
   ~Engine() { release(); }
   void release() {
     for (void* p : allocs) (void)hipFree(p);
     allocs.clear();
+    if (h_stage) (void)hipHostFree(h_stage);
+    if (d_stage) (void)hipFree(d_stage);
+    h_stage = d_stage = nullptr;
+    stage_cap = 0;
+  }
+
+  struct Put {
+    void* dst;
+    const void* src;
+    size_t bytes;
+  };
+
+  // every put in one host-to-device copy plus one scatter launch; returns when done
+  pabd_status staged_upload(const std::vector<Put>& puts, hipStream_t st) {
+    size_t total = 0;
+    std::vector<Seg> segs;
+    for (const Put& p : puts) {
+      if (!p.bytes) continue;
+      segs.push_back(Seg{static_cast<char*>(p.dst), (unsigned long long)total, (unsigned long long)p.bytes});
+      total += (p.bytes + 15) / 16 * 16;
+    }
+    if (segs.empty()) return PABD_OK;
+    const size_t need = total + segs.size() * sizeof(Seg);
+    if (need > stage_cap) {
+      size_t cap2 = std::max<size_t>(need, std::max<size_t>(2 * stage_cap, 1 << 20));
+      if (h_stage) (void)hipHostFree(h_stage);
+      if (d_stage) (void)hipFree(d_stage);
+      h_stage = d_stage = nullptr;
+      stage_cap = 0;
+      PABD_HIP(hipHostMalloc(reinterpret_cast<void**>(&h_stage), cap2, hipHostMallocDefault));
+      PABD_HIP(hipMalloc(reinterpret_cast<void**>(&d_stage), cap2));
+      stage_cap = cap2;
+    }
+    size_t k = 0;
+    for (const Put& p : puts) {
+      if (!p.bytes) continue;
+      std::memcpy(h_stage + segs[k].src_off, p.src, p.bytes);
+      ++k;
+    }
+    std::memcpy(h_stage + total, segs.data(), segs.size() * sizeof(Seg));
+    PABD_HIP(hipMemcpyAsync(d_stage, h_stage, need, hipMemcpyHostToDevice, st));
+    size_t largest = 0;
+    for (const Seg& g : segs) largest = std::max<size_t>(largest, g.bytes);
+    const unsigned gx = (unsigned)std::min<size_t>(1024, std::max<size_t>(1, (largest / 4 + 255) / 256));
+    hipLaunchKernelGGL(k_scatter, dim3(gx, (unsigned)segs.size()), dim3(256), 0, st, (const char*)d_stage,
+                       reinterpret_cast<const Seg*>(d_stage + total));
+    PABD_HIP(hipGetLastError());
+    PABD_HIP(hipStreamSynchronize(st));
+    return PABD_OK;
   }
 
   template <typename U>
@@ -259,39 +335,41 @@ struct Engine {
     S.body_off = boff;
     S.plane_off = poff;
     S.step = 0;
-    // the same staging vectors are used by asynchronous copies: finish them here
-    PABD_TRY(put(qn + QR * (size_t)boff, tq.data(), tq.size(), st));
-    PABD_TRY(put(vel + VW * (size_t)boff, tv.data(), tv.size(), st));
-    PABD_TRY(put(mass + MW * (size_t)boff, tm.data(), tm.size(), st));
-    PABD_TRY(put(mass64 + 8 * (size_t)boff, hs.mass64.data(), hs.mass64.size(), st));
-    PABD_TRY(put(half + 4 * (size_t)boff, th.data(), th.size(), st));
-    PABD_TRY(put(flags + boff, fl.data(), fl.size(), st));
-    PABD_TRY(put(shape + boff, hs.shape.data(), hs.shape.size(), st));
-    PABD_TRY(put(group + boff, hs.group.data(), hs.group.size(), st));
-    PABD_TRY(put(bscene + boff, bs.data(), bs.size(), st));
-    PABD_TRY(put(srow + boff, rows.data(), rows.size(), st));
-    PABD_TRY(put(srow_end + boff, rows_end.data(), rows_end.size(), st));
-    PABD_TRY(put(se_partner + eoff, part.data(), part.size(), st));
-    PABD_TRY(put(se + EW * (size_t)eoff, te.data(), te.size(), st));
-    PABD_TRY(put(se64 + 4 * (size_t)eoff, hs.se64.data(), hs.se64.size(), st));
-    PABD_TRY(put(planes + 4 * (size_t)poff, hs.planes.data(), hs.planes.size(), st));
-    PABD_TRY(put(scenes + sidx, &S, 1, st));
+    std::vector<Put> puts;
+    auto add = [&](auto* dst, const auto* src, size_t count) {
+      puts.push_back(Put{dst, src, count * sizeof(*src)});
+    };
+    add(qn + QR * (size_t)boff, tq.data(), tq.size());
+    add(vel + VW * (size_t)boff, tv.data(), tv.size());
+    add(mass + MW * (size_t)boff, tm.data(), tm.size());
+    add(mass64 + 8 * (size_t)boff, hs.mass64.data(), hs.mass64.size());
+    add(half + 4 * (size_t)boff, th.data(), th.size());
+    add(flags + boff, fl.data(), fl.size());
+    add(shape + boff, hs.shape.data(), hs.shape.size());
+    add(group + boff, hs.group.data(), hs.group.size());
+    add(bscene + boff, bs.data(), bs.size());
+    add(srow + boff, rows.data(), rows.size());
+    add(srow_end + boff, rows_end.data(), rows_end.size());
+    add(se_partner + eoff, part.data(), part.size());
+    add(se + EW * (size_t)eoff, te.data(), te.size());
+    add(se64 + 4 * (size_t)eoff, hs.se64.data(), hs.se64.size());
+    add(planes + 4 * (size_t)poff, hs.planes.data(), hs.planes.size());
+    add(scenes + sidx, &S, 1);
     int zero = 0;
-    PABD_TRY(put(health + sidx, &zero, 1, st));
-    if (!hs.drv_end_i.empty()) {
-      const size_t nd = hs.drv_end_i.size();
-      std::vector<int> di(nd), dj(nd), ds(nd, sidx);
-      for (size_t k = 0; k < nd; ++k) {
-        di[k] = hs.drv_end_i[k] < 0 ? -1 : hs.drv_end_i[k] + eoff;
-        dj[k] = hs.drv_end_j[k] < 0 ? -1 : hs.drv_end_j[k] + eoff;
-      }
-      PABD_TRY(put(drv_scene + doff, ds.data(), nd, st));
-      PABD_TRY(put(drv_end_i + doff, di.data(), nd, st));
-      PABD_TRY(put(drv_end_j + doff, dj.data(), nd, st));
-      PABD_TRY(put(drv_param + 13 * (size_t)doff, hs.drv_param.data(), hs.drv_param.size(), st));
+    add(health + sidx, &zero, 1);
+    const size_t nd = hs.drv_end_i.size();
+    std::vector<int> di(nd), dj(nd), ds(nd, sidx);
+    for (size_t k = 0; k < nd; ++k) {
+      di[k] = hs.drv_end_i[k] < 0 ? -1 : hs.drv_end_i[k] + eoff;
+      dj[k] = hs.drv_end_j[k] < 0 ? -1 : hs.drv_end_j[k] + eoff;
     }
-    PABD_HIP(hipStreamSynchronize(st));
-    return PABD_OK;
+    if (nd) {
+      add(drv_scene + doff, ds.data(), nd);
+      add(drv_end_i + doff, di.data(), nd);
+      add(drv_end_j + doff, dj.data(), nd);
+      add(drv_param + 13 * (size_t)doff, hs.drv_param.data(), hs.drv_param.size());
+    }
+    return staged_upload(puts, st);
   }
 
   // mark body slots [boff, boff + n) and driven entries [doff, doff + nd) unused

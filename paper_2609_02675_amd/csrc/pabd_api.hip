@@ -536,6 +536,17 @@ struct pabd_batch {
   bool any_stream = false, any_contact = false;
   int stream_kmax = 0, n_driven_hi = 0;
   int stream_hi = 0;  // one past the highest flat-path body in use
+  // launch extents, rounded so that most admissions and releases leave them
+  // (and so the captured step graph) unchanged; kernels skip unused slots
+  struct Launch {
+    int stream_n = 0, driven_n = 0, grid = 0, kmax = 0, tile = 0;
+    bool stream = false, contact = false;
+    const int* table = nullptr;
+    bool operator==(const Launch& o) const {
+      return stream_n == o.stream_n && driven_n == o.driven_n && grid == o.grid && kmax == o.kmax &&
+             tile == o.tile && stream == o.stream && contact == o.contact && table == o.table;
+    }
+  } launch;
 };
 
 namespace {
@@ -593,20 +604,34 @@ pabd_status batch_tables(pabd_batch* b) {
     if (s.nd > 0) b->n_driven_hi = std::max(b->n_driven_hi, s.doff + s.nd);
     b->stream_hi = std::max(b->stream_hi, s.boff + std::max(1, s.n));
   }
+  auto round_up = [](int x, int q, int cap) { return std::min(cap, (x + q - 1) / q * q); };
+  pabd_batch::Launch L;
+  L.stream = b->any_stream;
+  L.contact = b->any_contact;
+  L.kmax = b->stream_kmax;
+  L.stream_n = b->any_stream ? round_up(b->stream_hi, 16384, b->n_stream) : 0;
+  L.driven_n = b->n_driven_hi > 0 ? round_up(b->n_driven_hi, 256, b->caps.dr) : 0;
+  L.grid = b->grid_tiles > 0 ? round_up(b->grid_tiles, 256, INT_MAX) : 0;
+  L.tile = b->tile_bodies;
+  L.table = b->d_first;
+  if (!(L == b->launch)) {
+    b->launch = L;
+    b->graph.reset();
+  }
   return PABD_OK;
 }
 
 void batch_enqueue(pabd_batch* b, hipStream_t st) {
-  if (b->any_stream)
-    b->eng->flat_step(0, b->stream_hi, b->max_slots, b->stream_kmax, b->any_contact, b->n_driven_hi,
-                      false, false, st);
-  if (b->grid_tiles > 0) {
+  const pabd_batch::Launch& L = b->launch;
+  if (L.stream)
+    b->eng->flat_step(0, L.stream_n, b->max_slots, L.kmax, L.contact, L.driven_n, false, false, st);
+  if (L.grid > 0) {
     TileTable tt{b->d_first, b->d_count, b->d_kmax, b->d_ntiles};
-    b->eng->tile_step(b->tile_bodies, tt, b->grid_tiles, st);
+    b->eng->tile_step(L.tile, tt, L.grid, st);
   }
   // scenes on the flat path: residual reduction and step counters (tiled
   // scenes do both inside the tile kernel)
-  if (b->any_stream) b->eng->finish_scenes(b->max_slots, st);
+  if (L.stream) b->eng->finish_scenes(b->max_slots, st);
 }
 
 pabd_status place_tiled(pabd_batch* b, int slot, int n) {
@@ -866,10 +891,9 @@ pabd_status pabd_batch_release(pabd_batch* b, int32_t slot) {
 pabd_status pabd_batch_step(pabd_batch* b, void* hip_stream) {
   if (!b) return fail(PABD_E_INVALID, "null batch");
   hipStream_t st = hip_stream ? (hipStream_t)hip_stream : b->stream;
-  if (b->dirty) {
+  if (b->dirty) {  // new tables; the graph is rebuilt only if the launch extents changed
     pabd_status s2 = batch_tables(b);
     if (s2 != PABD_OK) return s2;
-    b->graph.reset();
     b->dirty = false;
   }
   if (use_graphs()) {
@@ -1008,7 +1032,6 @@ pabd_status pabd_batch_time_tile_kernel(pabd_batch* b, int32_t reps, double* avg
   if (b->dirty) {
     pabd_status s2 = batch_tables(b);
     if (s2 != PABD_OK) return s2;
-    b->graph.reset();
     b->dirty = false;
   }
   if (b->grid_tiles == 0) return PABD_OK;
