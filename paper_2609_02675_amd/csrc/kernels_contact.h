@@ -496,19 +496,43 @@ __device__ void narrow_pair(const View<T>& v, const ContactBuf& cb, int sc, int 
 
 // ---- broad phase ---------------------------------------------------------------
 
-// Append candidate pair (i, j), i < j, to the pair list.  Called by any subset of
-// a wavefront's lanes: one atomic per wavefront and call site.
-__device__ __forceinline__ void append_pair(const ContactBuf& cb, int* health, int sc, int i, int j) {
-  const unsigned long long m = __ballot(1);
-  const int lane = __lane_id();
-  const int leader = __ffsll((long long)m) - 1;
-  const int rank = __popcll(m & ((1ull << lane) - 1ull));
-  int base = 0;
-  if (lane == leader) base = atomicAdd(cb.counters + 1, __popcll(m));
-  base = __shfl(base, leader);
-  const int slot = base + rank;
+// Candidate pairs of one workgroup, gathered in LDS (one LDS atomic per pair) and
+// appended to the global list with one global atomic per workgroup; a pair that
+// does not fit the LDS buffer goes straight to the global list.
+constexpr int PAIR_LDS = 2048;
+
+struct PairBuf {
+  int2* buf;  // [PAIR_LDS] in LDS
+  int* count;
+  int* base;
+};
+
+__device__ __forceinline__ void global_pair(const ContactBuf& cb, int* health, int sc, int i, int j) {
+  const int slot = atomicAdd(cb.counters + 1, 1);
   if (slot < cb.pcap) cb.pairs[slot] = make_int2(i, j);
   else atomicOr(health + sc, 2);
+}
+
+__device__ __forceinline__ void append_pair(const PairBuf& pb, const ContactBuf& cb, int* health, int sc,
+                                            int i, int j) {
+  const int k = atomicAdd(pb.count, 1);
+  if (k < PAIR_LDS) pb.buf[k] = make_int2(i, j);
+  else global_pair(cb, health, sc, i, j);
+}
+
+// every thread of the workgroup calls this once, after its last append
+template <typename T>
+__device__ __forceinline__ void flush_pairs(const PairBuf& pb, const View<T>& v, const ContactBuf& cb) {
+  __syncthreads();
+  const int n = min(*pb.count, PAIR_LDS);
+  if (threadIdx.x == 0) *pb.base = n > 0 ? atomicAdd(cb.counters + 1, n) : 0;
+  __syncthreads();
+  const int base = *pb.base;
+  for (int k = threadIdx.x; k < n; k += blockDim.x) {
+    const int2 pr = pb.buf[k];
+    if (base + k < cb.pcap) cb.pairs[base + k] = pr;
+    else atomicOr(v.health + v.bscene[pr.x], 2);
+  }
 }
 
 // conservative bounding-sphere test (the narrow phase repeats it exactly)
@@ -586,45 +610,57 @@ constexpr int BLPB = 1;
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_broad_small(View<T> v, ContactBuf cb) {
+  __shared__ int2 lbuf[PAIR_LDS];
+  __shared__ int lcount, lbase;
+  if (threadIdx.x == 0) lcount = 0;
+  __syncthreads();
+  const PairBuf pb{lbuf, &lcount, &lbase};
   const long long gt = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const int i = (int)(gt / BLPB), sub = (int)(gt % BLPB);
-  if (i >= v.n) return;
-  const int sc = v.bscene[i];
-  if (!contact_body(v, i, sc)) return;
-  const SceneDev& S = v.scenes[sc];
-  const bool pin_i = (v.flags[i] & F_PINNED) != 0;
-  if (sub == 0 && !pin_i && S.n_planes > 0) {
-    BodyGeo<T> gi;
-    body_geo(v, i, gi);
-    plane_contacts(v, cb, sc, i, gi, own_pm(v, i, sc, gi));
-  }
-  if (is_large(v, cb, i, sc)) return;
-  double c[3];
-  int cc[3];
-  centre_of(v, i, c);
-  cell_of_pos(c, S.cell, cc);
-  const double ri = cb.breach[i];
-  const int group_i = v.group[i];
-  for (int t = 13 + sub; t < 27; t += BLPB) {  // offset t: own cell (13), then forward half
-    const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = t / 9 - 1;
-    const int tx = cc[0] + dx, ty = cc[1] + dy, tz = cc[2] + dz;
-    const unsigned long long key = pack_cell(tx, ty, tz);
-    const unsigned b = bucket_of(sc, tx, ty, tz, cb.tb);
-    const int e1 = cb.bucket_start[b + 1];
-    for (int e = cb.bucket_start[b]; e < e1; ++e) {
-      const BroadRec r = cb.rec[e];
-      if (r.cell != key || r.scene != sc || (t == 13 && r.body <= i)) continue;
-      if (!near_rec(c, ri, r)) continue;
-      const int j = r.body;
-      if (!pair_allowed(pin_i, group_i, v.flags[j], v.group[j])) continue;
-      append_pair(cb, v.health, sc, min(i, j), max(i, j));
+  const int sc = i < v.n ? v.bscene[i] : -1;
+  if (i < v.n && contact_body(v, i, sc)) {
+    const SceneDev& S = v.scenes[sc];
+    const bool pin_i = (v.flags[i] & F_PINNED) != 0;
+    if (sub == 0 && !pin_i && S.n_planes > 0) {
+      BodyGeo<T> gi;
+      body_geo(v, i, gi);
+      plane_contacts(v, cb, sc, i, gi, own_pm(v, i, sc, gi));
+    }
+    if (!is_large(v, cb, i, sc)) {
+      double c[3];
+      int cc[3];
+      centre_of(v, i, c);
+      cell_of_pos(c, S.cell, cc);
+      const double ri = cb.breach[i];
+      const int group_i = v.group[i];
+      for (int t = 13 + sub; t < 27; t += BLPB) {  // offset t: own cell (13), then forward half
+        const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = t / 9 - 1;
+        const int tx = cc[0] + dx, ty = cc[1] + dy, tz = cc[2] + dz;
+        const unsigned long long key = pack_cell(tx, ty, tz);
+        const unsigned b = bucket_of(sc, tx, ty, tz, cb.tb);
+        const int e1 = cb.bucket_start[b + 1];
+        for (int e = cb.bucket_start[b]; e < e1; ++e) {
+          const BroadRec r = cb.rec[e];
+          if (r.cell != key || r.scene != sc || (t == 13 && r.body <= i)) continue;
+          if (!near_rec(c, ri, r)) continue;
+          const int j = r.body;
+          if (!pair_allowed(pin_i, group_i, v.flags[j], v.group[j])) continue;
+          append_pair(pb, cb, v.health, sc, min(i, j), max(i, j));
+        }
+      }
     }
   }
+  flush_pairs(pb, v, cb);
 }
 
 // one workgroup per large body (grid-stride over the large list)
 template <typename T>
 __global__ void __launch_bounds__(256) k_broad_large(View<T> v, ContactBuf cb) {
+  __shared__ int2 lbuf[PAIR_LDS];
+  __shared__ int lcount, lbase;
+  if (threadIdx.x == 0) lcount = 0;
+  __syncthreads();
+  const PairBuf pb{lbuf, &lcount, &lbase};
   const int nl = cb.counters[0];
   for (int l = blockIdx.x; l < nl; l += gridDim.x) {
     const int L = cb.large[l];
@@ -656,7 +692,7 @@ __global__ void __launch_bounds__(256) k_broad_large(View<T> v, ContactBuf cb) {
           if (r.cell != key || r.scene != sc) continue;
           if (!near_rec(c, rL, r)) continue;
           if (!pair_allowed(pin_L, group_L, v.flags[r.body], v.group[r.body])) continue;
-          append_pair(cb, v.health, sc, min(L, r.body), max(L, r.body));
+          append_pair(pb, cb, v.health, sc, min(L, r.body), max(L, r.body));
         }
       }
     }
@@ -669,9 +705,10 @@ __global__ void __launch_bounds__(256) k_broad_large(View<T> v, ContactBuf cb) {
       if (!pair_allowed(pin_L, group_L, v.flags[j], v.group[j])) continue;
       double cj[3];
       centre_of(v, j, cj);
-      if (spheres_near(c, rL, cj, cb.breach[j])) append_pair(cb, v.health, sc, min(L, j), max(L, j));
+      if (spheres_near(c, rL, cj, cb.breach[j])) append_pair(pb, cb, v.health, sc, min(L, j), max(L, j));
     }
   }
+  flush_pairs(pb, v, cb);
 }
 
 // one thread per candidate pair (grid-stride)
