@@ -34,11 +34,12 @@ FP32_VALU_PEAK = 78.6e12     # flop/s: 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.
 # algorithmic bytes moved per body and step by the tile kernel: read q (16 floats:
 # c_hi, A, c_lo), v/w (8), mass (8), H^-1 factor (12), two bond ends (8 floats +
 # partner id each), scene id, flags, end range; write q, v/w and the two FP64
-# residual partials -- see the design doc
+# residual partials
 TILE_BYTES_PER_BODY_STEP = 64 + 32 + 32 + 48 + 2 * (32 + 4) + 4 + 1 + 8 + 64 + 32 + 16
-# flops of one body-iteration of a two-bond chain body (bond terms, inertia
-# term, block solve, increment, three Newton polar steps) -- see the design doc
-FLOPS_PER_BODY_ITER = 2 * 63 + 81 + 84 + 12 + 3 * 90
+# flops of one body-iteration of a two-bond chain body: bond terms (2 x 63),
+# inertia term (81), block solve (84), increment (12), two Newton polar steps
+# (2 x 90; FP32 converges in two from a near-rotation)
+FLOPS_PER_BODY_ITER = 2 * 63 + 81 + 84 + 12 + 2 * 90
 # bytes per body-iteration a streaming (one launch per iteration) sweep must move:
 # read q^k, s, mass, factor, two bond ends; write q^{k+1}
 STREAM_BYTES_PER_BODY_ITER = 64 + 64 + 32 + 48 + 2 * (32 + 4) + 64
@@ -108,6 +109,99 @@ def cpu_baseline(scenes, n_sample, steps, cores):
                        f"({body_its:.3g} body-iterations, {wall:.1f} s wall)")
 
 
+def host_info():
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return dict(logical_cpus=os.cpu_count(), model=model)
+
+
+def big_batch_leg(P, S, torch, n_scenes, steps):
+    """The batched chains at 16x the default count (about 2.2M bodies, a working
+    set well beyond the 256 MB last-level cache), tile 64, FP32."""
+    import oracle
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from parity import errors, scale_of
+    t = time.perf_counter()
+    scs = S.batched_chains(n_scenes, seed=2, precision=S.PREC_FP32)
+    nb = sum(x.n_bodies for x in scs)
+    b = P.Batch(n_scenes + 8, 16 << 30, S.PREC_FP32)
+    slots = [b.admit(x, 1 << 30) for x in scs]
+    assert all(x is not None for x in slots)
+    b.set_tile(64)
+    log(f"big batch: {n_scenes} scenes, {nb} bodies admitted in {time.perf_counter() - t:.1f}s")
+    stream = torch.cuda.Stream()
+    sptr = stream.cuda_stream
+    warm = 2
+    for _ in range(warm):
+        b.step(stream=sptr)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(steps):
+        b.step(stream=sptr)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    iters = scs[0].iters
+    tile_ms = b.time_tile_kernel(5)
+    flops = nb * iters * FLOPS_PER_BODY_ITER
+    byts = nb * TILE_BYTES_PER_BODY_STEP
+    acc = 0.0
+    for k in (0, n_scenes // 2, n_scenes - 1):
+        o = oracle.Oracle(scs[k].copy(precision=S.PREC_FP64))
+        o.step(warm + steps + 6)  # time_tile_kernel advanced every scene 1 + 5 steps
+        e = errors(b.state(slots[k]), o.state(), scale_of(scs[k]))
+        acc = max(acc, e["pos"], e["rot"])
+    b.close()
+    out = dict(scenes=n_scenes, bodies=nb, iters=iters, ms_per_step=ms,
+               body_its_per_s=nb * iters / (ms / 1e3), tile_kernel_ms=tile_ms,
+               alu_frac=flops / (tile_ms / 1e3) / FP32_VALU_PEAK,
+               hbm_GBs_algorithmic=byts / (tile_ms / 1e3) / 1e9,
+               working_set_bytes=nb * TILE_BYTES_PER_BODY_STEP,
+               max_rel_err_vs_fp64_oracle=acc, tile_bodies=64)
+    log("big batch", out)
+    return out
+
+
+def oracle_single_core(S, drop_state=None):
+    """The FP64 oracle, one thread, on the single-scene workloads: the 8-chain
+    (100 steps), the 1,000-box drop (5 steps with contacts active, from the
+    oracle's own state at step 60) and the granular bed with the robot (1 step)."""
+    import oracle
+    out = {}
+    sc = S.chain8(precision=S.PREC_FP64)
+    o = oracle.Oracle(sc)
+    t = time.perf_counter()
+    o.step(100)
+    dt = time.perf_counter() - t
+    out["chain8"] = dict(body_its_per_s=sc.n_bodies * sc.iters * 100 / dt, steps=100, seconds=dt)
+    drop = S.box_drop(precision=S.PREC_FP64)
+    if drop_state is not None:
+        drop = drop.with_state(*drop_state, t0=60 * drop.h)
+    o = oracle.Oracle(drop)
+    t = time.perf_counter()
+    o.step(5)
+    dt = time.perf_counter() - t
+    out["box_drop_1000"] = dict(body_its_per_s=drop.n_bodies * drop.iters * 5 / dt, steps=5,
+                                seconds=dt, start="step 60" if drop_state is not None else "step 0")
+    bed = S.granular_bed_quadruped(precision=S.PREC_FP64)
+    o = oracle.Oracle(bed)
+    t = time.perf_counter()
+    o.step(1)
+    dt = time.perf_counter() - t
+    out["granular_bed_quadruped"] = dict(body_its_per_s=bed.n_bodies * bed.iters / dt, steps=1, seconds=dt)
+    out["threads"] = 1
+    log("oracle single core", out)
+    return out
+
+
 # ---------------------------------------------------------------------------
 
 def main():
@@ -128,6 +222,10 @@ def main():
     ap.add_argument("--serve-budget-gib", type=float, default=8.0)
     ap.add_argument("--no-scenes", action="store_true",
                     help="skip the single-scene legs (1,000-box drop, granular bed)")
+    ap.add_argument("--big-scenes", type=int, default=65536,
+                    help="scenes in the cache-exceeding batched leg (0 = skip)")
+    ap.add_argument("--no-oracle-single", action="store_true",
+                    help="skip the single-core oracle timings of the single-scene workloads")
     ap.add_argument("--probe-only", action="store_true",
                     help="run only the 1 GiB HBM copy probe (counter calibration)")
     args = ap.parse_args()
@@ -331,6 +429,20 @@ def main():
             steps_timed="2..6", contacts_after=int(len(ct["i"])))
         log(f"granular bed: {rate:.3g} body-it/s, {ms:.3f} ms/step")
 
+    # the batched chains at 16x the count: a working set beyond the last-level cache
+    big = None
+    if args.big_scenes > 0:
+        del b
+        big = big_batch_leg(P, S, torch, args.big_scenes, 5)
+
+    oracle_1core = None
+    if not args.no_oracle_single:
+        oracle_1core = oracle_single_core(S, None if args.no_scenes else (c, A, v, w))
+    if cpu is not None:
+        cpu["host"] = host_info()
+        if oracle_1core is not None:
+            cpu["single_core_single_scene"] = oracle_1core
+
     out = {
         "metric": METRIC,
         "value": value,
@@ -361,6 +473,7 @@ def main():
         "served_saturated": served_sat,
         "roofline": roof,
         "single_scene": scene_legs,
+        "batched_beyond_cache": big,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

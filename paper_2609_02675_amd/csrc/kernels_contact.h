@@ -633,13 +633,25 @@ __global__ void __launch_bounds__(256) k_broad_small(View<T> v, ContactBuf cb) {
       cell_of_pos(c, S.cell, cc);
       const double ri = cb.breach[i];
       const int group_i = v.group[i];
-      for (int t = 13 + sub; t < 27; t += BLPB) {  // offset t: own cell (13), then forward half
-        const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = t / 9 - 1;
-        const int tx = cc[0] + dx, ty = cc[1] + dy, tz = cc[2] + dz;
+      // the 14 bucket ranges first, so that their loads are in flight together
+      constexpr int NC = (14 + BLPB - 1) / BLPB;
+      int e0s[NC], e1s[NC];
+#pragma unroll
+      for (int u = 0; u < NC; ++u) {
+        const int t = 13 + sub + u * BLPB;
+        e0s[u] = e1s[u] = 0;
+        if (t < 27) {
+          const unsigned b = bucket_of(sc, cc[0] + t % 3 - 1, cc[1] + (t / 3) % 3 - 1, cc[2] + t / 9 - 1, cb.tb);
+          e0s[u] = cb.bucket_start[b];
+          e1s[u] = cb.bucket_start[b + 1];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < NC; ++u) {  // offset t: own cell (13), then forward half
+        const int t = 13 + sub + u * BLPB;
+        const int tx = cc[0] + t % 3 - 1, ty = cc[1] + (t / 3) % 3 - 1, tz = cc[2] + t / 9 - 1;
         const unsigned long long key = pack_cell(tx, ty, tz);
-        const unsigned b = bucket_of(sc, tx, ty, tz, cb.tb);
-        const int e1 = cb.bucket_start[b + 1];
-        for (int e = cb.bucket_start[b]; e < e1; ++e) {
+        for (int e = e0s[u]; e < e1s[u]; ++e) {
           const BroadRec r = cb.rec[e];
           if (r.cell != key || r.scene != sc || (t == 13 && r.body <= i)) continue;
           if (!near_rec(c, ri, r)) continue;
