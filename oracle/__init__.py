@@ -18,7 +18,9 @@ LIB_PATH = os.path.join(_HERE, "libpabd_oracle.so")
 
 def build(force: bool = False) -> str:
     """Compile the oracle with gcc (plain C11, -O2, no fast-math)."""
-    if force or not os.path.exists(LIB_PATH):
+    stale = not os.path.exists(LIB_PATH) or any(
+        os.path.getmtime(src) > os.path.getmtime(LIB_PATH) for src in (_SRC, _SRC[:-2] + ".h"))
+    if force or stale:
         tmp = LIB_PATH + f".tmp{os.getpid()}"
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, LIB_PATH)
@@ -62,6 +64,7 @@ def lib():
         L.pabd_oracle_dense_H.argtypes = [C.c_void_p, C.c_int32, _d]
         L.pabd_oracle_contacts.argtypes = [C.c_void_p, C.c_int32, _i, _i, _i, _d, _d, _d, _d]
         L.pabd_oracle_detect.argtypes = [C.c_void_p]
+        L.pabd_oracle_detect_body.argtypes = [C.c_void_p, C.c_int32]
         _lib = L
     return _lib
 
@@ -165,6 +168,14 @@ class Oracle:
 
     def detect(self) -> int:
         return int(lib().pabd_oracle_detect(self._h))
+
+    def detect_body(self, body: int) -> int:
+        """Contacts involving one body on the current state (O(N)); read them with
+        contacts().  Replaces the stored contact set."""
+        n = int(lib().pabd_oracle_detect_body(self._h, int(body)))
+        if n < 0:
+            raise IndexError(body)
+        return n
 
     def contacts(self):
         """Contact bonds of the last detection: dict of arrays."""

@@ -818,6 +818,25 @@ int pabd_oracle_detect(pabd_oracle *o) {
   return o->n_contacts;
 }
 
+/* the contacts of one body on the current state, by the same rule: its plane
+ * contacts and every pair (lower index first) that contains it, against all
+ * other bodies -- O(N), for sampled checks of large scenes */
+int pabd_oracle_detect_body(pabd_oracle *o, int32_t body) {
+  if (body < 0 || body >= o->n) return -1;
+  o->n_bonds = 0;
+  o->n_contacts = 0;
+  for (int e = 0; e < o->n_static; ++e) push_bond(o, &o->static_bonds[e]);
+  if (!o->contact_enable) return 0;
+  const int i = body;
+  if (!pinned(o, i) && !(o->flags[i] & ORACLE_FLAG_NO_CONTACT)) detect_planes(o, i);
+  for (int j = 0; j < o->n; ++j) {
+    if (j == i) continue;
+    const int a = i < j ? i : j, b = i < j ? j : i;
+    if (may_collide(o, a, b)) detect_pair(o, a, b);
+  }
+  return o->n_contacts;
+}
+
 /* world point of a bond end at iterate q (all bodies, 12 per body) */
 static void end_point(const double *q, int body, const double *x, double *y) {
   if (body < 0) {

@@ -101,6 +101,10 @@ int pabd_oracle_contacts(const pabd_oracle *o, int32_t cap, int32_t *ci, int32_t
 /* build the contact set of the current state without stepping (same rule) */
 int pabd_oracle_detect(pabd_oracle *o);
 
+/* only the contacts that involve one body (its planes and its pairs), same rule;
+ * replaces the stored contact set; -1 for a bad index */
+int pabd_oracle_detect_body(pabd_oracle *o, int32_t body);
+
 #ifdef __cplusplus
 }
 #endif

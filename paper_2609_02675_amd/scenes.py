@@ -336,6 +336,40 @@ def pile(n: int, seed: int, precision: int = PREC_FP32, iters: int = 30) -> Scen
                      name=f"pile{n}_s{seed}")
 
 
+def block_pile(n_side: int = 50, layers: int = 50, size: float = 1.0, gap: float = 1e-3,
+               seed: int = 0, mu: float = 0.5, iters: int = 20, tilt_deg: float = 0.5,
+               precision: int = PREC_FP32) -> SceneDesc:
+    """n_side x n_side x layers cubes of side `size` (density 1000) stacked on the
+    plane y = 0 with `gap` between neighbours, each turned by a seeded random angle
+    below `tilt_deg` about a random axis (so faces are not exactly parallel), at
+    rest: every cube starts in resting contact with its neighbours.  50^3 = 125,000
+    cubes stand in for the paper's 50^3 block pile (Table 2)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    sp = size + gap
+    ix, iy, iz = np.meshgrid(np.arange(n_side), np.arange(layers), np.arange(n_side), indexing="ij")
+    grid = np.stack([ix.ravel(), iy.ravel(), iz.ravel()], axis=1).astype(np.float64)
+    n = grid.shape[0]
+    bd = _bodies(n)
+    bd["shape"][:] = SHAPE_BOX
+    bd["shape_param"][:] = size / 2
+    bd["density"][:] = 1000.0
+    bd["c0"][:, 0] = (grid[:, 0] - (n_side - 1) / 2) * sp
+    bd["c0"][:, 1] = size / 2 + gap + grid[:, 1] * sp
+    bd["c0"][:, 2] = (grid[:, 2] - (n_side - 1) / 2) * sp
+    axes = rng.normal(size=(n, 3))
+    axes /= np.linalg.norm(axes, axis=1, keepdims=True)
+    ang = np.radians(tilt_deg) * rng.uniform(0.0, 1.0, size=n)
+    K = np.zeros((n, 3, 3))
+    K[:, 0, 1], K[:, 0, 2], K[:, 1, 2] = -axes[:, 2], axes[:, 1], -axes[:, 0]
+    K[:, 1, 0], K[:, 2, 0], K[:, 2, 1] = axes[:, 2], -axes[:, 1], axes[:, 0]
+    sa, ca = np.sin(ang)[:, None, None], np.cos(ang)[:, None, None]
+    bd["A0"][:] = np.eye(3)[None] + sa * K + (1 - ca) * (K @ K)  # Rodrigues
+    return SceneDesc(**bd, **_empty_bonds(0), iters=iters, contact_enable=1, mu=mu,
+                     contact_kappa_scale=0.3, contact_margin=0.01,
+                     planes=np.array([[0.0, 1.0, 0.0, 0.0]]), precision=precision,
+                     max_contacts_per_body=96, name=f"blockpile{n}")
+
+
 def serving_requests(rate_hz: float = 200.0, duration_s: float = 60.0, seed: int = 3,
                      n_lo: int = 8, n_hi: int = 5000, steps_lo: int = 60, steps_hi: int = 600,
                      precision: int = PREC_FP32, max_requests: Optional[int] = None) -> List[Request]:

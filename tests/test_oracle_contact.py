@@ -140,3 +140,23 @@ def test_mass_ratio_stack_is_stable():
     assert np.all(np.diff(c[:, 1]) > 0.8)
     assert np.abs(c[:, [0, 2]]).max() < 1e-6
     assert c[0, 1] > 0.4
+
+
+def test_per_body_detection_is_the_full_detection_restricted_to_the_body():
+    """The O(N) per-body query (used for sampled parity on large scenes) must
+    return exactly the full brute-force contacts that involve the body."""
+    sc = S.block_pile(n_side=4, layers=3, precision=S.PREC_FP64, tilt_deg=3.0)
+    o = oracle.Oracle(sc)
+    o.detect()
+    full = o.contacts()
+    assert len(full["i"]) > 0
+    for b in range(sc.n_bodies):
+        o.detect_body(b)
+        mine = o.contacts()
+        sel = (full["i"] == b) | (full["j"] == b)
+        key_full = sorted(zip(full["i"][sel], full["j"][sel], full["feature"][sel]))
+        key_mine = sorted(zip(mine["i"], mine["j"], mine["feature"]))
+        assert key_full == key_mine
+        order_f = np.lexsort((full["feature"][sel], full["j"][sel], full["i"][sel]))
+        order_m = np.lexsort((mine["feature"], mine["j"], mine["i"]))
+        np.testing.assert_array_equal(full["x_j"][sel][order_f], mine["x_j"][order_m])
