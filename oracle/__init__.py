@@ -41,6 +41,7 @@ class _Desc(C.Structure):
         ("gravity", C.c_double * 3), ("h", C.c_double), ("t0", C.c_double), ("iters", C.c_int32),
         ("contact_enable", C.c_int32), ("mu", C.c_double), ("contact_kappa_scale", C.c_double),
         ("contact_margin", C.c_double), ("n_planes", C.c_int32), ("planes", _d),
+        ("al_beta", C.c_double), ("al_alpha", C.c_double), ("al_gamma", C.c_double),
     ]
 
 
@@ -65,6 +66,7 @@ def lib():
         L.pabd_oracle_contacts.argtypes = [C.c_void_p, C.c_int32, _i, _i, _i, _d, _d, _d, _d]
         L.pabd_oracle_detect.argtypes = [C.c_void_p]
         L.pabd_oracle_detect_body.argtypes = [C.c_void_p, C.c_int32]
+        L.pabd_oracle_bond_state.argtypes = [C.c_void_p, _d, _d]
         _lib = L
     return _lib
 
@@ -125,7 +127,11 @@ class Oracle:
         d.contact_margin = s.contact_margin
         d.n_planes = s.planes.shape[0]
         d.planes = _ptr(s.planes, C.c_double)
+        d.al_beta = s.al_beta
+        d.al_alpha = s.al_alpha
+        d.al_gamma = s.al_gamma
         self.n = s.n_bodies
+        self.n_bonds = s.n_bonds
         self.iters = s.iters
         self._h = lib().pabd_oracle_create(C.byref(d))
         if not self._h:
@@ -165,6 +171,15 @@ class Oracle:
         H = np.zeros(144)
         lib().pabd_oracle_dense_H(self._h, int(body), _ptr(H, C.c_double))
         return H.reshape(12, 12)
+
+    def bond_state(self):
+        """(kappa_j, lambda_j) of every bond after the last step (augmented bonds;
+        others report kappa and 0)."""
+        k = np.zeros(self.n_bonds)
+        lam = np.zeros(self.n_bonds)
+        if self.n_bonds:
+            lib().pabd_oracle_bond_state(self._h, _ptr(k, C.c_double), _ptr(lam, C.c_double))
+        return k, lam
 
     def detect(self) -> int:
         return int(lib().pabd_oracle_detect(self._h))

@@ -370,6 +370,7 @@ typedef struct {
   double normal[3]; /* contacts: unit normal of j's surface, pointing to i */
   double mu;
   int32_t feature;
+  double al_kappa, al_lambda; /* augmented bonds: kappa_j^k, lambda_j^k */
 } bond_t;
 
 struct pabd_oracle {
@@ -387,6 +388,7 @@ struct pabd_oracle {
   double mu, kscale, margin;
   int32_t n_planes;
   double *planes;
+  double al_beta, al_alpha, al_gamma;
   int64_t steps_done;
   int32_t debug;
   /* per step */
@@ -464,12 +466,20 @@ pabd_oracle *pabd_oracle_create(const pabd_oracle_desc *d) {
     bd->j = d->bond_j[e];
     bd->type = d->bond_type ? d->bond_type[e] : ORACLE_BOND_QUADRATIC;
     if (bd->i < 0 || bd->i >= n || bd->j < -1 || bd->j >= n || bd->i == bd->j) goto bad;
-    if (bd->type != ORACLE_BOND_QUADRATIC && bd->type != ORACLE_BOND_DRIVEN) goto bad;
+    if (bd->type != ORACLE_BOND_QUADRATIC && bd->type != ORACLE_BOND_DRIVEN &&
+        bd->type != ORACLE_BOND_AUGMENTED)
+      goto bad;
     memcpy(bd->xi, d->x_i + 3 * e, 3 * sizeof(double));
     memcpy(bd->xj, d->x_j + 3 * e, 3 * sizeof(double));
     bd->kappa = d->kappa[e];
     bd->rest = d->rest_len ? d->rest_len[e] : 0.0;
     if (!(bd->kappa > 0.0) || bd->rest < 0.0) goto bad;
+    /* an augmented bond needs l > 0: with l = 0 the elongation d >= 0 never
+     * changes sign and the multiplier could only grow */
+    if (bd->type == ORACLE_BOND_AUGMENTED && !(bd->rest > 0.0)) goto bad;
+    /* first step: kappa^0 = kappa_start, lambda = 0 */
+    bd->al_kappa = bd->kappa;
+    bd->al_lambda = 0.0;
     if (bd->type == ORACLE_BOND_DRIVEN) {
       if (!d->drive) goto bad;
       memcpy(o->drive + 13 * e, d->drive + 13 * e, 13 * sizeof(double));
@@ -483,6 +493,9 @@ pabd_oracle *pabd_oracle_create(const pabd_oracle_desc *d) {
   o->mu = d->mu;
   o->kscale = d->contact_kappa_scale;
   o->margin = d->contact_margin;
+  o->al_beta = d->al_beta;
+  o->al_alpha = d->al_alpha;
+  o->al_gamma = d->al_gamma;
   o->n_planes = d->n_planes;
   o->planes = calloc((size_t)(d->n_planes > 0 ? d->n_planes : 1) * 4, sizeof(double));
   if (d->n_planes > 0) memcpy(o->planes, d->planes, (size_t)d->n_planes * 4 * sizeof(double));
@@ -514,6 +527,15 @@ void pabd_oracle_last_iterates(const pabd_oracle *o, double *q_prev, double *q_h
 
 void pabd_oracle_dense_H(const pabd_oracle *o, int32_t body, double *H) {
   memcpy(H, o->H + (size_t)body * 144, 144 * sizeof(double));
+}
+
+void pabd_oracle_bond_state(const pabd_oracle *o, double *kappa, double *lambda) {
+  for (int e = 0; e < o->n_static; ++e) {
+    const bond_t *b = &o->static_bonds[e];
+    const int al = b->type == ORACLE_BOND_AUGMENTED;
+    if (kappa) kappa[e] = al ? b->al_kappa : b->kappa;
+    if (lambda) lambda[e] = al ? b->al_lambda : 0.0;
+  }
 }
 
 int pabd_oracle_contacts(const pabd_oracle *o, int32_t cap, int32_t *ci, int32_t *cj,
@@ -881,6 +903,16 @@ static int one_step(pabd_oracle *o) {
   const double h = o->h, h2 = h * h;
   const double t = o->t0 + (double)(o->steps_done + 1) * h;
 
+  /* augmented bonds, warm start (Sec. 5.2.2): kappa^0 = max(gamma kappa^n,
+   * kappa_start), lambda^0 = alpha gamma lambda^n (on the first step this keeps
+   * kappa_start and 0) */
+  for (int e = 0; e < o->n_static; ++e) {
+    bond_t *b = &o->static_bonds[e];
+    if (b->type != ORACLE_BOND_AUGMENTED) continue;
+    b->al_kappa = fmax(o->al_gamma * b->al_kappa, b->kappa);
+    b->al_lambda = o->al_alpha * o->al_gamma * b->al_lambda;
+  }
+
   /* Algorithm 1: collision detection */
   build_bonds(o, t);
 
@@ -914,8 +946,20 @@ static int one_step(pabd_oracle *o) {
    * bond kappa_c while it penetrates at iterate k, 0 otherwise (reading).  H is
    * assembled dense and solved by Cholesky every iteration. */
   int status = 0;
+  double *al_C = calloc((size_t)(o->n_static > 0 ? o->n_static : 1), sizeof(double));
   for (int k = 0; k < o->iters && status == 0; ++k) {
     double num = 0.0, den = 0.0;
+    /* augmented bonds: elongation C^k = d - l at the iterate q^k the forces of
+     * this iteration use (reading) */
+    for (int e = 0; e < o->n_static; ++e) {
+      const bond_t *bd = &o->bonds[e];
+      if (bd->type != ORACLE_BOND_AUGMENTED) continue;
+      double yi[3], yj[3];
+      end_point(qk, bd->i, bd->xi, yi);
+      end_point(qk, bd->j, bd->xj, yj);
+      double dv[3] = {yj[0] - yi[0], yj[1] - yi[1], yj[2] - yi[2]};
+      al_C[e] = v3_norm(dv) - bd->rest;
+    }
     for (int b = 0; b < n; ++b) {
       if (pinned(o, b)) {
         memcpy(qnext + 12 * b, qk + 12 * b, 12 * sizeof(double));
@@ -952,6 +996,28 @@ static int one_step(pabd_oracle *o) {
           add_JT(xs, fe, side ? -h2 : h2, r);
           continue;
         }
+        if (bd->type == ORACLE_BOND_AUGMENTED) {
+          /* Psi = 1/2 kappa C^2 + lambda C with the signed elongation C = d - l
+           * (reading): phi = dPsi/dd = kappa d + (lambda - kappa l).  Split
+           * (reading): kappa d is implicit; the remainder joins the implicit
+           * weight while it is a tension (w = kappa + (lambda - kappa l) / d^k)
+           * and is explicit along n otherwise, as the quadratic bond's -kappa l */
+          double dv[3] = {yo[0] - ys[0], yo[1] - ys[1], yo[2] - ys[2]};
+          double d = v3_norm(dv);
+          double phim = bd->al_lambda - bd->al_kappa * bd->rest;
+          double w = bd->al_kappa;
+          if (phim > 0.0 && d > 1e-12) {
+            w += phim / d;
+            phim = 0.0;
+          }
+          add_JTJ(xs, h2 * w, H);
+          add_JT(xs, yo, h2 * w, r);
+          if (d > 1e-12 && phim != 0.0) {
+            double nrm[3] = {dv[0] / d, dv[1] / d, dv[2] / d};
+            add_JT(xs, nrm, h2 * phim, r);
+          }
+          continue;
+        }
         /* implicit part: h^2 phi^+(d)/d J^T y_j with phi^+/d = kappa */
         add_JTJ(xs, h2 * bd->kappa, H);
         add_JT(xs, yo, h2 * bd->kappa, r);
@@ -986,6 +1052,14 @@ static int one_step(pabd_oracle *o) {
       den += m_norm2(o->mass[b], o->Pi + 9 * b, qk + 12 * b);
     }
     o->rho[k] = den > 0.0 ? sqrt(num / den) : 0.0;
+    /* augmented bonds (Sec. 5.2.2): lambda^{k+1} = kappa^k C^k + lambda^k and
+     * kappa^{k+1} = kappa^k + beta |C^k|, C^k taken above */
+    for (int e = 0; e < o->n_static; ++e) {
+      bond_t *bd = &o->bonds[e];
+      if (bd->type != ORACLE_BOND_AUGMENTED) continue;
+      bd->al_lambda = bd->al_kappa * al_C[e] + bd->al_lambda;
+      bd->al_kappa = bd->al_kappa + o->al_beta * fabs(al_C[e]);
+    }
     memcpy(o->q_prev, qk, (size_t)n * 12 * sizeof(double));
     double *tmp = qk;
     qk = qnext;
@@ -1015,6 +1089,12 @@ static int one_step(pabd_oracle *o) {
   for (int b = 0; b < n && status == 0; ++b)
     for (int k = 0; k < 3; ++k)
       if (!isfinite(o->c[3 * b + k]) || !isfinite(o->v[3 * b + k])) status = -1;
+  free(al_C);
+  for (int e = 0; e < o->n_static; ++e)
+    if (o->bonds[e].type == ORACLE_BOND_AUGMENTED) {
+      o->static_bonds[e].al_kappa = o->bonds[e].al_kappa;
+      o->static_bonds[e].al_lambda = o->bonds[e].al_lambda;
+    }
   free(s);
   free(qk);
   free(qnext);

@@ -32,6 +32,10 @@ extern "C" {
 #define ORACLE_BOND_QUADRATIC 0 /* Psi = 1/2 kappa (d - l)^2 (l = 0: ball joint) */
 #define ORACLE_BOND_DRIVEN 1    /* ball joint whose j-side anchor follows a target angle */
 #define ORACLE_BOND_CONTACT 2   /* created per step by collision detection      */
+/* augmented Lagrangian (Sec. 5.2.2): Psi = 1/2 kappa_j C^2 + lambda_j C with the
+ * signed elongation C = d - l (l > 0 required), kappa_j and lambda_j updated every
+ * iteration and warm-started every step; the bond's kappa is kappa_start */
+#define ORACLE_BOND_AUGMENTED 3
 
 typedef struct {
   int32_t n_bodies;
@@ -44,7 +48,7 @@ typedef struct {
   const double *v0, *w0;       /* [N*3], [N*3] */
   int32_t n_bonds;
   const int32_t *bond_i, *bond_j; /* [B]; j = -1: world anchor */
-  const int32_t *bond_type;       /* [B] QUADRATIC or DRIVEN */
+  const int32_t *bond_type;       /* [B] QUADRATIC, DRIVEN or AUGMENTED */
   const double *x_i, *x_j;        /* [B*3] material anchors (world coords if j = -1) */
   const double *kappa, *rest_len; /* [B] */
   const double *drive;            /* [B*13]: axis(3) pivot(3) base(3) theta0 amp freq phase */
@@ -58,6 +62,9 @@ typedef struct {
   double contact_margin;      /* base detection margin (m) */
   int32_t n_planes;
   const double *planes; /* [P*4]: unit normal n, offset o; free side n.y >= o */
+  /* augmented-Lagrangian constants: stiffness growth beta, warm-start factors
+   * alpha (multiplier) and gamma (both) */
+  double al_beta, al_alpha, al_gamma;
 } pabd_oracle_desc;
 
 typedef struct pabd_oracle pabd_oracle;
@@ -97,6 +104,10 @@ void pabd_oracle_dense_H(const pabd_oracle *o, int32_t body, double *H);
 int pabd_oracle_contacts(const pabd_oracle *o, int32_t cap, int32_t *ci, int32_t *cj,
                          int32_t *feature, double *xi, double *xj, double *normal,
                          double *kappa);
+
+/* augmented-Lagrangian state of every bond after the last step (kappa_j, lambda_j;
+ * kappa unchanged and lambda 0 for other kinds); any pointer may be NULL */
+void pabd_oracle_bond_state(const pabd_oracle *o, double *kappa, double *lambda);
 
 /* build the contact set of the current state without stepping (same rule) */
 int pabd_oracle_detect(pabd_oracle *o);

@@ -28,6 +28,7 @@ FLAG_PINNED = 1
 FLAG_NO_CONTACT = 2
 BOND_QUADRATIC = 0
 BOND_DRIVEN = 1
+BOND_AUGMENTED = 3  # augmented Lagrangian (Sec. 5.2.2); kappa is kappa_start
 
 PREC_FP32 = 0
 PREC_FP64 = 1
@@ -65,6 +66,10 @@ class SceneDesc:
     planes: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros((0, 4)))
     precision: int = PREC_FP64
     max_contacts_per_body: int = 64
+    # augmented-Lagrangian constants (the paper's values, Sec. 5.2.2)
+    al_beta: float = 1e4
+    al_alpha: float = 0.99
+    al_gamma: float = 0.999
     name: str = ""
 
     @property
@@ -188,6 +193,27 @@ def chain(n: int, *, tilt_deg: float = 45.0, joint_angles_deg=None, kappa: float
     bonds["x_j"][:] = xb
     bonds["kappa"][:] = kappa
     return SceneDesc(**bd, **bonds, h=h, iters=iters, precision=precision, name=name or f"chain{n}")
+
+
+def mass_ratio_chain(n: int = 19, ratio: float = 1000.0, augmented: bool = True,
+                     kappa: float = 1e4, rest: float = 0.1, iters: int = 10,
+                     tilt_deg: float = 30.0, precision: int = PREC_FP64) -> SceneDesc:
+    """The paper's mass-ratio chain (Sec. 5.2.2, Table 2): n unit cubes hanging
+    from a pinned top cube by n - 1 distance constraints between face centres
+    (rest length `rest`), the bottom cube `ratio` times heavier than the others,
+    released at rest, the chain tilted `tilt_deg` from vertical.  With `augmented`
+    the constraints are augmented-Lagrangian bonds with kappa_start = `kappa`;
+    otherwise quadratic bonds of stiffness `kappa`.  Neither the mass ratio nor
+    the rest length is printed in the paper (1000 and 0.1 m here)."""
+    sc = chain(n, tilt_deg=tilt_deg, kappa=kappa, iters=iters, precision=precision,
+               name=f"massratio{n}_{'al' if augmented else 'quad'}")
+    # open every joint to its rest length along the chain axis
+    axis = sc.A0[0] @ np.array([0.0, -1.0, 0.0])
+    c0 = sc.c0 + rest * np.arange(n)[:, None] * axis[None, :]
+    dens = sc.density.copy()
+    dens[-1] = ratio
+    bt = np.full(sc.n_bonds, BOND_AUGMENTED if augmented else BOND_QUADRATIC, np.int32)
+    return sc.copy(c0=c0, density=dens, bond_type=bt, rest_len=np.full(sc.n_bonds, rest))
 
 
 def chain8(precision: int = PREC_FP64, tilt_deg: float = 45.0) -> SceneDesc:
