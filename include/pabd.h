@@ -48,6 +48,13 @@ typedef enum {
 /* bond types */
 #define PABD_BOND_QUADRATIC 0 /* Psi = 1/2 kappa (d - l)^2 (Sec. 5.2.2); l = 0: ball joint */
 #define PABD_BOND_DRIVEN 1    /* ball joint whose j-side anchor is turned by theta(t) */
+/* augmented Lagrangian (Sec. 5.2.2): Psi = 1/2 kappa_j C^2 + lambda_j C with the signed
+ * elongation C = d - l (l > 0 required); kappa is kappa_start.  Every iteration
+ * lambda_j += kappa_j C and kappa_j += al_beta |C| (C at the iterate the forces use);
+ * every step kappa_j = max(al_gamma kappa_j, kappa_start), lambda_j *= al_alpha al_gamma.
+ * The multiplier's tension beyond kappa l is treated implicitly (weight
+ * kappa + (lambda - kappa l)/d).  Scenes with such bonds run on the flat path. */
+#define PABD_BOND_AUGMENTED 3
 /* precision of bond and body arithmetic; the block factorisation and the
  * convergence-residual reductions are always FP64 */
 #define PABD_FP32 0
@@ -90,6 +97,7 @@ typedef struct {
   const double *planes;       /* [P*4] unit normal n and offset o: free side n.y >= o */
   int32_t max_contacts_per_body; /* capacity of contact ends per body (> 0 if contacts) */
   int32_t precision;          /* PABD_FP32 or PABD_FP64 */
+  double al_beta, al_alpha, al_gamma; /* augmented-bond constants (the paper: 1e4, 0.99, 0.999) */
 } pabd_scene_desc;
 
 typedef struct pabd_scene pabd_scene;
@@ -121,6 +129,10 @@ pabd_status pabd_scene_residuals(pabd_scene *s, double *out, int32_t cap, int32_
 pabd_status pabd_scene_contacts(pabd_scene *s, int32_t cap, int32_t *ci, int32_t *cj,
                                 int32_t *feature, double *xi, double *xj, double *normal,
                                 double *kappa, int32_t *n_out);
+/* Augmented-Lagrangian state (kappa_j, lambda_j) of every bond after the last
+ * step, from its i-side end ([B] each, any may be NULL; other bond kinds report
+ * kappa and 0). */
+pabd_status pabd_scene_bond_state(pabd_scene *s, double *kappa, double *lambda);
 /* Device bytes the scene needs (admission bound for the batch). */
 size_t pabd_scene_bytes(const pabd_scene_desc *desc);
 /* debug switches: bit0 = skip the local (rigidification) step */

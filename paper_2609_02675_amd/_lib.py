@@ -27,7 +27,7 @@ SYMBOLS = [
     "pabd_batch_poll", "pabd_batch_read_state", "pabd_batch_residual", "pabd_batch_release",
     "pabd_batch_steps_done", "pabd_batch_autotune", "pabd_batch_set_tile", "pabd_batch_stream",
     "pabd_batch_memory", "pabd_batch_time_tile_kernel", "pabd_batch_layout",
-    "pabd_hbm_copy_probe", "pabd_batch_sync",
+    "pabd_hbm_copy_probe", "pabd_batch_sync", "pabd_scene_bond_state",
 ]
 
 
@@ -60,6 +60,7 @@ class _Desc(C.Structure):
         ("contact_enable", C.c_int32), ("mu", C.c_double), ("contact_kappa_scale", C.c_double),
         ("contact_margin", C.c_double), ("n_planes", C.c_int32), ("planes", _d),
         ("max_contacts_per_body", C.c_int32), ("precision", C.c_int32),
+        ("al_beta", C.c_double), ("al_alpha", C.c_double), ("al_gamma", C.c_double),
     ]
 
 
@@ -83,6 +84,7 @@ def lib():
     L.pabd_scene_read_state.argtypes = [vp, _d, _d, _d, _d]
     L.pabd_scene_residuals.argtypes = [vp, _d, C.c_int32, _i]
     L.pabd_scene_contacts.argtypes = [vp, C.c_int32, _i, _i, _i, _d, _d, _d, _d, _i]
+    L.pabd_scene_bond_state.argtypes = [vp, _d, _d]
     L.pabd_scene_bytes.argtypes = [_P(_Desc)]
     L.pabd_scene_bytes.restype = C.c_size_t
     L.pabd_scene_set_debug.argtypes = [vp, C.c_int32]
@@ -164,6 +166,9 @@ class _Marshalled:
         d.planes = _ptr(s.planes, C.c_double)
         d.max_contacts_per_body = s.max_contacts_per_body if s.contact_enable else 0
         d.precision = s.precision
+        d.al_beta = s.al_beta
+        d.al_alpha = s.al_alpha
+        d.al_gamma = s.al_gamma
         self.desc = d
 
 
@@ -193,6 +198,7 @@ class Scene:
     def __init__(self, scene: SceneDesc):
         self.n = scene.n_bodies
         self.iters = scene.iters
+        self._nb = scene.n_bonds
         m = _Marshalled(scene)
         h = C.c_void_p()
         _check(lib().pabd_scene_create(C.byref(m.desc), C.byref(h)))
@@ -231,6 +237,14 @@ class Scene:
 
     def poke(self, body: int, field: int, value: float):
         _check(lib().pabd_scene_poke(self._h, int(body), int(field), float(value)))
+
+    def bond_state(self):
+        """(kappa_j, lambda_j) of every bond after the last step."""
+        k = np.zeros(self._nb)
+        lam = np.zeros(self._nb)
+        if self._nb:
+            _check(lib().pabd_scene_bond_state(self._h, _ptr(k, C.c_double), _ptr(lam, C.c_double)))
+        return k, lam
 
     def contacts(self):
         n = C.c_int32()

@@ -39,12 +39,14 @@ struct Rec<float> {
   static constexpr int Q = 16;
 };
 constexpr uint8_t F_PINNED = 1, F_NOCONTACT = 2;
+constexpr uint8_t F_AUGMENTED = 4;  // set by the library: the body owns augmented-bond ends
 
 // per-scene parameters (device scene table)
 struct SceneDev {
   double h, g0, g1, g2;
   double t0;
   double kscale, margin, mu;
+  double al_beta, al_alpha, al_gamma;  // augmented-bond constants
   double cell;      // broad-phase cell size of the current step
   int iters;
   int body_off, n_bodies;
@@ -78,6 +80,7 @@ struct View {
   const int* srow_end;  // one past its last static end
   const int* se_partner;
   T* se;
+  T* al;  // 4 per end: kappa_j, lambda_j, l, kappa_start (kappa_start 0: not augmented)
   const double* se64;  // 4 per end: xs (3), kappa in FP64 (for the factorisation)
   // contacts
   int* ccount;

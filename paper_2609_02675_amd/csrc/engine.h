@@ -71,6 +71,7 @@ struct Engine {
   // static ends
   int* se_partner = nullptr;
   T* se = nullptr;
+  T* al = nullptr;
   double* se64 = nullptr;
   // contacts
   int *ccount = nullptr, *ce_partner = nullptr, *ce_st_partner = nullptr;
@@ -201,6 +202,7 @@ struct Engine {
     PABD_TRY(alloc(srow_end, n));
     PABD_TRY(alloc(se_partner, (size_t)c.e));
     PABD_TRY(alloc(se, EW * (size_t)c.e));
+    PABD_TRY(alloc(al, 4 * (size_t)c.e));
     PABD_TRY(alloc(se64, 4 * (size_t)c.e));
     PABD_TRY(alloc(ccount, n));
     PABD_TRY(alloc(scenes, (size_t)c.s));
@@ -277,6 +279,7 @@ struct Engine {
     v.srow_end = srow_end;
     v.se_partner = se_partner;
     v.se = se;
+    v.al = al;
     v.se64 = se64;
     v.ccount = ccount;
     v.ce_partner = ce_partner;
@@ -324,6 +327,8 @@ struct Engine {
     // bond records carry h^2 kappa and h^2 phi^- (the iteration sums h^2-scaled forces)
     const double h2 = hs.params.h * hs.params.h;
     for (size_t k = 0; k < EW * ne; ++k) te[k] = (T)((k % EW == 3 || k % EW == 7) ? h2 * hs.se[k] : hs.se[k]);
+    std::vector<T> ta(4 * ne);
+    for (size_t k = 0; k < 4 * ne; ++k) ta[k] = (T)hs.al[k];
     std::vector<int> part(ne), rows(n), rows_end(n), bs(n, sidx);
     for (size_t e = 0; e < ne; ++e) part[e] = hs.se_partner[e] < 0 ? -1 : hs.se_partner[e] + boff;
     for (size_t b = 0; b < n; ++b) {
@@ -352,6 +357,7 @@ struct Engine {
     add(srow_end + boff, rows_end.data(), rows_end.size());
     add(se_partner + eoff, part.data(), part.size());
     add(se + EW * (size_t)eoff, te.data(), te.size());
+    add(al + 4 * (size_t)eoff, ta.data(), ta.size());
     add(se64 + 4 * (size_t)eoff, hs.se64.data(), hs.se64.size());
     add(planes + 4 * (size_t)poff, hs.planes.data(), hs.planes.size());
     add(scenes + sidx, &S, 1);

@@ -22,11 +22,13 @@ struct HostScene {
   std::vector<int> srow, se_partner;  // scene-local partner ids
   std::vector<double> se;             // 8 per end (FP64 master copy)
   std::vector<double> se64;           // 4 per end
+  std::vector<double> al;             // 4 per end: kappa_j, lambda_j, l, kappa_start (0: not augmented)
+  std::vector<int> bond_end;          // scene-local end of every bond held by a free body (i side if free)
   std::vector<int> drv_end_i, drv_end_j;
   std::vector<double> drv_param;      // 13 per driven bond
   std::vector<double> planes;         // 4 per plane
   SceneDev params{};
-  bool contact = false, driven = false;
+  bool contact = false, driven = false, augmented = false;
   int ccap = 0;
   int max_ends = 0;  // largest number of static ends of one body
 };
@@ -57,7 +59,7 @@ inline std::string build_host_scene(const pabd_scene_desc* d, HostScene& hs) {
     const int sh = d->shape[b];
     if (sh != PABD_SHAPE_BOX && sh != PABD_SHAPE_SPHERE) return "unknown shape of body " + std::to_string(b);
     const double* p = d->shape_param + 3 * (size_t)b;
-    const uint8_t fl = d->flags ? d->flags[b] : 0;
+    const uint8_t fl = d->flags ? (uint8_t)(d->flags[b] & (PABD_FLAG_PINNED | PABD_FLAG_NO_CONTACT)) : 0;
     hs.flags[b] = fl;
     hs.shape[b] = (uint8_t)sh;
     hs.group[b] = d->group ? d->group[b] : 0;
@@ -104,9 +106,16 @@ inline std::string build_host_scene(const pabd_scene_desc* d, HostScene& hs) {
     const int i = d->bond_i[e], j = d->bond_j[e];
     const int ty = d->bond_type ? d->bond_type[e] : PABD_BOND_QUADRATIC;
     if (i < 0 || i >= n || j < -1 || j >= n || i == j) return "bond " + std::to_string(e) + " has bad endpoints";
-    if (ty != PABD_BOND_QUADRATIC && ty != PABD_BOND_DRIVEN) return "unknown bond type";
+    if (ty != PABD_BOND_QUADRATIC && ty != PABD_BOND_DRIVEN && ty != PABD_BOND_AUGMENTED)
+      return "unknown bond type";
     if (!(d->kappa[e] > 0.0)) return "bond stiffness must be positive";
     if (d->rest_len && d->rest_len[e] < 0.0) return "rest length must be >= 0";
+    if (ty == PABD_BOND_AUGMENTED) {
+      // with l = 0 the elongation d >= 0 never changes sign: the multiplier could only grow
+      if (!d->rest_len || !(d->rest_len[e] > 0.0)) return "augmented bond needs a rest length > 0";
+      if (!(d->al_beta >= 0.0 && d->al_alpha >= 0.0 && d->al_gamma >= 0.0))
+        return "augmented-bond constants must be >= 0";
+    }
     if (ty == PABD_BOND_DRIVEN) {
       if (!d->drive) return "driven bond without drive parameters";
       ++n_driven;
@@ -120,6 +129,9 @@ inline std::string build_host_scene(const pabd_scene_desc* d, HostScene& hs) {
   hs.se_partner.assign(hs.ne, -1);
   hs.se.assign(8 * (size_t)hs.ne, 0.0);
   hs.se64.assign(4 * (size_t)hs.ne, 0.0);
+  hs.al.assign(4 * (size_t)hs.ne, 0.0);
+  hs.bond_end.assign(B, -1);
+  hs.augmented = false;
   std::vector<int> fill(n, 0);
   hs.drv_end_i.clear();
   hs.drv_end_j.clear();
@@ -130,6 +142,7 @@ inline std::string build_host_scene(const pabd_scene_desc* d, HostScene& hs) {
     const double* xi = d->x_i + 3 * (size_t)e;
     const double* xj = d->x_j + 3 * (size_t)e;
     const int ei = hs.srow[i] + fill[i]++;
+    hs.bond_end[e] = ei;
     hs.se_partner[ei] = j;
     double* E = &hs.se[8 * (size_t)ei];
     E[0] = xi[0]; E[1] = xi[1]; E[2] = xi[2]; E[3] = kap;
@@ -147,6 +160,24 @@ inline std::string build_host_scene(const pabd_scene_desc* d, HostScene& hs) {
       F64[0] = xj[0]; F64[1] = xj[1]; F64[2] = xj[2]; F64[3] = kap;
     }
     const int ty = d->bond_type ? d->bond_type[e] : PABD_BOND_QUADRATIC;
+    if (ty == PABD_BOND_AUGMENTED) {
+      // per-end state (both ends keep identical copies); the stiffness changes
+      // every iteration, so the bond stays out of the static block (se64 kappa 0)
+      hs.augmented = true;
+      for (int ee : {ei, ej}) {
+        if (ee < 0) continue;
+        double* a = &hs.al[4 * (size_t)ee];
+        a[0] = kap;
+        a[1] = 0.0;
+        a[2] = l;
+        a[3] = kap;
+        hs.se64[4 * (size_t)ee + 3] = 0.0;
+      }
+      hs.flags[i] |= F_AUGMENTED;
+      if (j >= 0) hs.flags[j] |= F_AUGMENTED;
+      // a pinned body never iterates, so its copy of the state is not advanced
+      if ((hs.flags[i] & PABD_FLAG_PINNED) && ej >= 0) hs.bond_end[e] = ej;
+    }
     if (ty == PABD_BOND_DRIVEN) {
       hs.drv_end_i.push_back(ei);
       hs.drv_end_j.push_back(ej);
@@ -180,13 +211,16 @@ inline std::string build_host_scene(const pabd_scene_desc* d, HostScene& hs) {
   S.n_planes = hs.contact ? std::max(d->n_planes, 0) : 0;
   S.contact = hs.contact ? 1 : 0;
   S.ccap = hs.ccap;
+  S.al_beta = d->al_beta;
+  S.al_alpha = d->al_alpha;
+  S.al_gamma = d->al_gamma;
   return "";
 }
 
 // device bytes of one scene at arithmetic type size ts (admission bound)
 inline size_t scene_bytes(const HostScene& hs, int ts) {
   const size_t per_body = (size_t)ts * (4 * (QW + 4) + VW + MW + FW + 4) + 8 * (10 + 8 + 2) + 2 + 4 * 4;
-  const size_t per_end = (size_t)ts * EW + 4 + 8 * 4;
+  const size_t per_end = (size_t)ts * (EW + 4) + 4 + 8 * 4;
   // contact slots (final and staging) and the broad phase: record, reach,
   // large-list entry and max(16, ccap / 2) candidate pairs per body
   const size_t per_contact = 2 * ((size_t)ts * CW + 4 + 8);

@@ -43,6 +43,40 @@ __global__ void __launch_bounds__(256) k_predict(View<T> v) {
   predict_rotation(q + 3, vw + 3, h, s + 3);
   store<T, QR>(v.s + (size_t)QR * i, s);
   store<T, QR>(v.q[0] + (size_t)QR * i, s);
+  if (v.flags[i] & F_AUGMENTED) {
+    // augmented ends, warm start (Sec. 5.2.2): kappa = max(gamma kappa, kappa_start),
+    // lambda = alpha gamma lambda
+    const T ga = (T)S.al_gamma, ag = (T)(S.al_alpha * S.al_gamma);
+    for (int e = v.srow[i]; e < v.srow_end[i]; ++e) {
+      T* a = v.al + 4 * (size_t)e;
+      if (!(a[3] > (T)0)) continue;
+      a[0] = fmax(ga * a[0], a[3]);
+      a[1] = ag * a[1];
+    }
+  }
+}
+
+// one augmented end (Sec. 5.2.2) with bond vector d = y_o - y_s at iterate k:
+// h^2-scaled force and implicit weight of Psi = 1/2 kappa C^2 + lambda C, C = d - l
+// (the multiplier's tension beyond kappa l joins the weight), then the
+// multiplier and stiffness updates from C; a = (kappa, lambda, l, kappa_start)
+template <typename T>
+__device__ __forceinline__ T augmented_end(T* a, const T* d, T h2, T beta, T* f) {
+  const T kap = a[0], lam = a[1], l = a[2];
+  const T dn = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+  T w = kap, phim = lam - kap * l;
+  if (phim > (T)0 && dn > (T)1e-12) {
+    w += phim / dn;
+    phim = (T)0;
+  }
+  const T sc = dn > (T)1e-12 ? phim / dn : (T)0;
+  f[0] = h2 * (w + sc) * d[0];
+  f[1] = h2 * (w + sc) * d[1];
+  f[2] = h2 * (w + sc) * d[2];
+  const T C = dn - l;
+  a[1] = kap * C + lam;
+  a[0] = kap + beta * fabs(C);
+  return h2 * w;  // implicit weight (h^2-scaled) for the block
 }
 
 // mass64: 8 doubles per body (m, Pi sym 6, -)
@@ -166,6 +200,10 @@ __global__ void __launch_bounds__(256) k_iterate(View<T> v, int k, double* rh_nu
   T rb[QW];
 #pragma unroll
   for (int c = 0; c < QW; ++c) rb[c] = (T)0;
+  T fac[FW];
+  bool refactor = false;
+  Block dB{};  // contact and augmented part of H^k - H (this lane's ends)
+  const bool aug = (v.flags[i] & F_AUGMENTED) != 0;
   const int e1 = v.srow_end[i];
   for (int e = v.srow[i] + sub; e < e1; e += LPB) {
     const int j = v.se_partner[e];
@@ -179,12 +217,16 @@ __global__ void __launch_bounds__(256) k_iterate(View<T> v, int k, double* rh_nu
       load<T, QR>(qs + (size_t)QR * j, qj);
       bond_vec<T>(q, E, qj, E + 4, d);
     }
-    quad_end_force(E, d, f);
+    T* a = aug ? v.al + 4 * (size_t)e : nullptr;
+    if (a && a[3] > (T)0) {
+      const T w = augmented_end(a, d, (T)(S.h * S.h), (T)S.al_beta, f);
+      block_add_end(dB, (double)w, (double)E[0], (double)E[1], (double)E[2]);
+      refactor = true;
+    } else {
+      quad_end_force(E, d, f);
+    }
     add_JT(rb, E, f[0], f[1], f[2]);
   }
-  T fac[FW];
-  bool refactor = false;
-  Block dB{};  // contact part of H^k - H (this lane's ends)
   if constexpr (CONTACT) {
     int cnt = v.ccount[i];
     if (cnt > S.ccap) cnt = S.ccap;
@@ -210,7 +252,7 @@ __global__ void __launch_bounds__(256) k_iterate(View<T> v, int k, double* rh_nu
   if constexpr (LPB > 1) {
 #pragma unroll
     for (int c = 0; c < QW; ++c) rb[c] = lane_sum<LPB>(rb[c]);
-    if constexpr (CONTACT) {
+    {
       refactor = lane_sum<LPB>(refactor ? 1 : 0) > 0;
       if (refactor) {  // uniform across the body's lanes
         dB.a = lane_sum<LPB>(dB.a);

@@ -69,6 +69,8 @@ struct EngineBase {
   virtual pabd_status snapshot(int n, std::vector<char>& buf, hipStream_t st, bool restore) = 0;
   // raw q^n and velocity records of bodies [boff, boff + n) (read, or write back)
   virtual pabd_status raw_bodies(int boff, int n, std::vector<char>& buf, hipStream_t st, bool write) = 0;
+  // augmented-bond state of ends [0, ne) as doubles (4 per end)
+  virtual pabd_status read_al(int ne, std::vector<double>& out, hipStream_t st) = 0;
 };
 
 template <typename T>
@@ -187,6 +189,14 @@ struct EngineT final : EngineBase {
     if (hipStreamSynchronize(st) != hipSuccess) return fail(PABD_E_DEVICE, "stream sync failed");
     rec.resize(r.size());
     for (size_t k = 0; k < r.size(); ++k) rec[k] = (double)r[k];
+    return PABD_OK;
+  }
+  pabd_status read_al(int ne, std::vector<double>& out, hipStream_t st) override {
+    std::vector<T> a(4 * (size_t)std::max(ne, 0));
+    if (ne > 0 && (hipMemcpyAsync(a.data(), e.al, a.size() * sizeof(T), hipMemcpyDeviceToHost, st) != hipSuccess ||
+                   hipStreamSynchronize(st) != hipSuccess))
+      return fail(PABD_E_DEVICE, "bond state copy failed");
+    out.assign(a.begin(), a.end());
     return PABD_OK;
   }
   pabd_status raw_bodies(int boff, int n, std::vector<char>& buf, hipStream_t st, bool write) override {
@@ -396,6 +406,21 @@ pabd_status pabd_scene_poke(pabd_scene* s, int32_t body, int32_t field, double v
   if (body < 0 || body >= s->hs.n || field < 0 || field > 17) return fail(PABD_E_INVALID, "bad poke target");
   API_HIP(hipDeviceSynchronize());
   return s->eng->write_body_field(body, field, value, s->stream);
+}
+
+pabd_status pabd_scene_bond_state(pabd_scene* s, double* kappa, double* lambda) {
+  if (!s) return fail(PABD_E_INVALID, "null scene");
+  const int B = (int)s->hs.bond_end.size();
+  std::vector<double> al;
+  pabd_status st = s->eng->read_al(s->hs.ne, al, s->stream);
+  if (st != PABD_OK) return st;
+  for (int e = 0; e < B; ++e) {
+    const double* a = &al[4 * (size_t)s->hs.bond_end[e]];
+    const bool aug = a[3] > 0.0;
+    if (kappa) kappa[e] = aug ? a[0] : s->hs.se[8 * (size_t)s->hs.bond_end[e] + 3];
+    if (lambda) lambda[e] = aug ? a[1] : 0.0;
+  }
+  return PABD_OK;
 }
 
 pabd_status pabd_scene_contacts(pabd_scene* s, int32_t cap, int32_t* ci, int32_t* cj,
@@ -686,7 +711,7 @@ void unplace_tiled(pabd_batch* b, int slot) {
 pabd_status batch_place_and_upload(pabd_batch* b, int slot) {
   Slot& s = b->slots[slot];
   const HostScene& hs = *s.hs;
-  const bool tiled = !hs.contact && !hs.driven && hs.n > 0 && hs.n <= b->tile_bodies;
+  const bool tiled = !hs.contact && !hs.driven && !hs.augmented && hs.n > 0 && hs.n <= b->tile_bodies;
   s.tiled = tiled;
   if (tiled) {
     pabd_status st = place_tiled(b, slot, hs.n);

@@ -1,0 +1,72 @@
+"""Augmented-Lagrangian bonds on the GPU (flat path) against the oracle: the
+paper's mass-ratio chain in FP64 (states and the per-bond kappa_j, lambda_j) and
+FP32, a single hanging body, and an augmented scene admitted to a batch."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2609_02675_amd import scenes as S
+from parity import errors, fp64_ok, scale_of
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2609_02675_amd as P
+    if P.device_count() < 1:
+        pytest.fail("no HIP device visible")
+    return P
+
+
+@pytest.mark.parametrize("steps", [1, 5, 40])
+def test_mass_ratio_chain_fp64(P, steps):
+    sc = S.mass_ratio_chain(precision=S.PREC_FP64)
+    print(f"[case] augmented chain fp64 steps={steps}", flush=True)
+    g = P.Scene(sc)
+    g.step(steps)
+    o = oracle.Oracle(sc)
+    o.step(steps)
+    e = errors(g.state(), o.state(), scale_of(sc))
+    print(e)
+    assert fp64_ok(e, vel_tol=1e-6)
+    kg, lg = g.bond_state()
+    ko, lo = o.bond_state()
+    np.testing.assert_allclose(kg, ko, rtol=1e-9)
+    np.testing.assert_allclose(lg, lo, rtol=1e-8, atol=1e-8 * np.abs(lo).max())
+
+
+def test_mass_ratio_chain_fp32_one_step(P):
+    sc = S.mass_ratio_chain(precision=S.PREC_FP32)
+    g = P.Scene(sc)
+    g.step(1)
+    o = oracle.Oracle(sc.copy(precision=S.PREC_FP64))
+    o.step(1)
+    e = errors(g.state(), o.state(), scale_of(sc))
+    print(e)
+    assert e["pos"] <= 1e-4 and e["rot"] <= 1e-4
+
+
+def test_augmented_chain_in_a_batch_matches_alone(P):
+    """An augmented scene admitted beside chains runs on the flat path and gives
+    the same bits as alone."""
+    sc = S.mass_ratio_chain(precision=S.PREC_FP32)
+    alone = P.Batch(4, 1 << 28, S.PREC_FP32)
+    a = alone.admit(sc, 10)
+    for _ in range(10):
+        alone.step()
+    ref = alone.state(a)
+    mix = P.Batch(8, 1 << 28, S.PREC_FP32)
+    others = [mix.admit(x, 10) for x in S.batched_chains(5, seed=4, precision=S.PREC_FP32)]
+    m = mix.admit(sc, 10)
+    for _ in range(10):
+        mix.step()
+    for x, y in zip(mix.state(m), ref):
+        np.testing.assert_array_equal(x, y)
+    assert all(s is not None for s in others)
+
+
+def test_augmented_needs_rest_length(P):
+    sc = S.mass_ratio_chain(precision=S.PREC_FP64).copy(rest_len=np.zeros(18))
+    with pytest.raises(Exception):
+        P.Scene(sc)
