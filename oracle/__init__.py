@@ -42,6 +42,7 @@ class _Desc(C.Structure):
         ("contact_enable", C.c_int32), ("mu", C.c_double), ("contact_kappa_scale", C.c_double),
         ("contact_margin", C.c_double), ("n_planes", C.c_int32), ("planes", _d),
         ("al_beta", C.c_double), ("al_alpha", C.c_double), ("al_gamma", C.c_double),
+        ("order", _i),
     ]
 
 
@@ -67,12 +68,20 @@ def lib():
         L.pabd_oracle_detect.argtypes = [C.c_void_p]
         L.pabd_oracle_detect_body.argtypes = [C.c_void_p, C.c_int32]
         L.pabd_oracle_bond_state.argtypes = [C.c_void_p, _d, _d]
+        L.pabd_oracle_poly_split.argtypes = [C.c_double, C.c_int32, C.c_double, C.c_double, _d, _d]
         _lib = L
     return _lib
 
 
 def _ptr(a, t):
     return a.ctypes.data_as(_P(t)) if a is not None and a.size else None
+
+
+def poly_split(kappa: float, p: int, l: float, d: float):
+    """(w, phim) of a polynomial bond: implicit weight phi^+ / d and explicit phi^-."""
+    w, pm = C.c_double(), C.c_double()
+    lib().pabd_oracle_poly_split(kappa, p, l, d, C.byref(w), C.byref(pm))
+    return w.value, pm.value
 
 
 def body_mass(shape: int, param, density: float):
@@ -130,6 +139,7 @@ class Oracle:
         d.al_beta = s.al_beta
         d.al_alpha = s.al_alpha
         d.al_gamma = s.al_gamma
+        d.order = _ptr(s.order, C.c_int32)
         self.n = s.n_bodies
         self.n_bonds = s.n_bonds
         self.iters = s.iters

@@ -371,6 +371,7 @@ typedef struct {
   double mu;
   int32_t feature;
   double al_kappa, al_lambda; /* augmented bonds: kappa_j^k, lambda_j^k */
+  int32_t order;              /* polynomial bonds: p */
 } bond_t;
 
 struct pabd_oracle {
@@ -467,8 +468,12 @@ pabd_oracle *pabd_oracle_create(const pabd_oracle_desc *d) {
     bd->type = d->bond_type ? d->bond_type[e] : ORACLE_BOND_QUADRATIC;
     if (bd->i < 0 || bd->i >= n || bd->j < -1 || bd->j >= n || bd->i == bd->j) goto bad;
     if (bd->type != ORACLE_BOND_QUADRATIC && bd->type != ORACLE_BOND_DRIVEN &&
-        bd->type != ORACLE_BOND_AUGMENTED)
+        bd->type != ORACLE_BOND_AUGMENTED && bd->type != ORACLE_BOND_POLYNOMIAL)
       goto bad;
+    if (bd->type == ORACLE_BOND_POLYNOMIAL) {
+      bd->order = d->order ? d->order[e] : 0;
+      if (bd->order < 2 || bd->order % 2 != 0 || bd->order > 12) goto bad;
+    }
     memcpy(bd->xi, d->x_i + 3 * e, 3 * sizeof(double));
     memcpy(bd->xj, d->x_j + 3 * e, 3 * sizeof(double));
     bd->kappa = d->kappa[e];
@@ -887,6 +892,29 @@ static void contact_force(const bond_t *b, const double *yi, const double *yj, d
   for (int k = 0; k < 3; ++k) f[k] = fn * b->normal[k] + ft[k];
 }
 
+/* Polynomial bond Psi = kappa / p (d - l)^p (p even): phi = kappa (d - l)^{p-1} =
+ * kappa sum_k C(p-1, k) d^k (-l)^{p-1-k}.  For d, l >= 0 the terms with p-1-k even
+ * are >= 0 and the others <= 0, which gives the split of Sec. 4.2.1:
+ * phi^+ = kappa sum_{p-1-k even} C(p-1, k) d^k l^{p-1-k} (implicit) and
+ * phi^- = -kappa sum_{p-1-k odd} C(p-1, k) d^k l^{p-1-k} (explicit).  p - 1 is
+ * odd, so the k = 0 term is in phi^- and phi^+ / d is finite at d = 0. */
+void pabd_oracle_poly_split(double kappa, int32_t p, double l, double d, double *wplus,
+                            double *phim) {
+  double binom = 1.0; /* C(p-1, k) */
+  double wp = 0.0, pm = 0.0;
+  for (int k = 0; k <= p - 1; ++k) {
+    if (k > 0) binom = binom * (double)(p - k) / (double)k;
+    const double lp = pow(l, (double)(p - 1 - k));
+    if ((p - 1 - k) % 2 == 0) {
+      wp += binom * (k >= 1 ? pow(d, (double)(k - 1)) : 0.0) * lp; /* term / d */
+    } else {
+      pm -= binom * pow(d, (double)k) * lp;
+    }
+  }
+  *wplus = kappa * wp;
+  *phim = kappa * pm;
+}
+
 /* M-weighted squared norm q^T M q of one body */
 static double m_norm2(double m, const double *Pi, const double *q) {
   double s = m * (q[0] * q[0] + q[1] * q[1] + q[2] * q[2]);
@@ -996,12 +1024,25 @@ static int one_step(pabd_oracle *o) {
           add_JT(xs, fe, side ? -h2 : h2, r);
           continue;
         }
+        if (bd->type == ORACLE_BOND_POLYNOMIAL) {
+          double dv[3] = {yo[0] - ys[0], yo[1] - ys[1], yo[2] - ys[2]};
+          double d = v3_norm(dv), w, phim;
+          pabd_oracle_poly_split(bd->kappa, bd->order, bd->rest, d, &w, &phim);
+          add_JTJ(xs, h2 * w, H);
+          add_JT(xs, yo, h2 * w, r);
+          if (d > 1e-12 && phim != 0.0) {
+            double nrm[3] = {dv[0] / d, dv[1] / d, dv[2] / d};
+            add_JT(xs, nrm, h2 * phim, r);
+          }
+          continue;
+        }
         if (bd->type == ORACLE_BOND_AUGMENTED) {
           /* Psi = 1/2 kappa C^2 + lambda C with the signed elongation C = d - l
-           * (reading): phi = dPsi/dd = kappa d + (lambda - kappa l).  Split
-           * (reading): kappa d is implicit; the remainder joins the implicit
-           * weight while it is a tension (w = kappa + (lambda - kappa l) / d^k)
-           * and is explicit along n otherwise, as the quadratic bond's -kappa l */
+           * (reading): phi = dPsi/dd = kappa d + (lambda - kappa l), split by the
+           * rule of Sec. 4.2.1 (phi^+ >= 0 implicit, phi^- <= 0 explicit):
+           * phi^+ = kappa d + max(lambda - kappa l, 0), i.e. the weight
+           * w = kappa + (lambda - kappa l) / d^k while the remainder is a
+           * tension, and phi^- = min(lambda - kappa l, 0) explicit along n */
           double dv[3] = {yo[0] - ys[0], yo[1] - ys[1], yo[2] - ys[2]};
           double d = v3_norm(dv);
           double phim = bd->al_lambda - bd->al_kappa * bd->rest;

@@ -36,6 +36,9 @@ extern "C" {
  * signed elongation C = d - l (l > 0 required), kappa_j and lambda_j updated every
  * iteration and warm-started every step; the bond's kappa is kappa_start */
 #define ORACLE_BOND_AUGMENTED 3
+/* polynomial bond: Psi = kappa / p (d - l)^p, p even >= 2 (order[] of the bond);
+ * phi = kappa (d - l)^{p-1} split by the sign of its binomial terms */
+#define ORACLE_BOND_POLYNOMIAL 4
 
 typedef struct {
   int32_t n_bodies;
@@ -65,6 +68,7 @@ typedef struct {
   /* augmented-Lagrangian constants: stiffness growth beta, warm-start factors
    * alpha (multiplier) and gamma (both) */
   double al_beta, al_alpha, al_gamma;
+  const int32_t *order; /* [B] polynomial order p of POLYNOMIAL bonds, or NULL */
 } pabd_oracle_desc;
 
 typedef struct pabd_oracle pabd_oracle;
@@ -108,6 +112,11 @@ int pabd_oracle_contacts(const pabd_oracle *o, int32_t cap, int32_t *ci, int32_t
 /* augmented-Lagrangian state of every bond after the last step (kappa_j, lambda_j;
  * kappa unchanged and lambda 0 for other kinds); any pointer may be NULL */
 void pabd_oracle_bond_state(const pabd_oracle *o, double *kappa, double *lambda);
+
+/* split of a polynomial bond's phi = kappa (d - l)^{p-1}: implicit weight
+ * phi^+ / d and explicit phi^- (so w d + phim = phi, w >= 0, phim <= 0) */
+void pabd_oracle_poly_split(double kappa, int32_t p, double l, double d, double *wplus,
+                            double *phim);
 
 /* build the contact set of the current state without stepping (same rule) */
 int pabd_oracle_detect(pabd_oracle *o);

@@ -29,6 +29,7 @@ FLAG_NO_CONTACT = 2
 BOND_QUADRATIC = 0
 BOND_DRIVEN = 1
 BOND_AUGMENTED = 3  # augmented Lagrangian (Sec. 5.2.2); kappa is kappa_start
+BOND_POLYNOMIAL = 4  # Psi = kappa / p (d - l)^p, p = order (even >= 2)
 
 PREC_FP32 = 0
 PREC_FP64 = 1
@@ -55,6 +56,7 @@ class SceneDesc:
     kappa: np.ndarray          # [B]
     rest_len: np.ndarray       # [B]
     drive: np.ndarray          # [B,13]
+    order: Optional[np.ndarray] = None  # [B] int32 polynomial order (polynomial bonds)
     gravity: np.ndarray = dataclasses.field(default_factory=lambda: np.array([0.0, -9.81, 0.0]))
     h: float = 1.0 / 60.0
     t0: float = 0.0
@@ -113,6 +115,7 @@ class SceneDesc:
             bond_i=i32(self.bond_i), bond_j=i32(self.bond_j), bond_type=i32(self.bond_type),
             x_i=f64(self.x_i, (b, 3)), x_j=f64(self.x_j, (b, 3)), kappa=f64(self.kappa, (b,)),
             rest_len=f64(self.rest_len, (b,)), drive=f64(self.drive, (b, 13)),
+            order=i32(self.order if self.order is not None else np.full(b, 2)),
             gravity=f64(self.gravity, (3,)), planes=f64(self.planes, (-1, 4)))
 
 
@@ -216,6 +219,64 @@ def mass_ratio_chain(n: int = 19, ratio: float = 1000.0, augmented: bool = True,
     return sc.copy(c0=c0, density=dens, bond_type=bt, rest_len=np.full(sc.n_bonds, rest))
 
 
+def spring_pair(order: int = 2, stretch: float = 2.0, rest: float = 1.0, kappa: float = 1e4,
+                iters: int = 20, precision: int = PREC_FP64) -> SceneDesc:
+    """Two unit cubes (1 kg) joined centre to centre by one spring of rest length
+    `rest`, stretched to `stretch` times it, at rest, no gravity (the paper's
+    two-box spring, Sec. 5.2.2): order 2 is the quadratic bond, higher even orders
+    the polynomial bond kappa / p (d - l)^p."""
+    bd = _bodies(2)
+    bd["shape_param"][:] = 0.5
+    bd["flags"][:] = FLAG_NO_CONTACT
+    bd["c0"][0] = (-stretch * rest / 2, 0.0, 0.0)
+    bd["c0"][1] = (stretch * rest / 2, 0.0, 0.0)
+    bonds = _empty_bonds(1)
+    bonds["bond_i"][0], bonds["bond_j"][0] = 0, 1
+    bonds["kappa"][0] = kappa
+    bonds["rest_len"][0] = rest
+    bonds["bond_type"][0] = BOND_QUADRATIC if order == 2 else BOND_POLYNOMIAL
+    return SceneDesc(**bd, **bonds, order=np.array([order], np.int32), gravity=np.zeros(3),
+                     iters=iters, precision=precision, name=f"springpair_p{order}")
+
+
+def spring_net(n: int = 11, order: int = 2, spacing: float = 1.0, size: float = 0.5,
+               kappa: float = 1e4, pull: float = 0.3, iters: int = 20,
+               precision: int = PREC_FP64) -> SceneDesc:
+    """The paper's net (Sec. 5.2.2): an n x n grid of cubes (side `size`, 1000
+    kg/m^3) in the x-y plane joined to their four neighbours by centre-to-centre
+    springs of rest length `spacing` (2 n (n - 1) springs, 220 for n = 11).  Every
+    cube starts pulled a fraction `pull` of the way towards the centre of the
+    bottom edge, so the springs start stretched or compressed; the two top corners
+    are pinned; gravity on.  The pull and the pins are readings (the paper shows
+    the scene but does not list its parameters)."""
+    ix, iy = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    grid = np.stack([ix.ravel(), iy.ravel()], axis=1).astype(np.float64)
+    m = grid.shape[0]
+    bd = _bodies(m)
+    bd["shape_param"][:] = size / 2
+    bd["density"][:] = 1000.0
+    bd["flags"][:] = FLAG_NO_CONTACT
+    rest_xy = np.stack([(grid[:, 0] - (n - 1) / 2) * spacing, grid[:, 1] * spacing], axis=1)
+    target = np.array([0.0, 0.0])
+    xy = rest_xy + pull * (target - rest_xy)
+    top = grid[:, 1] == n - 1
+    corner = top & ((grid[:, 0] == 0) | (grid[:, 0] == n - 1))
+    xy[corner] = rest_xy[corner]
+    bd["c0"][:, :2] = xy
+    bd["flags"][corner] |= FLAG_PINNED
+    idx = lambda a, b: a * n + b
+    pairs = [(idx(a, b), idx(a + 1, b)) for a in range(n - 1) for b in range(n)] + \
+            [(idx(a, b), idx(a, b + 1)) for a in range(n) for b in range(n - 1)]
+    bonds = _empty_bonds(len(pairs))
+    bonds["bond_i"][:] = [p[0] for p in pairs]
+    bonds["bond_j"][:] = [p[1] for p in pairs]
+    bonds["kappa"][:] = kappa
+    bonds["rest_len"][:] = spacing
+    bonds["bond_type"][:] = BOND_QUADRATIC if order == 2 else BOND_POLYNOMIAL
+    return SceneDesc(**bd, **bonds, order=np.full(len(pairs), order, np.int32), iters=iters,
+                     precision=precision, name=f"net{n}_p{order}")
+
+
 def chain8(precision: int = PREC_FP64, tilt_deg: float = 45.0) -> SceneDesc:
     """8 unit cubes, 7 ball joints (kappa 1e5), body 0 pinned, g = 9.81, h = 1/60,
     20 iterations per step.  ``tilt_deg=10`` is the gentle, non-chaotic variant."""
@@ -255,7 +316,9 @@ def merge(scenes: List[SceneDesc], name: str = "merged") -> SceneDesc:
         flags=cat("flags"), group=cat("group"), c0=cat("c0"), A0=cat("A0"), v0=cat("v0"),
         w0=cat("w0"), bond_i=bi.astype(np.int32), bond_j=bj.astype(np.int32),
         bond_type=cat("bond_type"), x_i=cat("x_i"), x_j=cat("x_j"), kappa=cat("kappa"),
-        rest_len=cat("rest_len"), drive=cat("drive"), name=name)
+        rest_len=cat("rest_len"), drive=cat("drive"),
+        order=np.concatenate([s.order if s.order is not None else np.full(s.n_bonds, 2, np.int32)
+                              for s in scenes]).astype(np.int32), name=name)
 
 
 # ---------------------------------------------------------------------------
