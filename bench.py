@@ -446,6 +446,22 @@ def main():
                 paper_context="Table 2, mass-ratio chain (19 bodies, 10 iterations) on an RTX 3080: "
                               "t_solve 1.28 ms (AL on) / 1.25 ms (off) per frame")
             log(f"mass-ratio chain {tag}: {ms:.3f} ms/step, joint error {joint(st[0], st[1]):.3g} m")
+        # the paper's 11 x 11 net of 220 springs, quadratic and quartic bonds:
+        # convergence of the first step (relative error per iteration) and step time
+        for p_ in (2, 4):
+            net = S.spring_net(order=p_, iters=20, precision=S.PREC_FP32)
+            if p_ == 2:
+                net = net.copy(bond_type=np.full(net.n_bonds, S.BOND_POLYNOMIAL, np.int32))
+            gn = P.Scene(net)
+            gn.set_debug(2)
+            gn.step(1)
+            rho = gn.residuals()
+            gn.set_debug(0)
+            _, rate, ms = time_scene(net, 10, 100)
+            scene_legs[f"spring_net_11_p{p_}_fp32"] = dict(
+                body_its_per_s=rate, ms_per_step=ms, bonds=net.n_bonds, iters=net.iters,
+                first_step_rel_error=[float(x) for x in rho[:20]])
+            log(f"net p={p_}: {ms:.3f} ms/step, first-step rho {rho[0]:.2e} -> {rho[19]:.2e}")
         # 50^3 stacked cubes in resting contact (the paper's largest scene size)
         pile = S.block_pile(precision=S.PREC_FP32)
         g, rate, ms = time_scene(pile, 1, 10)

@@ -55,6 +55,10 @@ typedef enum {
  * The multiplier's tension beyond kappa l is treated implicitly (weight
  * kappa + (lambda - kappa l)/d).  Scenes with such bonds run on the flat path. */
 #define PABD_BOND_AUGMENTED 3
+/* polynomial bond (Sec. 4.2.1): Psi = kappa / p (d - l)^p, p = order[] even in [2, 12];
+ * phi = kappa (d - l)^{p-1} split by the signs of its binomial terms (non-negative terms
+ * implicit, the rest explicit); p = 2 is the quadratic bond.  Flat path. */
+#define PABD_BOND_POLYNOMIAL 4
 /* precision of bond and body arithmetic; the block factorisation and the
  * convergence-residual reductions are always FP64 */
 #define PABD_FP32 0
@@ -98,6 +102,7 @@ typedef struct {
   int32_t max_contacts_per_body; /* capacity of contact ends per body (> 0 if contacts) */
   int32_t precision;          /* PABD_FP32 or PABD_FP64 */
   double al_beta, al_alpha, al_gamma; /* augmented-bond constants (the paper: 1e4, 0.99, 0.999) */
+  const int32_t *order;       /* [B] order p of polynomial bonds, or NULL */
 } pabd_scene_desc;
 
 typedef struct pabd_scene pabd_scene;

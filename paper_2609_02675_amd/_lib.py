@@ -61,6 +61,7 @@ class _Desc(C.Structure):
         ("contact_margin", C.c_double), ("n_planes", C.c_int32), ("planes", _d),
         ("max_contacts_per_body", C.c_int32), ("precision", C.c_int32),
         ("al_beta", C.c_double), ("al_alpha", C.c_double), ("al_gamma", C.c_double),
+        ("order", _i),
     ]
 
 
@@ -169,6 +170,7 @@ class _Marshalled:
         d.al_beta = s.al_beta
         d.al_alpha = s.al_alpha
         d.al_gamma = s.al_gamma
+        d.order = _ptr(s.order, C.c_int32)
         self.desc = d
 
 

@@ -39,7 +39,7 @@ struct Rec<float> {
   static constexpr int Q = 16;
 };
 constexpr uint8_t F_PINNED = 1, F_NOCONTACT = 2;
-constexpr uint8_t F_AUGMENTED = 4;  // set by the library: the body owns augmented-bond ends
+constexpr uint8_t F_VARIABLE = 4;  // set by the library: the body owns ends whose weight changes every iteration
 
 // per-scene parameters (device scene table)
 struct SceneDev {
@@ -80,7 +80,9 @@ struct View {
   const int* srow_end;  // one past its last static end
   const int* se_partner;
   T* se;
-  T* al;  // 4 per end: kappa_j, lambda_j, l, kappa_start (kappa_start 0: not augmented)
+  // 4 per end for ends whose weight changes every iteration: augmented
+  // (kappa_j, lambda_j, l, kappa_start > 0), polynomial (kappa, 0, l, -p), else 0
+  T* al;
   const double* se64;  // 4 per end: xs (3), kappa in FP64 (for the factorisation)
   // contacts
   int* ccount;

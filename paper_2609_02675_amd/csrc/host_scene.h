@@ -22,13 +22,14 @@ struct HostScene {
   std::vector<int> srow, se_partner;  // scene-local partner ids
   std::vector<double> se;             // 8 per end (FP64 master copy)
   std::vector<double> se64;           // 4 per end
-  std::vector<double> al;             // 4 per end: kappa_j, lambda_j, l, kappa_start (0: not augmented)
+  std::vector<double> al;             // 4 per end: augmented (kappa_j, lambda_j, l, kappa_start),
+                                      // polynomial (kappa, 0, l, -p), else zeros
   std::vector<int> bond_end;          // scene-local end of every bond held by a free body (i side if free)
   std::vector<int> drv_end_i, drv_end_j;
   std::vector<double> drv_param;      // 13 per driven bond
   std::vector<double> planes;         // 4 per plane
   SceneDev params{};
-  bool contact = false, driven = false, augmented = false;
+  bool contact = false, driven = false, variable = false;
   int ccap = 0;
   int max_ends = 0;  // largest number of static ends of one body
 };
@@ -106,8 +107,13 @@ inline std::string build_host_scene(const pabd_scene_desc* d, HostScene& hs) {
     const int i = d->bond_i[e], j = d->bond_j[e];
     const int ty = d->bond_type ? d->bond_type[e] : PABD_BOND_QUADRATIC;
     if (i < 0 || i >= n || j < -1 || j >= n || i == j) return "bond " + std::to_string(e) + " has bad endpoints";
-    if (ty != PABD_BOND_QUADRATIC && ty != PABD_BOND_DRIVEN && ty != PABD_BOND_AUGMENTED)
+    if (ty != PABD_BOND_QUADRATIC && ty != PABD_BOND_DRIVEN && ty != PABD_BOND_AUGMENTED &&
+        ty != PABD_BOND_POLYNOMIAL)
       return "unknown bond type";
+    if (ty == PABD_BOND_POLYNOMIAL) {
+      const int p = d->order ? d->order[e] : 0;
+      if (p < 2 || p > 12 || p % 2 != 0) return "polynomial bond order must be even in [2, 12]";
+    }
     if (!(d->kappa[e] > 0.0)) return "bond stiffness must be positive";
     if (d->rest_len && d->rest_len[e] < 0.0) return "rest length must be >= 0";
     if (ty == PABD_BOND_AUGMENTED) {
@@ -131,7 +137,7 @@ inline std::string build_host_scene(const pabd_scene_desc* d, HostScene& hs) {
   hs.se64.assign(4 * (size_t)hs.ne, 0.0);
   hs.al.assign(4 * (size_t)hs.ne, 0.0);
   hs.bond_end.assign(B, -1);
-  hs.augmented = false;
+  hs.variable = false;
   std::vector<int> fill(n, 0);
   hs.drv_end_i.clear();
   hs.drv_end_j.clear();
@@ -160,21 +166,23 @@ inline std::string build_host_scene(const pabd_scene_desc* d, HostScene& hs) {
       F64[0] = xj[0]; F64[1] = xj[1]; F64[2] = xj[2]; F64[3] = kap;
     }
     const int ty = d->bond_type ? d->bond_type[e] : PABD_BOND_QUADRATIC;
-    if (ty == PABD_BOND_AUGMENTED) {
-      // per-end state (both ends keep identical copies); the stiffness changes
-      // every iteration, so the bond stays out of the static block (se64 kappa 0)
-      hs.augmented = true;
+    if (ty == PABD_BOND_AUGMENTED || ty == PABD_BOND_POLYNOMIAL) {
+      // per-end data (augmented: both ends keep identical copies of the state);
+      // the weight changes every iteration, so the bond stays out of the static
+      // block (se64 kappa 0)
+      hs.variable = true;
+      const bool aug = ty == PABD_BOND_AUGMENTED;
       for (int ee : {ei, ej}) {
         if (ee < 0) continue;
         double* a = &hs.al[4 * (size_t)ee];
         a[0] = kap;
         a[1] = 0.0;
         a[2] = l;
-        a[3] = kap;
+        a[3] = aug ? kap : -(double)d->order[e];
         hs.se64[4 * (size_t)ee + 3] = 0.0;
       }
-      hs.flags[i] |= F_AUGMENTED;
-      if (j >= 0) hs.flags[j] |= F_AUGMENTED;
+      hs.flags[i] |= F_VARIABLE;
+      if (j >= 0) hs.flags[j] |= F_VARIABLE;
       // a pinned body never iterates, so its copy of the state is not advanced
       if ((hs.flags[i] & PABD_FLAG_PINNED) && ej >= 0) hs.bond_end[e] = ej;
     }

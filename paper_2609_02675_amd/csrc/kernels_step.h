@@ -43,13 +43,13 @@ __global__ void __launch_bounds__(256) k_predict(View<T> v) {
   predict_rotation(q + 3, vw + 3, h, s + 3);
   store<T, QR>(v.s + (size_t)QR * i, s);
   store<T, QR>(v.q[0] + (size_t)QR * i, s);
-  if (v.flags[i] & F_AUGMENTED) {
+  if (v.flags[i] & F_VARIABLE) {
     // augmented ends, warm start (Sec. 5.2.2): kappa = max(gamma kappa, kappa_start),
     // lambda = alpha gamma lambda
     const T ga = (T)S.al_gamma, ag = (T)(S.al_alpha * S.al_gamma);
     for (int e = v.srow[i]; e < v.srow_end[i]; ++e) {
       T* a = v.al + 4 * (size_t)e;
-      if (!(a[3] > (T)0)) continue;
+      if (!(a[3] > (T)0)) continue;  // augmented ends only
       a[0] = fmax(ga * a[0], a[3]);
       a[1] = ag * a[1];
     }
@@ -77,6 +77,45 @@ __device__ __forceinline__ T augmented_end(T* a, const T* d, T h2, T beta, T* f)
   a[1] = kap * C + lam;
   a[0] = kap + beta * fabs(C);
   return h2 * w;  // implicit weight (h^2-scaled) for the block
+}
+
+// one polynomial end, Psi = kappa / p (d - l)^p (p even, at most 12): phi =
+// kappa (d - l)^{p-1} = kappa sum_k C(p-1, k) d^k (-l)^{p-1-k}; the terms with
+// p-1-k even are >= 0 and form phi^+ (implicit weight phi^+ / d), the others
+// phi^- (explicit) -- the split of Sec. 4.2.1; a = (kappa, 0, l, -p)
+template <typename T>
+__device__ __forceinline__ T polynomial_end(const T* a, const T* d, T h2, T* f) {
+  const T kap = a[0], l = a[2];
+  const int p = (int)(-a[3]);
+  const T dn = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+  T lp[12];  // l^j
+  lp[0] = (T)1;
+#pragma unroll
+  for (int j = 1; j < 12; ++j) lp[j] = lp[j - 1] * l;
+  T binom = (T)1, dk1 = (T)1, w = (T)0, phim = (T)0;  // dk1 = d^{k-1}
+#pragma unroll
+  for (int k = 0; k < 12; ++k) {
+    if (k >= p) break;
+    if (k > 0) binom = binom * (T)(p - k) / (T)k;
+    const int j = p - 1 - k;
+    T lj = (T)0;
+#pragma unroll
+    for (int u = 0; u < 12; ++u)
+      if (u == j) lj = lp[u];
+    if (j % 2 == 0) {
+      if (k >= 1) w += binom * dk1 * lj;
+    } else {
+      phim -= binom * (k >= 1 ? dk1 * dn : (T)1) * lj;
+    }
+    if (k >= 1) dk1 *= dn;
+  }
+  w *= kap;
+  phim *= kap;
+  const T sc = dn > (T)1e-12 ? phim / dn : (T)0;
+  f[0] = h2 * (w + sc) * d[0];
+  f[1] = h2 * (w + sc) * d[1];
+  f[2] = h2 * (w + sc) * d[2];
+  return h2 * w;
 }
 
 // mass64: 8 doubles per body (m, Pi sym 6, -)
@@ -203,7 +242,7 @@ __global__ void __launch_bounds__(256) k_iterate(View<T> v, int k, double* rh_nu
   T fac[FW];
   bool refactor = false;
   Block dB{};  // contact and augmented part of H^k - H (this lane's ends)
-  const bool aug = (v.flags[i] & F_AUGMENTED) != 0;
+  const bool var = (v.flags[i] & F_VARIABLE) != 0;
   const int e1 = v.srow_end[i];
   for (int e = v.srow[i] + sub; e < e1; e += LPB) {
     const int j = v.se_partner[e];
@@ -217,9 +256,10 @@ __global__ void __launch_bounds__(256) k_iterate(View<T> v, int k, double* rh_nu
       load<T, QR>(qs + (size_t)QR * j, qj);
       bond_vec<T>(q, E, qj, E + 4, d);
     }
-    T* a = aug ? v.al + 4 * (size_t)e : nullptr;
-    if (a && a[3] > (T)0) {
-      const T w = augmented_end(a, d, (T)(S.h * S.h), (T)S.al_beta, f);
+    T* a = var ? v.al + 4 * (size_t)e : nullptr;
+    if (a && a[3] != (T)0) {
+      const T w = a[3] > (T)0 ? augmented_end(a, d, (T)(S.h * S.h), (T)S.al_beta, f)
+                              : polynomial_end(a, d, (T)(S.h * S.h), f);
       block_add_end(dB, (double)w, (double)E[0], (double)E[1], (double)E[2]);
       refactor = true;
     } else {

@@ -417,7 +417,7 @@ pabd_status pabd_scene_bond_state(pabd_scene* s, double* kappa, double* lambda) 
   for (int e = 0; e < B; ++e) {
     const double* a = &al[4 * (size_t)s->hs.bond_end[e]];
     const bool aug = a[3] > 0.0;
-    if (kappa) kappa[e] = aug ? a[0] : s->hs.se[8 * (size_t)s->hs.bond_end[e] + 3];
+    if (kappa) kappa[e] = aug || a[3] < 0.0 ? a[0] : s->hs.se[8 * (size_t)s->hs.bond_end[e] + 3];
     if (lambda) lambda[e] = aug ? a[1] : 0.0;
   }
   return PABD_OK;
@@ -711,7 +711,7 @@ void unplace_tiled(pabd_batch* b, int slot) {
 pabd_status batch_place_and_upload(pabd_batch* b, int slot) {
   Slot& s = b->slots[slot];
   const HostScene& hs = *s.hs;
-  const bool tiled = !hs.contact && !hs.driven && !hs.augmented && hs.n > 0 && hs.n <= b->tile_bodies;
+  const bool tiled = !hs.contact && !hs.driven && !hs.variable && hs.n > 0 && hs.n <= b->tile_bodies;
   s.tiled = tiled;
   if (tiled) {
     pabd_status st = place_tiled(b, slot, hs.n);

@@ -1,0 +1,66 @@
+"""Polynomial bonds kappa/p (d - l)^p on the GPU (flat path) against the oracle:
+the two-box spring and the 11 x 11 net of Sec. 5.2.2 at orders 2, 4 and 6."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2609_02675_amd import scenes as S
+from parity import errors, fp64_ok, scale_of
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2609_02675_amd as P
+    if P.device_count() < 1:
+        pytest.fail("no HIP device visible")
+    return P
+
+
+@pytest.mark.parametrize("p", [2, 4, 6])
+def test_spring_pair_fp64(P, p):
+    sc = S.spring_pair(order=p, iters=30, precision=S.PREC_FP64)
+    if p == 2:  # order 2 as a polynomial bond, not the quadratic code path
+        sc = sc.copy(bond_type=np.array([S.BOND_POLYNOMIAL], np.int32))
+    print(f"[case] spring pair p={p}", flush=True)
+    g = P.Scene(sc)
+    g.step(10)
+    o = oracle.Oracle(sc)
+    o.step(10)
+    e = errors(g.state(), o.state(), scale_of(sc))
+    print(e)
+    assert fp64_ok(e, vel_tol=1e-6)
+
+
+@pytest.mark.parametrize("p", [4, 6])
+def test_net_fp64_and_residuals(P, p):
+    sc = S.spring_net(order=p, iters=20, precision=S.PREC_FP64)
+    print(f"[case] net p={p}", flush=True)
+    g = P.Scene(sc)
+    g.set_debug(2)  # residual history
+    g.step(3)
+    o = oracle.Oracle(sc)
+    o.step(3)
+    e = errors(g.state(), o.state(), scale_of(sc))
+    print(e)
+    assert fp64_ok(e, vel_tol=1e-6)
+    rg, ro = g.residuals(), o.residuals()
+    np.testing.assert_allclose(rg[:10], ro[:10], rtol=1e-6)
+
+
+def test_net_fp32(P):
+    sc = S.spring_net(order=4, iters=20, precision=S.PREC_FP32)
+    g = P.Scene(sc)
+    g.step(1)
+    o = oracle.Oracle(sc.copy(precision=S.PREC_FP64))
+    o.step(1)
+    e = errors(g.state(), o.state(), scale_of(sc))
+    print(e)
+    assert e["pos"] <= 1e-4 and e["rot"] <= 1e-4
+
+
+def test_bad_order_rejected(P):
+    sc = S.spring_pair(order=4, precision=S.PREC_FP64).copy(order=np.array([5], np.int32))
+    with pytest.raises(Exception):
+        P.Scene(sc)
