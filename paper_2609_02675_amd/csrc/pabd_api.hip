@@ -721,16 +721,17 @@ pabd_status batch_place_and_upload(pabd_batch* b, int slot) {
     if (s.boff < 0) return PABD_E_BUSY;
   }
   s.eoff = b->ends.take(std::max(1, hs.ne));
+  // planes and driven bonds take table space only when the scene has them
   s.np = (int)hs.planes.size() / 4;
-  s.poff = b->planes.take(std::max(1, s.np));
+  s.poff = s.np > 0 ? b->planes.take(s.np) : 0;
   s.nd = (int)hs.drv_end_i.size();
-  s.doff = b->driven.take(std::max(1, s.nd));
+  s.doff = s.nd > 0 ? b->driven.take(s.nd) : 0;
   auto undo = [&]() {
     if (s.tiled) unplace_tiled(b, slot);
     else if (s.boff >= 0) b->stream_bodies.give(s.boff, std::max(1, hs.n));
     if (s.eoff >= 0) b->ends.give(s.eoff, std::max(1, hs.ne));
-    if (s.poff >= 0) b->planes.give(s.poff, std::max(1, s.np));
-    if (s.doff >= 0) b->driven.give(s.doff, std::max(1, s.nd));
+    if (s.np > 0 && s.poff >= 0) b->planes.give(s.poff, s.np);
+    if (s.nd > 0 && s.doff >= 0) b->driven.give(s.doff, s.nd);
   };
   if (s.eoff < 0 || s.poff < 0 || s.doff < 0) {
     undo();
@@ -905,8 +906,8 @@ pabd_status pabd_batch_release(pabd_batch* b, int32_t slot) {
   if (s.tiled) unplace_tiled(b, slot);
   else b->stream_bodies.give(s.boff, std::max(1, s.n));
   b->ends.give(s.eoff, std::max(1, s.ne));
-  b->planes.give(s.poff, std::max(1, s.np));
-  b->driven.give(s.doff, std::max(1, s.nd));
+  if (s.np > 0) b->planes.give(s.poff, s.np);
+  if (s.nd > 0) b->driven.give(s.doff, s.nd);
   b->used_bytes -= s.bytes;
   s = Slot{};
   b->dirty = true;
@@ -1030,8 +1031,8 @@ static pabd_status batch_repack(pabd_batch* b, int tile_bodies) {
     if (s.tiled) unplace_tiled(b, k);
     else b->stream_bodies.give(s.boff, std::max(1, s.n));
     b->ends.give(s.eoff, std::max(1, s.ne));
-    b->planes.give(s.poff, std::max(1, s.np));
-    b->driven.give(s.doff, std::max(1, s.nd));
+    if (s.np > 0) b->planes.give(s.poff, s.np);
+    if (s.nd > 0) b->driven.give(s.doff, s.nd);
   }
   b->tiles.clear();
   b->tile_bodies = tile_bodies;
