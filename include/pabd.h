@@ -109,6 +109,15 @@ typedef struct pabd_scene pabd_scene;
 typedef struct pabd_batch pabd_batch;
 
 const char *pabd_last_error(void);
+/* Device memory of scenes and batches created from now on: alloc(bytes, ctx) must
+ * return device memory of the current device, aligned to 256 bytes, or NULL (then
+ * the create or admit fails with PABD_E_OOM); release(ptr, ctx) returns it.  A
+ * scene or batch releases its memory only at destroy, after the device is idle,
+ * and keeps the allocator that was in force at its creation.  alloc = NULL
+ * restores hipMalloc / hipFree.  Not thread-safe: set it before creating handles.
+ * (For a caching allocator such as PyTorch's.) */
+pabd_status pabd_set_allocator(void *(*alloc)(size_t bytes, void *ctx),
+                               void (*release)(void *ptr, void *ctx), void *ctx);
 /* number of HIP devices visible (0 without a GPU); never fails */
 int32_t pabd_device_count(void);
 

@@ -6,4 +6,4 @@ and the build script.
 """
 from . import scenes  # noqa: F401
 from ._lib import (Batch, Busy, Diverged, PabdError, Scene, device_count,  # noqa: F401
-                   hbm_copy_probe, lib, scene_bytes)
+                   hbm_copy_probe, lib, scene_bytes, use_torch_allocator)

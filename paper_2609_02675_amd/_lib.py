@@ -27,8 +27,11 @@ SYMBOLS = [
     "pabd_batch_poll", "pabd_batch_read_state", "pabd_batch_residual", "pabd_batch_release",
     "pabd_batch_steps_done", "pabd_batch_autotune", "pabd_batch_set_tile", "pabd_batch_stream",
     "pabd_batch_memory", "pabd_batch_time_tile_kernel", "pabd_batch_layout",
-    "pabd_hbm_copy_probe", "pabd_batch_sync", "pabd_scene_bond_state",
+    "pabd_hbm_copy_probe", "pabd_batch_sync", "pabd_scene_bond_state", "pabd_set_allocator",
 ]
+
+_ALLOC_T = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+_FREE_T = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 
 
 class PabdError(RuntimeError):
@@ -75,6 +78,13 @@ def lib():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build() first")
+    # PyTorch ships its own HIP runtime and exports its symbols globally; loading it
+    # first makes the library bind to that same runtime, so a process that also
+    # uses torch (streams, events, its allocator) has one HIP runtime, not two
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = C.CDLL(LIB_PATH)
     vp = C.c_void_p
     L.pabd_last_error.restype = C.c_char_p
@@ -86,6 +96,7 @@ def lib():
     L.pabd_scene_residuals.argtypes = [vp, _d, C.c_int32, _i]
     L.pabd_scene_contacts.argtypes = [vp, C.c_int32, _i, _i, _i, _d, _d, _d, _d, _i]
     L.pabd_scene_bond_state.argtypes = [vp, _d, _d]
+    L.pabd_set_allocator.argtypes = [_ALLOC_T, _FREE_T, vp]
     L.pabd_scene_bytes.argtypes = [_P(_Desc)]
     L.pabd_scene_bytes.restype = C.c_size_t
     L.pabd_scene_set_debug.argtypes = [vp, C.c_int32]
@@ -172,6 +183,34 @@ class _Marshalled:
         d.al_gamma = s.al_gamma
         d.order = _ptr(s.order, C.c_int32)
         self.desc = d
+
+
+_allocator_refs = None  # the callbacks must outlive every handle that uses them
+
+
+def use_torch_allocator(enable: bool = True):
+    """Route the device memory of scenes and batches created from now on through
+    PyTorch's caching allocator (enable=False restores hipMalloc).  Handles keep
+    the allocator they were created with."""
+    global _allocator_refs
+    if not enable:
+        _check(lib().pabd_set_allocator(_ALLOC_T(), _FREE_T(), None))
+        return
+    import torch
+
+    def _alloc(nbytes, ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes))
+        except Exception:  # out of memory: the library reports PABD_E_OOM
+            return None
+
+    def _free(ptr, ctx):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    refs = (_ALLOC_T(_alloc), _FREE_T(_free))
+    _check(lib().pabd_set_allocator(refs[0], refs[1], None))
+    keep = [] if _allocator_refs is None else list(_allocator_refs)
+    _allocator_refs = keep + [refs]
 
 
 def device_count() -> int:

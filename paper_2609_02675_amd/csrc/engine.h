@@ -28,6 +28,34 @@ namespace pabd {
     }                                                                      \
   } while (0)
 
+// device memory: hipMalloc/hipFree, or a caller's allocator (pabd_set_allocator);
+// each engine keeps the one in force when it was created, for its whole life
+struct DeviceAllocator {
+  void* (*alloc)(size_t, void*) = nullptr;
+  void (*release)(void*, void*) = nullptr;
+  void* ctx = nullptr;
+  hipError_t get(void** p, size_t bytes) const {
+    if (alloc) {
+      *p = alloc(bytes, ctx);
+      return *p ? hipSuccess : hipErrorOutOfMemory;
+    }
+    return hipMalloc(p, bytes);
+  }
+  void put(void* p) const {
+    if (!p) return;
+    if (alloc) {
+      if (release) release(p, ctx);
+    } else {
+      (void)hipFree(p);
+    }
+  }
+};
+
+inline DeviceAllocator& current_allocator() {
+  static DeviceAllocator a;
+  return a;
+}
+
 // one segment of a staged upload: bytes at src_off of the staging buffer go to dst
 struct Seg {
   char* dst;
@@ -97,6 +125,7 @@ struct Engine {
 
   std::vector<void*> allocs;
   std::string err;
+  DeviceAllocator dev = current_allocator();
   // staged uploads: one pinned host buffer, one device buffer, grown on demand
   char* h_stage = nullptr;
   char* d_stage = nullptr;
@@ -104,10 +133,10 @@ struct Engine {
 
   ~Engine() { release(); }
   void release() {
-    for (void* p : allocs) (void)hipFree(p);
+    for (void* p : allocs) dev.put(p);
     allocs.clear();
     if (h_stage) (void)hipHostFree(h_stage);
-    if (d_stage) (void)hipFree(d_stage);
+    dev.put(d_stage);
     h_stage = d_stage = nullptr;
     stage_cap = 0;
   }
@@ -132,11 +161,11 @@ struct Engine {
     if (need > stage_cap) {
       size_t cap2 = std::max<size_t>(need, std::max<size_t>(2 * stage_cap, 1 << 20));
       if (h_stage) (void)hipHostFree(h_stage);
-      if (d_stage) (void)hipFree(d_stage);
+      dev.put(d_stage);
       h_stage = d_stage = nullptr;
       stage_cap = 0;
       PABD_HIP(hipHostMalloc(reinterpret_cast<void**>(&h_stage), cap2, hipHostMallocDefault));
-      PABD_HIP(hipMalloc(reinterpret_cast<void**>(&d_stage), cap2));
+      PABD_HIP(dev.get(reinterpret_cast<void**>(&d_stage), cap2));
       stage_cap = cap2;
     }
     size_t k = 0;
@@ -160,9 +189,9 @@ struct Engine {
   template <typename U>
   pabd_status alloc(U*& p, size_t count) {
     void* v = nullptr;
-    hipError_t e = hipMalloc(&v, std::max<size_t>(count, 1) * sizeof(U));
+    hipError_t e = dev.get(&v, std::max<size_t>(count, 1) * sizeof(U));
     if (e != hipSuccess) {
-      err = std::string("hipMalloc of ") + std::to_string(count * sizeof(U)) +
+      err = std::string("device allocation of ") + std::to_string(count * sizeof(U)) +
             " bytes failed: " + hipGetErrorString(e);
       (void)hipGetLastError();
       return PABD_E_OOM;
@@ -445,6 +474,12 @@ struct Engine {
     hipLaunchKernelGGL(k_predict<T>, g, b, 0, st, v);
     double* hn = history ? rh_num : nullptr;
     double* hd = history ? rh_den : nullptr;
+    if (history) {
+      const long long nh = (long long)kmax * cap.n;
+      const dim3 gz((unsigned)std::max(1LL, (nh + 255) / 256));
+      hipLaunchKernelGGL(k_zero_double, gz, dim3(256), 0, st, rh_num, nh);
+      hipLaunchKernelGGL(k_zero_double, gz, dim3(256), 0, st, rh_den, nh);
+    }
     constexpr int LPB = 4;  // lanes per body when contacts are present
     const dim3 gc = grid_for((int)std::min<long long>((long long)cap.n * LPB, INT_MAX), 256);
     for (int k = 0; k < kmax; ++k) {

@@ -440,7 +440,15 @@ __global__ void __launch_bounds__(256) k_reduce_residual(const SceneDev* scenes,
   if (threadIdx.x == 0) rho[sc] = sd[0] > 0.0 ? sqrt(sn[0] / sd[0]) : 0.0;
 }
 
-// residual history: rho_k for every k of the last step (plain path diagnostics)
+// zero n doubles (a kernel, so that it can sit in a captured graph)
+__global__ void __launch_bounds__(256) k_zero_double(double* p, long long n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0;
+}
+
+// residual history: rho_k for every k of the last step (plain path diagnostics);
+// the partials of bodies that do not iterate (pinned) stay at the zero the step
+// starts from
 __global__ void __launch_bounds__(256) k_reduce_history(int n, int K, const double* num,
                                                        const double* den, double* rho) {
   __shared__ double sn[256], sd[256];

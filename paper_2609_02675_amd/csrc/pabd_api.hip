@@ -315,7 +315,7 @@ pabd_status pabd_scene_create(const pabd_scene_desc* desc, pabd_scene** out) {
 
 pabd_status pabd_scene_destroy(pabd_scene* s) {
   if (!s) return PABD_OK;
-  if (s->stream) (void)hipStreamSynchronize(s->stream);
+  (void)hipDeviceSynchronize();  // steps may have been enqueued on a caller's stream
   s->graph.reset();
   s->eng.reset();
   if (s->stream) (void)hipStreamDestroy(s->stream);
@@ -324,6 +324,16 @@ pabd_status pabd_scene_destroy(pabd_scene* s) {
 }
 
 void* pabd_scene_stream(pabd_scene* s) { return s ? (void*)s->stream : nullptr; }
+
+pabd_status pabd_set_allocator(void* (*alloc)(size_t bytes, void* ctx), void (*release)(void* ptr, void* ctx),
+                               void* ctx) {
+  if (alloc && !release) return fail(PABD_E_INVALID, "an allocator needs a matching free");
+  DeviceAllocator& a = current_allocator();
+  a.alloc = alloc;
+  a.release = alloc ? release : nullptr;
+  a.ctx = alloc ? ctx : nullptr;
+  return PABD_OK;
+}
 
 static void scene_enqueue_step(pabd_scene* s, hipStream_t st) {
   const HostScene& hs = s->hs;
@@ -555,6 +565,7 @@ struct pabd_batch {
   // device tile table
   int *d_first = nullptr, *d_count = nullptr, *d_kmax = nullptr, *d_ntiles = nullptr;
   int tile_table_cap = 0;
+  DeviceAllocator dev = current_allocator();
   Graph graph;
   bool dirty = true;
   int grid_tiles = 0;
@@ -598,16 +609,17 @@ pabd_status batch_tables(pabd_batch* b) {
   if (nt > b->tile_table_cap) {
     int cap = std::max(nt, 2 * b->tile_table_cap + 16);
     if (b->d_first) {
-      (void)hipFree(b->d_first);
-      (void)hipFree(b->d_count);
-      (void)hipFree(b->d_kmax);
+      API_HIP(hipStreamSynchronize(b->stream));
+      b->dev.put(b->d_first);
+      b->dev.put(b->d_count);
+      b->dev.put(b->d_kmax);
     }
-    API_HIP(hipMalloc(&b->d_first, cap * sizeof(int)));
-    API_HIP(hipMalloc(&b->d_count, cap * sizeof(int)));
-    API_HIP(hipMalloc(&b->d_kmax, cap * sizeof(int)));
+    API_HIP(b->dev.get(reinterpret_cast<void**>(&b->d_first), cap * sizeof(int)));
+    API_HIP(b->dev.get(reinterpret_cast<void**>(&b->d_count), cap * sizeof(int)));
+    API_HIP(b->dev.get(reinterpret_cast<void**>(&b->d_kmax), cap * sizeof(int)));
     b->tile_table_cap = cap;
   }
-  if (!b->d_ntiles) API_HIP(hipMalloc(&b->d_ntiles, sizeof(int)));
+  if (!b->d_ntiles) API_HIP(b->dev.get(reinterpret_cast<void**>(&b->d_ntiles), sizeof(int)));
   if (nt) {
     API_HIP(hipMemcpyAsync(b->d_first, first.data(), nt * sizeof(int), hipMemcpyHostToDevice, b->stream));
     API_HIP(hipMemcpyAsync(b->d_count, count.data(), nt * sizeof(int), hipMemcpyHostToDevice, b->stream));
@@ -820,12 +832,12 @@ pabd_status pabd_batch_create(int32_t max_slots, size_t hbm_budget, int32_t prec
 
 pabd_status pabd_batch_destroy(pabd_batch* b) {
   if (!b) return PABD_OK;
-  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  (void)hipDeviceSynchronize();  // steps may have been enqueued on a caller's stream
   b->graph.reset();
-  if (b->d_first) (void)hipFree(b->d_first);
-  if (b->d_count) (void)hipFree(b->d_count);
-  if (b->d_kmax) (void)hipFree(b->d_kmax);
-  if (b->d_ntiles) (void)hipFree(b->d_ntiles);
+  b->dev.put(b->d_first);
+  b->dev.put(b->d_count);
+  b->dev.put(b->d_kmax);
+  b->dev.put(b->d_ntiles);
   b->eng.reset();
   if (b->stream) (void)hipStreamDestroy(b->stream);
   delete b;

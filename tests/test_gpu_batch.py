@@ -140,3 +140,18 @@ def test_full_size_batched_chains_sampled(P):
         e = errors(b.state(slots[k]), _oracle_state(scs[k], 100), scale_of(scs[k]))
         print(scs[k].name, e)
         assert e["pos"] <= 1e-3 and e["rot"] <= 1e-3
+
+
+def test_many_scenes_without_planes_or_driven_bonds_all_admit(P):
+    """Scenes without planes or driven bonds take no space in those tables, so the
+    number of resident scenes is not capped by their size (20,000 small chains
+    in a batch whose driven-bond table holds about 15,000 entries)."""
+    scs = S.batched_chains(20000, seed=11, lo=4, hi=6, precision=S.PREC_FP32)
+    print(f"[case] {len(scs)} small chains", flush=True)
+    b = P.Batch(len(scs) + 8, 1 << 30, S.PREC_FP32)
+    slots = [b.admit(s, 3) for s in scs]
+    assert all(x is not None for x in slots)
+    for _ in range(3):
+        b.step()
+    b.sync()
+    assert sorted(b.poll()) == sorted(slots)
