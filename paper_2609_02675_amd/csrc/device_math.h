@@ -171,58 +171,65 @@ __device__ void nearest_rotation_svd(const T* A, T* R) {
     for (int c = 0; c < 3; ++c) R[3 * r + c] = u1[r] * v1[c] + u2[r] * v2[c] + u3[r] * v3[c];
 }
 
-// One Newton step X <- (zeta X + X^{-T} / zeta) / 2 for the orthogonal polar factor,
-// with determinant scaling zeta = det^{-1/3} only far from orthogonal (near
-// SO(3), det ~ 1).  Returns false when det X is not safely positive.
+// One Newton step X <- (zeta X + X^{-T} / zeta) / 2 for the orthogonal polar
+// factor, in place as X += D with D = (zeta / 2 - 1) X + C / (2 zeta det) (C the
+// cofactor matrix, X^{-T} = C / det), and *step2 = |D|^2.  The determinant
+// scaling zeta = det^{-1/3} applies only far from orthogonal (near SO(3),
+// det ~ 1).  Returns false when det X is not safely positive.
 template <typename T>
 __device__ __forceinline__ bool polar_newton_step(T* X, T* step2) {
   T C[9];
   const T det = cofactor(X, C);
   if (!(det > Eps<T>::det_floor)) return false;
   const T zeta = (det > (T)0.5 && det < (T)1.5) ? (T)1 : rcp(cbrt(det));
-  const T a = (T)0.5 * zeta, b = (T)0.5 * rcp(zeta * det);
-  if (step2) {
-    T diff = 0;
+  const T a = (T)0.5 * zeta - (T)1, b = (T)0.5 * rcp(zeta * det);
+  T diff = 0;
 #pragma unroll
-    for (int k = 0; k < 9; ++k) {
-      const T xn = a * X[k] + b * C[k];
-      const T dk = xn - X[k];
-      diff += dk * dk;
-      X[k] = xn;
-    }
-    *step2 = diff;
-  } else {
-#pragma unroll
-    for (int k = 0; k < 9; ++k) X[k] = a * X[k] + b * C[k];
+  for (int k = 0; k < 9; ++k) {
+    const T dk = a * X[k] + b * C[k];
+    X[k] += dk;
+    diff += dk * dk;
   }
+  *step2 = diff;
   return true;
 }
 
-// Rotation factor of the polar decomposition of A (local step, Sec. 4.2.2):
-// Newton steps in pairs, the size of the second step of each pair ending the
-// iteration (near SO(3) the first pair converges); if det A is not safely
-// positive or Newton stalls, the nearest proper rotation from the SVD.
+// Rotation factor of the polar decomposition (local step, Sec. 4.2.2), in place:
+// X <- R where X = R S.  Newton's iteration: writing X = R (I + E) with E
+// symmetric, one step leaves E' ~ E^2 / 2 and moves X by ~|E|, so a step of
+// squared size below polar_tol2 leaves an error below about polar_tol2 / 2, and
+// the iteration ends after the first such step (one step late in a solve, where
+// the increments are small).  Every Newton iterate has the same orthogonal
+// factor as the input, so if det X is not safely positive or Newton stalls, the
+// nearest proper rotation from the SVD of the current iterate is the answer.
 template <typename T>
-__device__ __forceinline__ void polar_rotation(const T* A, T* R) {
-  T X[9];
-#pragma unroll
-  for (int k = 0; k < 9; ++k) X[k] = A[k];
-  bool ok = false;
+__device__ __forceinline__ void polar_rotation_inplace(T* X) {
+  T d2;
+  bool ok = polar_newton_step<T>(X, &d2);
+  bool done = ok && d2 < Eps<T>::polar_tol2;
+  if (ok && !done) {
 #pragma unroll 1
-  for (int it = 0; it < 8; ++it) {
-    T d2;
-    if (!polar_newton_step<T>(X, nullptr) || !polar_newton_step<T>(X, &d2)) break;
-    if (d2 < Eps<T>::polar_tol2) {
-      ok = true;
-      break;
+    for (int it = 1; it < 16; ++it) {
+      if (!polar_newton_step<T>(X, &d2)) break;
+      if (d2 < Eps<T>::polar_tol2) {
+        done = true;
+        break;
+      }
     }
   }
-  if (ok) {
+  if (!done) {
+    T Y[9];
+    nearest_rotation_svd(X, Y);
 #pragma unroll
-    for (int k = 0; k < 9; ++k) R[k] = X[k];
-  } else {
-    nearest_rotation_svd(A, R);
+    for (int k = 0; k < 9; ++k) X[k] = Y[k];
   }
+}
+
+template <typename T>
+__device__ __forceinline__ void polar_rotation(const T* A, T* R) {
+#pragma unroll
+  for (int k = 0; k < 9; ++k) R[k] = A[k];
+  polar_rotation_inplace(R);
 }
 
 // ---- prediction (Algorithm 1, prediction loop) ---------------------------------

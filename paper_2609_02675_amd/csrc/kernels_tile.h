@@ -78,9 +78,12 @@ __global__ void __launch_bounds__(TB) k_tile_step(View<T> v, TileTable tt) {
       if (present) store<T, QR>(buf + QR * lane, q);
       __syncthreads();
       if (moving && k < K) {
-        T rb[QW];
+        // r = M (s - q^k) + sum of the ends' J^T f (the forces carry h^2); starting
+        // from the inertia term leaves no accumulator to clear
+        T r[QW];
 #pragma unroll
-        for (int c = 0; c < QW; ++c) rb[c] = (T)0;
+        for (int c = 0; c < QW; ++c) r[c] = (T)0;
+        add_inertia(r, m, s, q);
 #pragma unroll
         for (int u = 0; u < MAXE; ++u)
           if (u < ne) {
@@ -93,7 +96,7 @@ __global__ void __launch_bounds__(TB) k_tile_step(View<T> v, TileTable tt) {
               bond_vec<T>(q, E[u], qj, E[u] + 4, d);
             }
             quad_end_force(E[u], d, f);
-            add_JT(rb, E[u], f[0], f[1], f[2]);
+            add_JT(r, E[u], f[0], f[1], f[2]);
           }
         for (int e = e0 + MAXE; e < e0 + ne; ++e) {
           T Eg[EW];
@@ -108,30 +111,34 @@ __global__ void __launch_bounds__(TB) k_tile_step(View<T> v, TileTable tt) {
             bond_vec<T>(q, Eg, qj, Eg + 4, d);
           }
           quad_end_force(Eg, d, f);
-          add_JT(rb, Eg, f[0], f[1], f[2]);
+          add_JT(r, Eg, f[0], f[1], f[2]);
         }
-        T r[QW];  // the forces carry h^2 already
-#pragma unroll
-        for (int c = 0; c < QW; ++c) r[c] = rb[c];
-        add_inertia(r, m, s, q);
         T dq[QW];
         block_apply(fac, r, dq);
-        T qo[QR];
+        // q^{k+1} in place; a lane's last iteration keeps what its residual
+        // |q^{k+1} - q^k|_M / |q^k|_M needs (the position part of the
+        // difference is the increment itself)
+        const bool last = k == K - 1;
+        T Aold[9];
+        if (last) {
+          const double cc[3] = {pos_value(q, 0), pos_value(q, 1), pos_value(q, 2)};
+          den = m_norm2(m, cc, q);
 #pragma unroll
-        for (int c = 0; c < QR; ++c) qo[c] = q[c];
-        pos_add_lo(qo, dq[0], dq[1], dq[2]);
-        T Ah[9];
-#pragma unroll
-        for (int c = 0; c < 9; ++c) Ah[c] = q[3 + c] + dq[3 + c];
-        if (debug & 1) {
-#pragma unroll
-          for (int c = 0; c < 9; ++c) qo[3 + c] = Ah[c];
-        } else {
-          polar_rotation(Ah, qo + 3);
+          for (int c = 0; c < 9; ++c) Aold[c] = q[3 + c];
         }
-        if (k == K - 1) residual_terms(m, qo, q, &num, &den);
+        pos_add_lo(q, dq[0], dq[1], dq[2]);
 #pragma unroll
-        for (int c = 0; c < QR; ++c) q[c] = qo[c];
+        for (int c = 0; c < 9; ++c) q[3 + c] += dq[3 + c];
+        if (!(debug & 1)) polar_rotation_inplace(q + 3);
+        if (last) {
+          T dd[QW];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) dd[c] = dq[c];
+#pragma unroll
+          for (int c = 0; c < 9; ++c) dd[3 + c] = q[3 + c] - Aold[c];
+          const double dc[3] = {(double)dq[0], (double)dq[1], (double)dq[2]};
+          num = m_norm2(m, dc, dd);
+        }
       }
     }
     __syncthreads();  // every lane is done with the q buffers
