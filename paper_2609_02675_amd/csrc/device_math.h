@@ -15,14 +15,22 @@ namespace pabd {
 
 template <typename T>
 struct Eps;
+// polar_tol2: squared Newton step below which the polar iteration ends (the
+// error left is below polar_tol2 / 2); polar_one / polar_two: first-step sizes
+// up to which one / two further unchecked steps leave that same error
+// (2 sqrt(tol) and (64 tol)^(1/4), rounded down)
 template <>
 struct Eps<float> {
-  static constexpr float polar_tol2 = 1e-7f;   // squared step norm that ends Newton
+  static constexpr float polar_tol2 = 1e-7f;
+  static constexpr float polar_one = 6.0e-4f;
+  static constexpr float polar_two = 4.5e-2f;
   static constexpr float det_floor = 1e-6f;
 };
 template <>
 struct Eps<double> {
   static constexpr double polar_tol2 = 1e-16;
+  static constexpr double polar_one = 1.9e-8;
+  static constexpr double polar_two = 2.7e-4;
   static constexpr double det_floor = 1e-12;
 };
 
@@ -175,13 +183,15 @@ __device__ void nearest_rotation_svd(const T* A, T* R) {
 // factor, in place as X += D with D = (zeta / 2 - 1) X + C / (2 zeta det) (C the
 // cofactor matrix, X^{-T} = C / det), and *step2 = |D|^2.  The determinant
 // scaling zeta = det^{-1/3} applies only far from orthogonal (near SO(3),
-// det ~ 1).  Returns false when det X is not safely positive.
+// det ~ 1); *unscaled tells whether the step ran with zeta = 1.  Returns false
+// when det X is not safely positive.
 template <typename T>
-__device__ __forceinline__ bool polar_newton_step(T* X, T* step2) {
+__device__ __forceinline__ bool polar_newton_step(T* X, T* step2, bool* unscaled) {
   T C[9];
   const T det = cofactor(X, C);
   if (!(det > Eps<T>::det_floor)) return false;
-  const T zeta = (det > (T)0.5 && det < (T)1.5) ? (T)1 : rcp(cbrt(det));
+  *unscaled = det > (T)0.5 && det < (T)1.5;
+  const T zeta = *unscaled ? (T)1 : rcp(cbrt(det));
   const T a = (T)0.5 * zeta - (T)1, b = (T)0.5 * rcp(zeta * det);
   T diff = 0;
 #pragma unroll
@@ -194,34 +204,64 @@ __device__ __forceinline__ bool polar_newton_step(T* X, T* step2) {
   return true;
 }
 
+// An unscaled Newton step X <- (X + X^{-T}) / 2 whose size is not measured, for
+// the lanes with on set (only right after a step, when det X >= 1); the other
+// lanes keep X (coefficients 1 and 0).  Run by the whole wave, so that no lane's
+// registers need merging afterwards.
+template <typename T>
+__device__ __forceinline__ void polar_newton_plain(T* X, bool on) {
+  T C[9];
+  const T det = cofactor(X, C);
+  const T a = on ? (T)0.5 : (T)1;
+  const T b = on ? (T)0.5 * rcp(det) : (T)0;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) X[k] = a * X[k] + b * C[k];
+}
+
+__device__ __forceinline__ bool wave_any(bool p) { return __builtin_amdgcn_ballot_w64(p) != 0; }
+
 // Rotation factor of the polar decomposition (local step, Sec. 4.2.2), in place:
-// X <- R where X = R S.  Newton's iteration: writing X = R (I + E) with E
-// symmetric, one step leaves E' ~ E^2 / 2 and moves X by ~|E|, so a step of
-// squared size below polar_tol2 leaves an error below about polar_tol2 / 2, and
-// the iteration ends after the first such step (one step late in a solve, where
-// the increments are small).  Every Newton iterate has the same orthogonal
-// factor as the input, so if det X is not safely positive or Newton stalls, the
-// nearest proper rotation from the SVD of the current iterate is the answer.
+// X <- R where X = R S.  Newton's iteration acts on each singular value alone,
+// s <- (s + 1/s) / 2, so with e = s - 1 a step moves s by |s^2 - 1| / (2 s) and
+// leaves e' = (s - 1)^2 / (2 s), at most half the square of that move, and each
+// later move is at most the e it starts from.  Hence for Frobenius norms: the
+// error left after a step of squared size D is at most D / 2, and the next
+// step's squared size is at most D^2 / 4.  The first step is measured: below
+// polar_tol2 the iteration ends; below polar_one (polar_two) one (two) further
+// steps leave an error below polar_tol2 / 2 without being measured; otherwise
+// measured steps continue.  Every Newton iterate has the input's orthogonal
+// factor, so if det X is not safely positive or Newton stalls, the nearest
+// proper rotation from the SVD of the current iterate is the answer.
 template <typename T>
 __device__ __forceinline__ void polar_rotation_inplace(T* X) {
   T d2;
-  bool ok = polar_newton_step<T>(X, &d2);
-  bool done = ok && d2 < Eps<T>::polar_tol2;
-  if (ok && !done) {
+  bool unscaled = false;
+  const bool ok = polar_newton_step<T>(X, &d2, &unscaled);
+  const bool conv = ok && d2 < Eps<T>::polar_tol2;
+  const bool one = ok && !conv && unscaled && d2 <= Eps<T>::polar_two;
+  const bool two = one && d2 > Eps<T>::polar_one;
+  if (wave_any(one)) {
+    polar_newton_plain<T>(X, one);
+    if (wave_any(two)) polar_newton_plain<T>(X, two);
+  }
+  bool done = conv || one;
+  if (wave_any(!done)) {
+    if (ok && !done) {
 #pragma unroll 1
-    for (int it = 1; it < 16; ++it) {
-      if (!polar_newton_step<T>(X, &d2)) break;
-      if (d2 < Eps<T>::polar_tol2) {
-        done = true;
-        break;
+      for (int it = 1; it < 16; ++it) {
+        if (!polar_newton_step<T>(X, &d2, &unscaled)) break;
+        if (d2 < Eps<T>::polar_tol2) {
+          done = true;
+          break;
+        }
       }
     }
-  }
-  if (!done) {
-    T Y[9];
-    nearest_rotation_svd(X, Y);
+    if (!done) {
+      T Y[9];
+      nearest_rotation_svd(X, Y);
 #pragma unroll
-    for (int k = 0; k < 9; ++k) X[k] = Y[k];
+      for (int k = 0; k < 9; ++k) X[k] = Y[k];
+    }
   }
 }
 
