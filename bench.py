@@ -31,11 +31,18 @@ sys.path.insert(0, ROOT)
 METRIC = "affine-body SSM iterations/s (served/batched vs plain); p50/p99 step ms"
 HBM_PEAK = 8.0e12            # B/s, MI355X HBM3E
 FP32_VALU_PEAK = 78.6e12     # flop/s: 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz, unpacked FP32
-# algorithmic bytes moved per body and step by the tile kernel: read q (16 floats:
-# c_hi, A, c_lo), v/w (8), mass (8), H^-1 factor (12), two bond ends (8 floats +
-# partner id each), scene id, flags, end range; write q, v/w and the two FP64
-# residual partials
-TILE_BYTES_PER_BODY_STEP = 64 + 32 + 32 + 48 + 2 * (32 + 4) + 4 + 1 + 8 + 64 + 32 + 16
+# algorithmic bytes the tile kernel moves per body: once per launch it reads q
+# (16 floats: c_hi, A, c_lo), v/w (8), mass (8), H^-1 factor (12), two bond ends
+# (8 floats + partner id each), scene id, flags and end range; after every step
+# it writes q and v/w
+TILE_LOAD_BYTES_PER_BODY = 64 + 32 + 32 + 48 + 2 * (32 + 4) + 4 + 1 + 8
+TILE_STORE_BYTES_PER_BODY_STEP = 64 + 32
+
+
+def tile_bytes(n_bodies, steps_per_launch):
+    return n_bodies * (TILE_LOAD_BYTES_PER_BODY + steps_per_launch * TILE_STORE_BYTES_PER_BODY_STEP)
+
+
 # flops of one body-iteration of a two-bond chain body: bond terms (2 x 63),
 # inertia term (81), block solve (84), increment (12), two Newton polar steps
 # (2 x 90; FP32 converges in two from a near-rotation)
@@ -53,9 +60,10 @@ TILE_SOURCES = ["common.h", "device_math.h", "kernels_step.h", "kernels_tile.h"]
 TILE_PROFILE = os.path.join(ROOT, "profiles", "k_tile_step_batched_chains_4096.md")
 
 
-def tile_traffic():
+def tile_traffic(steps_per_launch):
     """HBM bytes per tile-kernel launch from the committed counter profile, if the
-    kernel sources still hash to what was profiled; else None."""
+    kernel sources still hash to what was profiled and the profile ran the same
+    steps per launch; else None."""
     import hashlib
     h = hashlib.sha256()
     for f in TILE_SOURCES:
@@ -68,7 +76,8 @@ def tile_traffic():
     import re
     m = re.search(r"kernel-source-sha256-16:\s*([0-9a-f]{16})", text)
     t = re.search(r"traffic_bytes_per_launch:\s*(\d+)", text)
-    if not m or not t or m.group(1) != h.hexdigest()[:16]:
+    n = re.search(r"steps_per_launch:\s*(\d+)", text)
+    if not m or not t or not n or m.group(1) != h.hexdigest()[:16] or int(n.group(1)) != steps_per_launch:
         return None
     return float(t.group(1))
 
@@ -122,9 +131,10 @@ def host_info():
     return dict(logical_cpus=os.cpu_count(), model=model)
 
 
-def big_batch_leg(P, S, torch, n_scenes, steps):
+def big_batch_leg(P, S, torch, n_scenes, steps, spl):
     """The batched chains at 16x the default count (about 2.2M bodies, a working
-    set well beyond the 256 MB last-level cache), tile 64, FP32."""
+    set well beyond the 256 MB last-level cache), tile 64, FP32, spl steps per
+    tile-kernel launch."""
     import oracle
     sys.path.insert(0, os.path.join(ROOT, "tests"))
     from parity import errors, scale_of
@@ -138,33 +148,35 @@ def big_batch_leg(P, S, torch, n_scenes, steps):
     log(f"big batch: {n_scenes} scenes, {nb} bodies admitted in {time.perf_counter() - t:.1f}s")
     stream = torch.cuda.Stream()
     sptr = stream.cuda_stream
-    warm = 2
-    for _ in range(warm):
-        b.step(stream=sptr)
+    launches = max(1, steps // spl)
+    b.step(stream=sptr, nsteps=spl)  # warm-up and graph capture
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     e0.record(stream)
-    for _ in range(steps):
-        b.step(stream=sptr)
+    for _ in range(launches):
+        b.step(stream=sptr, nsteps=spl)
     e1.record(stream)
     torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / steps
+    ms = e0.elapsed_time(e1) / (launches * spl)
     iters = scs[0].iters
-    tile_ms = b.time_tile_kernel(5)
+    reps = 2
+    launch_ms = b.time_tile_kernel(reps, spl)
+    tile_ms = launch_ms / spl
     flops = nb * iters * FLOPS_PER_BODY_ITER
-    byts = nb * TILE_BYTES_PER_BODY_STEP
     acc = 0.0
     for k in (0, n_scenes // 2, n_scenes - 1):
         o = oracle.Oracle(scs[k].copy(precision=S.PREC_FP64))
-        o.step(warm + steps + 6)  # time_tile_kernel advanced every scene 1 + 5 steps
+        # time_tile_kernel advanced every scene (1 + reps) launches
+        o.step((1 + launches + 1 + reps) * spl)
         e = errors(b.state(slots[k]), o.state(), scale_of(scs[k]))
         acc = max(acc, e["pos"], e["rot"])
     b.close()
-    out = dict(scenes=n_scenes, bodies=nb, iters=iters, ms_per_step=ms,
-               body_its_per_s=nb * iters / (ms / 1e3), tile_kernel_ms=tile_ms,
+    out = dict(scenes=n_scenes, bodies=nb, iters=iters, steps_per_launch=spl, ms_per_step=ms,
+               body_its_per_s=nb * iters / (ms / 1e3), tile_kernel_ms_per_launch=launch_ms,
+               tile_kernel_ms_per_step=tile_ms,
                alu_frac=flops / (tile_ms / 1e3) / FP32_VALU_PEAK,
-               hbm_GBs_algorithmic=byts / (tile_ms / 1e3) / 1e9,
-               working_set_bytes=nb * TILE_BYTES_PER_BODY_STEP,
+               hbm_GBs_algorithmic=tile_bytes(nb, spl) / (launch_ms / 1e3) / 1e9,
+               load_bytes_per_launch=nb * TILE_LOAD_BYTES_PER_BODY,
                max_rel_err_vs_fp64_oracle=acc, tile_bodies=64)
     log("big batch", out)
     return out
@@ -209,6 +221,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps-per-launch", type=int, default=10,
+                    help="batched leg: steps one tile-kernel launch (one graph replay) runs")
     ap.add_argument("--scenes", type=int, default=4096)
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--tile", type=int, default=0)
@@ -256,7 +270,12 @@ def main():
     import paper_2609_02675_amd as P
     if P.device_count() < 1:
         raise SystemExit("no HIP device visible")
-    total_steps = args.warmup + args.steps
+    spl = args.steps_per_launch
+    if spl < 1 or args.steps % spl:
+        raise SystemExit("--steps must be a multiple of --steps-per-launch")
+    launches = args.steps // spl
+    warm_launches = max(1, -(-args.warmup // spl))
+    total_steps = warm_launches * spl + args.steps
     b = P.Batch(len(scenes) + 8, 4 << 30, S.PREC_FP32)
     t = time.perf_counter()
     slots = [b.admit(s, 1 << 30) for s in scenes]
@@ -270,26 +289,30 @@ def main():
         log(f"autotune picked tile {tb} in {time.perf_counter() - t:.1f}s")
     lay = b.layout()
 
+    # timed: `launches` graph replays of spl steps each (one tile-kernel launch
+    # runs all spl steps of every tile), an event after every replay
     stream = torch.cuda.Stream()
     sptr = stream.cuda_stream
-    for _ in range(args.warmup):
-        b.step(stream=sptr)
+    for _ in range(warm_launches):
+        b.step(stream=sptr, nsteps=spl)
     torch.cuda.synchronize()
-    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(launches + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     evs[0].record(stream)
-    for k in range(args.steps):
-        b.step(stream=sptr)
+    for k in range(launches):
+        b.step(stream=sptr, nsteps=spl)
         evs[k + 1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    step_ms = np.array([evs[k].elapsed_time(evs[k + 1]) for k in range(args.steps)])
+    launch_ms = np.array([evs[k].elapsed_time(evs[k + 1]) for k in range(launches)])
+    step_ms = launch_ms / spl
     total_ms = evs[0].elapsed_time(evs[-1])
     ms_per_step = total_ms / args.steps
     body_its = n_bodies * iters * args.steps
     value = body_its / (total_ms / 1e3)
-    log(f"batched: {ms_per_step:.4f} ms/step, {value:.4g} body-it/s (host wall {wall:.3f}s)")
+    log(f"batched: {ms_per_step:.4f} ms/step, {value:.4g} body-it/s, {spl} steps per launch "
+        f"(host wall {wall:.3f}s)")
 
     # accuracy of the benchmarked run on sampled scenes vs the FP64 oracle
     import oracle
@@ -304,25 +327,27 @@ def main():
         acc = max(acc, e["pos"], e["rot"])
     log(f"accuracy vs oracle after {total_steps} steps: {acc:.3e}")
 
-    # dominant kernel: the tile kernel alone, timed with HIP events on its stream
-    tile_ms = b.time_tile_kernel(20)
-    body_steps = n_bodies
-    tile_bytes = body_steps * TILE_BYTES_PER_BODY_STEP
-    tile_flops = n_bodies * iters * FLOPS_PER_BODY_ITER
-    hbm_ach = tile_bytes / (tile_ms / 1e3)
-    alu_ach = tile_flops / (tile_ms / 1e3)
-    traffic = tile_traffic()
+    # dominant kernel: the tile kernel alone (spl steps per launch), timed with
+    # HIP events on its stream
+    tile_launch_ms = b.time_tile_kernel(max(2, 20 // spl), spl)
+    tile_ms = tile_launch_ms / spl
+    tbytes = tile_bytes(n_bodies, spl)
+    tile_flops = n_bodies * iters * spl * FLOPS_PER_BODY_ITER
+    hbm_ach = tbytes / (tile_launch_ms / 1e3)
+    alu_ach = tile_flops / (tile_launch_ms / 1e3)
+    traffic = tile_traffic(spl)
+    common = dict(traffic=traffic, traffic_unit="bytes/launch", kernel="k_tile_step<float>",
+                  steps_per_launch=spl, kernel_ms_per_launch=tile_launch_ms, kernel_ms_per_step=tile_ms,
+                  flops_per_launch=tile_flops, bytes_per_launch=tbytes)
     if alu_ach / FP32_VALU_PEAK >= hbm_ach / HBM_PEAK:
         roof = dict(bound="alu", achieved=alu_ach / 1e12, peak=FP32_VALU_PEAK / 1e12, unit="TFLOP/s",
-                    frac=alu_ach / FP32_VALU_PEAK, traffic=traffic, traffic_unit="bytes/launch", kernel="k_tile_step<float>",
-                    kernel_ms=tile_ms, flops_per_launch=tile_flops, bytes_per_launch=tile_bytes,
-                    hbm_achieved_GBs=hbm_ach / 1e9)
+                    frac=alu_ach / FP32_VALU_PEAK, hbm_achieved_GBs=hbm_ach / 1e9, **common)
     else:
         roof = dict(bound="hbm", achieved=hbm_ach / 1e9, peak=HBM_PEAK / 1e9, unit="GB/s",
-                    frac=hbm_ach / HBM_PEAK, traffic=traffic, traffic_unit="bytes/launch", kernel="k_tile_step<float>",
-                    kernel_ms=tile_ms, flops_per_launch=tile_flops, bytes_per_launch=tile_bytes)
+                    frac=hbm_ach / HBM_PEAK, **common)
     eff_bw = value * STREAM_BYTES_PER_BODY_ITER
-    log(f"tile kernel {tile_ms:.4f} ms; roofline {roof['bound']} frac {roof['frac']:.3f}")
+    log(f"tile kernel {tile_launch_ms:.4f} ms per launch of {spl} steps ({tile_ms:.4f} ms per step); "
+        f"roofline {roof['bound']} frac {roof['frac']:.3f}")
 
     # achievable HBM bandwidth: device-wide streaming copy of 1 GiB
     probe_gbs, _ = P.hbm_copy_probe(1 << 30, 10)
@@ -478,7 +503,7 @@ def main():
     big = None
     if args.big_scenes > 0:
         del b
-        big = big_batch_leg(P, S, torch, args.big_scenes, 5)
+        big = big_batch_leg(P, S, torch, args.big_scenes, 2 * spl, spl)
 
     oracle_1core = None
     if not args.no_oracle_single:
@@ -504,9 +529,12 @@ def main():
         "config": {"workload": f"batched_chains_{len(scenes)}", "scenes": len(scenes),
                    "bodies": n_bodies, "iters": iters, "dt": scenes[0].h,
                    "tile_bodies": lay["tile_bodies"], "tiles": lay["tiles"],
-                   "mode": "batched, one graph replay per step"},
+                   "steps_per_launch": spl,
+                   "mode": f"batched, one graph replay (one tile-kernel launch) per {spl} steps"},
+        # per step: each replay's event-timed duration divided by its steps
         "p50_step_ms": float(np.percentile(step_ms, 50)),
         "p99_step_ms": float(np.percentile(step_ms, 99)),
+        "p50_launch_ms": float(np.percentile(launch_ms, 50)),
         "accuracy": {"max_rel_err_vs_fp64_oracle": acc, "after_steps": total_steps,
                      "tolerance": 1e-3},
         "effective_stream_bandwidth_GBs": eff_bw / 1e9,

@@ -174,6 +174,15 @@ pabd_status pabd_batch_admit(pabd_batch *b, const pabd_scene_desc *desc, int32_t
                              int32_t *slot);
 /* One step of every resident scene that has steps left. */
 pabd_status pabd_batch_step(pabd_batch *b, void *hip_stream);
+/* nsteps steps (1..PABD_MAX_STEPS_PER_LAUNCH) of every resident scene, each
+ * scene stopping at its own step count: the same result as nsteps calls of
+ * pabd_batch_step.  Tiled scenes run all nsteps in one launch of the tile
+ * kernel (a tile's bodies are loaded once and stored after every step);
+ * flat-path scenes take one launch sequence per step.  Nothing can be admitted,
+ * released or read between the steps of one call.  PABD_E_INVALID for nsteps
+ * out of range. */
+#define PABD_MAX_STEPS_PER_LAUNCH 256
+pabd_status pabd_batch_steps(pabd_batch *b, int32_t nsteps, void *hip_stream);
 /* Slots whose scenes finished all their steps (host bookkeeping, no sync). */
 pabd_status pabd_batch_poll(pabd_batch *b, int32_t *done, int32_t cap, int32_t *n_done);
 pabd_status pabd_batch_read_state(pabd_batch *b, int32_t slot, double *c, double *A, double *v,
@@ -190,10 +199,12 @@ pabd_status pabd_batch_set_tile(pabd_batch *b, int32_t tile_bodies);
 void *pabd_batch_stream(pabd_batch *b);
 /* Block until all work enqueued on the batch's stream has finished. */
 pabd_status pabd_batch_sync(pabd_batch *b);
-/* Measurement: launch the tile kernel alone reps times on the batch's stream
- * between two HIP events and return its average duration in ms (0 if no scene
- * is tiled).  Advances the tiled scenes' bodies like extra steps would. */
-pabd_status pabd_batch_time_tile_kernel(pabd_batch *b, int32_t reps, double *avg_ms);
+/* Measurement: launch the tile kernel alone reps times, nsteps steps per
+ * launch, on the batch's stream between two HIP events and return the average
+ * duration of one launch in ms (0 if no scene is tiled).  Advances the tiled
+ * scenes like reps * nsteps extra steps would. */
+pabd_status pabd_batch_time_tile_kernel(pabd_batch *b, int32_t reps, int32_t nsteps,
+                                        double *avg_ms);
 /* Bodies, tiles and tile size currently in the batch. */
 pabd_status pabd_batch_layout(pabd_batch *b, int32_t *n_bodies, int32_t *n_tiles,
                               int32_t *tile_bodies);

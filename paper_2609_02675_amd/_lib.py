@@ -24,6 +24,7 @@ SYMBOLS = [
     "pabd_scene_step", "pabd_scene_read_state", "pabd_scene_residuals", "pabd_scene_contacts",
     "pabd_scene_bytes", "pabd_scene_set_debug", "pabd_scene_poke", "pabd_scene_stream",
     "pabd_batch_create", "pabd_batch_destroy", "pabd_batch_admit", "pabd_batch_step",
+    "pabd_batch_steps",
     "pabd_batch_poll", "pabd_batch_read_state", "pabd_batch_residual", "pabd_batch_release",
     "pabd_batch_steps_done", "pabd_batch_autotune", "pabd_batch_set_tile", "pabd_batch_stream",
     "pabd_batch_memory", "pabd_batch_time_tile_kernel", "pabd_batch_layout",
@@ -107,6 +108,7 @@ def lib():
     L.pabd_batch_destroy.argtypes = [vp]
     L.pabd_batch_admit.argtypes = [vp, _P(_Desc), C.c_int32, _i]
     L.pabd_batch_step.argtypes = [vp, vp]
+    L.pabd_batch_steps.argtypes = [vp, C.c_int32, vp]
     L.pabd_batch_poll.argtypes = [vp, _i, C.c_int32, _i]
     L.pabd_batch_read_state.argtypes = [vp, C.c_int32, _d, _d, _d, _d]
     L.pabd_batch_residual.argtypes = [vp, C.c_int32, _d]
@@ -117,7 +119,7 @@ def lib():
     L.pabd_batch_stream.argtypes = [vp]
     L.pabd_batch_stream.restype = vp
     L.pabd_batch_memory.argtypes = [vp, _P(C.c_size_t), _P(C.c_size_t)]
-    L.pabd_batch_time_tile_kernel.argtypes = [vp, C.c_int32, _d]
+    L.pabd_batch_time_tile_kernel.argtypes = [vp, C.c_int32, C.c_int32, _d]
     L.pabd_batch_layout.argtypes = [vp, _i, _i, _i]
     L.pabd_hbm_copy_probe.argtypes = [C.c_size_t, C.c_int32, _d, _d]
     L.pabd_batch_sync.argtypes = [vp]
@@ -333,8 +335,14 @@ class Batch:
         self._n[slot.value] = scene.n_bodies
         return slot.value
 
-    def step(self, stream: Optional[int] = None):
-        _check(lib().pabd_batch_step(self._h, C.c_void_p(stream) if stream else None))
+    def step(self, stream: Optional[int] = None, nsteps: int = 1):
+        """nsteps steps of every resident scene (pabd_batch_steps; one tile
+        kernel launch runs all of them)."""
+        s = C.c_void_p(stream) if stream else None
+        if nsteps == 1:
+            _check(lib().pabd_batch_step(self._h, s))
+        else:
+            _check(lib().pabd_batch_steps(self._h, int(nsteps), s))
 
     def sync(self):
         _check(lib().pabd_batch_sync(self._h))
@@ -376,9 +384,10 @@ class Batch:
     def set_tile(self, tile_bodies: int):
         _check(lib().pabd_batch_set_tile(self._h, int(tile_bodies)))
 
-    def time_tile_kernel(self, reps: int) -> float:
+    def time_tile_kernel(self, reps: int, nsteps: int = 1) -> float:
+        """Average ms of one tile-kernel launch running nsteps steps."""
         ms = np.zeros(1)
-        _check(lib().pabd_batch_time_tile_kernel(self._h, int(reps), _ptr(ms, C.c_double)))
+        _check(lib().pabd_batch_time_tile_kernel(self._h, int(reps), int(nsteps), _ptr(ms, C.c_double)))
         return float(ms[0])
 
     def layout(self):

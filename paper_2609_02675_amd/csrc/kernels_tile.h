@@ -2,10 +2,11 @@
 // bodies made of whole scenes (joint scenes without contacts), and runs the
 // complete step of Algorithm 1 for them -- prediction, K global/local Jacobi
 // iterations, velocity recovery -- with the bodies' q^k exchanged through LDS
-// (double-buffered: one barrier per iteration).  HBM is touched once per step
-// to load and once to store each body.  The grid is persistent: workgroups
-// stride over the device tile table, so the captured graph's launch shape does
-// not depend on which scenes are resident.
+// (double-buffered: one barrier per iteration).  Tiles never interact, so one
+// launch runs nsteps consecutive steps of its tiles: a body's data is loaded
+// once per launch, and its q and v are stored after every step.  The grid is
+// persistent: workgroups stride over the device tile table, so the captured
+// graph's launch shape does not depend on which scenes are resident.
 #pragma once
 
 #include "common.h"
@@ -22,33 +23,26 @@ struct TileTable {
 };
 
 template <typename T, int TB, int MAXE>
-__global__ void __launch_bounds__(TB) k_tile_step(View<T> v, TileTable tt) {
+__global__ void __launch_bounds__(TB, sizeof(T) == 4 ? 3 : 1) k_tile_step(View<T> v, TileTable tt, int nsteps) {
   constexpr int QR = Rec<T>::Q;
   __shared__ T lq[2][TB * QR];
+  __shared__ T lqn[TB * QR];  // q^n of each lane's body, for velocity recovery
   const int lane = threadIdx.x;
   const int ntiles = *tt.n_tiles;
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const int first = tt.first[t], nb = tt.count[t], kmax = tt.kmax[t];
     const int i = first + lane;
     const int scn = lane < nb ? v.bscene[i] : -1;
-    const bool present = scn >= 0 && v.scenes[scn].step < v.scenes[scn].steps_total;
-    const bool pinned = present && (v.flags[i] & F_PINNED);
-    const bool moving = present && !pinned;
-    T q[QR], s[QR], m[MW], fac[FW];
+    // what no step changes is loaded once per launch; q and v stay in
+    // registers from step to step and are written back after every step
+    const bool pinned = scn >= 0 && (v.flags[i] & F_PINNED);
+    T q[QR], vw[VW], m[MW], fac[FW];
     T E[MAXE][EW];
     int part[MAXE];
-    int e0 = 0, ne = 0, K = 0;
-    T ih = (T)1;
-    int debug = 0;
-    if (present) {
+    int e0 = 0, ne = 0;
+    if (scn >= 0) {
       load<T, QR>(v.qn + (size_t)QR * i, q);
-      const SceneDev& S = v.scenes[scn];
-      K = S.iters;
-      debug = S.debug;
-      const T h = (T)S.h;
-      ih = (T)(1.0 / S.h);
-      if (moving) {
-        T vw[VW];
+      if (!pinned) {
         load<T, VW>(v.vel + (size_t)VW * i, vw);
         load<T, MW>(v.mass + (size_t)MW * i, m);
         load<T, FW>(v.fac + (size_t)FW * i, fac);
@@ -61,118 +55,139 @@ __global__ void __launch_bounds__(TB) k_tile_step(View<T> v, TileTable tt) {
             const int p = v.se_partner[e0 + u];
             part[u] = p < 0 ? -1 : p - first;
           }
+      }
+    }
+    for (int step = 0; step < nsteps; ++step) {
+      // the scene's step counter was advanced by its first lane before the
+      // previous step's last barrier
+      const bool present = scn >= 0 && v.scenes[scn].step < v.scenes[scn].steps_total;
+      const bool moving = present && !pinned;
+      // scene constants are re-read every step rather than held in registers
+      // through the iterations
+      int K = 0, debug = 0;
+      if (present) {
+        K = v.scenes[scn].iters;
+        debug = v.scenes[scn].debug;
+      }
+      T s[QR];
+      if (moving) {
+        store<T, QR>(lqn + QR * lane, q);
         // prediction
+        const SceneDev& S = v.scenes[scn];
+        const T h = (T)S.h;
 #pragma unroll
         for (int c = 0; c < QR; ++c) s[c] = q[c];
         pos_add_lo(s, h * (vw[0] + h * (T)S.g0), h * (vw[1] + h * (T)S.g1), h * (vw[2] + h * (T)S.g2));
         predict_rotation(q + 3, vw + 3, h, s + 3);
+#pragma unroll
+        for (int c = 0; c < QR; ++c) q[c] = s[c];
       }
-    }
-    if (moving) {
+      // v is rebuilt from q^{n+1} and q^n after the iterations: nothing of it
+      // needs to live through them
 #pragma unroll
-      for (int c = 0; c < QR; ++c) q[c] = s[c];
-    }
-    double num = 0.0, den = 0.0;
-    for (int k = 0; k < kmax; ++k) {
-      T* buf = lq[k & 1];
-      if (present) store<T, QR>(buf + QR * lane, q);
-      __syncthreads();
-      if (moving && k < K) {
-        // r = M (s - q^k) + sum of the ends' J^T f (the forces carry h^2); starting
-        // from the inertia term leaves no accumulator to clear
-        T r[QW];
+      for (int c = 0; c < VW; ++c) vw[c] = (T)0;
+      double num = 0.0, den = 0.0;
+      for (int k = 0; k < kmax; ++k) {
+        T* buf = lq[k & 1];
+        if (present) store<T, QR>(buf + QR * lane, q);
+        __syncthreads();
+        if (moving && k < K) {
+          // r = M (s - q^k) + sum of the ends' J^T f (the forces carry h^2);
+          // starting from the inertia term leaves no accumulator to clear
+          T r[QW];
 #pragma unroll
-        for (int c = 0; c < QW; ++c) r[c] = (T)0;
-        add_inertia(r, m, s, q);
+          for (int c = 0; c < QW; ++c) r[c] = (T)0;
+          add_inertia(r, m, s, q);
 #pragma unroll
-        for (int u = 0; u < MAXE; ++u)
-          if (u < ne) {
+          for (int u = 0; u < MAXE; ++u)
+            if (u < ne) {
+              T d[3], f[3];
+              if (part[u] < 0) {
+                bond_vec<T>(q, E[u], nullptr, E[u] + 4, d);
+              } else {
+                T qj[QR];
+                load<T, QR>(buf + QR * part[u], qj);
+                bond_vec<T>(q, E[u], qj, E[u] + 4, d);
+              }
+              quad_end_force(E[u], d, f);
+              add_JT(r, E[u], f[0], f[1], f[2]);
+            }
+          for (int e = e0 + MAXE; e < e0 + ne; ++e) {
+            T Eg[EW];
+            load<T, EW>(v.se + (size_t)EW * e, Eg);
+            const int p = v.se_partner[e];
             T d[3], f[3];
-            if (part[u] < 0) {
-              bond_vec<T>(q, E[u], nullptr, E[u] + 4, d);
+            if (p < 0) {
+              bond_vec<T>(q, Eg, nullptr, Eg + 4, d);
             } else {
               T qj[QR];
-              load<T, QR>(buf + QR * part[u], qj);
-              bond_vec<T>(q, E[u], qj, E[u] + 4, d);
+              load<T, QR>(buf + QR * (p - first), qj);
+              bond_vec<T>(q, Eg, qj, Eg + 4, d);
             }
-            quad_end_force(E[u], d, f);
-            add_JT(r, E[u], f[0], f[1], f[2]);
+            quad_end_force(Eg, d, f);
+            add_JT(r, Eg, f[0], f[1], f[2]);
           }
-        for (int e = e0 + MAXE; e < e0 + ne; ++e) {
-          T Eg[EW];
-          load<T, EW>(v.se + (size_t)EW * e, Eg);
-          const int p = v.se_partner[e];
-          T d[3], f[3];
-          if (p < 0) {
-            bond_vec<T>(q, Eg, nullptr, Eg + 4, d);
-          } else {
-            T qj[QR];
-            load<T, QR>(buf + QR * (p - first), qj);
-            bond_vec<T>(q, Eg, qj, Eg + 4, d);
+          T dq[QW];
+          block_apply(fac, r, dq);
+          // q^{k+1} in place; a lane's last iteration keeps what its residual
+          // |q^{k+1} - q^k|_M / |q^k|_M needs (the position part of the
+          // difference is the increment itself)
+          const bool last = k == K - 1;
+          T Aold[9];
+          if (last) {
+            const double cc[3] = {pos_value(q, 0), pos_value(q, 1), pos_value(q, 2)};
+            den = m_norm2(m, cc, q);
+#pragma unroll
+            for (int c = 0; c < 9; ++c) Aold[c] = q[3 + c];
           }
-          quad_end_force(Eg, d, f);
-          add_JT(r, Eg, f[0], f[1], f[2]);
-        }
-        T dq[QW];
-        block_apply(fac, r, dq);
-        // q^{k+1} in place; a lane's last iteration keeps what its residual
-        // |q^{k+1} - q^k|_M / |q^k|_M needs (the position part of the
-        // difference is the increment itself)
-        const bool last = k == K - 1;
-        T Aold[9];
-        if (last) {
-          const double cc[3] = {pos_value(q, 0), pos_value(q, 1), pos_value(q, 2)};
-          den = m_norm2(m, cc, q);
+          pos_add_lo(q, dq[0], dq[1], dq[2]);
 #pragma unroll
-          for (int c = 0; c < 9; ++c) Aold[c] = q[3 + c];
-        }
-        pos_add_lo(q, dq[0], dq[1], dq[2]);
+          for (int c = 0; c < 9; ++c) q[3 + c] += dq[3 + c];
+          if (!(debug & 1)) polar_rotation_inplace(q + 3);
+          if (last) {
+            T dd[QW];
 #pragma unroll
-        for (int c = 0; c < 9; ++c) q[3 + c] += dq[3 + c];
-        if (!(debug & 1)) polar_rotation_inplace(q + 3);
-        if (last) {
-          T dd[QW];
+            for (int c = 0; c < 3; ++c) dd[c] = dq[c];
 #pragma unroll
-          for (int c = 0; c < 3; ++c) dd[c] = dq[c];
-#pragma unroll
-          for (int c = 0; c < 9; ++c) dd[3 + c] = q[3 + c] - Aold[c];
-          const double dc[3] = {(double)dq[0], (double)dq[1], (double)dq[2]};
-          num = m_norm2(m, dc, dd);
+            for (int c = 0; c < 9; ++c) dd[3 + c] = q[3 + c] - Aold[c];
+            const double dc[3] = {(double)dq[0], (double)dq[1], (double)dq[2]};
+            num = m_norm2(m, dc, dd);
+          }
         }
       }
-    }
-    __syncthreads();  // every lane is done with the q buffers
-    // per-scene FP64 residual: partials through LDS, summed by the scene's first
-    // body in body order (independent of where the scene sits in the tile)
-    double* red = reinterpret_cast<double*>(&lq[0][0]);
-    red[lane] = num;
-    red[TB + lane] = den;
-    if (moving) {
-      T qn[QR], o[VW];
-      load<T, QR>(v.qn + (size_t)QR * i, qn);
-      recover_velocity(q, qn, ih, o);
-      bool finite = true;
+      __syncthreads();  // every lane is done with the q buffers
+      // per-scene FP64 residual: partials through LDS, summed by the scene's
+      // first body in body order (independent of where the scene sits in the tile)
+      double* red = reinterpret_cast<double*>(&lq[0][0]);
+      red[lane] = num;
+      red[TB + lane] = den;
+      if (moving) {
+        T qn[QR];
+        load<T, QR>(lqn + QR * lane, qn);
+        recover_velocity(q, qn, (T)(1.0 / v.scenes[scn].h), vw);
+        bool finite = true;
 #pragma unroll
-      for (int c = 0; c < QR; ++c) finite = finite && isfinite(q[c]);
+        for (int c = 0; c < QR; ++c) finite = finite && isfinite(q[c]);
 #pragma unroll
-      for (int c = 0; c < 6; ++c) finite = finite && isfinite(o[c]);
-      if (!finite) atomicOr(v.health + scn, 1);
-      pos_renorm(q);
-      store<T, QR>(v.qn + (size_t)QR * i, q);
-      store<T, VW>(v.vel + (size_t)VW * i, o);
-    }
-    __syncthreads();
-    if (present && i == v.scenes[scn].body_off) {
-      const int nbs = v.scenes[scn].n_bodies;
-      double a = 0.0, b = 0.0;
-      for (int t = 0; t < nbs; ++t) {
-        a += red[lane + t];
-        b += red[TB + lane + t];
+        for (int c = 0; c < 6; ++c) finite = finite && isfinite(vw[c]);
+        if (!finite) atomicOr(v.health + scn, 1);
+        pos_renorm(q);
+        store<T, QR>(v.qn + (size_t)QR * i, q);
+        store<T, VW>(v.vel + (size_t)VW * i, vw);
       }
-      v.rho[scn] = b > 0.0 ? sqrt(a / b) : 0.0;
-      v.scenes[scn].step += 1;
+      __syncthreads();
+      if (present && i == v.scenes[scn].body_off) {
+        const int nbs = v.scenes[scn].n_bodies;
+        double a = 0.0, b = 0.0;
+        for (int t = 0; t < nbs; ++t) {
+          a += red[lane + t];
+          b += red[TB + lane + t];
+        }
+        v.rho[scn] = b > 0.0 ? sqrt(a / b) : 0.0;
+        v.scenes[scn].step += 1;
+      }
+      __syncthreads();  // LDS and step counters settled for the next step or tile
     }
-    __syncthreads();  // LDS reused by the next tile of this workgroup
   }
 }
 

@@ -49,7 +49,8 @@ struct EngineBase {
   virtual void factor(hipStream_t st, int first = 0, int count = -1) = 0;
   virtual void flat_step(int first, int n, int n_scenes, int kmax, bool contacts, int n_driven,
                          bool history, bool finish_scenes, hipStream_t st) = 0;
-  virtual void tile_step(int tile_bodies, const TileTable& tt, int grid, hipStream_t st) = 0;
+  virtual void tile_step(int tile_bodies, const TileTable& tt, int grid, int nsteps,
+                         hipStream_t st) = 0;
   virtual void finish_scenes(int n_scenes, hipStream_t st) = 0;
   virtual pabd_status read_bodies(int boff, int n, double* c, double* A, double* v, double* w,
                                   hipStream_t st) = 0;
@@ -93,20 +94,20 @@ struct EngineT final : EngineBase {
     e.launch_flat_step(n_scenes, kmax, contacts, n_driven, history, fin, st);
     e.cap.n = saved;
   }
-  void tile_step(int tb, const TileTable& tt, int grid, hipStream_t st) override {
+  void tile_step(int tb, const TileTable& tt, int grid, int nsteps, hipStream_t st) override {
     View<T> v = e.view();
     switch (tb) {
       case 32:
-        hipLaunchKernelGGL((k_tile_step<T, 32, 2>), dim3(grid), dim3(32), 0, st, v, tt);
+        hipLaunchKernelGGL((k_tile_step<T, 32, 2>), dim3(grid), dim3(32), 0, st, v, tt, nsteps);
         break;
       case 64:
-        hipLaunchKernelGGL((k_tile_step<T, 64, 2>), dim3(grid), dim3(64), 0, st, v, tt);
+        hipLaunchKernelGGL((k_tile_step<T, 64, 2>), dim3(grid), dim3(64), 0, st, v, tt, nsteps);
         break;
       case 128:
-        hipLaunchKernelGGL((k_tile_step<T, 128, 2>), dim3(grid), dim3(128), 0, st, v, tt);
+        hipLaunchKernelGGL((k_tile_step<T, 128, 2>), dim3(grid), dim3(128), 0, st, v, tt, nsteps);
         break;
       default:
-        hipLaunchKernelGGL((k_tile_step<T, 256, 2>), dim3(grid), dim3(256), 0, st, v, tt);
+        hipLaunchKernelGGL((k_tile_step<T, 256, 2>), dim3(grid), dim3(256), 0, st, v, tt, nsteps);
         break;
     }
   }
@@ -567,6 +568,7 @@ struct pabd_batch {
   int tile_table_cap = 0;
   DeviceAllocator dev = current_allocator();
   Graph graph;
+  int graph_steps = 0;  // steps one replay of the captured graph advances
   bool dirty = true;
   int grid_tiles = 0;
   bool any_stream = false, any_contact = false;
@@ -658,17 +660,22 @@ pabd_status batch_tables(pabd_batch* b) {
   return PABD_OK;
 }
 
-void batch_enqueue(pabd_batch* b, hipStream_t st) {
+// nsteps steps of every resident scene: the flat path one step after another,
+// the tiles in one launch that runs all nsteps
+void batch_enqueue(pabd_batch* b, int nsteps, hipStream_t st) {
   const pabd_batch::Launch& L = b->launch;
-  if (L.stream)
-    b->eng->flat_step(0, L.stream_n, b->max_slots, L.kmax, L.contact, L.driven_n, false, false, st);
   if (L.grid > 0) {
     TileTable tt{b->d_first, b->d_count, b->d_kmax, b->d_ntiles};
-    b->eng->tile_step(L.tile, tt, L.grid, st);
+    b->eng->tile_step(L.tile, tt, L.grid, nsteps, st);
   }
-  // scenes on the flat path: residual reduction and step counters (tiled
-  // scenes do both inside the tile kernel)
-  if (L.stream) b->eng->finish_scenes(b->max_slots, st);
+  if (L.stream) {
+    for (int k = 0; k < nsteps; ++k) {
+      b->eng->flat_step(0, L.stream_n, b->max_slots, L.kmax, L.contact, L.driven_n, false, false, st);
+      // scenes on the flat path: residual reduction and step counters (tiled
+      // scenes do both inside the tile kernel)
+      b->eng->finish_scenes(b->max_slots, st);
+    }
+  }
 }
 
 pabd_status place_tiled(pabd_batch* b, int slot, int n) {
@@ -926,8 +933,9 @@ pabd_status pabd_batch_release(pabd_batch* b, int32_t slot) {
   return PABD_OK;
 }
 
-pabd_status pabd_batch_step(pabd_batch* b, void* hip_stream) {
+pabd_status pabd_batch_steps(pabd_batch* b, int32_t nsteps, void* hip_stream) {
   if (!b) return fail(PABD_E_INVALID, "null batch");
+  if (nsteps < 1 || nsteps > PABD_MAX_STEPS_PER_LAUNCH) return fail(PABD_E_INVALID, "nsteps out of range");
   hipStream_t st = hip_stream ? (hipStream_t)hip_stream : b->stream;
   if (b->dirty) {  // new tables; the graph is rebuilt only if the launch extents changed
     pabd_status s2 = batch_tables(b);
@@ -935,21 +943,25 @@ pabd_status pabd_batch_step(pabd_batch* b, void* hip_stream) {
     b->dirty = false;
   }
   if (use_graphs()) {
+    if (b->graph.x && b->graph_steps != nsteps) b->graph.reset();
     if (!b->graph.x) {
       API_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-      batch_enqueue(b, b->stream);
+      batch_enqueue(b, nsteps, b->stream);
       hipError_t e = hipStreamEndCapture(b->stream, &b->graph.g);
       if (e != hipSuccess) return fail(PABD_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
       API_HIP(hipGraphInstantiate(&b->graph.x, b->graph.g, nullptr, nullptr, 0));
+      b->graph_steps = nsteps;
     }
     API_HIP(hipGraphLaunch(b->graph.x, st));
   } else {
-    batch_enqueue(b, st);
+    batch_enqueue(b, nsteps, st);
     API_HIP(hipGetLastError());
   }
-  b->substeps++;
+  b->substeps += nsteps;
   return PABD_OK;
 }
+
+pabd_status pabd_batch_step(pabd_batch* b, void* hip_stream) { return pabd_batch_steps(b, 1, hip_stream); }
 
 pabd_status pabd_batch_steps_done(pabd_batch* b, int32_t slot, int32_t* steps) {
   if (!b) return fail(PABD_E_INVALID, "null batch");
@@ -1064,8 +1076,9 @@ static pabd_status batch_repack(pabd_batch* b, int tile_bodies) {
   return PABD_OK;
 }
 
-pabd_status pabd_batch_time_tile_kernel(pabd_batch* b, int32_t reps, double* avg_ms) {
+pabd_status pabd_batch_time_tile_kernel(pabd_batch* b, int32_t reps, int32_t nsteps, double* avg_ms) {
   if (!b || reps < 1 || !avg_ms) return fail(PABD_E_INVALID, "bad arguments");
+  if (nsteps < 1 || nsteps > PABD_MAX_STEPS_PER_LAUNCH) return fail(PABD_E_INVALID, "nsteps out of range");
   *avg_ms = 0.0;
   if (b->dirty) {
     pabd_status s2 = batch_tables(b);
@@ -1077,9 +1090,9 @@ pabd_status pabd_batch_time_tile_kernel(pabd_batch* b, int32_t reps, double* avg
   API_HIP(hipEventCreate(&e0));
   API_HIP(hipEventCreate(&e1));
   TileTable tt{b->d_first, b->d_count, b->d_kmax, b->d_ntiles};
-  b->eng->tile_step(b->tile_bodies, tt, b->grid_tiles, b->stream);  // warm
+  b->eng->tile_step(b->tile_bodies, tt, b->grid_tiles, nsteps, b->stream);  // warm
   API_HIP(hipEventRecord(e0, b->stream));
-  for (int r = 0; r < reps; ++r) b->eng->tile_step(b->tile_bodies, tt, b->grid_tiles, b->stream);
+  for (int r = 0; r < reps; ++r) b->eng->tile_step(b->tile_bodies, tt, b->grid_tiles, nsteps, b->stream);
   API_HIP(hipEventRecord(e1, b->stream));
   API_HIP(hipEventSynchronize(e1));
   float ms = 0.f;

@@ -155,3 +155,50 @@ def test_many_scenes_without_planes_or_driven_bonds_all_admit(P):
         b.step()
     b.sync()
     assert sorted(b.poll()) == sorted(slots)
+
+
+@pytest.mark.parametrize("prec", [S.PREC_FP32, S.PREC_FP64])
+def test_several_steps_per_launch_equal_single_steps(P, prec):
+    """pabd_batch_steps runs nsteps steps of every tile in one launch: the same
+    bits as nsteps single-step calls, for scenes that run through the launch,
+    scenes whose step budget ends inside it, and flat-path scenes beside them."""
+    tiled = S.batched_chains(30, seed=13, precision=prec)
+    big = S.chain(300, tilt_deg=20.0, joint_angles_deg=np.linspace(-5, 5, 299),
+                  precision=prec, iters=12)
+    scs = tiled + [big]
+    budgets = [7 if k % 3 else 3 for k in range(len(tiled))] + [7]
+    print(f"[case] several steps per launch, prec {prec}", flush=True)
+
+    def run(launch_steps):
+        b = P.Batch(len(scs) + 2, 1 << 30, prec)
+        slots = [b.admit(s, n) for s, n in zip(scs, budgets)]
+        done = 0
+        for n in launch_steps:
+            b.step(nsteps=n)
+            done += n
+        assert done == 7
+        return b, slots
+
+    b1, s1 = run([1] * 7)
+    b2, s2 = run([5, 2])
+    for k, (x, y) in enumerate(zip(s1, s2)):
+        assert b2.steps_done(y) == budgets[k]
+        for u, w in zip(b1.state(x), b2.state(y)):
+            np.testing.assert_array_equal(u, w)
+        assert b1.residual(x) == b2.residual(y)
+    assert sorted(b2.poll()) == sorted(s2)
+    # and against the oracle
+    for k in (0, 1, len(scs) - 1):
+        e = errors(b2.state(s2[k]), _oracle_state(scs[k], budgets[k]), scale_of(scs[k]))
+        if prec == S.PREC_FP64:
+            assert fp64_ok(e), (scs[k].name, e)
+        else:
+            assert e["pos"] <= 1e-3 and e["rot"] <= 1e-3, (scs[k].name, e)
+
+
+def test_steps_per_launch_out_of_range_is_rejected(P):
+    b = P.Batch(2, 1 << 26, S.PREC_FP32)
+    b.admit(S.chain8(precision=S.PREC_FP32), 5)
+    for n in (0, 257):
+        with pytest.raises(P.PabdError):
+            b.step(nsteps=n)
