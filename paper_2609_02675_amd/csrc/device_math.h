@@ -240,10 +240,8 @@ __device__ __forceinline__ void polar_rotation_inplace(T* X) {
   const bool conv = ok && d2 < Eps<T>::polar_tol2;
   const bool one = ok && !conv && unscaled && d2 <= Eps<T>::polar_two;
   const bool two = one && d2 > Eps<T>::polar_one;
-  if (wave_any(one)) {
-    polar_newton_plain<T>(X, one);
-    if (wave_any(two)) polar_newton_plain<T>(X, two);
-  }
+  polar_newton_plain<T>(X, one);
+  if (wave_any(two)) polar_newton_plain<T>(X, two);
   bool done = conv || one;
   if (wave_any(!done)) {
     if (ok && !done) {
@@ -391,18 +389,6 @@ __device__ __forceinline__ void pos_diff(const T* qa, const T* qb, T* d) {
   }
 }
 
-// d = p - c for a world point p
-template <typename T>
-__device__ __forceinline__ void point_minus_pos(const T* p, const T* q, T* d) {
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    if constexpr (sizeof(T) == 4)
-      d[k] = (p[k] - q[k]) - q[12 + k];
-    else
-      d[k] = p[k] - q[k];
-  }
-}
-
 // c += dc within a step: in FP32 the increment goes to the low word only, so the
 // high word stays the step's starting position and the low word carries the
 // displacement (small, hence exact to a few 1e-9 m); pos_renorm folds it back
@@ -438,23 +424,29 @@ __device__ __forceinline__ double pos_value(const T* q, int k) {
     return (double)q[k];
 }
 
-// bond vector d = y_o - y_s = (c_o - c_s) + (A_o x_o - A_s x_s); world partner
-// (qo == nullptr): y_o = x_o
+// bond vector d = y_o - y_s = (c_o - c_s) + A_o x_o - A_s x_s; world partner
+// (qo == nullptr): y_o = x_o.  Each component is one fused chain that starts
+// from the difference of the high position words and ends with the low words'.
 template <typename T>
 __device__ __forceinline__ void bond_vec(const T* qs, const T* xs, const T* qo, const T* xo, T* d) {
-  const T as0 = qs[3] * xs[0] + qs[4] * xs[1] + qs[5] * xs[2];
-  const T as1 = qs[6] * xs[0] + qs[7] * xs[1] + qs[8] * xs[2];
-  const T as2 = qs[9] * xs[0] + qs[10] * xs[1] + qs[11] * xs[2];
-  if (qo) {
-    pos_diff(qo, qs, d);
-    d[0] += (qo[3] * xo[0] + qo[4] * xo[1] + qo[5] * xo[2]) - as0;
-    d[1] += (qo[6] * xo[0] + qo[7] * xo[1] + qo[8] * xo[2]) - as1;
-    d[2] += (qo[9] * xo[0] + qo[10] * xo[1] + qo[11] * xo[2]) - as2;
-  } else {
-    point_minus_pos(xo, qs, d);
-    d[0] -= as0;
-    d[1] -= as1;
-    d[2] -= as2;
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const T* as = qs + 3 + 3 * r;
+    T u;
+    if (qo) {
+      const T* ao = qo + 3 + 3 * r;
+      u = qo[r] - qs[r];
+      u = fma(ao[0], xo[0], u);
+      u = fma(ao[1], xo[1], u);
+      u = fma(ao[2], xo[2], u);
+    } else {
+      u = xo[r] - qs[r];
+    }
+    u = fma(-as[0], xs[0], u);
+    u = fma(-as[1], xs[1], u);
+    u = fma(-as[2], xs[2], u);
+    if constexpr (sizeof(T) == 4) u += qo ? qo[12 + r] - qs[12 + r] : -qs[12 + r];
+    d[r] = u;
   }
 }
 

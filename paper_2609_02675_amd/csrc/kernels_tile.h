@@ -25,7 +25,10 @@ struct TileTable {
 template <typename T, int TB, int MAXE>
 __global__ void __launch_bounds__(TB, sizeof(T) == 4 ? 3 : 1) k_tile_step(View<T> v, TileTable tt, int nsteps) {
   constexpr int QR = Rec<T>::Q;
-  __shared__ T lq[2][TB * QR];
+  // q^k of the tile's bodies (double-buffered) plus, in slot TB, a still body
+  // at the origin (c = 0, A = I): an end anchored in the world takes it as its
+  // partner, so every end runs the same code
+  __shared__ T lq[2][(TB + 1) * QR];
   __shared__ T lqn[TB * QR];  // q^n of each lane's body, for velocity recovery
   const int lane = threadIdx.x;
   const int ntiles = *tt.n_tiles;
@@ -33,6 +36,11 @@ __global__ void __launch_bounds__(TB, sizeof(T) == 4 ? 3 : 1) k_tile_step(View<T
     const int first = tt.first[t], nb = tt.count[t], kmax = tt.kmax[t];
     const int i = first + lane;
     const int scn = lane < nb ? v.bscene[i] : -1;
+    if (lane < QR) {
+      const T o = (lane == 3 || lane == 7 || lane == 11) ? (T)1 : (T)0;
+      lq[0][TB * QR + lane] = o;
+      lq[1][TB * QR + lane] = o;
+    }
     // what no step changes is loaded once per launch; q and v stay in
     // registers from step to step and are written back after every step
     const bool pinned = scn >= 0 && (v.flags[i] & F_PINNED);
@@ -53,7 +61,7 @@ __global__ void __launch_bounds__(TB, sizeof(T) == 4 ? 3 : 1) k_tile_step(View<T
           if (u < ne) {
             load<T, EW>(v.se + (size_t)EW * (e0 + u), E[u]);
             const int p = v.se_partner[e0 + u];
-            part[u] = p < 0 ? -1 : p - first;
+            part[u] = p < 0 ? TB : p - first;
           }
       }
     }
@@ -101,14 +109,9 @@ __global__ void __launch_bounds__(TB, sizeof(T) == 4 ? 3 : 1) k_tile_step(View<T
 #pragma unroll
           for (int u = 0; u < MAXE; ++u)
             if (u < ne) {
-              T d[3], f[3];
-              if (part[u] < 0) {
-                bond_vec<T>(q, E[u], nullptr, E[u] + 4, d);
-              } else {
-                T qj[QR];
-                load<T, QR>(buf + QR * part[u], qj);
-                bond_vec<T>(q, E[u], qj, E[u] + 4, d);
-              }
+              T d[3], f[3], qj[QR];
+              load<T, QR>(buf + QR * part[u], qj);
+              bond_vec<T>(q, E[u], qj, E[u] + 4, d);
               quad_end_force(E[u], d, f);
               add_JT(r, E[u], f[0], f[1], f[2]);
             }
@@ -116,14 +119,9 @@ __global__ void __launch_bounds__(TB, sizeof(T) == 4 ? 3 : 1) k_tile_step(View<T
             T Eg[EW];
             load<T, EW>(v.se + (size_t)EW * e, Eg);
             const int p = v.se_partner[e];
-            T d[3], f[3];
-            if (p < 0) {
-              bond_vec<T>(q, Eg, nullptr, Eg + 4, d);
-            } else {
-              T qj[QR];
-              load<T, QR>(buf + QR * (p - first), qj);
-              bond_vec<T>(q, Eg, qj, Eg + 4, d);
-            }
+            T d[3], f[3], qj[QR];
+            load<T, QR>(buf + QR * (p < 0 ? TB : p - first), qj);
+            bond_vec<T>(q, Eg, qj, Eg + 4, d);
             quad_end_force(Eg, d, f);
             add_JT(r, Eg, f[0], f[1], f[2]);
           }
