@@ -154,8 +154,7 @@ __global__ void __launch_bounds__(TB, sizeof(T) == 4 ? 3 : 1) k_tile_step(View<T
         }
       }
       __syncthreads();  // every lane is done with the q buffers
-      // per-scene FP64 residual: partials through LDS, summed by the scene's
-      // first body in body order (independent of where the scene sits in the tile)
+      // per-scene FP64 residual: each body's partials through LDS
       double* red = reinterpret_cast<double*>(&lq[0][0]);
       red[lane] = num;
       red[TB + lane] = den;
@@ -174,13 +173,20 @@ __global__ void __launch_bounds__(TB, sizeof(T) == 4 ? 3 : 1) k_tile_step(View<T
         store<T, VW>(v.vel + (size_t)VW * i, vw);
       }
       __syncthreads();
-      if (present && i == v.scenes[scn].body_off) {
-        const int nbs = v.scenes[scn].n_bodies;
-        double a = 0.0, b = 0.0;
-        for (int t = 0; t < nbs; ++t) {
-          a += red[lane + t];
-          b += red[TB + lane + t];
+      // pairwise sums over the scene's bodies by their index within the scene:
+      // the same order wherever the scene sits in the tile
+      const int loc = present ? i - v.scenes[scn].body_off : 1;
+      const int nbs = present ? v.scenes[scn].n_bodies : 0;
+#pragma unroll
+      for (int w = 1; w < TB; w <<= 1) {
+        if ((loc & (2 * w - 1)) == 0 && loc + w < nbs) {
+          red[lane] += red[lane + w];
+          red[TB + lane] += red[TB + lane + w];
         }
+        __syncthreads();
+      }
+      if (present && loc == 0) {
+        const double a = red[lane], b = red[TB + lane];
         v.rho[scn] = b > 0.0 ? sqrt(a / b) : 0.0;
         v.scenes[scn].step += 1;
       }

@@ -202,3 +202,15 @@ def test_steps_per_launch_out_of_range_is_rejected(P):
     for n in (0, 257):
         with pytest.raises(P.PabdError):
             b.step(nsteps=n)
+
+
+def test_batched_residuals_match_oracle_fp64(P):
+    """The per-scene residual of the last iteration (summed in FP64 inside the
+    tile kernel) against the oracle's."""
+    scs = S.batched_chains(12, seed=4, precision=S.PREC_FP64)
+    print("[case] batched residuals fp64", flush=True)
+    b, slots, _ = _run_batch(P, scs, 6, S.PREC_FP64)
+    for sc, sl in zip(scs, slots):
+        o = oracle.Oracle(sc)
+        o.step(6)
+        assert b.residual(sl) == pytest.approx(o.residuals()[-1], rel=1e-6), sc.name
