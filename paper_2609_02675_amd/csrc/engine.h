@@ -446,9 +446,7 @@ struct Engine {
     hipLaunchKernelGGL(k_broad_large<T>, dim3(256), dim3(256), 0, st, v, cb);
     const int ng = std::min(8192, std::max(1, (pcap + 255) / 256));
     hipLaunchKernelGGL(k_narrow_pairs<T>, dim3(ng), dim3(256), 0, st, v, cb);
-    const long long ns = (long long)n * cap.ccap;
-    hipLaunchKernelGGL(k_sort_contacts<T>, dim3((unsigned)std::max(1LL, (ns + 255) / 256)), dim3(256), 0, st,
-                       v, cap.ccap);
+    hipLaunchKernelGGL(k_sort_contacts<T>, dim3((unsigned)std::max(1, n)), dim3(64), 0, st, v, cap.ccap);
   }
 
   // FP64 block factorisation of bodies [first, first + count)

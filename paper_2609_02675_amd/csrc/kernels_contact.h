@@ -28,9 +28,9 @@
 //                    fewer), large partners of higher index over the scene
 //   k_narrow_pairs   one thread per candidate pair: narrow phase, bond ends into
 //                    the owners' staging slots
-//   k_sort_contacts  per body, ends copied in canonical key order to their final
-//                    slots, so the iteration sums in a fixed order whatever order
-//                    the atomics produced
+//   k_sort_contacts  one wave per body, ends copied in canonical key order to
+//                    their final slots, so the iteration sums in a fixed order
+//                    whatever order the atomics produced
 // Candidate tests are conservative (a relative slack of 1e-12 on the sum of
 // reaches); the narrow phase repeats the exact bounding test, so the contact
 // set does not depend on the broad phase.
@@ -499,7 +499,7 @@ __device__ void narrow_pair(const View<T>& v, const ContactBuf& cb, int sc, int 
 // Candidate pairs of one workgroup, gathered in LDS (one LDS atomic per pair) and
 // appended to the global list with one global atomic per workgroup; a pair that
 // does not fit the LDS buffer goes straight to the global list.
-constexpr int PAIR_LDS = 2048;
+constexpr int PAIR_LDS = 4096;  // a workgroup's candidate pairs before one global append
 
 struct PairBuf {
   int2* buf;  // [PAIR_LDS] in LDS
@@ -738,28 +738,72 @@ __global__ void __launch_bounds__(256) k_narrow_pairs(View<T> v, ContactBuf cb) 
 }
 
 // each body's ends from the staging slots to their final slots in key order
-// (keys of one body are distinct: partner, feature, side).  One lane per slot:
-// the lanes of a body read the same keys, which the hardware broadcasts.
+// (keys of one body are distinct: partner, feature, side).  One wave per body:
+// lane l holds the keys of slots l, l + 64, ... (up to SORT_REG of them); each
+// key is broadcast from its lane in turn and every lane counts the keys below
+// its own, which is the slot's rank.  Bodies with more ends than the registers
+// hold count against the keys in memory instead.
+constexpr int SORT_REG = 4;
+
+__device__ __forceinline__ unsigned long long lane_key(unsigned long long k, int src) {
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(k & 0xffffffffull), src);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(k >> 32), src);
+  return ((unsigned long long)hi << 32) | lo;
+}
+
 template <typename T>
-__global__ void __launch_bounds__(256) k_sort_contacts(View<T> v, int cap) {
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const int i = (int)(t / cap), a = (int)(t % cap);
+__device__ __forceinline__ void move_end(const View<T>& v, size_t base, int from, int to,
+                                         unsigned long long key) {
+  T C[CW];
+  load<T, CW>(v.ce_st + CW * (base + from), C);
+  store<T, CW>(v.ce + CW * (base + to), C);
+  v.ce_partner[base + to] = v.ce_st_partner[base + from];
+  v.ce_key[base + to] = key;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(64) k_sort_contacts(View<T> v, int cap) {
+  const int i = blockIdx.x;  // the whole wave works on body i
   if (i >= v.n) return;
   const int sc = v.bscene[i];
   if (!contact_body(v, i, sc)) return;
   int cnt = v.ccount[i];
   if (cnt > cap) cnt = cap;
-  if (a >= cnt) return;
+  if (cnt <= 0) return;
+  const int lane = threadIdx.x;
   const size_t base = (size_t)i * cap;
   const unsigned long long* keys = v.ce_st_key + base;
-  const unsigned long long key = keys[a];
-  int r = 0;
-  for (int b = 0; b < cnt; ++b) r += keys[b] < key ? 1 : 0;
-  T C[CW];
-  load<T, CW>(v.ce_st + CW * (base + a), C);
-  store<T, CW>(v.ce + CW * (base + r), C);
-  v.ce_partner[base + r] = v.ce_st_partner[base + a];
-  v.ce_key[base + r] = key;
+  if (cnt <= 64 * SORT_REG) {
+    const int rounds = (cnt + 63) / 64;
+    unsigned long long k[SORT_REG];
+    int r[SORT_REG];
+#pragma unroll
+    for (int u = 0; u < SORT_REG; ++u) {
+      const int a = lane + 64 * u;
+      k[u] = a < cnt ? keys[a] : ~0ull;
+      r[u] = 0;
+    }
+    for (int b = 0; b < cnt; ++b) {
+      const int u = b >> 6;  // wave-uniform
+      const unsigned long long own = u == 0 ? k[0] : u == 1 ? k[1] : u == 2 ? k[2] : k[3];
+      const unsigned long long kb = lane_key(own, b & 63);
+#pragma unroll
+      for (int w = 0; w < SORT_REG; ++w)
+        if (w < rounds) r[w] += k[w] > kb ? 1 : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < SORT_REG; ++u) {
+      const int a = lane + 64 * u;
+      if (a < cnt) move_end(v, base, a, r[u], k[u]);
+    }
+  } else {
+    for (int a = lane; a < cnt; a += 64) {
+      const unsigned long long key = keys[a];
+      int r = 0;
+      for (int b = 0; b < cnt; ++b) r += keys[b] < key ? 1 : 0;
+      move_end(v, base, a, r, key);
+    }
+  }
 }
 
 }  // namespace pabd
