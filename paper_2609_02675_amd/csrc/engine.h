@@ -488,7 +488,7 @@ struct Engine {
     }
     hipLaunchKernelGGL(k_finish<T>, g, b, 0, st, v);
     if (!finish_scenes) return;
-    hipLaunchKernelGGL(k_reduce_residual, dim3(std::max(1, n_scenes)), dim3(256), 0, st,
+    hipLaunchKernelGGL(k_reduce_residual, dim3(std::max(1, n_scenes)), dim3(RED_THREADS), 0, st,
                        (const SceneDev*)scenes, n_scenes, (const double*)r_num,
                        (const double*)r_den, rho);
     if (history)

@@ -271,18 +271,21 @@ __global__ void __launch_bounds__(256) k_iterate(View<T> v, int k, double* rh_nu
     int cnt = v.ccount[i];
     if (cnt > S.ccap) cnt = S.ccap;
     const size_t base = (size_t)i * S.ccap;
+    // the lanes of a body take its ends in turn (neighbouring lanes read
+    // neighbouring records); the ends are in key order, partner first, so a
+    // lane often meets the same partner again and keeps its state
+    int jprev = -1;
+    T qj[QR];
     for (int c = sub; c < cnt; c += LPB) {
       const int j = v.ce_partner[base + c];
       T C[CW];
       load<T, CW>(v.ce + (size_t)CW * (base + c), C);
-      T d[3], f[3];
-      if (j < 0) {
-        bond_vec<T>(q, C, nullptr, C + 4, d);
-      } else {
-        T qj[QR];
+      if (j >= 0 && j != jprev) {
         load<T, QR>(qs + (size_t)QR * j, qj);
-        bond_vec<T>(q, C, qj, C + 4, d);
+        jprev = j;
       }
+      T d[3], f[3];
+      bond_vec<T>(q, C, j < 0 ? nullptr : qj, C + 4, d);
       if (!contact_end_force(C, d, f)) continue;
       add_JT(rb, C, f[0], f[1], f[2]);
       block_add_end(dB, (double)C[3], (double)C[0], (double)C[1], (double)C[2]);
@@ -414,23 +417,28 @@ __global__ void __launch_bounds__(256) k_finish(View<T> v) {
 
 // one block per scene; rho = sqrt(sum num / sum den) over the scene's bodies in a
 // fixed order (strided partial sums, then a tree), so results are reproducible
-__global__ void __launch_bounds__(256) k_reduce_residual(const SceneDev* scenes, int n_scenes,
-                                                        const double* num, const double* den,
-                                                        double* rho) {
-  __shared__ double sn[256], sd[256];
+constexpr int RED_THREADS = 1024;
+
+__global__ void __launch_bounds__(RED_THREADS) k_reduce_residual(const SceneDev* scenes, int n_scenes,
+                                                                const double* num, const double* den,
+                                                                double* rho) {
+  __shared__ double sn[RED_THREADS], sd[RED_THREADS];
   const int sc = blockIdx.x;
   if (sc >= n_scenes) return;
   if (scenes[sc].tiled) return;  // the tile kernel reduces its own scenes
   const int off = scenes[sc].body_off, nb = scenes[sc].n_bodies;
+  // each thread sums a fixed stride of the scene's bodies in order; the unrolled
+  // loop keeps several loads in flight
   double a = 0.0, b = 0.0;
-  for (int t = threadIdx.x; t < nb; t += blockDim.x) {
+#pragma unroll 8
+  for (int t = threadIdx.x; t < nb; t += RED_THREADS) {
     a += num[off + t];
     b += den[off + t];
   }
   sn[threadIdx.x] = a;
   sd[threadIdx.x] = b;
   __syncthreads();
-  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+  for (int w = RED_THREADS / 2; w > 0; w >>= 1) {
     if (threadIdx.x < w) {
       sn[threadIdx.x] += sn[threadIdx.x + w];
       sd[threadIdx.x] += sd[threadIdx.x + w];

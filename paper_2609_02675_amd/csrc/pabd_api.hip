@@ -112,7 +112,7 @@ struct EngineT final : EngineBase {
     }
   }
   void finish_scenes(int n_scenes, hipStream_t st) override {
-    hipLaunchKernelGGL(k_reduce_residual, dim3(std::max(1, n_scenes)), dim3(256), 0, st,
+    hipLaunchKernelGGL(k_reduce_residual, dim3(std::max(1, n_scenes)), dim3(RED_THREADS), 0, st,
                        (const SceneDev*)e.scenes, n_scenes, (const double*)e.r_num,
                        (const double*)e.r_den, e.rho);
     hipLaunchKernelGGL(k_end_step, Engine<T>::grid_for(n_scenes, 64), dim3(64), 0, st, e.scenes,
