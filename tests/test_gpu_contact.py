@@ -134,3 +134,29 @@ def test_contact_scenes_in_a_batch_fp64(P):
         o = oracle.Oracle(sc)
         o.step(8)
         assert fp64_ok(errors(b.state(sl), o.state(), scale_of(sc))), sc.name
+
+
+def test_body_with_more_ends_than_a_wave_holds_fp64(P):
+    """A wide plate resting on an 18 x 18 grid of spheres holds 324 contact ends,
+    more than the sort keeps in registers (256 per body): its ends take the
+    sort's path through memory, and the contact set and state still match."""
+    r, n = 0.1, 18
+    sp = S.single_body(shape=S.SHAPE_SPHERE, half=(r, 0, 0), density=1000.0)
+    xs = (np.arange(n) - (n - 1) / 2) * 2.2 * r
+    balls = [sp.copy(c0=np.array([[x, r - 1e-4, z]])) for x in xs for z in xs]
+    half = 0.5 * n * 2.2 * r
+    plate = S.single_body(shape=S.SHAPE_BOX, half=(half, 0.05, half), density=200.0,
+                          c=(0.0, 2 * r + 0.05 - 2e-4, 0.0))
+    sc = S.merge([plate] + balls).copy(contact_enable=1, planes=np.array([[0.0, 1.0, 0.0, 0.0]]),
+                                       max_contacts_per_body=512, precision=S.PREC_FP64)
+    print(f"[case] plate on {n * n} spheres, n={sc.n_bodies}", flush=True)
+    g = P.Scene(sc)
+    g.step(1)
+    o = oracle.Oracle(sc)
+    o.step(1)
+    _compare_contacts(g, o)
+    ct = g.contacts()  # every bond gives an end to each of its two bodies
+    assert np.count_nonzero((ct["i"] == 0) | (ct["j"] == 0)) > 256
+    g.step(2)
+    o.step(2)
+    assert fp64_ok(errors(g.state(), o.state(), scale_of(sc)))
