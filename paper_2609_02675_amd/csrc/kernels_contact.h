@@ -367,67 +367,98 @@ __device__ __forceinline__ void vertex_of(int k, const double* he, double* x) {
   x[2] = (k & 4) ? he[2] : -he[2];
 }
 
+// the k-th of three values (k known only at run time) by selects, so that no
+// array needs memory to be indexed
+__device__ __forceinline__ double pick3(const double* a, int k) {
+  return k == 0 ? a[0] : (k == 1 ? a[1] : a[2]);
+}
+
 // box-box, vertex-face: reference face = face axis (3 of i, then 3 of j) of least
 // overlap; incident vertices within the margin of that face and inside its
-// lateral extent become contacts (incident box = i side, reference box = j side)
+// lateral extent become contacts (incident box = i side, reference box = j side).
+// All loops are unrolled and run-time choices are selects, so the geometry stays
+// in registers.
 template <typename T>
-__device__ void narrow_box_box(const View<T>& v, const ContactBuf& cb, int sc, int bi, int bj,
-                               const BodyGeo<T>& gi, const BodyGeo<T>& gj, double pm) {
+__device__ __forceinline__ void narrow_box_box(const View<T>& v, const ContactBuf& cb, int sc, int bi,
+                                               int bj, const BodyGeo<T>& gi, const BodyGeo<T>& gj,
+                                               double pm) {
   const double dc[3] = {gj.c[0] - gi.c[0], gj.c[1] - gi.c[1], gj.c[2] - gi.c[2]};
   int best = -1;
   double best_ov = 0.0;
+  bool apart = false;
+#pragma unroll
   for (int ax = 0; ax < 6; ++ax) {
     const double* A = ax < 3 ? gi.A : gj.A;
     const int k = ax % 3;
     const double u[3] = {A[k], A[3 + k], A[6 + k]};
     double ri = 0.0, rj = 0.0;
+#pragma unroll
     for (int m = 0; m < 3; ++m) {
       ri += gi.he[m] * fabs(u[0] * gi.A[m] + u[1] * gi.A[3 + m] + u[2] * gi.A[6 + m]);
       rj += gj.he[m] * fabs(u[0] * gj.A[m] + u[1] * gj.A[3 + m] + u[2] * gj.A[6 + m]);
     }
-    double ov = ri + rj - fabs(u[0] * dc[0] + u[1] * dc[1] + u[2] * dc[2]);
-    if (ov < -pm) return;
+    const double ov = ri + rj - fabs(u[0] * dc[0] + u[1] * dc[1] + u[2] * dc[2]);
+    if (ov < -pm) apart = true;
     if (best < 0 || ov < best_ov) {
       best = ax;
       best_ov = ov;
     }
   }
+  if (apart) return;
   const bool ref_is_i = best < 3;
-  const BodyGeo<T>& R = ref_is_i ? gi : gj;
-  const BodyGeo<T>& I = ref_is_i ? gj : gi;
-  const int ref = ref_is_i ? bi : bj, inc = ref_is_i ? bj : bi;
   const int k = best % 3;
-  const double ax[3] = {R.A[k], R.A[3 + k], R.A[6 + k]};
-  const double tw = ax[0] * (I.c[0] - R.c[0]) + ax[1] * (I.c[1] - R.c[1]) + ax[2] * (I.c[2] - R.c[2]);
+  double RA[9], IA[9], Rc[3], Ic[3], Rhe[3], Ihe[3];
+#pragma unroll
+  for (int m = 0; m < 9; ++m) {
+    RA[m] = ref_is_i ? gi.A[m] : gj.A[m];
+    IA[m] = ref_is_i ? gj.A[m] : gi.A[m];
+  }
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    Rc[m] = ref_is_i ? gi.c[m] : gj.c[m];
+    Ic[m] = ref_is_i ? gj.c[m] : gi.c[m];
+    Rhe[m] = ref_is_i ? gi.he[m] : gj.he[m];
+    Ihe[m] = ref_is_i ? gj.he[m] : gi.he[m];
+  }
+  const int ref = ref_is_i ? bi : bj, inc = ref_is_i ? bj : bi;
+  const double ax[3] = {pick3(RA, k), pick3(RA + 3, k), pick3(RA + 6, k)};
+  const double tw = ax[0] * (Ic[0] - Rc[0]) + ax[1] * (Ic[1] - Rc[1]) + ax[2] * (Ic[2] - Rc[2]);
   const double sgn = tw >= 0.0 ? 1.0 : -1.0;
   const double nw[3] = {sgn * ax[0], sgn * ax[1], sgn * ax[2]};
+  const double hek = pick3(Rhe, k);
+#pragma unroll
   for (int vtx = 0; vtx < 8; ++vtx) {
     double xv[3], p[3], rel[3], pl[3];
-    vertex_of(vtx, I.he, xv);
-    mat_vec(I.A, xv, p);
-    for (int r = 0; r < 3; ++r) rel[r] = p[r] + I.c[r] - R.c[r];
-    mat_tvec(R.A, rel, pl);
-    const double gap = sgn * pl[k] - R.he[k];
-    if (!(gap < pm) || gap < -2.0 * R.he[k]) continue;
+    vertex_of(vtx, Ihe, xv);
+    mat_vec(IA, xv, p);
+#pragma unroll
+    for (int r = 0; r < 3; ++r) rel[r] = p[r] + Ic[r] - Rc[r];
+    mat_tvec(RA, rel, pl);
+    const double gap = sgn * pick3(pl, k) - hek;
+    if (!(gap < pm) || gap < -2.0 * hek) continue;
     bool lateral = true;
+#pragma unroll
     for (int m = 0; m < 3; ++m)
-      if (m != k && fabs(pl[m]) > R.he[m] + pm) lateral = false;
+      if (m != k && fabs(pl[m]) > Rhe[m] + pm) lateral = false;
     if (!lateral) continue;
     double xs[3];
-    for (int m = 0; m < 3; ++m) xs[m] = pl[m] < -R.he[m] ? -R.he[m] : (pl[m] > R.he[m] ? R.he[m] : pl[m]);
-    xs[k] = sgn * R.he[k];
+#pragma unroll
+    for (int m = 0; m < 3; ++m)
+      xs[m] = m == k ? sgn * Rhe[m] : (pl[m] < -Rhe[m] ? -Rhe[m] : (pl[m] > Rhe[m] ? Rhe[m] : pl[m]));
     emit_contact(v, cb, sc, inc, ref, vtx, xv, xs, nw);
   }
 }
 
 // sphere s (i side) against box b (j side)
 template <typename T>
-__device__ void narrow_sphere_box(const View<T>& v, const ContactBuf& cb, int sc, int s, int b,
-                                  const BodyGeo<T>& gs, const BodyGeo<T>& gb, double pm) {
+__device__ __forceinline__ void narrow_sphere_box(const View<T>& v, const ContactBuf& cb, int sc, int s,
+                                                  int b, const BodyGeo<T>& gs, const BodyGeo<T>& gb,
+                                                  double pm) {
   const double r = gs.he[0];
   double rel[3] = {gs.c[0] - gb.c[0], gs.c[1] - gb.c[1], gs.c[2] - gb.c[2]}, pl[3], q[3], nl[3];
   mat_tvec(gb.A, rel, pl);
   bool inside = true;
+#pragma unroll
   for (int k = 0; k < 3; ++k) {
     q[k] = pl[k] < -gb.he[k] ? -gb.he[k] : (pl[k] > gb.he[k] ? gb.he[k] : pl[k]);
     if (q[k] != pl[k]) inside = false;
@@ -436,33 +467,38 @@ __device__ void narrow_sphere_box(const View<T>& v, const ContactBuf& cb, int sc
   if (inside) {
     int ks = 0;
     double bestd = gb.he[0] - fabs(pl[0]);
+#pragma unroll
     for (int k = 1; k < 3; ++k)
       if (gb.he[k] - fabs(pl[k]) < bestd) {
         bestd = gb.he[k] - fabs(pl[k]);
         ks = k;
       }
-    const double sg = pl[ks] >= 0.0 ? 1.0 : -1.0;
-    q[ks] = sg * gb.he[ks];
-    nl[0] = nl[1] = nl[2] = 0.0;
-    nl[ks] = sg;
+    const double sg = pick3(pl, ks) >= 0.0 ? 1.0 : -1.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      if (k == ks) q[k] = sg * gb.he[k];
+      nl[k] = k == ks ? sg : 0.0;
+    }
     gap = -bestd - r;
   } else {
     const double dl[3] = {pl[0] - q[0], pl[1] - q[1], pl[2] - q[2]};
     const double dist = sqrt(dl[0] * dl[0] + dl[1] * dl[1] + dl[2] * dl[2]);
     if (dist == 0.0) return;
+#pragma unroll
     for (int k = 0; k < 3; ++k) nl[k] = dl[k] / dist;
     gap = dist - r;
   }
   if (!(gap < pm)) return;
   double nw[3], pw[3], xi[3];
   mat_vec(gb.A, nl, nw);
+#pragma unroll
   for (int k = 0; k < 3; ++k) pw[k] = -r * nw[k];
   mat_tvec(gs.A, pw, xi);
   emit_contact(v, cb, sc, s, b, 8, xi, q, nw);
 }
 
 template <typename T>
-__device__ void narrow_pair(const View<T>& v, const ContactBuf& cb, int sc, int i, int j,
+__device__ __forceinline__ void narrow_pair(const View<T>& v, const ContactBuf& cb, int sc, int i, int j,
                             const BodyGeo<T>& gi, double pmi) {
   BodyGeo<T> gj;
   body_geo(v, j, gj);
