@@ -160,3 +160,31 @@ def test_body_with_more_ends_than_a_wave_holds_fp64(P):
     g.step(2)
     o.step(2)
     assert fp64_ok(errors(g.state(), o.state(), scale_of(sc)))
+
+
+def test_contact_and_plain_flat_scenes_share_a_batch_fp64(P):
+    """A 300-body chain (flat path, no contacts) beside two box piles in one batch:
+    the chain then iterates with the four-lane contact variant, and its result
+    alone and in the mix agree within the FP64 bar; every scene matches the
+    oracle."""
+    big = S.chain(300, tilt_deg=20.0, joint_angles_deg=np.linspace(-5, 5, 299),
+                  precision=S.PREC_FP64, iters=12)
+    piles = [settled_drop(n_side=3, layers=1, steps=60, seed=s) for s in (5, 6)]
+    print("[case] chain 300 beside two piles", flush=True)
+    b = P.Batch(8, 1 << 28, S.PREC_FP64)
+    sb = b.admit(big, 8)
+    sp = [b.admit(p, 8) for p in piles]
+    for _ in range(8):
+        b.step()
+    alone = P.Batch(4, 1 << 28, S.PREC_FP64)
+    sa = alone.admit(big, 8)
+    for _ in range(8):
+        alone.step()
+    assert fp64_ok(errors(b.state(sb), alone.state(sa), scale_of(big)))
+    o = oracle.Oracle(big)
+    o.step(8)
+    assert fp64_ok(errors(b.state(sb), o.state(), scale_of(big)))
+    for pl, s in zip(piles, sp):
+        o = oracle.Oracle(pl)
+        o.step(8)
+        assert fp64_ok(errors(b.state(s), o.state(), scale_of(pl))), pl.name
