@@ -188,3 +188,26 @@ def test_contact_and_plain_flat_scenes_share_a_batch_fp64(P):
         o = oracle.Oracle(pl)
         o.step(8)
         assert fp64_ok(errors(b.state(s), o.state(), scale_of(pl))), pl.name
+
+
+def test_box_drop_1000_full_size_from_a_landing_state(P):
+    """The 1,000-box drop at full size, from the oracle's state at step 60 (the
+    lowest boxes landing, about 600 contact bonds): one GPU step in FP64 has the
+    oracle's contact set and state; in FP32, positions and rotations within 1e-4."""
+    sc = S.box_drop(precision=S.PREC_FP64)
+    o = oracle.Oracle(sc)
+    o.step(60)
+    c, A, v, w = o.state()
+    st = sc.with_state(c, A, v, w, t0=60 * sc.h)
+    print(f"[case] box drop n={st.n_bodies} from step 60", flush=True)
+    ref = oracle.Oracle(st)
+    ref.step(1)
+    g = P.Scene(st)
+    g.step(1)
+    _compare_contacts(g, ref)
+    assert fp64_ok(errors(g.state(), ref.state(), scale_of(st)))
+    g32 = P.Scene(st.copy(precision=S.PREC_FP32))
+    g32.step(1)
+    e = errors(g32.state(), ref.state(), scale_of(st))
+    print("box drop fp32 one step", e)
+    assert e["pos"] <= 1e-4 and e["rot"] <= 1e-4
