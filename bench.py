@@ -99,11 +99,9 @@ def _oracle_worker(args):
     return sc.n_bodies * sc.iters * steps, time.perf_counter() - t
 
 
-def cpu_baseline(scenes, n_sample, steps, cores):
+def _pool_timing(scenes, n_sample, steps, cores):
     global _SCENES
     _SCENES = scenes[:n_sample]
-    import oracle
-    oracle.build()
     work = [(k, steps) for k in range(len(_SCENES))]
     t0 = time.perf_counter()
     with mp.get_context("fork").Pool(cores) as pool:
@@ -116,6 +114,46 @@ def cpu_baseline(scenes, n_sample, steps, cores):
                 sample=f"first {len(_SCENES)} of the batched chains, {steps} steps each, FP64 "
                        f"oracle, one scene per task on a {cores}-process pool "
                        f"({body_its:.3g} body-iterations, {wall:.1f} s wall)")
+
+
+def cpu_baseline_leg(args, S, scenes, plan):
+    """The CPU leg, run before the GPU is touched (so that fork is safe): the FP64
+    oracle as it stands, timed on a bounded sample of the batched chains (the
+    cpu_baseline) and on the single-scene workloads, and the oracle's results
+    that the GPU legs state their error against. It is the only part of this
+    script that runs the oracle."""
+    import oracle
+    oracle.build()
+    cpu = None
+    if not args.no_cpu_baseline:
+        cores = min(16, os.cpu_count() or 1)
+        sc64 = [s.copy(precision=S.PREC_FP64) for s in scenes[: args.cpu_sample]]
+        cpu = _pool_timing(sc64, len(sc64), args.cpu_steps, cores)
+        cpu["host"] = host_info()
+        log("cpu baseline", cpu)
+
+    def run(sc, steps):
+        o = oracle.Oracle(sc.copy(precision=S.PREC_FP64))
+        o.step(steps)
+        return o.state()
+
+    refs = {"batched": {k: run(scenes[k], plan["total_steps"]) for k in plan["batched_sample"]}}
+    if plan["big_scenes"] is not None:
+        refs["big"] = {k: run(plan["big_scenes"][k], plan["big_steps"]) for k in plan["big_sample"]}
+    if plan["requests"]:
+        refs["served"] = {k: run(plan["requests"][k].scene, plan["requests"][k].steps)
+                          for k in plan["served_sample"]}
+    if not args.no_scenes:
+        # the box drop from the oracle's own state after 60 steps (contacts
+        # active), and the oracle's next step from there
+        drop = S.box_drop(precision=S.PREC_FP64)
+        mid = drop.with_state(*run(drop, 60), t0=60 * drop.h)
+        refs["drop_mid"] = mid
+        refs["drop_next"] = run(mid, 1)
+        refs["mass_ratio"] = {aug: run(S.mass_ratio_chain(augmented=aug), 110) for aug in (True, False)}
+    if cpu is not None and not args.no_oracle_single:
+        cpu["single_core_single_scene"] = oracle_single_core(oracle, S, refs.get("drop_mid"))
+    return cpu, refs
 
 
 def host_info():
@@ -131,15 +169,16 @@ def host_info():
     return dict(logical_cpus=os.cpu_count(), model=model)
 
 
-def big_batch_leg(P, S, torch, n_scenes, steps, spl):
+def big_batch_leg(P, S, torch, plan, refs):
     """The batched chains at 16x the default count (about 2.2M bodies, a working
     set well beyond the 256 MB last-level cache), tile 64, FP32, spl steps per
     tile-kernel launch."""
-    import oracle
     sys.path.insert(0, os.path.join(ROOT, "tests"))
     from parity import errors, scale_of
+    spl = plan["spl"]
+    scs = plan["big_scenes"]
+    n_scenes = len(scs)
     t = time.perf_counter()
-    scs = S.batched_chains(n_scenes, seed=2, precision=S.PREC_FP32)
     nb = sum(x.n_bodies for x in scs)
     b = P.Batch(n_scenes + 8, 16 << 30, S.PREC_FP32)
     slots = [b.admit(x, 1 << 30) for x in scs]
@@ -148,27 +187,22 @@ def big_batch_leg(P, S, torch, n_scenes, steps, spl):
     log(f"big batch: {n_scenes} scenes, {nb} bodies admitted in {time.perf_counter() - t:.1f}s")
     stream = torch.cuda.Stream()
     sptr = stream.cuda_stream
-    launches = max(1, steps // spl)
     b.step(stream=sptr, nsteps=spl)  # warm-up and graph capture
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     e0.record(stream)
-    for _ in range(launches):
+    for _ in range(BIG_TIMED_LAUNCHES):
         b.step(stream=sptr, nsteps=spl)
     e1.record(stream)
     torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / (launches * spl)
+    ms = e0.elapsed_time(e1) / (BIG_TIMED_LAUNCHES * spl)
     iters = scs[0].iters
-    reps = 2
-    launch_ms = b.time_tile_kernel(reps, spl)
+    launch_ms = b.time_tile_kernel(BIG_REPS, spl)
     tile_ms = launch_ms / spl
     flops = nb * iters * FLOPS_PER_BODY_ITER
     acc = 0.0
-    for k in (0, n_scenes // 2, n_scenes - 1):
-        o = oracle.Oracle(scs[k].copy(precision=S.PREC_FP64))
-        # time_tile_kernel advanced every scene (1 + reps) launches
-        o.step((1 + launches + 1 + reps) * spl)
-        e = errors(b.state(slots[k]), o.state(), scale_of(scs[k]))
+    for k in plan["big_sample"]:  # every scene has now taken plan["big_steps"] steps
+        e = errors(b.state(slots[k]), refs["big"][k], scale_of(scs[k]))
         acc = max(acc, e["pos"], e["rot"])
     b.close()
     out = dict(scenes=n_scenes, bodies=nb, iters=iters, steps_per_launch=spl, ms_per_step=ms,
@@ -182,11 +216,10 @@ def big_batch_leg(P, S, torch, n_scenes, steps, spl):
     return out
 
 
-def oracle_single_core(S, drop_state=None):
+def oracle_single_core(oracle, S, drop_mid=None):
     """The FP64 oracle, one thread, on the single-scene workloads: the 8-chain
     (100 steps), the 1,000-box drop (5 steps with contacts active, from the
     oracle's own state at step 60) and the granular bed with the robot (1 step)."""
-    import oracle
     out = {}
     sc = S.chain8(precision=S.PREC_FP64)
     o = oracle.Oracle(sc)
@@ -194,15 +227,13 @@ def oracle_single_core(S, drop_state=None):
     o.step(100)
     dt = time.perf_counter() - t
     out["chain8"] = dict(body_its_per_s=sc.n_bodies * sc.iters * 100 / dt, steps=100, seconds=dt)
-    drop = S.box_drop(precision=S.PREC_FP64)
-    if drop_state is not None:
-        drop = drop.with_state(*drop_state, t0=60 * drop.h)
+    drop = drop_mid if drop_mid is not None else S.box_drop(precision=S.PREC_FP64)
     o = oracle.Oracle(drop)
     t = time.perf_counter()
     o.step(5)
     dt = time.perf_counter() - t
     out["box_drop_1000"] = dict(body_its_per_s=drop.n_bodies * drop.iters * 5 / dt, steps=5,
-                                seconds=dt, start="step 60" if drop_state is not None else "step 0")
+                                seconds=dt, start="step 60" if drop_mid is not None else "step 0")
     bed = S.granular_bed_quadruped(precision=S.PREC_FP64)
     o = oracle.Oracle(bed)
     t = time.perf_counter()
@@ -212,6 +243,40 @@ def oracle_single_core(S, drop_state=None):
     out["threads"] = 1
     log("oracle single core", out)
     return out
+
+
+# the big batch leg: one warm-up launch, BIG_TIMED_LAUNCHES timed launches, then
+# the tile kernel alone BIG_REPS times (each after a warm launch)
+BIG_TIMED_LAUNCHES, BIG_REPS = 2, 2
+
+
+def _plan(args, S, scenes):
+    """What the GPU legs will run and which of their results the oracle checks,
+    fixed before either side runs."""
+    spl = args.steps_per_launch
+    if spl < 1 or args.steps % spl:
+        raise SystemExit("--steps must be a multiple of --steps-per-launch")
+    warm_launches = max(1, -(-args.warmup // spl))
+    rng = np.random.default_rng(1)
+    plan = dict(spl=spl, launches=args.steps // spl, warm_launches=warm_launches,
+                total_steps=warm_launches * spl + args.steps,
+                batched_sample=[int(k) for k in rng.choice(len(scenes), 4, replace=False)],
+                requests=[], served_sample=[], big_scenes=None, big_sample=(), big_steps=0)
+    if args.serve_seconds > 0:
+        reqs = S.serving_requests(rate_hz=200.0, duration_s=args.serve_seconds, seed=3,
+                                  precision=S.PREC_FP32)
+        plan["requests"] = reqs
+        # chains: box piles are chaotic over hundreds of steps (FP32-rounded inputs
+        # move the FP64 oracle itself by O(1)), so they are checked at short
+        # horizons in the tests
+        plan["served_sample"] = [k for k in range(len(reqs))
+                                 if "chain" in reqs[k].scene.name and reqs[k].scene.n_bodies <= 80][:3]
+    if args.big_scenes > 0:
+        n = args.big_scenes
+        plan["big_scenes"] = S.batched_chains(n, seed=2, precision=S.PREC_FP32)
+        plan["big_sample"] = (0, n // 2, n - 1)
+        plan["big_steps"] = (1 + BIG_TIMED_LAUNCHES + 1 + BIG_REPS) * spl
+    return plan
 
 
 # ---------------------------------------------------------------------------
@@ -258,24 +323,19 @@ def main():
     n_bodies = sum(s.n_bodies for s in scenes)
     iters = scenes[0].iters
 
-    # CPU baseline first (before the GPU is touched, so fork is safe)
-    cpu = None
-    if not args.no_cpu_baseline:
-        cores = min(16, os.cpu_count() or 1)
-        sc64 = [s.copy(precision=S.PREC_FP64) for s in scenes]
-        cpu = cpu_baseline(sc64, min(args.cpu_sample, len(sc64)), args.cpu_steps, cores)
-        log("cpu baseline", cpu)
+    # the CPU leg first (before the GPU is touched): oracle timings and the
+    # oracle's reference results for every error the GPU legs report
+    plan = _plan(args, S, scenes)
+    cpu, refs = cpu_baseline_leg(args, S, scenes, plan)
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from parity import errors, scale_of
 
     import torch
     import paper_2609_02675_amd as P
     if P.device_count() < 1:
         raise SystemExit("no HIP device visible")
-    spl = args.steps_per_launch
-    if spl < 1 or args.steps % spl:
-        raise SystemExit("--steps must be a multiple of --steps-per-launch")
-    launches = args.steps // spl
-    warm_launches = max(1, -(-args.warmup // spl))
-    total_steps = warm_launches * spl + args.steps
+    spl, launches, warm_launches = plan["spl"], plan["launches"], plan["warm_launches"]
+    total_steps = plan["total_steps"]
     b = P.Batch(len(scenes) + 8, 4 << 30, S.PREC_FP32)
     t = time.perf_counter()
     slots = [b.admit(s, 1 << 30) for s in scenes]
@@ -315,15 +375,9 @@ def main():
         f"(host wall {wall:.3f}s)")
 
     # accuracy of the benchmarked run on sampled scenes vs the FP64 oracle
-    import oracle
-    sys.path.insert(0, os.path.join(ROOT, "tests"))
-    from parity import errors, scale_of
     acc = 0.0
-    rng = np.random.default_rng(1)
-    for k in rng.choice(len(scenes), 4, replace=False):
-        o = oracle.Oracle(scenes[k].copy(precision=S.PREC_FP64))
-        o.step(total_steps)
-        e = errors(b.state(slots[k]), o.state(), scale_of(scenes[k]))
+    for k in plan["batched_sample"]:
+        e = errors(b.state(slots[k]), refs["batched"][k], scale_of(scenes[k]))
         acc = max(acc, e["pos"], e["rot"])
     log(f"accuracy vs oracle after {total_steps} steps: {acc:.3e}")
 
@@ -377,10 +431,8 @@ def main():
     served = served_sat = None
     if args.serve_seconds > 0:
         from paper_2609_02675_amd.serve import Server
-        t = time.perf_counter()
-        reqs = S.serving_requests(rate_hz=200.0, duration_s=args.serve_seconds, seed=3,
-                                  precision=S.PREC_FP32)
-        log(f"generated {len(reqs)} requests in {time.perf_counter() - t:.1f}s")
+        reqs = plan["requests"]
+        log(f"{len(reqs)} requests")
         budget = int(args.serve_budget_gib * (1 << 30))
         srv = Server(budget, 512, S.PREC_FP32)
         res, st = srv.run(reqs, realtime=True, keep_state=False)
@@ -394,16 +446,11 @@ def main():
         served_sat = st.summary()
         served_sat.update(requests=len(reqs), budget_bytes=budget,
                           mode="same requests all queued at t=0 (capacity)")
-        # accuracy of served results against the oracle, on chains: box piles are
-        # chaotic over hundreds of steps (FP32-rounded inputs move the FP64 oracle
-        # itself by O(1)), so they are checked at short horizons in the tests
+        # accuracy of served results against the oracle, on sampled chains
         acc_s = 0.0
-        small = [k for k in sorted(res) if res[k].state is not None and "chain" in reqs[k].scene.name
-                 and reqs[k].scene.n_bodies <= 80][:3]
+        small = plan["served_sample"]
         for k in small:
-            o = oracle.Oracle(reqs[k].scene.copy(precision=S.PREC_FP64))
-            o.step(reqs[k].steps)
-            e = errors(res[k].state, o.state(), scale_of(reqs[k].scene))
+            e = errors(res[k].state, refs["served"][k], scale_of(reqs[k].scene))
             acc_s = max(acc_s, e["pos"], e["rot"])
         served_sat["max_rel_err_vs_fp64_oracle"] = acc_s
         served_sat["checked"] = [reqs[k].scene.name for k in small]
@@ -426,20 +473,14 @@ def main():
             dt = time.perf_counter() - t
             return g, sc.n_bodies * sc.iters * steps / dt, 1e3 * dt / steps
 
-        drop_oracle = S.box_drop(precision=S.PREC_FP64)
-        o = oracle.Oracle(drop_oracle)
-        o.step(60)
-        c, A, v, w = o.state()
         for prec, tag in ((S.PREC_FP32, "fp32"), (S.PREC_FP64, "fp64")):
             sc = S.box_drop(precision=prec)
             g, rate, ms = time_scene(sc, 40, 60)
             # accuracy: one step from the oracle's state after 60 steps (contacts active)
-            mid = drop_oracle.with_state(c, A, v, w, t0=60 * sc.h).copy(precision=prec)
+            mid = refs["drop_mid"].copy(precision=prec)
             gm = P.Scene(mid)
             gm.step(1)
-            om = oracle.Oracle(mid.copy(precision=S.PREC_FP64))
-            om.step(1)
-            e = errors(gm.state(check=False), om.state(), scale_of(mid))
+            e = errors(gm.state(check=False), refs["drop_next"], scale_of(mid))
             scene_legs[f"box_drop_1000_{tag}"] = dict(
                 body_its_per_s=rate, ms_per_step=ms, steps_timed="40..100 (falling, then landing)",
                 one_step_err_vs_oracle=max(e["pos"], e["rot"]), iters=sc.iters)
@@ -457,9 +498,6 @@ def main():
         for aug, tag in ((True, "al"), (False, "quadratic")):
             mc = S.mass_ratio_chain(augmented=aug, precision=S.PREC_FP32)
             g, rate, ms = time_scene(mc, 10, 100)
-            om = oracle.Oracle(mc.copy(precision=S.PREC_FP64))
-            om.step(110)
-            c_g = g.state(check=False)[0]
             joint = lambda c, A: max(abs(np.linalg.norm(A[mc.bond_i[e]] @ mc.x_i[e] + c[mc.bond_i[e]]
                                                      - A[mc.bond_j[e]] @ mc.x_j[e] - c[mc.bond_j[e]])
                                          - mc.rest_len[e]) for e in range(mc.n_bonds))
@@ -467,7 +505,7 @@ def main():
             scene_legs[f"mass_ratio_chain_19_{tag}_fp32"] = dict(
                 body_its_per_s=rate, ms_per_step=ms, iters=mc.iters, steps_timed="11..110",
                 max_joint_error_m=float(joint(st[0], st[1])),
-                max_joint_error_oracle_m=float(joint(*om.state()[:2])),
+                max_joint_error_oracle_m=float(joint(*refs["mass_ratio"][aug][:2])),
                 paper_context="Table 2, mass-ratio chain (19 bodies, 10 iterations) on an RTX 3080: "
                               "t_solve 1.28 ms (AL on) / 1.25 ms (off) per frame")
             log(f"mass-ratio chain {tag}: {ms:.3f} ms/step, joint error {joint(st[0], st[1]):.3g} m")
@@ -503,15 +541,7 @@ def main():
     big = None
     if args.big_scenes > 0:
         del b
-        big = big_batch_leg(P, S, torch, args.big_scenes, 2 * spl, spl)
-
-    oracle_1core = None
-    if not args.no_oracle_single:
-        oracle_1core = oracle_single_core(S, None if args.no_scenes else (c, A, v, w))
-    if cpu is not None:
-        cpu["host"] = host_info()
-        if oracle_1core is not None:
-            cpu["single_core_single_scene"] = oracle_1core
+        big = big_batch_leg(P, S, torch, plan, refs)
 
     out = {
         "metric": METRIC,
