@@ -3,14 +3,14 @@
 
 Default workload: 4,096 independent joint chains of 4..64 unit cubes (ball joints,
 +-30 degree random joint angles, top body pinned), FP32, 20 iterations per step,
-all advanced together by the batched path (one captured-graph replay per step,
-tile kernel running each scene's whole step from LDS).  Also reported on the
-same accuracy bar: the plain single-scene path (one kernel launch per
+all advanced together by the batched path (one captured-graph replay per 10
+steps: one tile-kernel launch running every scene's steps from registers and
+LDS).  Also reported on the same accuracy bar: the plain single-scene path (one kernel launch per
 iteration) on a sample of the same scenes, the served mix (continuous
 batching, see paper_2609_02675_amd/serve.py), and the FP64 CPU oracle on a
 bounded sample (the CPU baseline).
 
-Prints ONE JSON line.  `python bench.py --gpus N` with N > 1 exits: this build
+Prints ONE JSON line.  `python bench.py --gpus N` with N > 1 exits: the library
 runs on one GPU.
 """
 from __future__ import annotations
@@ -309,7 +309,7 @@ def main():
                     help="run only the 1 GiB HBM copy probe (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "the library runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
 
     if args.probe_only:

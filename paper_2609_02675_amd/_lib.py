@@ -78,7 +78,7 @@ def lib():
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
-        raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build() first")
+        raise RuntimeError(f"{LIB_PATH} is not built: run python paper_2609_02675_amd/build.py first")
     # PyTorch ships its own HIP runtime and exports its symbols globally; loading it
     # first makes the library bind to that same runtime, so a process that also
     # uses torch (streams, events, its allocator) has one HIP runtime, not two
