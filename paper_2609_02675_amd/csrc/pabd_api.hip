@@ -262,7 +262,14 @@ struct pabd_scene {
   int debug = 0;
   bool history = false;
   Graph graph;
-  hipStream_t graph_stream = nullptr;
+  // releases what the handle holds, also after a create that failed part-way
+  // (its own stream is drained first; work on callers' streams is the caller's)
+  ~pabd_scene() {
+    if (stream) (void)hipStreamSynchronize(stream);
+    graph.reset();
+    eng.reset();
+    if (stream) (void)hipStreamDestroy(stream);
+  }
 };
 
 extern "C" {
@@ -317,9 +324,6 @@ pabd_status pabd_scene_create(const pabd_scene_desc* desc, pabd_scene** out) {
 pabd_status pabd_scene_destroy(pabd_scene* s) {
   if (!s) return PABD_OK;
   (void)hipDeviceSynchronize();  // steps may have been enqueued on a caller's stream
-  s->graph.reset();
-  s->eng.reset();
-  if (s->stream) (void)hipStreamDestroy(s->stream);
   delete s;
   return PABD_OK;
 }
@@ -585,6 +589,18 @@ struct pabd_batch {
              tile == o.tile && stream == o.stream && contact == o.contact && table == o.table;
     }
   } launch;
+  // releases what the handle holds, also after a create that failed part-way
+  // (its own stream is drained first; work on callers' streams is the caller's)
+  ~pabd_batch() {
+    if (stream) (void)hipStreamSynchronize(stream);
+    graph.reset();
+    dev.put(d_first);
+    dev.put(d_count);
+    dev.put(d_kmax);
+    dev.put(d_ntiles);
+    eng.reset();
+    if (stream) (void)hipStreamDestroy(stream);
+  }
 };
 
 namespace {
@@ -840,13 +856,6 @@ pabd_status pabd_batch_create(int32_t max_slots, size_t hbm_budget, int32_t prec
 pabd_status pabd_batch_destroy(pabd_batch* b) {
   if (!b) return PABD_OK;
   (void)hipDeviceSynchronize();  // steps may have been enqueued on a caller's stream
-  b->graph.reset();
-  b->dev.put(b->d_first);
-  b->dev.put(b->d_count);
-  b->dev.put(b->d_kmax);
-  b->dev.put(b->d_ntiles);
-  b->eng.reset();
-  if (b->stream) (void)hipStreamDestroy(b->stream);
   delete b;
   return PABD_OK;
 }
@@ -1086,19 +1095,23 @@ pabd_status pabd_batch_time_tile_kernel(pabd_batch* b, int32_t reps, int32_t nst
     b->dirty = false;
   }
   if (b->grid_tiles == 0) return PABD_OK;
-  hipEvent_t e0, e1;
-  API_HIP(hipEventCreate(&e0));
-  API_HIP(hipEventCreate(&e1));
+  struct Events {  // released on every path, failures included
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ~Events() {
+      if (e0) (void)hipEventDestroy(e0);
+      if (e1) (void)hipEventDestroy(e1);
+    }
+  } ev;
+  API_HIP(hipEventCreate(&ev.e0));
+  API_HIP(hipEventCreate(&ev.e1));
   TileTable tt{b->d_first, b->d_count, b->d_kmax, b->d_ntiles};
   b->eng->tile_step(b->tile_bodies, tt, b->grid_tiles, nsteps, b->stream);  // warm
-  API_HIP(hipEventRecord(e0, b->stream));
+  API_HIP(hipEventRecord(ev.e0, b->stream));
   for (int r = 0; r < reps; ++r) b->eng->tile_step(b->tile_bodies, tt, b->grid_tiles, nsteps, b->stream);
-  API_HIP(hipEventRecord(e1, b->stream));
-  API_HIP(hipEventSynchronize(e1));
+  API_HIP(hipEventRecord(ev.e1, b->stream));
+  API_HIP(hipEventSynchronize(ev.e1));
   float ms = 0.f;
-  API_HIP(hipEventElapsedTime(&ms, e0, e1));
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  API_HIP(hipEventElapsedTime(&ms, ev.e0, ev.e1));
   *avg_ms = (double)ms / reps;
   return PABD_OK;
 }
@@ -1181,33 +1194,36 @@ pabd_status pabd_hbm_copy_probe(size_t bytes, int32_t reps, double* gbps, double
   if (reps < 1 || bytes < 16) return fail(PABD_E_INVALID, "bad probe arguments");
   if (pabd_device_count() < 1) return fail(PABD_E_DEVICE, "no HIP device");
   const size_t n = bytes / 16;
-  float4 *a = nullptr, *b = nullptr;
-  hipStream_t st;
-  API_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
-  if (hipMalloc(&a, n * 16) != hipSuccess || hipMalloc(&b, n * 16) != hipSuccess) {
-    if (a) (void)hipFree(a);
-    (void)hipStreamDestroy(st);
+  // every resource is released on every path, failures included
+  struct Res {
+    float4 *a = nullptr, *b = nullptr;
+    hipStream_t st = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ~Res() {
+      if (st) (void)hipStreamSynchronize(st);
+      if (e0) (void)hipEventDestroy(e0);
+      if (e1) (void)hipEventDestroy(e1);
+      if (a) (void)hipFree(a);
+      if (b) (void)hipFree(b);
+      if (st) (void)hipStreamDestroy(st);
+    }
+  } r;
+  API_HIP(hipStreamCreateWithFlags(&r.st, hipStreamNonBlocking));
+  if (hipMalloc(&r.a, n * 16) != hipSuccess || hipMalloc(&r.b, n * 16) != hipSuccess)
     return fail(PABD_E_OOM, "probe allocation failed");
-  }
-  API_HIP(hipMemsetAsync(a, 0, n * 16, st));
+  API_HIP(hipMemsetAsync(r.a, 0, n * 16, r.st));
   int cus = 256;
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, 0);
   const dim3 grid((unsigned)std::min<size_t>((n + 255) / 256, (size_t)cus * 16)), block(256);
-  hipLaunchKernelGGL(k_copy_probe, grid, block, 0, st, (const float4*)a, b, n);
-  hipEvent_t e0, e1;
-  API_HIP(hipEventCreate(&e0));
-  API_HIP(hipEventCreate(&e1));
-  API_HIP(hipEventRecord(e0, st));
-  for (int r = 0; r < reps; ++r) hipLaunchKernelGGL(k_copy_probe, grid, block, 0, st, (const float4*)a, b, n);
-  API_HIP(hipEventRecord(e1, st));
-  API_HIP(hipEventSynchronize(e1));
+  hipLaunchKernelGGL(k_copy_probe, grid, block, 0, r.st, (const float4*)r.a, r.b, n);
+  API_HIP(hipEventCreate(&r.e0));
+  API_HIP(hipEventCreate(&r.e1));
+  API_HIP(hipEventRecord(r.e0, r.st));
+  for (int k = 0; k < reps; ++k) hipLaunchKernelGGL(k_copy_probe, grid, block, 0, r.st, (const float4*)r.a, r.b, n);
+  API_HIP(hipEventRecord(r.e1, r.st));
+  API_HIP(hipEventSynchronize(r.e1));
   float ms = 0.f;
-  API_HIP(hipEventElapsedTime(&ms, e0, e1));
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  (void)hipFree(a);
-  (void)hipFree(b);
-  (void)hipStreamDestroy(st);
+  API_HIP(hipEventElapsedTime(&ms, r.e0, r.e1));
   const double per = (double)ms / reps;
   if (avg_ms) *avg_ms = per;
   if (gbps) *gbps = 2.0 * (double)(n * 16) / (per * 1e-3) / 1e9;
