@@ -215,7 +215,7 @@ __device__ __forceinline__ void polar_newton_plain(T* X, bool on) {
   const T a = on ? (T)0.5 : (T)1;
   const T b = on ? (T)0.5 * rcp(det) : (T)0;
 #pragma unroll
-  for (int k = 0; k < 9; ++k) X[k] = a * X[k] + b * C[k];
+  for (int k = 0; k < 9; ++k) X[k] = fma(b, C[k], a * X[k]);
 }
 
 __device__ __forceinline__ bool wave_any(bool p) { return __builtin_amdgcn_ballot_w64(p) != 0; }
@@ -233,7 +233,7 @@ __device__ __forceinline__ bool wave_any(bool p) { return __builtin_amdgcn_ballo
 // factor, so if det X is not safely positive or Newton stalls, the nearest
 // proper rotation from the SVD of the current iterate is the answer.
 template <typename T>
-__device__ __forceinline__ void polar_rotation_inplace(T* X) {
+__device__ __forceinline__ bool polar_fast(T* X, bool* ok_out) {
   T d2;
   bool unscaled = false;
   const bool ok = polar_newton_step<T>(X, &d2, &unscaled);
@@ -242,24 +242,65 @@ __device__ __forceinline__ void polar_rotation_inplace(T* X) {
   const bool two = one && d2 > Eps<T>::polar_one;
   polar_newton_plain<T>(X, one);
   if (wave_any(two)) polar_newton_plain<T>(X, two);
-  bool done = conv || one;
-  if (wave_any(!done)) {
-    if (ok && !done) {
+  *ok_out = ok;
+  return conv || one;
+}
+
+// The rest for a lane whose first step was too large: measured steps while det X
+// stays safely positive, then, if they did not converge, the SVD.
+template <typename T>
+__device__ __forceinline__ void polar_finish(T* X, bool ok) {
+  bool done = false;
+  if (ok) {
+    T d2;
+    bool unscaled;
 #pragma unroll 1
-      for (int it = 1; it < 16; ++it) {
-        if (!polar_newton_step<T>(X, &d2, &unscaled)) break;
-        if (d2 < Eps<T>::polar_tol2) {
-          done = true;
-          break;
-        }
+    for (int it = 1; it < 16; ++it) {
+      if (!polar_newton_step<T>(X, &d2, &unscaled)) break;
+      if (d2 < Eps<T>::polar_tol2) {
+        done = true;
+        break;
       }
     }
+  }
+  if (!done) {
+    T Y[9];
+    nearest_rotation_svd(X, Y);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) X[k] = Y[k];
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void polar_rotation_inplace(T* X) {
+  bool ok;
+  const bool done = polar_fast(X, &ok);
+  if (wave_any(!done))
+    if (!done) polar_finish(X, ok);
+}
+
+// The same for a caller short of registers: around the rare continuation X
+// goes through the lane's own 9 words `spill` of LDS, so that the compiler need
+// not keep a second copy of X in registers beside the continuation's own.
+template <typename T>
+__device__ __forceinline__ void polar_rotation_spill(T* X, T* spill) {
+  bool ok;
+  const bool done = polar_fast(X, &ok);
+  if (wave_any(!done)) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) spill[k] = X[k];
+    asm volatile("" ::: "memory");
     if (!done) {
       T Y[9];
-      nearest_rotation_svd(X, Y);
 #pragma unroll
-      for (int k = 0; k < 9; ++k) X[k] = Y[k];
+      for (int k = 0; k < 9; ++k) Y[k] = spill[k];
+      polar_finish(Y, ok);
+#pragma unroll
+      for (int k = 0; k < 9; ++k) spill[k] = Y[k];
     }
+    asm volatile("" ::: "memory");
+#pragma unroll
+    for (int k = 0; k < 9; ++k) X[k] = spill[k];
   }
 }
 
@@ -467,6 +508,44 @@ __device__ __forceinline__ void add_inertia(T* r, const T* mass, const T* s, con
     r[3 + 3 * k] += p00 * d0 + p01 * d1 + p02 * d2;
     r[4 + 3 * k] += p01 * d0 + p11 * d1 + p12 * d2;
     r[5 + 3 * k] += p02 * d0 + p12 * d1 + p22 * d2;
+  }
+}
+
+// The constant part of the inertia term when s stays fixed through a step's
+// iterations: ms = M s, so that M (s - q) = ms - M q costs one fused chain per
+// component.  In FP32 only the low position words enter: the caller keeps the
+// high words of q equal to those of s through the iterations (increments go to
+// the low word), so m (c_s - c_q) = m lo_s - m lo_q.
+template <typename T>
+__device__ __forceinline__ void mass_times(const T* mass, const T* s, T* ms) {
+  constexpr int L = sizeof(T) == 4 ? 12 : 0;
+  const T m = mass[0], p00 = mass[1], p01 = mass[2], p02 = mass[3], p11 = mass[4],
+          p12 = mass[5], p22 = mass[6];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) ms[c] = m * s[L + c];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const T a0 = s[3 + 3 * k], a1 = s[4 + 3 * k], a2 = s[5 + 3 * k];
+    ms[3 + 3 * k] = p00 * a0 + p01 * a1 + p02 * a2;
+    ms[4 + 3 * k] = p01 * a0 + p11 * a1 + p12 * a2;
+    ms[5 + 3 * k] = p02 * a0 + p12 * a1 + p22 * a2;
+  }
+}
+
+// r = ms - M q (the inertia term M (s - q) with ms = M s from mass_times)
+template <typename T>
+__device__ __forceinline__ void inertia_from(T* r, const T* mass, const T* ms, const T* q) {
+  constexpr int L = sizeof(T) == 4 ? 12 : 0;
+  const T m = mass[0], p00 = mass[1], p01 = mass[2], p02 = mass[3], p11 = mass[4],
+          p12 = mass[5], p22 = mass[6];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) r[c] = fma(-m, q[L + c], ms[c]);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const T a0 = q[3 + 3 * k], a1 = q[4 + 3 * k], a2 = q[5 + 3 * k];
+    r[3 + 3 * k] = fma(-p02, a2, fma(-p01, a1, fma(-p00, a0, ms[3 + 3 * k])));
+    r[4 + 3 * k] = fma(-p12, a2, fma(-p11, a1, fma(-p01, a0, ms[4 + 3 * k])));
+    r[5 + 3 * k] = fma(-p22, a2, fma(-p12, a1, fma(-p02, a0, ms[5 + 3 * k])));
   }
 }
 

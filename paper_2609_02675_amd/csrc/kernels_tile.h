@@ -72,23 +72,21 @@ __global__ void __launch_bounds__(TB, sizeof(T) == 4 ? 3 : 1) k_tile_step(View<T
       const bool moving = present && !pinned;
       // scene constants are re-read every step rather than held in registers
       // through the iterations
-      int K = 0, debug = 0;
-      if (present) {
-        K = v.scenes[scn].iters;
-        debug = v.scenes[scn].debug;
-      }
-      T s[QR];
+      const int K = present ? v.scenes[scn].iters : 0;
+      // M s of the prediction s: the inertia term's part that no iteration
+      // changes (q's high position words stay those of s through the step)
+      T ms[QW];
       if (moving) {
         store<T, QR>(lqn + QR * lane, q);
-        // prediction
+        // prediction, in place: q becomes s
         const SceneDev& S = v.scenes[scn];
         const T h = (T)S.h;
+        T As[9];
+        predict_rotation(q + 3, vw + 3, h, As);
 #pragma unroll
-        for (int c = 0; c < QR; ++c) s[c] = q[c];
-        pos_add_lo(s, h * (vw[0] + h * (T)S.g0), h * (vw[1] + h * (T)S.g1), h * (vw[2] + h * (T)S.g2));
-        predict_rotation(q + 3, vw + 3, h, s + 3);
-#pragma unroll
-        for (int c = 0; c < QR; ++c) q[c] = s[c];
+        for (int c = 0; c < 9; ++c) q[3 + c] = As[c];
+        pos_add_lo(q, h * (vw[0] + h * (T)S.g0), h * (vw[1] + h * (T)S.g1), h * (vw[2] + h * (T)S.g2));
+        mass_times(m, q, ms);
       }
       // v is rebuilt from q^{n+1} and q^n after the iterations: nothing of it
       // needs to live through them
@@ -103,9 +101,7 @@ __global__ void __launch_bounds__(TB, sizeof(T) == 4 ? 3 : 1) k_tile_step(View<T
           // r = M (s - q^k) + sum of the ends' J^T f (the forces carry h^2);
           // starting from the inertia term leaves no accumulator to clear
           T r[QW];
-#pragma unroll
-          for (int c = 0; c < QW; ++c) r[c] = (T)0;
-          add_inertia(r, m, s, q);
+          inertia_from(r, m, ms, q);
 #pragma unroll
           for (int u = 0; u < MAXE; ++u)
             if (u < ne) {
@@ -141,7 +137,10 @@ __global__ void __launch_bounds__(TB, sizeof(T) == 4 ? 3 : 1) k_tile_step(View<T
           pos_add_lo(q, dq[0], dq[1], dq[2]);
 #pragma unroll
           for (int c = 0; c < 9; ++c) q[3 + c] += dq[3 + c];
-          if (!(debug & 1)) polar_rotation_inplace(q + 3);
+          // the rare polar continuation passes X through this lane's words of
+          // the other q buffer, which no lane reads before the next iteration
+          // has rewritten them
+          polar_rotation_spill(q + 3, lq[(k + 1) & 1] + QR * lane);
           if (last) {
             T dd[QW];
 #pragma unroll
