@@ -204,18 +204,24 @@ __device__ __forceinline__ bool polar_newton_step(T* X, T* step2, bool* unscaled
   return true;
 }
 
-// An unscaled Newton step X <- (X + X^{-T}) / 2 whose size is not measured, for
-// the lanes with on set (only right after a step, when det X >= 1); the other
-// lanes keep X (coefficients 1 and 0).  Run by the whole wave, so that no lane's
-// registers need merging afterwards.
+// The fast steps work on X = sigma Y with a per-lane scalar sigma: from
+// C(X) = sigma^2 C(Y) and det X = sigma^3 det Y, the step
+// X' = (zeta X + X^{-T} / zeta) / 2 is sigma' = zeta sigma / 2 with
+// Y' = Y + gamma C(Y), gamma = 1 / (zeta^2 sigma^2 det Y): one fma per entry.
+//
+// An unscaled step (zeta = 1) whose size is not measured, for the lanes with
+// on set (only right after a step, when det X >= 1); the other lanes keep Y and
+// sigma.  Run by the whole wave, so that no lane's registers need merging
+// afterwards.
 template <typename T>
-__device__ __forceinline__ void polar_newton_plain(T* X, bool on) {
+__device__ __forceinline__ void polar_newton_plain(T* Y, T* sigma, bool on) {
   T C[9];
-  const T det = cofactor(X, C);
-  const T a = on ? (T)0.5 : (T)1;
-  const T b = on ? (T)0.5 * rcp(det) : (T)0;
+  const T det = cofactor(Y, C);
+  const T s = *sigma;
+  const T g = on ? rcp(s * s * det) : (T)0;
+  *sigma = on ? (T)0.5 * s : s;
 #pragma unroll
-  for (int k = 0; k < 9; ++k) X[k] = fma(b, C[k], a * X[k]);
+  for (int k = 0; k < 9; ++k) Y[k] = fma(g, C[k], Y[k]);
 }
 
 __device__ __forceinline__ bool wave_any(bool p) { return __builtin_amdgcn_ballot_w64(p) != 0; }
@@ -234,14 +240,30 @@ __device__ __forceinline__ bool wave_any(bool p) { return __builtin_amdgcn_ballo
 // proper rotation from the SVD of the current iterate is the answer.
 template <typename T>
 __device__ __forceinline__ bool polar_fast(T* X, bool* ok_out) {
-  T d2;
-  bool unscaled = false;
-  const bool ok = polar_newton_step<T>(X, &d2, &unscaled);
+  // the measured first step, on Y = X (sigma = 1); |X' - X| = |zeta Y' / 2 - Y|
+  T C[9];
+  const T det = cofactor(X, C);
+  const bool ok = det > Eps<T>::det_floor;
+  const bool unscaled = det > (T)0.5 && det < (T)1.5;
+  const T zeta = unscaled || !ok ? (T)1 : rcp(cbrt(det));
+  const T g = ok ? rcp(zeta * zeta * det) : (T)0;
+  const T hz = ok ? (T)0.5 * zeta : (T)1;
+  T d2 = 0;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    const T y = fma(g, C[k], X[k]);
+    const T t = fma(hz, y, -X[k]);
+    d2 = fma(t, t, d2);
+    X[k] = y;
+  }
+  T sigma = hz;
   const bool conv = ok && d2 < Eps<T>::polar_tol2;
   const bool one = ok && !conv && unscaled && d2 <= Eps<T>::polar_two;
   const bool two = one && d2 > Eps<T>::polar_one;
-  polar_newton_plain<T>(X, one);
-  if (wave_any(two)) polar_newton_plain<T>(X, two);
+  polar_newton_plain<T>(X, &sigma, one);
+  if (wave_any(two)) polar_newton_plain<T>(X, &sigma, two);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) X[k] *= sigma;
   *ok_out = ok;
   return conv || one;
 }
@@ -286,21 +308,23 @@ template <typename T>
 __device__ __forceinline__ void polar_rotation_spill(T* X, T* spill) {
   bool ok;
   const bool done = polar_fast(X, &ok);
+  // spill word w holds X[(w + 1) % 9]: X[1..8] in two 16-byte groups, which
+  // for X = q + 3 are register quads of the record q
   if (wave_any(!done)) {
 #pragma unroll
-    for (int k = 0; k < 9; ++k) spill[k] = X[k];
+    for (int k = 0; k < 9; ++k) spill[(k + 8) % 9] = X[k];
     asm volatile("" ::: "memory");
     if (!done) {
       T Y[9];
 #pragma unroll
-      for (int k = 0; k < 9; ++k) Y[k] = spill[k];
+      for (int k = 0; k < 9; ++k) Y[k] = spill[(k + 8) % 9];
       polar_finish(Y, ok);
 #pragma unroll
-      for (int k = 0; k < 9; ++k) spill[k] = Y[k];
+      for (int k = 0; k < 9; ++k) spill[(k + 8) % 9] = Y[k];
     }
     asm volatile("" ::: "memory");
 #pragma unroll
-    for (int k = 0; k < 9; ++k) X[k] = spill[k];
+    for (int k = 0; k < 9; ++k) X[k] = spill[(k + 8) % 9];
   }
 }
 
@@ -488,6 +512,33 @@ __device__ __forceinline__ void bond_vec(const T* qs, const T* xs, const T* qo, 
     u = fma(-as[2], xs[2], u);
     if constexpr (sizeof(T) == 4) u += qo ? qo[12 + r] - qs[12 + r] : -qs[12 + r];
     d[r] = u;
+  }
+}
+
+// The part of the bond point y = c + A x that changes within a step: in FP32 the
+// low word c_lo + A x (the high word c_hi of the body position stays fixed
+// through a step), in FP64 all of y.  One fused chain per component.
+template <typename T>
+__device__ __forceinline__ void bond_point_part(const T* q, const T* x, T* y) {
+  constexpr int L = sizeof(T) == 4 ? 12 : 0;
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const T* a = q + 3 + 3 * r;
+    y[r] = fma(a[2], x[2], fma(a[1], x[1], fma(a[0], x[0], q[L + r])));
+  }
+}
+
+// d = y_o - y_s from both points' parts (bond_point_part); in FP32 the
+// difference of the two bodies' high position words is added first
+template <typename T>
+__device__ __forceinline__ void bond_vec_points(const T* qs, const T* qo, const T* ys, const T* yo,
+                                                T* d) {
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    if constexpr (sizeof(T) == 4)
+      d[r] = (qo[r] - qs[r]) + (yo[r] - ys[r]);
+    else
+      d[r] = yo[r] - ys[r];
   }
 }
 

@@ -150,20 +150,23 @@ __global__ void __launch_bounds__(256) k_factor(View<T> v, const double* mass64,
 // by h^2 (the record holds h^2 kappa and h^2 phi^-):
 // h^2 f = h^2 kappa d + h^2 phim d/|d| (phi^+ / d = kappa implicit, phi^- explicit)
 template <typename T>
-__device__ __forceinline__ void quad_end_force(const T* E, const T* d, T* f) {
-  const T kap = E[3];
+__device__ __forceinline__ void end_force(T kap, T phim, const T* d, T* f) {
   f[0] = kap * d[0];
   f[1] = kap * d[1];
   f[2] = kap * d[2];
-  if (E[7] != (T)0) {
+  if (phim != (T)0) {
     T dn2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
     if (dn2 > (T)1e-24) {
-      T sc = E[7] * rsqrt_(dn2);
+      T sc = phim * rsqrt_(dn2);
       f[0] += sc * d[0];
       f[1] += sc * d[1];
       f[2] += sc * d[2];
     }
   }
+}
+template <typename T>
+__device__ __forceinline__ void quad_end_force(const T* E, const T* d, T* f) {
+  end_force(E[3], E[7], d, f);
 }
 
 // contact end (reading of the paper's contact bond), d = y_o - y_s: stick force
