@@ -528,20 +528,6 @@ __device__ __forceinline__ void bond_point_part(const T* q, const T* x, T* y) {
   }
 }
 
-// d = y_o - y_s from both points' parts (bond_point_part); in FP32 the
-// difference of the two bodies' high position words is added first
-template <typename T>
-__device__ __forceinline__ void bond_vec_points(const T* qs, const T* qo, const T* ys, const T* yo,
-                                                T* d) {
-#pragma unroll
-  for (int r = 0; r < 3; ++r) {
-    if constexpr (sizeof(T) == 4)
-      d[r] = (qo[r] - qs[r]) + (yo[r] - ys[r]);
-    else
-      d[r] = yo[r] - ys[r];
-  }
-}
-
 // r += M (s - q): translational block m I, three affine blocks Pi (sym)
 template <typename T>
 __device__ __forceinline__ void add_inertia(T* r, const T* mass, const T* s, const T* q) {
@@ -600,19 +586,21 @@ __device__ __forceinline__ void inertia_from(T* r, const T* mass, const T* ms, c
   }
 }
 
-// q^T M q in FP64 of a 12-component vector (positions already combined)
+// q^T M q of a 12-component vector whose position part c is given apart,
+// formed in the arithmetic type (one body's share) and handed over in FP64 for
+// the sums across bodies
 template <typename T>
-__device__ __forceinline__ double m_norm2(const T* mass, const double* c, const T* q) {
-  double m = mass[0], p00 = mass[1], p01 = mass[2], p02 = mass[3], p11 = mass[4],
-         p12 = mass[5], p22 = mass[6];
-  double s = m * (c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+__device__ __forceinline__ double m_norm2(const T* mass, const T* c, const T* q) {
+  const T m = mass[0], p00 = mass[1], p01 = mass[2], p02 = mass[3], p11 = mass[4],
+          p12 = mass[5], p22 = mass[6];
+  T s = m * (c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    double a0 = q[3 + 3 * k], a1 = q[4 + 3 * k], a2 = q[5 + 3 * k];
+    const T a0 = q[3 + 3 * k], a1 = q[4 + 3 * k], a2 = q[5 + 3 * k];
     s += a0 * (p00 * a0 + p01 * a1 + p02 * a2) + a1 * (p01 * a0 + p11 * a1 + p12 * a2) +
          a2 * (p02 * a0 + p12 * a1 + p22 * a2);
   }
-  return s;
+  return (double)s;
 }
 
 }  // namespace pabd

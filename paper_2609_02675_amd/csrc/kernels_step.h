@@ -197,7 +197,7 @@ __device__ __forceinline__ bool contact_end_force(const T* C, const T* d, T* f) 
   return true;
 }
 
-// FP64 residual partials of one body: |q_new - q|_M^2 and |q|_M^2
+// residual partials of one body: |q_new - q|_M^2 and |q|_M^2
 template <typename T>
 __device__ __forceinline__ void residual_terms(const T* m, const T* qo, const T* q, double* num,
                                                double* den) {
@@ -205,9 +205,8 @@ __device__ __forceinline__ void residual_terms(const T* m, const T* qo, const T*
   pos_diff(qo, q, dd);
 #pragma unroll
   for (int c = 3; c < QW; ++c) dd[c] = qo[c] - q[c];
-  const double dc[3] = {(double)dd[0], (double)dd[1], (double)dd[2]};
-  const double cc[3] = {pos_value(q, 0), pos_value(q, 1), pos_value(q, 2)};
-  *num = m_norm2(m, dc, dd);
+  const T cc[3] = {(T)pos_value(q, 0), (T)pos_value(q, 1), (T)pos_value(q, 2)};
+  *num = m_norm2(m, dd, dd);
   *den = m_norm2(m, cc, q);
 }
 

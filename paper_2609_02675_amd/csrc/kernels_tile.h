@@ -170,6 +170,7 @@ __global__ void __launch_bounds__(TB, sizeof(T) == 4 ? 3 : 1) k_tile_step(View<T
 #pragma unroll
       for (int c = 0; c < VW; ++c) vw[c] = (T)0;
       double num = 0.0, den = 0.0;
+      T dh[MAXE][3];  // FP32: c_hi of the partner minus c_hi of this body, per end
       for (int k = 0; k < kmax; ++k) {
         T* buf = lq[k & 1];
         T* ybuf = ly[k & 1];
@@ -193,12 +194,24 @@ __global__ void __launch_bounds__(TB, sizeof(T) == 4 ? 3 : 1) k_tile_step(View<T
 #pragma unroll
           for (int u = 0; u < MAXE; ++u)
             if (u < ne) {
-              // d = y_o - y_s from the two published points (and in FP32 the
-              // difference of the high position words)
+              // d = y_o - y_s from the two published points; in FP32 plus the
+              // difference of the high position words, fixed through the step
+              // and so taken once, in its first iteration
               T ys[4], yo[4], d[3], f[3];
               load<T, 4>(ybuf + L::YS * (u * TB + lane), ys);
               load<T, 4>(ybuf + yoff[u], yo);
-              bond_vec_points(q, buf + L::CS * qslot[u], ys, yo, d);
+              if constexpr (sizeof(T) == 4) {
+                if (k == 0) {
+                  const T* co = buf + L::CS * qslot[u];
+#pragma unroll
+                  for (int c = 0; c < 3; ++c) dh[u][c] = co[c] - q[c];
+                }
+#pragma unroll
+                for (int c = 0; c < 3; ++c) d[c] = dh[u][c] + (yo[c] - ys[c]);
+              } else {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) d[c] = yo[c] - ys[c];
+              }
               if (some_unmirrored[u]) {
                 // an end anchored in the world, or whose mirror is not among the
                 // partner's register ends: from the partner's q and its record
@@ -230,7 +243,7 @@ __global__ void __launch_bounds__(TB, sizeof(T) == 4 ? 3 : 1) k_tile_step(View<T
           const bool last = k == K - 1;
           T Aold[9];
           if (last) {
-            const double cc[3] = {pos_value(q, 0), pos_value(q, 1), pos_value(q, 2)};
+            const T cc[3] = {(T)pos_value(q, 0), (T)pos_value(q, 1), (T)pos_value(q, 2)};
             den = m_norm2(m, cc, q);
 #pragma unroll
             for (int c = 0; c < 9; ++c) Aold[c] = q[3 + c];
@@ -248,8 +261,7 @@ __global__ void __launch_bounds__(TB, sizeof(T) == 4 ? 3 : 1) k_tile_step(View<T
             for (int c = 0; c < 3; ++c) dd[c] = dq[c];
 #pragma unroll
             for (int c = 0; c < 9; ++c) dd[3 + c] = q[3 + c] - Aold[c];
-            const double dc[3] = {(double)dq[0], (double)dq[1], (double)dq[2]};
-            num = m_norm2(m, dc, dd);
+            num = m_norm2(m, dd, dd);
           }
         }
       }
