@@ -57,27 +57,33 @@ def log(*a):
 
 
 TILE_SOURCES = ["common.h", "device_math.h", "kernels_step.h", "kernels_tile.h"]
-TILE_PROFILE = os.path.join(ROOT, "profiles", "k_tile_step_batched_chains_4096.md")
+# counter profile of the tile kernel, one file per workload
+TILE_PROFILE = os.path.join(ROOT, "profiles", "k_tile_step_{workload}.md")
 
 
-def tile_traffic(steps_per_launch):
+def tile_traffic(steps_per_launch, tile_bodies, workload):
     """HBM bytes per tile-kernel launch from the committed counter profile, if the
     kernel sources still hash to what was profiled and the profile ran the same
-    steps per launch; else None."""
+    workload, tile size and steps per launch; else None."""
     import hashlib
     h = hashlib.sha256()
     for f in TILE_SOURCES:
         with open(os.path.join(ROOT, "paper_2609_02675_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     try:
-        text = open(TILE_PROFILE).read()
+        text = open(TILE_PROFILE.format(workload=workload)).read()
     except OSError:
         return None
     import re
     m = re.search(r"kernel-source-sha256-16:\s*([0-9a-f]{16})", text)
     t = re.search(r"traffic_bytes_per_launch:\s*(\d+)", text)
     n = re.search(r"steps_per_launch:\s*(\d+)", text)
-    if not m or not t or not n or m.group(1) != h.hexdigest()[:16] or int(n.group(1)) != steps_per_launch:
+    tb = re.search(r"tile_bodies:\s*(\d+)", text)
+    w = re.search(r"workload:\s*(\S+)", text)
+    if not (m and t and n and tb and w):
+        return None
+    if (m.group(1) != h.hexdigest()[:16] or int(n.group(1)) != steps_per_launch
+            or int(tb.group(1)) != tile_bodies or w.group(1) != workload):
         return None
     return float(t.group(1))
 
@@ -389,7 +395,7 @@ def main():
     tile_flops = n_bodies * iters * spl * FLOPS_PER_BODY_ITER
     hbm_ach = tbytes / (tile_launch_ms / 1e3)
     alu_ach = tile_flops / (tile_launch_ms / 1e3)
-    traffic = tile_traffic(spl)
+    traffic = tile_traffic(spl, lay["tile_bodies"], f"batched_chains_{len(scenes)}")
     common = dict(traffic=traffic, traffic_unit="bytes/launch", kernel="k_tile_step<float>",
                   steps_per_launch=spl, kernel_ms_per_launch=tile_launch_ms, kernel_ms_per_step=tile_ms,
                   flops_per_launch=tile_flops, bytes_per_launch=tbytes)

@@ -191,8 +191,10 @@ pabd_status pabd_batch_residual(pabd_batch *b, int32_t slot, double *rho_last);
 pabd_status pabd_batch_release(pabd_batch *b, int32_t slot);
 /* Steps taken so far by the scene in slot. */
 pabd_status pabd_batch_steps_done(pabd_batch *b, int32_t slot, int32_t *steps);
-/* Time candidate tile schedules on the resident scenes (their state is saved
- * and restored) and keep the fastest; writes the chosen tile size. */
+/* Time candidate tile sizes on the resident scenes (their state is saved and
+ * restored): the tile kernel alone, event-timed at the steps per launch the
+ * batch last ran (10 before any), best of three; keep the fastest and write the
+ * chosen tile size. */
 pabd_status pabd_batch_autotune(pabd_batch *b, int32_t *tile_bodies);
 /* Force a tile size (32, 64, 128 or 256 bodies; 0 = automatic). */
 pabd_status pabd_batch_set_tile(pabd_batch *b, int32_t tile_bodies);
@@ -200,9 +202,10 @@ void *pabd_batch_stream(pabd_batch *b);
 /* Block until all work enqueued on the batch's stream has finished. */
 pabd_status pabd_batch_sync(pabd_batch *b);
 /* Measurement: launch the tile kernel alone reps times, nsteps steps per
- * launch, on the batch's stream between two HIP events and return the average
- * duration of one launch in ms (0 if no scene is tiled).  Advances the tiled
- * scenes like reps * nsteps extra steps would. */
+ * launch, on the batch's stream between two HIP events (after one untimed
+ * launch) and return the average duration of one launch in ms (0 if no scene
+ * is tiled).  Advances the tiled scenes like (reps + 1) * nsteps extra steps
+ * would. */
 pabd_status pabd_batch_time_tile_kernel(pabd_batch *b, int32_t reps, int32_t nsteps,
                                         double *avg_ms);
 /* Bodies, tiles and tile size currently in the batch. */
