@@ -21,8 +21,9 @@
 //                    bodies (scene id in the hash), each bucket a run of 64-byte
 //                    records holding the body's centre, reach, cell and filters;
 //                    large bodies go to a list instead
-//   k_broad_small    one thread per body: planes; then the 27 neighbour cells of
-//                    a small body, pairs with small bodies of higher index
+//   k_broad_small    14 lanes per body: planes; then own cell and the 13 cells
+//                    of the forward half-neighbourhood of a small body, one per
+//                    lane, pairs with small bodies
 //   k_broad_large    one workgroup per large body: small partners over the cells
 //                    its reach spans (or over the scene's bodies when that is
 //                    fewer), large partners of higher index over the scene
@@ -641,8 +642,12 @@ __device__ __forceinline__ double own_pm(const View<T>& v, int i, int sc, const 
 // BLPB lanes per body: the first lane does the plane contacts; then, for a
 // small body, the lanes split the 14 cells made of its own cell (partners of
 // higher index) and the 13 cells of the forward half of its neighbourhood, so
-// each pair of neighbouring cells is searched from one side only
-constexpr int BLPB = 1;
+// each pair of neighbouring cells is searched from one side only.  One cell per
+// lane: each lane's loads form one short dependent chain (bucket range, then
+// records), which keeps small scenes from waiting on fourteen such chains in a
+// row (1, 2, 7 and 14 lanes were measured; 14 was fastest on every contact
+// workload)
+constexpr int BLPB = 14;
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_broad_small(View<T> v, ContactBuf cb) {
