@@ -1,12 +1,13 @@
 // kernels_tile.h -- the batched substep: one workgroup owns a tile of up to TB
 // bodies made of whole scenes (joint scenes without contacts), and runs the
 // complete step of Algorithm 1 for them -- prediction, K global/local Jacobi
-// iterations, velocity recovery -- with the bodies' q^k and the points of their
-// bond ends exchanged through LDS (double-buffered: one barrier per iteration).  Tiles never interact, so one
-// launch runs nsteps consecutive steps of its tiles: a body's data is loaded
-// once per launch, and its q and v are stored after every step.  The grid is
-// persistent: workgroups stride over the device tile table, so the captured
-// graph's launch shape does not depend on which scenes are resident.
+// iterations, velocity recovery -- with the bodies' q^k and the points of
+// their bond ends exchanged through LDS (double-buffered: one barrier per
+// iteration).  Tiles never interact, so one launch runs nsteps consecutive
+// steps of its tiles: a body's data is loaded once per launch, and its q and v
+// are stored after every step.  The grid is persistent: workgroups stride over
+// the device tile table, so the captured graph's launch shape does not depend
+// on which scenes are resident.
 #pragma once
 
 #include "common.h"
