@@ -458,8 +458,11 @@ struct Engine {
   }
 
   // One step of Algorithm 1 with flat per-body kernels (one launch per iteration).
+  // With a wave table (batches), the iterations run over it instead: four lanes
+  // per body of a contact scene, one per body of any other scene.
   void launch_flat_step(int n_scenes, int kmax, bool contacts, int n_driven, bool history,
-                        bool finish_scenes, hipStream_t st) {
+                        bool finish_scenes, hipStream_t st, const FlatWave* waves = nullptr,
+                        const int* n_waves = nullptr, int wave_grid = 0) {
     View<T> v = view();
     const dim3 g = grid_for(cap.n, 256), b(256);
     if (n_driven > 0) {
@@ -480,8 +483,11 @@ struct Engine {
     }
     constexpr int LPB = 4;  // lanes per body when contacts are present
     const dim3 gc = grid_for((int)std::min<long long>((long long)cap.n * LPB, INT_MAX), 256);
+    const dim3 gw((unsigned)std::max(1, (wave_grid + 3) / 4));
     for (int k = 0; k < kmax; ++k) {
-      if (contacts)
+      if (waves && !history)
+        hipLaunchKernelGGL(k_iterate_waves<T>, gw, b, 0, st, v, k, waves, n_waves);
+      else if (contacts)
         hipLaunchKernelGGL((k_iterate<T, true, LPB>), gc, b, 0, st, v, k, hn, hd);
       else
         hipLaunchKernelGGL((k_iterate<T, false, 1>), g, b, 0, st, v, k, hn, hd);

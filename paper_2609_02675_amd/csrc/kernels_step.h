@@ -224,11 +224,9 @@ __device__ __forceinline__ U lane_sum(U x) {
 // force terms and the contact change of the FP64 block across the lanes, and the
 // first lane solves, projects and stores.
 template <typename T, bool CONTACT, int LPB>
-__global__ void __launch_bounds__(256) k_iterate(View<T> v, int k, double* rh_num, double* rh_den) {
+__device__ __forceinline__ void iterate_body(const View<T>& v, int k, double* rh_num, double* rh_den,
+                                             int i, int sub) {
   constexpr int QR = Rec<T>::Q;
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const int i = (int)(t / LPB), sub = (int)(t % LPB);
-  if (i >= v.n) return;
   const int sc = v.bscene[i];
   if (sc < 0 || (v.flags[i] & F_PINNED)) return;
   const SceneDev& S = v.scenes[sc];
@@ -359,6 +357,39 @@ __global__ void __launch_bounds__(256) k_iterate(View<T> v, int k, double* rh_nu
       rh_num[(size_t)k * v.n + i] = num;
       rh_den[(size_t)k * v.n + i] = den;
     }
+  }
+}
+
+template <typename T, bool CONTACT, int LPB>
+__global__ void __launch_bounds__(256) k_iterate(View<T> v, int k, double* rh_num, double* rh_den) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = (int)(t / LPB), sub = (int)(t % LPB);
+  if (i >= v.n) return;
+  iterate_body<T, CONTACT, LPB>(v, k, rh_num, rh_den, i, sub);
+}
+
+// The same iteration over a table of wavefronts (first body, bodies, lanes per
+// body): a wave covers 16 bodies of a contact scene with four lanes each, or 64
+// bodies of a contact-free scene with one lane each, and never spans two
+// scenes.  Waves past the table's count leave at once, so the grid can stay
+// fixed while scenes come and go.
+struct FlatWave {
+  int first, count, lpb, pad;
+};
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_iterate_waves(View<T> v, int k, const FlatWave* waves,
+                                                       const int* n_waves) {
+  const int w = (int)((blockIdx.x * (long long)blockDim.x + threadIdx.x) / 64);
+  const int l = (int)(threadIdx.x & 63);
+  if (w >= *n_waves) return;
+  const FlatWave fw = waves[w];
+  if (fw.lpb == 4) {
+    if (l / 4 >= fw.count) return;
+    iterate_body<T, true, 4>(v, k, nullptr, nullptr, fw.first + l / 4, l % 4);
+  } else {
+    if (l >= fw.count) return;
+    iterate_body<T, false, 1>(v, k, nullptr, nullptr, fw.first + l, 0);
   }
 }
 

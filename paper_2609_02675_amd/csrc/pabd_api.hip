@@ -47,7 +47,9 @@ struct EngineBase {
   virtual pabd_status clear_bodies(int boff, int n, hipStream_t st, int doff, int nd) = 0;
   virtual void factor(hipStream_t st, int first = 0, int count = -1) = 0;
   virtual void flat_step(int first, int n, int n_scenes, int kmax, bool contacts, int n_driven,
-                         bool history, bool finish_scenes, hipStream_t st) = 0;
+                         bool history, bool finish_scenes, hipStream_t st,
+                         const FlatWave* waves = nullptr, const int* n_waves = nullptr,
+                         int wave_grid = 0) = 0;
   virtual void tile_step(int tile_bodies, const TileTable& tt, int grid, int nsteps,
                          hipStream_t st) = 0;
   virtual void finish_scenes(int n_scenes, hipStream_t st) = 0;
@@ -86,11 +88,12 @@ struct EngineT final : EngineBase {
   }
   void factor(hipStream_t st, int first, int count) override { e.launch_factor(st, first, count); }
   void flat_step(int first, int n, int n_scenes, int kmax, bool contacts, int n_driven, bool history,
-                 bool fin, hipStream_t st) override {
+                 bool fin, hipStream_t st, const FlatWave* waves, const int* n_waves,
+                 int wave_grid) override {
     (void)first;
     const int saved = e.cap.n;
     e.cap.n = n;  // flat kernels cover bodies [0, n)
-    e.launch_flat_step(n_scenes, kmax, contacts, n_driven, history, fin, st);
+    e.launch_flat_step(n_scenes, kmax, contacts, n_driven, history, fin, st, waves, n_waves, wave_grid);
     e.cap.n = saved;
   }
   void tile_step(int tb, const TileTable& tt, int grid, int nsteps, hipStream_t st) override {
@@ -569,6 +572,10 @@ struct pabd_batch {
   // device tile table
   int *d_first = nullptr, *d_count = nullptr, *d_kmax = nullptr, *d_ntiles = nullptr;
   int tile_table_cap = 0;
+  // wave table of the flat-path iterations when contact scenes are on it
+  FlatWave* d_waves = nullptr;
+  int* d_nwaves = nullptr;
+  int wave_table_cap = 0;
   DeviceAllocator dev = current_allocator();
   Graph graph;
   int graph_steps = 0;  // steps one replay of the captured graph advances
@@ -580,12 +587,14 @@ struct pabd_batch {
   // launch extents, rounded so that most admissions and releases leave them
   // (and so the captured step graph) unchanged; kernels skip unused slots
   struct Launch {
-    int stream_n = 0, driven_n = 0, grid = 0, kmax = 0, tile = 0;
+    int stream_n = 0, driven_n = 0, grid = 0, kmax = 0, tile = 0, wave_grid = 0;
     bool stream = false, contact = false;
     const int* table = nullptr;
+    const FlatWave* waves = nullptr;
     bool operator==(const Launch& o) const {
       return stream_n == o.stream_n && driven_n == o.driven_n && grid == o.grid && kmax == o.kmax &&
-             tile == o.tile && stream == o.stream && contact == o.contact && table == o.table;
+             tile == o.tile && stream == o.stream && contact == o.contact && table == o.table &&
+             wave_grid == o.wave_grid && waves == o.waves;
     }
   } launch;
   // releases what the handle holds, also after a create that failed part-way
@@ -596,6 +605,8 @@ struct pabd_batch {
     dev.put(d_first);
     dev.put(d_count);
     dev.put(d_kmax);
+    dev.put(d_waves);
+    dev.put(d_nwaves);
     dev.put(d_ntiles);
     eng.reset();
     if (stream) (void)hipStreamDestroy(stream);
@@ -659,6 +670,36 @@ pabd_status batch_tables(pabd_batch* b) {
     b->stream_hi = std::max(b->stream_hi, s.boff + std::max(1, s.n));
   }
   auto round_up = [](int x, int q, int cap) { return std::min(cap, (x + q - 1) / q * q); };
+  // flat-path waves, when contact scenes share the flat path with others: a
+  // contact scene's bodies take four lanes each (16 per wave), any other
+  // scene's one lane each (64 per wave); a wave stays within one scene
+  std::vector<FlatWave> waves;
+  if (b->any_contact) {
+    std::vector<const Slot*> flat;
+    for (const Slot& s : b->slots)
+      if (s.used && !s.tiled && s.n > 0) flat.push_back(&s);
+    std::sort(flat.begin(), flat.end(), [](const Slot* x, const Slot* y) { return x->boff < y->boff; });
+    for (const Slot* s : flat) {
+      const int lpb = s->contact ? 4 : 1, per = 64 / lpb;
+      for (int f = 0; f < s->n; f += per) waves.push_back(FlatWave{s->boff + f, std::min(per, s->n - f), lpb, 0});
+    }
+  }
+  const int nw = (int)waves.size();
+  if (b->any_contact) {
+    if (nw > b->wave_table_cap || !b->d_waves) {
+      const int cap = std::max(nw, 2 * b->wave_table_cap + 256);
+      API_HIP(hipStreamSynchronize(b->stream));
+      b->dev.put(b->d_waves);
+      b->d_waves = nullptr;
+      API_HIP(b->dev.get(reinterpret_cast<void**>(&b->d_waves), cap * sizeof(FlatWave)));
+      b->wave_table_cap = cap;
+    }
+    if (!b->d_nwaves) API_HIP(b->dev.get(reinterpret_cast<void**>(&b->d_nwaves), sizeof(int)));
+    if (nw)
+      API_HIP(hipMemcpyAsync(b->d_waves, waves.data(), nw * sizeof(FlatWave), hipMemcpyHostToDevice, b->stream));
+    API_HIP(hipMemcpyAsync(b->d_nwaves, &nw, sizeof(int), hipMemcpyHostToDevice, b->stream));
+    API_HIP(hipStreamSynchronize(b->stream));
+  }
   pabd_batch::Launch L;
   L.stream = b->any_stream;
   L.contact = b->any_contact;
@@ -668,6 +709,10 @@ pabd_status batch_tables(pabd_batch* b) {
   L.grid = b->grid_tiles > 0 ? round_up(b->grid_tiles, 256, INT_MAX) : 0;
   L.tile = b->tile_bodies;
   L.table = b->d_first;
+  // the wave grid is rounded like the other extents, so most admissions and
+  // releases reuse the captured graph
+  L.wave_grid = b->any_contact ? round_up(std::max(1, nw), 256, INT_MAX) : 0;
+  L.waves = b->any_contact ? b->d_waves : nullptr;
   if (!(L == b->launch)) {
     b->launch = L;
     b->graph.reset();
@@ -685,7 +730,8 @@ void batch_enqueue(pabd_batch* b, int nsteps, hipStream_t st) {
   }
   if (L.stream) {
     for (int k = 0; k < nsteps; ++k) {
-      b->eng->flat_step(0, L.stream_n, b->max_slots, L.kmax, L.contact, L.driven_n, false, false, st);
+      b->eng->flat_step(0, L.stream_n, b->max_slots, L.kmax, L.contact, L.driven_n, false, false, st,
+                        L.wave_grid > 0 ? b->d_waves : nullptr, b->d_nwaves, L.wave_grid);
       // scenes on the flat path: residual reduction and step counters (tiled
       // scenes do both inside the tile kernel)
       b->eng->finish_scenes(b->max_slots, st);

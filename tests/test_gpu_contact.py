@@ -162,32 +162,46 @@ def test_body_with_more_ends_than_a_wave_holds_fp64(P):
     assert fp64_ok(errors(g.state(), o.state(), scale_of(sc)))
 
 
-def test_contact_and_plain_flat_scenes_share_a_batch_fp64(P):
+@pytest.mark.parametrize("prec", [S.PREC_FP64, S.PREC_FP32])
+def test_contact_and_plain_flat_scenes_share_a_batch(P, prec):
     """A 300-body chain (flat path, no contacts) beside two box piles in one batch:
-    the chain then iterates with the four-lane contact variant, and its result
-    alone and in the mix agree within the FP64 bar; every scene matches the
-    oracle."""
+    the chain's waves take one lane per body as they do alone, so its result is
+    the same alone and in the mix bit for bit; the chain matches the oracle
+    (FP64 bar, or FP32 within 1e-4 after 8 steps), and so do the piles in FP64
+    (box piles are chaotic under FP32 rounding, so they are not held to the
+    oracle over 8 steps in FP32)."""
     big = S.chain(300, tilt_deg=20.0, joint_angles_deg=np.linspace(-5, 5, 299),
-                  precision=S.PREC_FP64, iters=12)
-    piles = [settled_drop(n_side=3, layers=1, steps=60, seed=s) for s in (5, 6)]
-    print("[case] chain 300 beside two piles", flush=True)
-    b = P.Batch(8, 1 << 28, S.PREC_FP64)
+                  precision=prec, iters=12)
+    piles = [settled_drop(n_side=3, layers=1, steps=60, seed=s).copy(precision=prec) for s in (5, 6)]
+    print(f"[case] chain 300 beside two piles prec {prec}", flush=True)
+    b = P.Batch(8, 1 << 28, prec)
     sb = b.admit(big, 8)
     sp = [b.admit(p, 8) for p in piles]
     for _ in range(8):
         b.step()
-    alone = P.Batch(4, 1 << 28, S.PREC_FP64)
+    alone = P.Batch(4, 1 << 28, prec)
     sa = alone.admit(big, 8)
     for _ in range(8):
         alone.step()
-    assert fp64_ok(errors(b.state(sb), alone.state(sa), scale_of(big)))
+    for x, y in zip(b.state(sb), alone.state(sa)):
+        np.testing.assert_array_equal(x, y)
+
+    def ok(e):
+        if prec == S.PREC_FP64:
+            return fp64_ok(e)
+        return e["pos"] <= 1e-4 and e["rot"] <= 1e-4
+
     o = oracle.Oracle(big)
     o.step(8)
-    assert fp64_ok(errors(b.state(sb), o.state(), scale_of(big)))
+    e = errors(b.state(sb), o.state(), scale_of(big))
+    assert ok(e), e
+    if prec != S.PREC_FP64:
+        return
     for pl, s in zip(piles, sp):
         o = oracle.Oracle(pl)
         o.step(8)
-        assert fp64_ok(errors(b.state(s), o.state(), scale_of(pl))), pl.name
+        e = errors(b.state(s), o.state(), scale_of(pl))
+        assert ok(e), (pl.name, e)
 
 
 def test_box_drop_1000_full_size_from_a_landing_state(P):
