@@ -272,24 +272,28 @@ __device__ __forceinline__ void iterate_body(const View<T>& v, int k, double* rh
     if (cnt > S.ccap) cnt = S.ccap;
     const size_t base = (size_t)i * S.ccap;
     // the lanes of a body take its ends in turn (neighbouring lanes read
-    // neighbouring records); the ends are in key order, partner first, so a
-    // lane often meets the same partner again and keeps its state
-    int jprev = -1;
-    T qj[QR];
-    for (int c = sub; c < cnt; c += LPB) {
-      const int j = v.ce_partner[base + c];
-      T C[CW];
-      load<T, CW>(v.ce + (size_t)CW * (base + c), C);
-      if (j >= 0 && j != jprev) {
-        load<T, QR>(qs + (size_t)QR * j, qj);
-        jprev = j;
-      }
+    // neighbouring records), two ends per round with both ends' loads (record
+    // and partner state) in flight together
+    auto contact_end = [&](const T* C, int j, const T* qj) {
       T d[3], f[3];
       bond_vec<T>(q, C, j < 0 ? nullptr : qj, C + 4, d);
-      if (!contact_end_force(C, d, f)) continue;
+      if (!contact_end_force(C, d, f)) return;
       add_JT(rb, C, f[0], f[1], f[2]);
       block_add_end(dB, (double)C[3], (double)C[0], (double)C[1], (double)C[2]);
       refactor = true;
+    };
+    for (int c = sub; c < cnt; c += 2 * LPB) {
+      const int cb = c + LPB;
+      const bool hb = cb < cnt;
+      const int ja = v.ce_partner[base + c];
+      const int jb = hb ? v.ce_partner[base + cb] : -1;
+      T Ca[CW], Cb[CW], qa[QR], qb[QR];
+      load<T, CW>(v.ce + (size_t)CW * (base + c), Ca);
+      if (hb) load<T, CW>(v.ce + (size_t)CW * (base + cb), Cb);
+      if (ja >= 0) load<T, QR>(qs + (size_t)QR * ja, qa);
+      if (jb >= 0) load<T, QR>(qs + (size_t)QR * jb, qb);
+      contact_end(Ca, ja, qa);
+      if (hb) contact_end(Cb, jb, qb);
     }
   }
   if constexpr (LPB > 1) {
