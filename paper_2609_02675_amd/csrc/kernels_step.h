@@ -7,6 +7,8 @@
 //               q^k, writes q^{k+1} to the other buffer), increment form:
 //               dq = H^{-1} (M (s - q^k) + h^2 sum [w J^T (y_o - y_s) + phi^- J^T n
 //                    + J^T f_contact]),  then A <- polar rotation (Sec. 4.2.2)
+//   k_iterate_waves  the same over a batch's table of wavefronts (four lanes per
+//               body of a contact scene, one per body of any other scene)
 //   k_finish    velocity recovery (Sec. 4.4) and health flags
 //   k_reduce_residual  per-scene FP64 residual, fixed summation order
 #pragma once
