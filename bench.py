@@ -305,6 +305,9 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=6.0,
                     help="seconds of Poisson arrivals (200 req/s) in the served leg; 0 = skip")
     ap.add_argument("--serve-budget-gib", type=float, default=8.0)
+    ap.add_argument("--only-scene", default="",
+                    choices=["", "box_drop", "granular_bed", "mass_ratio_chain", "spring_net", "block_pile"],
+                    help="run only this one of the single-scene legs (for profiling it alone)")
     ap.add_argument("--no-scenes", action="store_true",
                     help="skip the single-scene legs (1,000-box drop, granular bed)")
     ap.add_argument("--big-scenes", type=int, default=65536,
@@ -479,7 +482,10 @@ def main():
             dt = time.perf_counter() - t
             return g, sc.n_bodies * sc.iters * steps / dt, 1e3 * dt / steps
 
-        for prec, tag in ((S.PREC_FP32, "fp32"), (S.PREC_FP64, "fp64")):
+        def want(leg):
+            return not args.only_scene or args.only_scene == leg
+
+        for prec, tag in ((S.PREC_FP32, "fp32"), (S.PREC_FP64, "fp64")) if want("box_drop") else ():
             sc = S.box_drop(precision=prec)
             g, rate, ms = time_scene(sc, 40, 60)
             # accuracy: one step from the oracle's state after 60 steps (contacts active)
@@ -491,17 +497,18 @@ def main():
                 body_its_per_s=rate, ms_per_step=ms, steps_timed="40..100 (falling, then landing)",
                 one_step_err_vs_oracle=max(e["pos"], e["rot"]), iters=sc.iters)
             log(f"box drop {tag}: {rate:.3g} body-it/s, {ms:.3f} ms/step, 1-step err {max(e['pos'], e['rot']):.2e}")
-        bed = S.granular_bed_quadruped(precision=S.PREC_FP32)
-        # the bed churns as it sinks (a property of the method as read for 1 cm
-        # spheres at h = 1/60), so the timed window is its first steps
-        g, rate, ms = time_scene(bed, 1, 5)
-        ct = g.contacts()
-        scene_legs["granular_bed_quadruped_fp32"] = dict(
-            body_its_per_s=rate, ms_per_step=ms, bodies=bed.n_bodies, iters=bed.iters,
-            steps_timed="2..6", contacts_after=int(len(ct["i"])))
-        log(f"granular bed: {rate:.3g} body-it/s, {ms:.3f} ms/step")
+        if want("granular_bed"):
+            bed = S.granular_bed_quadruped(precision=S.PREC_FP32)
+            # the bed churns as it sinks (a property of the method as read for 1 cm
+            # spheres at h = 1/60), so the timed window is its first steps
+            g, rate, ms = time_scene(bed, 1, 5)
+            ct = g.contacts()
+            scene_legs["granular_bed_quadruped_fp32"] = dict(
+                body_its_per_s=rate, ms_per_step=ms, bodies=bed.n_bodies, iters=bed.iters,
+                steps_timed="2..6", contacts_after=int(len(ct["i"])))
+            log(f"granular bed: {rate:.3g} body-it/s, {ms:.3f} ms/step")
         # the paper's mass-ratio chain, augmented-Lagrangian joints on and off
-        for aug, tag in ((True, "al"), (False, "quadratic")):
+        for aug, tag in ((True, "al"), (False, "quadratic")) if want("mass_ratio_chain") else ():
             mc = S.mass_ratio_chain(augmented=aug, precision=S.PREC_FP32)
             g, rate, ms = time_scene(mc, 10, 100)
             joint = lambda c, A: max(abs(np.linalg.norm(A[mc.bond_i[e]] @ mc.x_i[e] + c[mc.bond_i[e]]
@@ -517,7 +524,7 @@ def main():
             log(f"mass-ratio chain {tag}: {ms:.3f} ms/step, joint error {joint(st[0], st[1]):.3g} m")
         # the paper's 11 x 11 net of 220 springs, quadratic and quartic bonds:
         # convergence of the first step (relative error per iteration) and step time
-        for p_ in (2, 4):
+        for p_ in (2, 4) if want("spring_net") else ():
             net = S.spring_net(order=p_, iters=20, precision=S.PREC_FP32)
             if p_ == 2:
                 net = net.copy(bond_type=np.full(net.n_bonds, S.BOND_POLYNOMIAL, np.int32))
@@ -532,16 +539,17 @@ def main():
                 first_step_rel_error=[float(x) for x in rho[:20]])
             log(f"net p={p_}: {ms:.3f} ms/step, first-step rho {rho[0]:.2e} -> {rho[19]:.2e}")
         # 50^3 stacked cubes in resting contact (the paper's largest scene size)
-        pile = S.block_pile(precision=S.PREC_FP32)
-        g, rate, ms = time_scene(pile, 1, 10)
-        ct = g.contacts()
-        scene_legs["block_pile_125k_fp32"] = dict(
-            body_its_per_s=rate, ms_per_step=ms, bodies=pile.n_bodies, iters=pile.iters,
-            steps_timed="2..11", contacts_after=int(len(ct["i"])),
-            paper_context="Table 2, 50^3 block pile on an RTX 3080: 72.56 ms collision + 87.55 ms "
-                          "solve per frame at 20 iterations (2.9e7 body-iterations/s for the solve)")
-        del g
-        log(f"block pile: {rate:.3g} body-it/s, {ms:.3f} ms/step, {len(ct['i'])} contacts")
+        if want("block_pile"):
+            pile = S.block_pile(precision=S.PREC_FP32)
+            g, rate, ms = time_scene(pile, 1, 10)
+            ct = g.contacts()
+            scene_legs["block_pile_125k_fp32"] = dict(
+                body_its_per_s=rate, ms_per_step=ms, bodies=pile.n_bodies, iters=pile.iters,
+                steps_timed="2..11", contacts_after=int(len(ct["i"])),
+                paper_context="Table 2, 50^3 block pile on an RTX 3080: 72.56 ms collision + 87.55 ms "
+                              "solve per frame at 20 iterations (2.9e7 body-iterations/s for the solve)")
+            del g
+            log(f"block pile: {rate:.3g} body-it/s, {ms:.3f} ms/step, {len(ct['i'])} contacts")
 
     # the batched chains at 16x the count: a working set beyond the last-level cache
     big = None
