@@ -54,7 +54,7 @@ struct SceneDev {
   int contact;      // collision detection enabled
   int ccap;         // contact ends per body
   int step;         // completed steps
-  int debug;        // bit0: skip the local step
+  int debug;        // bit0: skip the local step (single scenes on the flat path only)
   int steps_total;  // the scene is frozen once step reaches this
   int tiled;        // advanced by the tile kernel (which also reduces its residual)
   int pad;
