@@ -60,6 +60,19 @@ struct SceneDev {
   int pad;
 };
 
+// A contact end as the narrow phase stages it, in the order its atomics give:
+// the end's record, its partner and its sort key (partner + 1, feature, side)
+// side by side, so that staging an end writes one run of bytes (64 in FP32)
+// and the sort reads one.
+template <typename T>
+struct alignas(16) StageRec {
+  T C[CW];
+  int partner;
+  int pad;
+  unsigned long long key;
+};
+static_assert(sizeof(StageRec<float>) == 64, "an FP32 staged end is one 64-byte run");
+
 template <typename T>
 struct View {
   int n;  // bodies covered by the arrays
@@ -89,10 +102,8 @@ struct View {
   int* ce_partner;
   unsigned long long* ce_key;
   T* ce;
-  // narrow-phase output before the canonical sort
-  int* ce_st_partner;
-  unsigned long long* ce_st_key;
-  T* ce_st;
+  // narrow-phase output before the canonical sort, one record per end
+  StageRec<T>* ce_stage;
   const double* planes;
   // residual partials
   double* r_num;

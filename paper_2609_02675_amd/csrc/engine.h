@@ -102,9 +102,10 @@ struct Engine {
   T* al = nullptr;
   double* se64 = nullptr;
   // contacts
-  int *ccount = nullptr, *ce_partner = nullptr, *ce_st_partner = nullptr;
-  unsigned long long *ce_key = nullptr, *ce_st_key = nullptr, *reach = nullptr;
-  T *ce = nullptr, *ce_st = nullptr;
+  int *ccount = nullptr, *ce_partner = nullptr;
+  unsigned long long *ce_key = nullptr, *reach = nullptr;
+  T* ce = nullptr;
+  StageRec<T>* ce_stage = nullptr;
   int *bucket_count = nullptr, *bucket_start = nullptr, *bucket_fill = nullptr, *scan_tmp = nullptr;
   int *hist = nullptr, *large = nullptr, *counters = nullptr;
   double* breach = nullptr;
@@ -249,9 +250,7 @@ struct Engine {
       PABD_TRY(alloc(ce, CW * nc));
       PABD_TRY(alloc(ce_partner, nc));
       PABD_TRY(alloc(ce_key, nc));
-      PABD_TRY(alloc(ce_st, CW * nc));
-      PABD_TRY(alloc(ce_st_partner, nc));
-      PABD_TRY(alloc(ce_st_key, nc));
+      PABD_TRY(alloc(ce_stage, nc));
       // power of two, at most 2^20 so the three-pass scan (1024 x 1024) covers it
       tb = 1024;
       while (tb < 2 * ncb && tb < (1 << 20)) tb <<= 1;
@@ -314,9 +313,7 @@ struct Engine {
     v.ce_partner = ce_partner;
     v.ce_key = ce_key;
     v.ce = ce;
-    v.ce_st_partner = ce_st_partner;
-    v.ce_st_key = ce_st_key;
-    v.ce_st = ce_st;
+    v.ce_stage = ce_stage;
     v.planes = planes;
     v.r_num = r_num;
     v.r_den = r_den;

@@ -326,10 +326,12 @@ __device__ __forceinline__ void push_end(const View<T>& v, int owner, int sc, in
   const size_t e = (size_t)owner * cap + slot;
   T C[CW] = {(T)xs[0], (T)xs[1], (T)xs[2], (T)kap, (T)xo[0], (T)xo[1], (T)xo[2], (T)mu,
              (T)n[0], (T)n[1], (T)n[2], (T)0};
-  store<T, CW>(v.ce_st + CW * e, C);
-  v.ce_st_partner[e] = partner;
-  v.ce_st_key[e] = ((unsigned long long)(unsigned)(partner + 1) << 32) |
-                   ((unsigned long long)(unsigned)feature << 1) | (unsigned)side;
+  StageRec<T>& r = v.ce_stage[e];
+  store<T, CW>(r.C, C);
+  r.partner = partner;
+  r.pad = 0;
+  r.key = ((unsigned long long)(unsigned)(partner + 1) << 32) |
+          ((unsigned long long)(unsigned)feature << 1) | (unsigned)side;
 }
 
 template <typename T>
@@ -795,10 +797,11 @@ __device__ __forceinline__ unsigned long long lane_key(unsigned long long k, int
 template <typename T>
 __device__ __forceinline__ void move_end(const View<T>& v, size_t base, int from, int to,
                                          unsigned long long key) {
+  const StageRec<T>& r = v.ce_stage[base + from];
   T C[CW];
-  load<T, CW>(v.ce_st + CW * (base + from), C);
+  load<T, CW>(r.C, C);
   store<T, CW>(v.ce + CW * (base + to), C);
-  v.ce_partner[base + to] = v.ce_st_partner[base + from];
+  v.ce_partner[base + to] = r.partner;
   v.ce_key[base + to] = key;
 }
 
@@ -813,7 +816,7 @@ __global__ void __launch_bounds__(64) k_sort_contacts(View<T> v, int cap) {
   if (cnt <= 0) return;
   const int lane = threadIdx.x;
   const size_t base = (size_t)i * cap;
-  const unsigned long long* keys = v.ce_st_key + base;
+  const StageRec<T>* st = v.ce_stage + base;
   if (cnt <= 64 * SORT_REG) {
     const int rounds = (cnt + 63) / 64;
     unsigned long long k[SORT_REG];
@@ -821,7 +824,7 @@ __global__ void __launch_bounds__(64) k_sort_contacts(View<T> v, int cap) {
 #pragma unroll
     for (int u = 0; u < SORT_REG; ++u) {
       const int a = lane + 64 * u;
-      k[u] = a < cnt ? keys[a] : ~0ull;
+      k[u] = a < cnt ? st[a].key : ~0ull;
       r[u] = 0;
     }
     for (int b = 0; b < cnt; ++b) {
@@ -839,9 +842,9 @@ __global__ void __launch_bounds__(64) k_sort_contacts(View<T> v, int cap) {
     }
   } else {
     for (int a = lane; a < cnt; a += 64) {
-      const unsigned long long key = keys[a];
+      const unsigned long long key = st[a].key;
       int r = 0;
-      for (int b = 0; b < cnt; ++b) r += keys[b] < key ? 1 : 0;
+      for (int b = 0; b < cnt; ++b) r += st[b].key < key ? 1 : 0;
       move_end(v, base, a, r, key);
     }
   }

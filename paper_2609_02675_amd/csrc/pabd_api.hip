@@ -618,7 +618,9 @@ namespace {
 size_t body_cost(int ts) { return (size_t)ts * (4 * (QW + 4) + VW + MW + FW + 4) + 8 * (10 + 8 + 2) + 2 + 4 * 5; }
 size_t end_cost(int ts) { return (size_t)ts * EW + 4 + 8 * 4; }
 // one contact slot: final and staging copies of the record, partner and key
-size_t contact_cost(int ts) { return 2 * ((size_t)ts * CW + 4 + 8); }
+size_t contact_cost(int ts) {
+  return (size_t)ts * CW + 4 + 8 + (ts == 4 ? sizeof(StageRec<float>) : sizeof(StageRec<double>));
+}
 // per contact body: broad-phase record, reach, large-list entry, candidate pairs
 size_t contact_body_cost(int ccap) { return sizeof(BroadRec) + 8 + 4 + 8 * (size_t)pairs_per_body(ccap); }
 
