@@ -202,6 +202,36 @@ def test_several_steps_per_launch_equal_single_steps(P, prec):
             assert e["pos"] <= 1e-3 and e["rot"] <= 1e-3, (scs[k].name, e)
 
 
+@pytest.mark.parametrize("prec", [S.PREC_FP32, S.PREC_FP64])
+def test_largest_steps_per_launch_equal_single_steps(P, prec):
+    """256 steps in one launch, the largest count allowed: the same bits as 256
+    single steps, for scenes that run through the launch and scenes whose budget
+    ends inside it; in FP64 the early-ending scenes also match the oracle."""
+    scs = S.batched_chains(12, seed=21, precision=prec)
+    budgets = [256 if k % 2 else 97 for k in range(len(scs))]
+    print(f"[case] 256 steps per launch, prec {prec}", flush=True)
+
+    def run(launch_steps):
+        b = P.Batch(len(scs) + 2, 1 << 30, prec)
+        slots = [b.admit(s, n) for s, n in zip(scs, budgets)]
+        for n in launch_steps:
+            b.step(nsteps=n)
+        return b, slots
+
+    b1, s1 = run([1] * 256)
+    b2, s2 = run([256])
+    for k, (x, y) in enumerate(zip(s1, s2)):
+        assert b2.steps_done(y) == budgets[k]
+        for u, w in zip(b1.state(x), b2.state(y)):
+            np.testing.assert_array_equal(u, w)
+    assert sorted(b2.poll()) == sorted(s2)
+    if prec != S.PREC_FP64:
+        return
+    for k in (0, 2):
+        e = errors(b2.state(s2[k]), _oracle_state(scs[k], budgets[k]), scale_of(scs[k]))
+        assert fp64_ok(e), (scs[k].name, e)
+
+
 def test_steps_per_launch_out_of_range_is_rejected(P):
     b = P.Batch(2, 1 << 26, S.PREC_FP32)
     b.admit(S.chain8(precision=S.PREC_FP32), 5)
