@@ -14,10 +14,15 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "pabd_oracle.c")
 LIB_PATH = os.path.join(_HERE, "libpabd_oracle.so")
+# a library built elsewhere from a copy of the source, used as it is; the test
+# that plants mistakes in such copies sets it, nothing else does
+_LIB_OVERRIDE = os.environ.get("PABD_ORACLE_LIB")
 
 
 def build(force: bool = False) -> str:
     """Compile the oracle with gcc (plain C11, -O2, no fast-math)."""
+    if _LIB_OVERRIDE:
+        return _LIB_OVERRIDE
     stale = not os.path.exists(LIB_PATH) or any(
         os.path.getmtime(src) > os.path.getmtime(LIB_PATH) for src in (_SRC, _SRC[:-2] + ".h"))
     if force or stale:

@@ -48,6 +48,18 @@ def test_first_iteration_updates_from_the_predicted_stretch():
     assert kap[0] == pytest.approx(1e4 + 1e4 * C0, rel=1e-12)
 
 
+def test_first_iteration_updates_from_a_compression():
+    """Without gravity, from rest with the bond compressed by 0.02: the first
+    elongation is C = -0.02, so lambda = kappa_start C < 0 and the stiffness still
+    grows by beta |C|."""
+    sc = _hanging(iters=1).copy(gravity=np.zeros(3), c0=np.array([[0.0, -0.5 - 0.08, 0.0]]))
+    o = oracle.Oracle(sc)
+    o.step(1)
+    kap, lam = o.bond_state()
+    assert lam[0] == pytest.approx(1e4 * -0.02, rel=1e-9)
+    assert kap[0] == pytest.approx(1e4 + 1e4 * 0.02, rel=1e-9)
+
+
 def test_augmented_bond_closes_the_joint_that_a_quadratic_bond_leaves_open():
     """At rest the quadratic bond keeps the compliance gap m g / kappa plus the
     projection offset (about 9e-3 m here); the multiplier drives the elongation

@@ -32,6 +32,37 @@ def test_box_plane_contacts_are_the_vertices_within_the_margin():
         np.testing.assert_allclose(ct["x_j"][k], [y[f, 0], 0.0, y[f, 2]], atol=1e-14)
 
 
+def _on_plane(shape, half, gap, v=(0.0, 0.0, 0.0), w=(0.0, 0.0, 0.0)):
+    """One body above the plane y = 0 with its lowest point at height gap."""
+    sc = S.single_body(shape=shape, half=half, v=v, w=w, c=(0.0, half[0 if shape == S.SHAPE_SPHERE else 1] + gap, 0.0))
+    return sc.copy(contact_enable=1, planes=np.array([[0.0, 1.0, 0.0, 0.0]]))
+
+
+def _detected(sc):
+    o = oracle.Oracle(sc)
+    o.detect()
+    return sorted(o.contacts()["feature"].tolist())
+
+
+def test_detection_margin_grows_with_the_motion_of_the_step():
+    """Detection on q^n looks ahead by the distance the surface can travel in the
+    step, h (|v| + |w| R): a box whose bottom face is 0.04 above the margin is
+    found when it falls at 3 m/s (h |v| = 0.05) or spins at 10 rad/s about y
+    (h |w| R = 0.144 with R = |half extents|), not at rest; a sphere spinning in
+    place is not found (its distance to the plane does not change)."""
+    half = (0.5, 0.5, 0.5)
+    m = S.SceneDesc.contact_margin
+    gap = m + 0.04
+    bottom = [0, 1, 4, 5]  # vertices with -half along y
+    assert _detected(_on_plane(S.SHAPE_BOX, half, gap)) == []
+    assert _detected(_on_plane(S.SHAPE_BOX, half, gap, v=(0.0, -3.0, 0.0))) == bottom
+    assert _detected(_on_plane(S.SHAPE_BOX, half, gap, v=(0.0, 3.0, 0.0))) == bottom
+    assert _detected(_on_plane(S.SHAPE_BOX, half, gap, w=(0.0, 10.0, 0.0))) == bottom
+    assert _detected(_on_plane(S.SHAPE_BOX, half, m + 0.06, v=(0.0, -3.0, 0.0))) == []
+    assert _detected(_on_plane(S.SHAPE_SPHERE, (0.5, 0.0, 0.0), gap, w=(0.0, 10.0, 0.0))) == []
+    assert len(_detected(_on_plane(S.SHAPE_SPHERE, (0.5, 0.0, 0.0), gap, v=(0.0, -3.0, 0.0)))) == 1
+
+
 def test_sphere_sphere_contact_geometry():
     sc = S.single_body(shape=S.SHAPE_SPHERE, half=(0.3, 0, 0), density=500.0)
     sc = S.merge([sc, sc.copy(c0=np.array([[0.35, 0.4, 0.1]]), shape_param=np.array([[0.25, 0, 0]]))])

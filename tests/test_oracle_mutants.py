@@ -1,0 +1,113 @@
+"""The oracle's pins catch plausible mistakes.  Each case plants one mistake in a
+copy of the oracle's C source (a dropped term, a wrong sign, a wrong index or
+constant, a transposed operand), builds the copy on the CPU, and runs the
+oracle's pin tests against it in a fresh process: at least one pin must fail.
+The oracle itself is left untouched; only the copies are changed."""
+import os
+import shutil
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "pabd_oracle.c")
+HDR = os.path.join(ROOT, "oracle", "pabd_oracle.h")
+PINS = ["tests/test_oracle_math.py", "tests/test_oracle_dynamics.py", "tests/test_oracle_contact.py",
+        "tests/test_oracle_polynomial.py", "tests/test_oracle_augmented.py"]
+
+# (name, text in the oracle, planted replacement); each text occurs once
+MUTANTS = [
+    # prediction (Algorithm 1: explicit velocity and orientation update)
+    ("gravity_dropped",
+     "vs[k] = o->v[3 * b + k] + h * o->gravity[k];", "vs[k] = o->v[3 * b + k];"),
+    ("quaternion_half_factor",
+     "Qs[k] = Q[k] + 0.5 * h * dQ[k];", "Qs[k] = Q[k] + h * dQ[k];"),
+    ("quaternion_product_order", "quat_mul(wq, Q, dQ);", "quat_mul(Q, wq, dQ);"),
+    # generalised mass (Sec. 4.1.1)
+    ("box_moment_axis",
+     "Pi0[4] = *m * sy * sy / 12.0;", "Pi0[4] = *m * sx * sx / 12.0;"),
+    ("sphere_moment_constant", "*m * r * r / 5.0", "*m * r * r / 3.0"),
+    ("mass_block_index",
+     "M[12 * (3 + 3 * blk + r) + 3 + 3 * blk + c] = Pi[3 * r + c];",
+     "M[12 * (3 + 3 * blk + r) + 3 + 3 * blk + c] = Pi[3 * r + r];"),
+    ("jacobian_transposed",
+     "J[12 * r + 3 + 3 * r + k] = x[k];", "J[12 * r + 3 + 3 * k + r] = x[k];"),
+    # global step (Sec. 4.2.1: implicit weight and explicit remainder)
+    ("bond_h2_dropped_in_H",
+     "/* implicit part: h^2 phi^+(d)/d J^T y_j with phi^+/d = kappa */\n"
+     "        add_JTJ(xs, h2 * bd->kappa, H);",
+     "/* implicit part: h^2 phi^+(d)/d J^T y_j with phi^+/d = kappa */\n"
+     "        add_JTJ(xs, bd->kappa, H);"),
+    ("spring_rest_sign",
+     "add_JT(xs, nrm, h2 * (-bd->kappa * bd->rest), r);",
+     "add_JT(xs, nrm, h2 * (bd->kappa * bd->rest), r);"),
+    ("polynomial_binomial",
+     "binom = binom * (double)(p - k) / (double)k;", "binom = binom * (double)(p - 1 - k) / (double)k;"),
+    ("polynomial_split_sign",
+     "pm -= binom * pow(d, (double)k) * lp;", "pm += binom * pow(d, (double)k) * lp;"),
+    ("polynomial_weight_power",
+     "pow(d, (double)(k - 1))", "pow(d, (double)k)"),
+    # local step (Sec. 4.2.2)
+    ("local_step_skipped",
+     "pabd_oracle_polar(qh + 3, qnext + 12 * b + 3);",
+     "memcpy(qnext + 12 * b + 3, qh + 3, 9 * sizeof(double));"),
+    ("polar_reflection_kept",
+     "double dsign = m3_det(UVt) < 0.0 ? -1.0 : 1.0;", "double dsign = 1.0;"),
+    # residual
+    ("residual_of_the_iterate",
+     "num += m_norm2(o->mass[b], o->Pi + 9 * b, dq);",
+     "num += m_norm2(o->mass[b], o->Pi + 9 * b, qk + 12 * b);"),
+    # velocity recovery (Algorithm 1)
+    ("recovery_gravity_twice",
+     "o->v[3 * b + k] = (cnew[k] - o->c[3 * b + k]) / h;",
+     "o->v[3 * b + k] = (cnew[k] - o->c[3 * b + k]) / h + h * o->gravity[k];"),
+    ("recovery_product_transposed", "m3_mul(dA, Ainv, W);", "m3_mul(Ainv, dA, W);"),
+    ("omega_sign",
+     "o->w[3 * b + 0] = 0.5 * (W[7] - W[5]);", "o->w[3 * b + 0] = 0.5 * (W[5] - W[7]);"),
+    # contacts and friction
+    ("contact_gate_sign", "if (!(gap < 0.0)) {", "if (!(gap > 0.0)) {"),
+    ("contact_kappa_h_power",
+     "return o->kscale * m / (o->h * o->h);", "return o->kscale * m / o->h;"),
+    ("friction_mu_dropped", "double s = b->mu * fn / ftn;", "double s = fn / ftn;"),
+    ("contact_remainder_sign",
+     "add_JT(xs, fe, side ? -h2 : h2, r);", "add_JT(xs, fe, side ? h2 : -h2, r);"),
+    ("contact_end_swapped",
+     "memcpy(yi, side ? yo : ys, sizeof yi);", "memcpy(yi, side ? ys : yo, sizeof yi);"),
+    ("detection_margin_motion_dropped",
+     "return o->margin + o->h * (v3_norm(o->v + 3 * b) + spin);", "return o->margin;"),
+    # augmented bonds (Sec. 5.2.2)
+    ("augmented_lambda_term_dropped",
+     "bd->al_lambda = bd->al_kappa * al_C[e] + bd->al_lambda;",
+     "bd->al_lambda = bd->al_kappa * al_C[e];"),
+    ("augmented_kappa_abs_dropped",
+     "bd->al_kappa = bd->al_kappa + o->al_beta * fabs(al_C[e]);",
+     "bd->al_kappa = bd->al_kappa + o->al_beta * al_C[e];"),
+    ("augmented_split_side",
+     "if (phim > 0.0 && d > 1e-12) {", "if (phim < 0.0 && d > 1e-12) {"),
+]
+
+
+def test_every_planted_text_occurs_once():
+    src = open(SRC).read()
+    for name, old, new in MUTANTS:
+        assert src.count(old) == 1, name
+        assert old != new, name
+
+
+@pytest.mark.skipif(shutil.which("gcc") is None, reason="gcc is needed to build the copies")
+@pytest.mark.parametrize("name,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_planted_mistake_fails_a_pin(tmp_path, name, old, new):
+    src = open(SRC).read()
+    assert src.count(old) == 1
+    (tmp_path / "pabd_oracle.c").write_text(src.replace(old, new))
+    shutil.copy(HDR, tmp_path / "pabd_oracle.h")
+    lib = tmp_path / "libpabd_oracle_mutant.so"
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", str(lib),
+                           str(tmp_path / "pabd_oracle.c"), "-lm"])
+    env = dict(os.environ, PABD_ORACLE_LIB=str(lib))
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-m", "not gpu",
+                        "-p", "no:cacheprovider", *PINS],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    # 0: every pin passed (the mistake went unnoticed); 5: nothing collected
+    assert r.returncode not in (0, 5), f"{name} passed every pin:\n{r.stdout[-1500:]}"
