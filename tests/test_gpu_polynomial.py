@@ -64,3 +64,28 @@ def test_bad_order_rejected(P):
     sc = S.spring_pair(order=4, precision=S.PREC_FP64).copy(order=np.array([5], np.int32))
     with pytest.raises(Exception):
         P.Scene(sc)
+
+
+@pytest.mark.parametrize("prec", [S.PREC_FP64, S.PREC_FP32])
+@pytest.mark.parametrize("p", [2, 4])
+def test_spring_at_zero_length(P, p, prec):
+    """A spring whose two ends coincide (d = 0, so its direction is undefined):
+    the explicit part along the direction is left out, as in the oracle, and the
+    pair stays where it is, with finite values, alone and in a batch (where the
+    quadratic spring runs in a tile and the polynomial one on the flat path)."""
+    sc = S.spring_pair(order=p, stretch=0.0, precision=prec)
+    print(f"[case] zero-length spring p={p} prec {prec}", flush=True)
+    o = oracle.Oracle(sc)
+    o.step(3)
+    ref = o.state()
+    g = P.Scene(sc)
+    g.step(3)
+    b = P.Batch(4, 1 << 26, prec)
+    slot = b.admit(sc, 3)
+    for _ in range(3):
+        b.step()
+    tol = 1e-12 if prec == S.PREC_FP64 else 1e-6
+    for got in (g.state(), b.state(slot)):
+        for x, y in zip(got, ref):
+            assert np.all(np.isfinite(x))
+            np.testing.assert_allclose(x, y, rtol=0, atol=tol)
