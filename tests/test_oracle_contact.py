@@ -63,6 +63,22 @@ def test_detection_margin_grows_with_the_motion_of_the_step():
     assert len(_detected(_on_plane(S.SHAPE_SPHERE, (0.5, 0.0, 0.0), gap, v=(0.0, -3.0, 0.0)))) == 1
 
 
+def test_box_box_contacts_stop_at_the_lateral_extent_of_the_face():
+    """Two unit cubes, the upper one 5 mm above the lower one's top face and
+    shifted 0.9 m along x: its bottom face overlaps the lower top face over
+    x in [0.4, 0.5] only, so of its four bottom vertices within the margin only
+    the two at x = 0.4 become contacts, on the lower box's face with normal +y."""
+    lo = S.single_body(c=(0.0, 0.0, 0.0))
+    up = S.single_body(c=(0.9, 1.005, 0.0))
+    sc = S.merge([lo, up]).copy(contact_enable=1)
+    o = oracle.Oracle(sc)
+    o.detect()
+    ct = o.contacts()
+    assert sorted(ct["feature"].tolist()) == [0, 4]  # -x and -y in the upper box's frame
+    assert np.all(ct["i"] == 1) and np.all(ct["j"] == 0)
+    np.testing.assert_allclose(ct["normal"], [[0.0, 1.0, 0.0]] * 2, atol=1e-15)
+
+
 def test_sphere_sphere_contact_geometry():
     sc = S.single_body(shape=S.SHAPE_SPHERE, half=(0.3, 0, 0), density=500.0)
     sc = S.merge([sc, sc.copy(c0=np.array([[0.35, 0.4, 0.1]]), shape_param=np.array([[0.25, 0, 0]]))])

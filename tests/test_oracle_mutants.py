@@ -16,7 +16,9 @@ HDR = os.path.join(ROOT, "oracle", "pabd_oracle.h")
 PINS = ["tests/test_oracle_math.py", "tests/test_oracle_dynamics.py", "tests/test_oracle_contact.py",
         "tests/test_oracle_polynomial.py", "tests/test_oracle_augmented.py"]
 
-# (name, text in the oracle, planted replacement); each text occurs once
+# (name, text in the oracle, planted replacement); each text occurs once.
+# Not listed: dropping alpha from the augmented bonds' warm start, which no pin
+# catches (the paper prints alpha but no result that depends on it alone)
 MUTANTS = [
     # prediction (Algorithm 1: explicit velocity and orientation update)
     ("gravity_dropped",
@@ -76,7 +78,17 @@ MUTANTS = [
      "memcpy(yi, side ? yo : ys, sizeof yi);", "memcpy(yi, side ? ys : yo, sizeof yi);"),
     ("detection_margin_motion_dropped",
      "return o->margin + o->h * (v3_norm(o->v + 3 * b) + spin);", "return o->margin;"),
+    ("box_face_axis_most_overlap",
+     "if (best_axis < 0 || overlap < best) best = overlap, best_axis = ax;",
+     "if (best_axis < 0 || overlap > best) best = overlap, best_axis = ax;"),
+    ("box_face_normal_sign",
+     "double sgn = v3_dot(axis, towards) >= 0.0 ? 1.0 : -1.0;",
+     "double sgn = v3_dot(axis, towards) >= 0.0 ? -1.0 : 1.0;"),
+    ("box_lateral_extent_ignored", "if (!lateral) continue;", "if (!lateral && 0) continue;"),
     # augmented bonds (Sec. 5.2.2)
+    ("augmented_warm_start_floor_dropped",
+     "b->al_kappa = fmax(o->al_gamma * b->al_kappa, b->kappa);",
+     "b->al_kappa = o->al_gamma * b->al_kappa;"),
     ("augmented_lambda_term_dropped",
      "bd->al_lambda = bd->al_kappa * al_C[e] + bd->al_lambda;",
      "bd->al_lambda = bd->al_kappa * al_C[e];"),
