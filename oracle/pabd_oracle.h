@@ -10,6 +10,12 @@
  *
  * Everything is double precision, row-major, SI units.  All arrays passed in are
  * owned by the caller and copied at create time.
+ *
+ * Parity unpinned: the contact and friction model and the driven joint are
+ * readings of material the paper does not print (they are held to invariants and
+ * closed forms of their own reading, not to the paper's model), and the factor
+ * alpha of the augmented bonds' warm start of lambda (Sec. 5.2.2) changes no
+ * result the paper prints or any pin checks.
  */
 #ifndef PABD_ORACLE_H
 #define PABD_ORACLE_H
