@@ -11,11 +11,14 @@
  * Everything is double precision, row-major, SI units.  All arrays passed in are
  * owned by the caller and copied at create time.
  *
- * Parity unpinned: the contact and friction model and the driven joint are
- * readings of material the paper does not print (they are held to invariants and
- * closed forms of their own reading, not to the paper's model), and the factor
- * alpha of the augmented bonds' warm start of lambda (Sec. 5.2.2) changes no
- * result the paper prints or any pin checks.
+ * Parity unpinned: the contact and friction model (contact bond, normal gate,
+ * Coulomb clamp, stiffness and margin) is a reading of material the paper does
+ * not print; it is held to the geometry and invariants of that reading
+ * (closed-form contact points and normals, resting gaps, incline stick and
+ * slip), not to the paper's own model.  The driven joint is a reading as well
+ * (Sec. 5.3.3 gives a periodic target angle, not the joint's energy); it is
+ * pinned against a ball joint to the target point turned by an independent
+ * rotation routine.
  */
 #ifndef PABD_ORACLE_H
 #define PABD_ORACLE_H

@@ -99,3 +99,28 @@ def test_mass_ratio_chain_keeps_its_joints_with_augmented_bonds():
         worst_q, worst_a = max(worst_q, eq), max(worst_a, ea)
         assert ea < eq
     assert worst_q > 1.0 and worst_a < 0.1 and worst_a < worst_q / 20
+
+
+def test_warm_start_scales_the_multiplier_by_alpha_gamma():
+    """Warm start of Sec. 5.2.2: each step begins from lambda^0 = alpha gamma
+    lambda^n.  With one iteration per step and beta = 0 the stiffness stays
+    kappa_start and the step's elongation C is measured at the prediction, which
+    does not depend on the multiplier carried over; so after two steps lambda
+    differs between two values alpha, alpha' of the factor by exactly
+    (alpha - alpha') gamma lambda_1, lambda_1 being the multiplier after the first
+    step (the same for both, since the first step starts from lambda = 0)."""
+    gamma = 0.9
+    base = _hanging(iters=1, beta=0.0).copy(al_gamma=gamma, c0=np.array([[0.05, -0.5 - 0.13, 0.02]]),
+                                           w0=np.array([[0.4, -0.2, 0.9]]))
+    lam1, lam2 = {}, {}
+    for alpha in (0.99, 0.5, 0.0):
+        o = oracle.Oracle(base.copy(al_alpha=alpha))
+        o.step(1)
+        lam1[alpha] = o.bond_state()[1][0]
+        o.step(1)
+        lam2[alpha] = o.bond_state()[1][0]
+        assert o.bond_state()[0][0] == pytest.approx(1e4, rel=1e-15)
+    assert lam1[0.99] == lam1[0.5] == lam1[0.0] != 0.0
+    l1 = lam1[0.99]
+    assert lam2[0.99] - lam2[0.5] == pytest.approx((0.99 - 0.5) * gamma * l1, rel=1e-9)
+    assert lam2[0.5] - lam2[0.0] == pytest.approx(0.5 * gamma * l1, rel=1e-9)

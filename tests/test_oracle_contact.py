@@ -207,3 +207,73 @@ def test_per_body_detection_is_the_full_detection_restricted_to_the_body():
         order_f = np.lexsort((full["feature"][sel], full["j"][sel], full["i"][sel]))
         order_m = np.lexsort((mine["feature"], mine["j"], mine["i"]))
         np.testing.assert_array_equal(full["x_j"][sel][order_f], mine["x_j"][order_m])
+
+
+_HE = np.array([0.3, 0.5, 0.7])
+_RB = S.rot_axis((1.0, -0.4, 0.7), 0.9)
+_RS = S.rot_axis((-0.3, 1.0, 0.2), 2.1)
+_CB = np.array([0.4, 1.3, -0.2])
+_R = 0.2
+
+
+def _sphere_box(local_centre, box_first):
+    """A sphere of radius 0.2 whose centre sits at `local_centre` in the material
+    frame of a turned box with half extents (0.3, 0.5, 0.7); both at rest, so the
+    detection margin of the pair is twice the base margin."""
+    box = S.single_body(half=tuple(_HE), c=tuple(_CB), A=_RB)
+    sph = S.single_body(shape=S.SHAPE_SPHERE, half=(_R, 0.0, 0.0), density=700.0,
+                        c=tuple(_CB + _RB @ np.asarray(local_centre, float)), A=_RS)
+    sc = S.merge([box, sph] if box_first else [sph, box]).copy(contact_enable=1)
+    o = oracle.Oracle(sc)
+    o.detect()
+    return o.contacts(), (1 if box_first else 0), (0 if box_first else 1)
+
+
+def _expect_contact(local_centre, closest, normal_local, box_first):
+    ct, s, b = _sphere_box(local_centre, box_first)
+    assert len(ct["i"]) == 1 and ct["i"][0] == s and ct["j"][0] == b
+    n = _RB @ (np.asarray(normal_local, float) / np.linalg.norm(normal_local))
+    np.testing.assert_allclose(ct["normal"][0], n, atol=1e-14)
+    np.testing.assert_allclose(ct["x_j"][0], closest, atol=1e-14)
+    # the sphere's point is its surface point facing the box: -r n in the world,
+    # stored in the sphere's material frame
+    np.testing.assert_allclose(_RS @ ct["x_i"][0], -_R * n, atol=1e-14)
+    assert ct["feature"][0] == 8
+
+
+@pytest.mark.parametrize("box_first", [True, False])
+def test_sphere_box_contact_geometry_face_edge_corner(box_first):
+    """Closed-form geometry of a sphere outside a box, 5 mm from its surface
+    (inside the margin 2 x 0.01): against a face the closest point is the foot of
+    the perpendicular and the normal the face normal; against an edge and a corner
+    the closest point is the edge point or the vertex and the normal points from
+    it to the sphere's centre."""
+    g = 0.005
+    _expect_contact((_HE[0] + _R + g, 0.1, -0.2), (_HE[0], 0.1, -0.2), (1, 0, 0), box_first)
+    e = np.array([1.0, 1.0, 0.0]) / math.sqrt(2.0)
+    _expect_contact(np.array([_HE[0], _HE[1], 0.1]) + (_R + g) * e, (_HE[0], _HE[1], 0.1), e, box_first)
+    k = np.array([1.0, -1.0, 1.0]) / math.sqrt(3.0)
+    corner = np.array([_HE[0], -_HE[1], _HE[2]])
+    _expect_contact(corner + (_R + g) * k, corner, k, box_first)
+
+
+@pytest.mark.parametrize("box_first", [True, False])
+def test_sphere_box_contact_inside_uses_the_nearest_face(box_first):
+    """A sphere whose centre is inside the box, 0.05 from the +x face and further
+    from every other face: the contact goes to that face (its foot point, its
+    outward normal), although the centre is only 0.05 deep and the sphere's
+    radius is 0.2."""
+    _expect_contact((_HE[0] - 0.05, 0.1, -0.2), (_HE[0], 0.1, -0.2), (1, 0, 0), box_first)
+    # just inside the -z face
+    _expect_contact((0.05, -0.1, -_HE[2] + 0.02), (0.05, -0.1, -_HE[2]), (0, 0, -1), box_first)
+
+
+def test_sphere_box_beyond_the_margin_has_no_contact():
+    """3 cm from a face, an edge or a corner (beyond the pair's 2 cm margin) the
+    sphere has no contact; 1.5 cm from them it has one."""
+    for g, n_expect in ((0.03, 0), (0.015, 1)):
+        assert len(_sphere_box((_HE[0] + _R + g, 0.1, -0.2), True)[0]["i"]) == n_expect
+        e = np.array([0.0, 1.0, -1.0]) / math.sqrt(2.0)
+        assert len(_sphere_box(np.array([0.1, _HE[1], -_HE[2]]) + (_R + g) * e, True)[0]["i"]) == n_expect
+        k = np.array([-1.0, -1.0, -1.0]) / math.sqrt(3.0)
+        assert len(_sphere_box(-_HE + (_R + g) * k, False)[0]["i"]) == n_expect

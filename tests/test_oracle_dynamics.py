@@ -239,3 +239,32 @@ def test_residual_decreases_geometrically_on_chain():
     ratios = rho[21:60] / rho[20:59]
     assert ratios.max() < 0.99 and ratios.max() - ratios.min() < 0.1
     assert rho[-1] < 1e-2 * rho[0]
+
+
+@pytest.mark.parametrize("axis", [(1, 0, 0), (0, 1, 0), (0, 0, 1)], ids=["x", "y", "z"])
+def test_free_rotation_from_a_large_turn_takes_each_quaternion_branch(axis):
+    """The prediction of Algorithm 1 reads the quaternion of A^n off the rotation
+    matrix by Shepperd's rule, which picks the largest of (A00, A11, A22, trace).
+    A turn of 150 degrees about x, y or z makes that diagonal entry the largest,
+    so each of the three non-trace branches is taken; a free body must still turn
+    by 2 atan(h|w|/2) per step about the fixed axis w (P-5), with
+    |w_{n+1}| = |w_n| / (1 + h^2 |w_n|^2 / 4)."""
+    R0 = S.rot_axis(axis, math.radians(150.0))
+    diag = [R0[0, 0], R0[1, 1], R0[2, 2], np.trace(R0)]
+    assert int(np.argmax(diag)) == int(np.argmax(axis))
+    w0 = np.array([0.9, -2.3, 1.4])
+    sc = S.single_body(half=(0.2, 0.5, 0.3), w=w0, A=R0, gravity=(0, 0, 0))
+    o = oracle.Oracle(sc)
+    h = sc.h
+    R = R0.copy()
+    wn = np.linalg.norm(w0)
+    for _ in range(8):
+        o.step(1)
+        R = S.rot_axis(w0, 2 * math.atan(h * wn / 2)) @ R
+        wn = wn / (1 + h * h * wn * wn / 4)
+        c, A, v, w = o.state()
+        np.testing.assert_allclose(A[0], R, atol=1e-13)
+        # still in the same branch of the read-off at the next step
+        assert int(np.argmax([A[0][0, 0], A[0][1, 1], A[0][2, 2], np.trace(A[0])])) == int(np.argmax(axis))
+    assert np.linalg.norm(w[0]) == pytest.approx(wn, rel=1e-12)
+    np.testing.assert_allclose(w[0] / np.linalg.norm(w[0]), w0 / np.linalg.norm(w0), atol=1e-12)

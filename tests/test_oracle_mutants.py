@@ -14,11 +14,9 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "pabd_oracle.c")
 HDR = os.path.join(ROOT, "oracle", "pabd_oracle.h")
 PINS = ["tests/test_oracle_math.py", "tests/test_oracle_dynamics.py", "tests/test_oracle_contact.py",
-        "tests/test_oracle_polynomial.py", "tests/test_oracle_augmented.py"]
+        "tests/test_oracle_polynomial.py", "tests/test_oracle_augmented.py", "tests/test_oracle_driven.py"]
 
 # (name, text in the oracle, planted replacement); each text occurs once.
-# Not listed: dropping alpha from the augmented bonds' warm start, which no pin
-# catches (the paper prints alpha but no result that depends on it alone)
 MUTANTS = [
     # prediction (Algorithm 1: explicit velocity and orientation update)
     ("gravity_dropped",
@@ -26,6 +24,10 @@ MUTANTS = [
     ("quaternion_half_factor",
      "Qs[k] = Q[k] + 0.5 * h * dQ[k];", "Qs[k] = Q[k] + h * dQ[k];"),
     ("quaternion_product_order", "quat_mul(wq, Q, dQ);", "quat_mul(Q, wq, dQ);"),
+    # quaternion read-off (Shepperd), the three non-trace branches
+    ("shepperd_x_branch_sign", "q[3] = (R[7] - R[5]) / s;", "q[3] = (R[5] - R[7]) / s;"),
+    ("shepperd_y_branch_sign", "q[3] = (R[2] - R[6]) / s;", "q[3] = (R[6] - R[2]) / s;"),
+    ("shepperd_z_branch_index", "q[1] = (R[5] + R[7]) / s;\n  }\n}", "q[1] = (R[2] + R[7]) / s;\n  }\n}"),
     # generalised mass (Sec. 4.1.1)
     ("box_moment_axis",
      "Pi0[4] = *m * sy * sy / 12.0;", "Pi0[4] = *m * sx * sx / 12.0;"),
@@ -85,6 +87,19 @@ MUTANTS = [
      "double sgn = v3_dot(axis, towards) >= 0.0 ? 1.0 : -1.0;",
      "double sgn = v3_dot(axis, towards) >= 0.0 ? -1.0 : 1.0;"),
     ("box_lateral_extent_ignored", "if (!lateral) continue;", "if (!lateral && 0) continue;"),
+    ("sphere_box_gap_sign", "gap = dist - r;", "gap = dist + r;"),
+    ("sphere_box_inside_gap", "gap = -best - r;", "gap = -best + r;"),
+    ("sphere_box_point_side", "pw[k] = -r * nw[k];", "pw[k] = r * nw[k];"),
+    ("sphere_box_inside_normal_side",
+     "double sgn = pl[ks] >= 0.0 ? 1.0 : -1.0;", "double sgn = pl[ks] >= 0.0 ? -1.0 : 1.0;"),
+    # driven joint (reading of Sec. 5.3.3)
+    ("driven_amplitude_sign",
+     "double th = dr[9] + dr[10] * sin(2.0 * M_PI * dr[11] * t + dr[12]);",
+     "double th = dr[9] - dr[10] * sin(2.0 * M_PI * dr[11] * t + dr[12]);"),
+    ("driven_turn_sense", "rotate_about(dr, th, rel, rot);", "rotate_about(dr, -th, rel, rot);"),
+    ("driven_time_at_step_start",
+     "const double t = o->t0 + (double)(o->steps_done + 1) * h;",
+     "const double t = o->t0 + (double)o->steps_done * h;"),
     # augmented bonds (Sec. 5.2.2)
     ("augmented_warm_start_floor_dropped",
      "b->al_kappa = fmax(o->al_gamma * b->al_kappa, b->kappa);",
@@ -95,6 +110,12 @@ MUTANTS = [
     ("augmented_kappa_abs_dropped",
      "bd->al_kappa = bd->al_kappa + o->al_beta * fabs(al_C[e]);",
      "bd->al_kappa = bd->al_kappa + o->al_beta * al_C[e];"),
+    ("augmented_warm_start_alpha_dropped",
+     "b->al_lambda = o->al_alpha * o->al_gamma * b->al_lambda;",
+     "b->al_lambda = o->al_gamma * b->al_lambda;"),
+    ("augmented_warm_start_gamma_dropped",
+     "b->al_lambda = o->al_alpha * o->al_gamma * b->al_lambda;",
+     "b->al_lambda = o->al_alpha * b->al_lambda;"),
     ("augmented_split_side",
      "if (phim > 0.0 && d > 1e-12) {", "if (phim < 0.0 && d > 1e-12) {"),
 ]
