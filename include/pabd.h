@@ -66,10 +66,18 @@ typedef enum {
 
 /*
  * Scene description: the statement of the problem of Sec. 4 -- bodies with mass
- * density and shape (from which m and the affine moment Pi = int rho x x^T dV of
- * the generalised mass matrix follow, Sec. 4.1.1), initial q and velocities,
- * bonds with material anchors and energy parameters, gravity, time step h and
- * the number K of global/local iterations per step (Algorithm 1).
+ * m and affine moment Pi0 = int rho x x^T dV of the generalised mass matrix
+ * M = diag(m I, Pi0, Pi0, Pi0) (Sec. 4.1.1), given directly (mass, Pi0) or
+ * derived from a uniform density and the body's shape; initial q (c0, A0) and
+ * velocities; bonds with material anchors and energy parameters (Sec. 4.2.1,
+ * Sec. 5.2.2); gravity; time step h; and the number K of global/local
+ * iterations per step (Algorithm 1).  The shape is also the body's contact
+ * geometry.
+ *
+ * Validation (PABD_E_INVALID): h > 0, K >= 1; every free body needs m > 0 and
+ * a symmetric positive definite Pi0; A0 must be a rotation (|A0^T A0 - I|_F <=
+ * 1e-6 and det A0 > 0); bond endpoints in range (-1 = world), no bond from a
+ * body to itself, kappa > 0, rest length >= 0.
  */
 typedef struct {
   int32_t n_bodies;
@@ -103,6 +111,13 @@ typedef struct {
   int32_t precision;          /* PABD_FP32 or PABD_FP64 */
   double al_beta, al_alpha, al_gamma; /* augmented-bond constants (the paper: 1e4, 0.99, 0.999) */
   const int32_t *order;       /* [B] order p of polynomial bonds, or NULL */
+  /* optional generalised mass (Sec. 4.1.1), overriding what density and shape
+   * give: mass [N] in kg, Pi0 [N*6] = int rho x x^T dV in kg m^2 as the packed
+   * symmetric (00, 01, 02, 11, 12, 22) in the body's material frame.  Either may
+   * be NULL (then that part comes from density and shape); pinned bodies may
+   * give anything (their mass never enters a step). */
+  const double *mass;
+  const double *Pi0;
 } pabd_scene_desc;
 
 typedef struct pabd_scene pabd_scene;
@@ -123,37 +138,64 @@ int32_t pabd_device_count(void);
 
 /* ---- plain path: one scene, one kernel launch per iteration --------------- */
 
-/* Validate the descriptor, derive m and Pi per body, build the bond incidence
- * lists, upload, and factor every body's 12x12 block in FP64 (Sec. 4.3). */
+/* Validate the descriptor, take m and Pi0 per body (given, or from density and
+ * shape: Sec. 4.1.1), build the bond incidence lists in (body, bond id) order,
+ * upload, and factor every body's 12x12 block H = M + h^2 sum w J^T J in FP64
+ * by its closed-form inverse (Sec. 4.2.1 block matrix; Sec. 4.3).  *out is a
+ * library-owned handle (NULL on failure). */
 pabd_status pabd_scene_create(const pabd_scene_desc *desc, pabd_scene **out);
+/* Wait for the device, then free the handle and its device memory. */
 pabd_status pabd_scene_destroy(pabd_scene *s);
-/* Advance nsteps steps of Algorithm 1 (collision detection, prediction, K
- * global/local iterations, velocity recovery), enqueued on hip_stream. */
+/* Advance nsteps steps of Algorithm 1: collision detection on q^n (contact
+ * bonds, Sec. 4.2), prediction, K Jacobi iterations of the body-wise global
+ * update (Sec. 4.2.1) each followed by the local polar projection (Sec. 4.2.2),
+ * and velocity recovery (Sec. 4.4).  Enqueued on hip_stream; returns at once. */
 pabd_status pabd_scene_step(pabd_scene *s, int32_t nsteps, void *hip_stream);
-/* Copy the state (c [N*3], A [N*9], v [N*3], w [N*3]; any may be NULL) to the
- * host after the scene's stream is idle.  Returns PABD_E_DIVERGED (state still
- * copied) if a step produced a non-finite state or overflowed contact capacity. */
+/* Copy the state q^n = (c, A) and velocities (v, w) of Algorithm 1 to the host
+ * (c [N*3], A [N*9], v [N*3], w [N*3]; any may be NULL) after the device is
+ * idle.  Returns PABD_E_DIVERGED (state still copied) if a step produced a
+ * non-finite state or overflowed contact capacity. */
 pabd_status pabd_scene_read_state(pabd_scene *s, double *c, double *A, double *v, double *w);
-/* FP64 convergence residual rho_k = ||q^{k+1} - q^k||_M / ||q^k||_M of every
- * iteration k of the last step (out[K]); writes K to *k_out. */
+/* FP64 convergence residual of the last iteration of the last step,
+ * rho = ||q^K - q^{K-1}||_M / ||q^{K-1}||_M over the scene's free bodies (the
+ * relative change that the stopping test of Algorithm 1 reads; K is fixed
+ * here, so it is reported, not tested).  0 before the first step. */
+pabd_status pabd_scene_residual(const pabd_scene *s, double *rho_last);
+/* The same residual for every iteration k of the last step (out[k], k < cap;
+ * iterations other than the last are recorded only with debug bit1 set, else
+ * reported as 0); writes K to *k_out. */
 pabd_status pabd_scene_residuals(pabd_scene *s, double *out, int32_t cap, int32_t *k_out);
-/* Contact bonds built by the last step's collision detection, in a canonical
- * order (i, j, feature).  Arrays of length cap (any may be NULL); *n_out is the
- * total count. */
+/* Contact bonds built by the last step's collision detection (the contact bonds
+ * of Sec. 4.2; geometry as read: the owner's point x_i, the partner's surface
+ * point x_j, the normal and kappa_c), in a canonical order (i, j, feature).
+ * Arrays of length cap (any may be NULL); *n_out is the total count. */
 pabd_status pabd_scene_contacts(pabd_scene *s, int32_t cap, int32_t *ci, int32_t *cj,
                                 int32_t *feature, double *xi, double *xj, double *normal,
                                 double *kappa, int32_t *n_out);
-/* Augmented-Lagrangian state (kappa_j, lambda_j) of every bond after the last
- * step, from its i-side end ([B] each, any may be NULL; other bond kinds report
- * kappa and 0). */
+/* Augmented-Lagrangian state (kappa_j, lambda_j of Sec. 5.2.2) of every bond
+ * after the last step, from its i-side end ([B] each, any may be NULL; other
+ * bond kinds report kappa and 0). */
 pabd_status pabd_scene_bond_state(pabd_scene *s, double *kappa, double *lambda);
-/* Device bytes the scene needs (admission bound for the batch). */
+/* Device bytes the scene needs (admission bound for the batch); 0 for an
+ * invalid descriptor. */
 size_t pabd_scene_bytes(const pabd_scene_desc *desc);
-/* debug switches: bit0 = skip the local (rigidification) step */
+/* Debug switches: bit0 = skip the local step (the global step of Sec. 4.2.1
+ * alone, a block Jacobi iteration), bit1 = record the residual of every
+ * iteration. */
 pabd_status pabd_scene_set_debug(pabd_scene *s, int32_t flags);
-/* Fault injection for tests: overwrite one state component of one body
- * (field 0..2 = c, 3..11 = A, 12..14 = v, 15..17 = w). */
+/* Fault injection for tests: overwrite one component of one body's state q^n
+ * or velocity (field 0..2 = c, 3..11 = A row-major, 12..14 = v, 15..17 = w)
+ * after the device is idle.  PABD_E_INVALID for a body or field out of range. */
+pabd_status pabd_debug_poke(pabd_scene *s, int32_t body, int32_t field, double value);
+/* The same call under its earlier name. */
 pabd_status pabd_scene_poke(pabd_scene *s, int32_t body, int32_t field, double value);
+/* How often the local step (Sec. 4.2.2) fell back from Newton's iteration to
+ * the nearest proper rotation U diag(1, 1, det U V^T) V^T of the SVD, since
+ * create: *svd counts body-iterations whose A^{k+1/2} had a determinant that
+ * was not safely positive or whose Newton iteration did not converge, and
+ * *det_nonpositive those among them with det A^{k+1/2} <= 0 (either pointer may
+ * be NULL). */
+pabd_status pabd_scene_polar_fallbacks(const pabd_scene *s, int64_t *svd, int64_t *det_nonpositive);
 /* the hipStream_t of the handle, as void* */
 void *pabd_scene_stream(pabd_scene *s);
 
@@ -185,10 +227,27 @@ pabd_status pabd_batch_step(pabd_batch *b, void *hip_stream);
 pabd_status pabd_batch_steps(pabd_batch *b, int32_t nsteps, void *hip_stream);
 /* Slots whose scenes finished all their steps (host bookkeeping, no sync). */
 pabd_status pabd_batch_poll(pabd_batch *b, int32_t *done, int32_t cap, int32_t *n_done);
+/* State of the scene in slot, as pabd_scene_read_state (PABD_E_DIVERGED when
+ * that scene, and only it, produced a non-finite state or overflowed its
+ * contact capacity; PABD_E_NOTFOUND for a slot not in use). */
 pabd_status pabd_batch_read_state(pabd_batch *b, int32_t slot, double *c, double *A, double *v,
                                   double *w);
+/* Residual of the scene in slot, as pabd_scene_residual. */
 pabd_status pabd_batch_residual(pabd_batch *b, int32_t slot, double *rho_last);
+/* Free the slot and its share of the HBM budget (the scene's state is lost). */
 pabd_status pabd_batch_release(pabd_batch *b, int32_t slot);
+/* Slots whose scene has failed, after the device is idle: slots[k] and its
+ * health bits codes[k] (bit0 = non-finite state, bit1 = contact capacity
+ * overflow), k < cap; *n_out is the total count.  Other scenes of the batch are
+ * unaffected by a failed one (scenes never read each other's data). */
+pabd_status pabd_batch_faults(pabd_batch *b, int32_t *slots, int32_t *codes, int32_t cap,
+                              int32_t *n_out);
+/* Fault injection for tests: as pabd_debug_poke, on body `body` of the scene in
+ * slot (takes effect at the next step). */
+pabd_status pabd_batch_poke(pabd_batch *b, int32_t slot, int32_t body, int32_t field, double value);
+/* As pabd_scene_polar_fallbacks, for the scene in slot (counted since admit). */
+pabd_status pabd_batch_polar_fallbacks(pabd_batch *b, int32_t slot, int64_t *svd,
+                                       int64_t *det_nonpositive);
 /* Steps taken so far by the scene in slot. */
 pabd_status pabd_batch_steps_done(pabd_batch *b, int32_t slot, int32_t *steps);
 /* Time candidate tile sizes on the resident scenes (their state is saved and

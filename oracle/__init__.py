@@ -47,7 +47,7 @@ class _Desc(C.Structure):
         ("contact_enable", C.c_int32), ("mu", C.c_double), ("contact_kappa_scale", C.c_double),
         ("contact_margin", C.c_double), ("n_planes", C.c_int32), ("planes", _d),
         ("al_beta", C.c_double), ("al_alpha", C.c_double), ("al_gamma", C.c_double),
-        ("order", _i),
+        ("order", _i), ("mass", _d), ("Pi0", _d),
     ]
 
 
@@ -145,6 +145,8 @@ class Oracle:
         d.al_alpha = s.al_alpha
         d.al_gamma = s.al_gamma
         d.order = _ptr(s.order, C.c_int32)
+        d.mass = _ptr(s.mass, C.c_double)
+        d.Pi0 = _ptr(s.Pi0, C.c_double)
         self.n = s.n_bodies
         self.n_bonds = s.n_bonds
         self.iters = s.iters

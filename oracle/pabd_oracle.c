@@ -448,9 +448,34 @@ pabd_oracle *pabd_oracle_create(const pabd_oracle_desc *d) {
     if (d->v0) memcpy(o->v + 3 * b, d->v0 + 3 * b, 3 * sizeof(double));
     if (d->w0) memcpy(o->w + 3 * b, d->w0 + 3 * b, 3 * sizeof(double));
     if (d->shape[b] != ORACLE_SHAPE_BOX && d->shape[b] != ORACLE_SHAPE_SPHERE) goto bad;
-    pabd_oracle_body_mass(d->shape[b], d->shape_param + 3 * b, d->density[b], o->mass + b,
-                          o->Pi + 9 * b);
-    if (!(o->mass[b] > 0.0) && !pinned(o, b)) goto bad;
+    pabd_oracle_body_mass(d->shape[b], d->shape_param + 3 * b, d->density ? d->density[b] : 0.0,
+                          o->mass + b, o->Pi + 9 * b);
+    if (d->mass) o->mass[b] = d->mass[b];
+    if (d->Pi0) {
+      /* packed symmetric 00 01 02 11 12 22 into the full 3 x 3 matrix */
+      const double *p6 = d->Pi0 + 6 * b;
+      double full[9] = {p6[0], p6[1], p6[2], p6[1], p6[3], p6[4], p6[2], p6[4], p6[5]};
+      memcpy(o->Pi + 9 * b, full, sizeof full);
+    }
+    if (!pinned(o, b)) {
+      if (!(o->mass[b] > 0.0)) goto bad;
+      /* Pi0 positive definite: its Cholesky factorisation exists */
+      double L[9];
+      memcpy(L, o->Pi + 9 * b, sizeof L);
+      if (cholesky(L, 3) != 0) goto bad;
+    }
+    {
+      /* A0 must be a rotation: |A0^T A0 - I|_F <= 1e-6 and det A0 > 0 */
+      const double *A = d->A0 + 9 * b;
+      double At[9], AtA[9], e2 = 0.0;
+      m3_transpose(A, At);
+      m3_mul(At, A, AtA);
+      for (int k = 0; k < 9; ++k) {
+        double g = AtA[k] - (k % 4 == 0 ? 1.0 : 0.0);
+        e2 += g * g;
+      }
+      if (!(e2 <= 1e-12) || !(m3_det(A) > 0.0)) goto bad;
+    }
     o->radius[b] = d->shape[b] == ORACLE_SHAPE_BOX ? v3_norm(d->shape_param + 3 * b)
                                                      : d->shape_param[3 * b];
     if (pinned(o, b)) {

@@ -78,11 +78,18 @@ typedef struct {
    * alpha (multiplier) and gamma (both) */
   double al_beta, al_alpha, al_gamma;
   const int32_t *order; /* [B] polynomial order p of POLYNOMIAL bonds, or NULL */
+  /* optional mass [N] and affine moment Pi0 [N*6] (packed symmetric 00 01 02 11
+   * 12 22, material frame) of each body, replacing what density and shape give
+   * (Sec. 4.1.1); NULL: from density and shape */
+  const double *mass;
+  const double *Pi0;
 } pabd_oracle_desc;
 
 typedef struct pabd_oracle pabd_oracle;
 
-/* create / destroy; create returns NULL on an invalid descriptor */
+/* create / destroy; create returns NULL on an invalid descriptor (among others:
+ * an A0 that is not a rotation, or a free body whose mass is not positive or
+ * whose Pi0 is not positive definite) */
 pabd_oracle *pabd_oracle_create(const pabd_oracle_desc *d);
 void pabd_oracle_destroy(pabd_oracle *o);
 

@@ -29,6 +29,8 @@ SYMBOLS = [
     "pabd_batch_steps_done", "pabd_batch_autotune", "pabd_batch_set_tile", "pabd_batch_stream",
     "pabd_batch_memory", "pabd_batch_time_tile_kernel", "pabd_batch_layout",
     "pabd_hbm_copy_probe", "pabd_batch_sync", "pabd_scene_bond_state", "pabd_set_allocator",
+    "pabd_scene_residual", "pabd_debug_poke", "pabd_scene_polar_fallbacks", "pabd_batch_faults",
+    "pabd_batch_poke", "pabd_batch_polar_fallbacks",
 ]
 
 _ALLOC_T = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -65,7 +67,7 @@ class _Desc(C.Structure):
         ("contact_margin", C.c_double), ("n_planes", C.c_int32), ("planes", _d),
         ("max_contacts_per_body", C.c_int32), ("precision", C.c_int32),
         ("al_beta", C.c_double), ("al_alpha", C.c_double), ("al_gamma", C.c_double),
-        ("order", _i),
+        ("order", _i), ("mass", _d), ("Pi0", _d),
     ]
 
 
@@ -123,6 +125,13 @@ def lib():
     L.pabd_batch_layout.argtypes = [vp, _i, _i, _i]
     L.pabd_hbm_copy_probe.argtypes = [C.c_size_t, C.c_int32, _d, _d]
     L.pabd_batch_sync.argtypes = [vp]
+    L.pabd_scene_residual.argtypes = [vp, _d]
+    L.pabd_debug_poke.argtypes = [vp, C.c_int32, C.c_int32, C.c_double]
+    _i64 = _P(C.c_int64)
+    L.pabd_scene_polar_fallbacks.argtypes = [vp, _i64, _i64]
+    L.pabd_batch_faults.argtypes = [vp, _i, _i, C.c_int32, _i]
+    L.pabd_batch_poke.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, C.c_double]
+    L.pabd_batch_polar_fallbacks.argtypes = [vp, C.c_int32, _i64, _i64]
     _lib = L
     return L
 
@@ -184,6 +193,8 @@ class _Marshalled:
         d.al_alpha = s.al_alpha
         d.al_gamma = s.al_gamma
         d.order = _ptr(s.order, C.c_int32)
+        d.mass = _ptr(s.mass, C.c_double)
+        d.Pi0 = _ptr(s.Pi0, C.c_double)
         self.desc = d
 
 
@@ -275,11 +286,23 @@ class Scene:
         _check(lib().pabd_scene_residuals(self._h, _ptr(out, C.c_double), self.iters, C.byref(k)))
         return out
 
+    def residual(self) -> float:
+        """FP64 residual of the last iteration of the last step."""
+        r = np.zeros(1)
+        _check(lib().pabd_scene_residual(self._h, _ptr(r, C.c_double)))
+        return float(r[0])
+
+    def polar_fallbacks(self):
+        """(body-iterations whose local step took the SVD, those with det <= 0)."""
+        a, b = C.c_int64(), C.c_int64()
+        _check(lib().pabd_scene_polar_fallbacks(self._h, C.byref(a), C.byref(b)))
+        return a.value, b.value
+
     def set_debug(self, flags: int):
         _check(lib().pabd_scene_set_debug(self._h, int(flags)))
 
     def poke(self, body: int, field: int, value: float):
-        _check(lib().pabd_scene_poke(self._h, int(body), int(field), float(value)))
+        _check(lib().pabd_debug_poke(self._h, int(body), int(field), float(value)))
 
     def bond_state(self):
         """(kappa_j, lambda_j) of every bond after the last step."""
@@ -375,6 +398,25 @@ class Batch:
     def release(self, slot: int):
         _check(lib().pabd_batch_release(self._h, int(slot)))
         self._n.pop(slot, None)
+
+    def faults(self) -> dict:
+        """{slot: health bits} of the resident scenes that failed (bit0 non-finite
+        state, bit1 contact capacity overflow)."""
+        cap = max(1, len(self._n))
+        sl = np.zeros(cap, np.int32)
+        co = np.zeros(cap, np.int32)
+        n = C.c_int32()
+        _check(lib().pabd_batch_faults(self._h, _ptr(sl, C.c_int32), _ptr(co, C.c_int32), cap, C.byref(n)))
+        k = min(n.value, cap)
+        return {int(a): int(b) for a, b in zip(sl[:k], co[:k])}
+
+    def poke(self, slot: int, body: int, field: int, value: float):
+        _check(lib().pabd_batch_poke(self._h, int(slot), int(body), int(field), float(value)))
+
+    def polar_fallbacks(self, slot: int):
+        a, b = C.c_int64(), C.c_int64()
+        _check(lib().pabd_batch_polar_fallbacks(self._h, int(slot), C.byref(a), C.byref(b)))
+        return a.value, b.value
 
     def autotune(self) -> int:
         t = C.c_int32()

@@ -57,8 +57,14 @@ struct SceneDev {
   int debug;        // bit0: skip the local step (single scenes on the flat path only)
   int steps_total;  // the scene is frozen once step reaches this
   int tiled;        // advanced by the tile kernel (which also reduces its residual)
-  int pad;
+  int ce_off;       // first contact slot of the scene: body b of the scene owns
+                    // slots ce_off + (b - body_off) * ccap ... + ccap - 1
 };
+
+// first contact slot of body i of scene S
+__device__ __forceinline__ size_t ce_base(const SceneDev& S, int i) {
+  return (size_t)S.ce_off + (size_t)(i - S.body_off) * (size_t)S.ccap;
+}
 
 // A contact end as the narrow phase stages it, in the order its atomics give:
 // the end's record, its partner and its sort key (partner + 1, feature, side)
@@ -112,6 +118,9 @@ struct View {
   SceneDev* scenes;
   int* health;  // per scene: bit0 non-finite, bit1 contact overflow
   double* rho;  // per scene: residual of the last iteration of the last step
+  // per scene, 2 each: local steps whose rotation came from the SVD, and those
+  // whose input had det <= 0
+  unsigned long long* polar;
 };
 
 // ---- vector load/store of packed records --------------------------------------

@@ -269,10 +269,14 @@ __device__ __forceinline__ bool polar_fast(T* X, bool* ok_out) {
 }
 
 // The rest for a lane whose first step was too large: measured steps while det X
-// stays safely positive, then, if they did not converge, the SVD.
+// stays safely positive, then, if they did not converge, the SVD.  Returns how
+// the rotation was found: bit0 = from the SVD (det X not safely positive, or
+// Newton stalled), bit1 = det X <= 0 (X is still the input when the first step
+// could not run, and Newton iterates keep the sign of the determinant).
 template <typename T>
-__device__ __forceinline__ void polar_finish(T* X, bool ok) {
+__device__ __forceinline__ int polar_finish(T* X, bool ok) {
   bool done = false;
+  int how = 0;
   if (ok) {
     T d2;
     bool unscaled;
@@ -284,28 +288,41 @@ __device__ __forceinline__ void polar_finish(T* X, bool ok) {
         break;
       }
     }
+  } else {
+    T C[9];
+    if (!(cofactor(X, C) > (T)0)) how = 2;
   }
   if (!done) {
     T Y[9];
     nearest_rotation_svd(X, Y);
 #pragma unroll
     for (int k = 0; k < 9; ++k) X[k] = Y[k];
+    how |= 1;
   }
+  return how;
+}
+
+// per-scene counts of the local step's fallback: [0] rotations from the SVD,
+// [1] those whose input had det <= 0
+__device__ __forceinline__ void count_polar(unsigned long long* cnt, int how) {
+  if (!cnt) return;
+  if (how & 1) atomicAdd(cnt, 1ull);
+  if (how & 2) atomicAdd(cnt + 1, 1ull);
 }
 
 template <typename T>
-__device__ __forceinline__ void polar_rotation_inplace(T* X) {
+__device__ __forceinline__ void polar_rotation_inplace(T* X, unsigned long long* cnt) {
   bool ok;
   const bool done = polar_fast(X, &ok);
   if (wave_any(!done))
-    if (!done) polar_finish(X, ok);
+    if (!done) count_polar(cnt, polar_finish(X, ok));
 }
 
 // The same for a caller short of registers: around the rare continuation X
 // goes through the lane's own 9 words `spill` of LDS, so that the compiler need
 // not keep a second copy of X in registers beside the continuation's own.
 template <typename T>
-__device__ __forceinline__ void polar_rotation_spill(T* X, T* spill) {
+__device__ __forceinline__ void polar_rotation_spill(T* X, T* spill, unsigned long long* cnt) {
   bool ok;
   const bool done = polar_fast(X, &ok);
   // spill word w holds X[(w + 1) % 9]: X[1..8] in two 16-byte groups, which
@@ -318,7 +335,7 @@ __device__ __forceinline__ void polar_rotation_spill(T* X, T* spill) {
       T Y[9];
 #pragma unroll
       for (int k = 0; k < 9; ++k) Y[k] = spill[(k + 8) % 9];
-      polar_finish(Y, ok);
+      count_polar(cnt, polar_finish(Y, ok));
 #pragma unroll
       for (int k = 0; k < 9; ++k) spill[(k + 8) % 9] = Y[k];
     }
@@ -329,10 +346,10 @@ __device__ __forceinline__ void polar_rotation_spill(T* X, T* spill) {
 }
 
 template <typename T>
-__device__ __forceinline__ void polar_rotation(const T* A, T* R) {
+__device__ __forceinline__ void polar_rotation(const T* A, T* R, unsigned long long* cnt) {
 #pragma unroll
   for (int k = 0; k < 9; ++k) R[k] = A[k];
-  polar_rotation_inplace(R);
+  polar_rotation_inplace(R, cnt);
 }
 
 // ---- prediction (Algorithm 1, prediction loop) ---------------------------------

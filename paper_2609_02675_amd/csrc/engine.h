@@ -79,13 +79,12 @@ __global__ void __launch_bounds__(256) k_scatter(const char* src, const Seg* seg
 }
 
 struct Caps {
-  int n = 0, e = 0, s = 0, p = 0, dr = 0, ccap = 0;
-  int nc = -1;  // bodies [0, nc) may have contacts (-1: all n)
+  int n = 0, e = 0, s = 0, p = 0, dr = 0;
+  int nc = -1;        // bodies [0, nc) may have contacts (-1: all n)
+  long long cslots = 0;  // contact slots, shared by the contact scenes (SceneDev::ce_off)
   bool contacts = false;
 };
 
-// candidate pairs provisioned per contact body
-inline int pairs_per_body(int ccap) { return std::max(16, ccap / 2); }
 
 template <typename T>
 struct Engine {
@@ -116,6 +115,7 @@ struct Engine {
   SceneDev* scenes = nullptr;
   int* health = nullptr;
   double* rho = nullptr;
+  unsigned long long* polar = nullptr;  // 2 per scene (View::polar)
   double* planes = nullptr;
   // driven bonds
   int *drv_scene = nullptr, *drv_end_i = nullptr, *drv_end_j = nullptr;
@@ -237,6 +237,7 @@ struct Engine {
     PABD_TRY(alloc(ccount, n));
     PABD_TRY(alloc(scenes, (size_t)c.s));
     PABD_TRY(alloc(health, (size_t)c.s));
+    PABD_TRY(alloc(polar, 2 * (size_t)c.s));
     PABD_TRY(alloc(rho, (size_t)c.s));
     PABD_TRY(alloc(reach, (size_t)c.s));
     PABD_TRY(alloc(planes, 4 * (size_t)c.p));
@@ -246,7 +247,7 @@ struct Engine {
     PABD_TRY(alloc(drv_param, 13 * (size_t)c.dr));
     if (c.contacts) {
       ncb = c.nc < 0 ? c.n : std::min(c.nc, c.n);
-      const size_t nb = (size_t)ncb, nc = nb * (size_t)c.ccap;
+      const size_t nb = (size_t)ncb, nc = (size_t)std::max(1LL, c.cslots);
       PABD_TRY(alloc(ce, CW * nc));
       PABD_TRY(alloc(ce_partner, nc));
       PABD_TRY(alloc(ce_key, nc));
@@ -263,7 +264,8 @@ struct Engine {
       PABD_TRY(alloc(large, nb));
       PABD_TRY(alloc(counters, 2));
       PABD_TRY(alloc(hist, (size_t)REACH_BINS * c.s));
-      const size_t pc = nb * (size_t)pairs_per_body(c.ccap);
+      // candidate pairs: half a pair per slot, at least 16 per body
+      const size_t pc = std::max(nb * 16, nc / 2);
       if (pc > (size_t)INT_MAX) {
         err = "candidate pair capacity exceeds 2^31";
         return PABD_E_INVALID;
@@ -279,6 +281,10 @@ struct Engine {
     PABD_HIP(hipMemcpy(srow_end, zero.data(), n * sizeof(int), hipMemcpyHostToDevice));
     PABD_HIP(hipMemcpy(ccount, zero.data(), n * sizeof(int), hipMemcpyHostToDevice));
     PABD_HIP(hipMemcpy(health, zero.data(), (size_t)c.s * sizeof(int), hipMemcpyHostToDevice));
+    std::vector<double> rz((size_t)c.s, 0.0);
+    PABD_HIP(hipMemcpy(rho, rz.data(), rz.size() * sizeof(double), hipMemcpyHostToDevice));
+    std::vector<unsigned long long> zero64(2 * (size_t)c.s, 0ull);
+    PABD_HIP(hipMemcpy(polar, zero64.data(), zero64.size() * sizeof(unsigned long long), hipMemcpyHostToDevice));
     std::vector<int> dneg(std::max(1, c.dr), -1);
     PABD_HIP(hipMemcpy(drv_scene, dneg.data(), dneg.size() * sizeof(int), hipMemcpyHostToDevice));
     std::vector<double> dz(n, 0.0);
@@ -319,6 +325,7 @@ struct Engine {
     v.r_den = r_den;
     v.scenes = scenes;
     v.health = health;
+    v.polar = polar;
     v.rho = rho;
     return v;
   }
@@ -389,6 +396,10 @@ struct Engine {
     add(scenes + sidx, &S, 1);
     int zero = 0;
     add(health + sidx, &zero, 1);
+    const unsigned long long zero2[2] = {0ull, 0ull};
+    add(polar + 2 * (size_t)sidx, zero2, 2);
+    const double rho0 = 0.0;  // no step taken yet
+    add(rho + sidx, &rho0, 1);
     const size_t nd = hs.drv_end_i.size();
     std::vector<int> di(nd), dj(nd), ds(nd, sidx);
     for (size_t k = 0; k < nd; ++k) {
@@ -443,7 +454,7 @@ struct Engine {
     hipLaunchKernelGGL(k_broad_large<T>, dim3(256), dim3(256), 0, st, v, cb);
     const int ng = std::min(8192, std::max(1, (pcap + 255) / 256));
     hipLaunchKernelGGL(k_narrow_pairs<T>, dim3(ng), dim3(256), 0, st, v, cb);
-    hipLaunchKernelGGL(k_sort_contacts<T>, dim3((unsigned)std::max(1, n)), dim3(64), 0, st, v, cap.ccap);
+    hipLaunchKernelGGL(k_sort_contacts<T>, dim3((unsigned)std::max(1, n)), dim3(64), 0, st, v);
   }
 
   // FP64 block factorisation of bodies [first, first + count)

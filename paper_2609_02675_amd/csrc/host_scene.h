@@ -44,7 +44,7 @@ inline std::string build_host_scene(const pabd_scene_desc* d, HostScene& hs) {
   if (d->iters < 1) return "iters must be >= 1";
   if (d->precision != PABD_FP32 && d->precision != PABD_FP64) return "unknown precision";
   const int n = d->n_bodies;
-  if (n > 0 && (!d->shape || !d->shape_param || !d->density || !d->c0 || !d->A0))
+  if (n > 0 && (!d->shape || !d->shape_param || !d->c0 || !d->A0 || (!d->density && !(d->mass && d->Pi0))))
     return "missing body arrays";
   if (d->n_bonds > 0 && (!d->bond_i || !d->bond_j || !d->x_i || !d->x_j || !d->kappa))
     return "missing bond arrays";
@@ -64,7 +64,7 @@ inline std::string build_host_scene(const pabd_scene_desc* d, HostScene& hs) {
     hs.flags[b] = fl;
     hs.shape[b] = (uint8_t)sh;
     hs.group[b] = d->group ? d->group[b] : 0;
-    const double rho = d->density[b];
+    const double rho = d->density ? d->density[b] : 0.0;
     double m, P0, P1, P2;
     if (sh == PABD_SHAPE_BOX) {
       if (!(p[0] > 0 && p[1] > 0 && p[2] > 0)) return "box half extents must be positive";
@@ -85,9 +85,24 @@ inline std::string build_host_scene(const pabd_scene_desc* d, HostScene& hs) {
       for (int k = 0; k < 4; ++k) hs.half[4 * b + k] = p[0];
     }
     const bool pinned = (fl & PABD_FLAG_PINNED) != 0;
-    if (!pinned && !(m > 0.0 && std::isfinite(m))) return "free body " + std::to_string(b) + " needs positive mass";
+    // packed symmetric Pi0: 00 01 02 11 12 22; given, or the shape's principal moments
+    double P[6] = {P0, 0.0, 0.0, P1, 0.0, P2};
+    if (d->mass) m = d->mass[b];
+    if (d->Pi0)
+      for (int k = 0; k < 6; ++k) P[k] = d->Pi0[6 * (size_t)b + k];
+    if (!pinned) {
+      if (!(m > 0.0 && std::isfinite(m))) return "free body " + std::to_string(b) + " needs positive mass";
+      // Sylvester's criterion on the leading minors
+      const double m1 = P[0], m2 = P[0] * P[3] - P[1] * P[1];
+      const double m3 = P[0] * (P[3] * P[5] - P[4] * P[4]) - P[1] * (P[1] * P[5] - P[4] * P[2]) +
+                        P[2] * (P[1] * P[4] - P[3] * P[2]);
+      bool finite = true;
+      for (double x : P) finite = finite && std::isfinite(x);
+      if (!finite || !(m1 > 0.0 && m2 > 0.0 && m3 > 0.0))
+        return "free body " + std::to_string(b) + " needs a symmetric positive definite Pi0";
+    }
     double* M = &hs.mass64[8 * (size_t)b];
-    M[0] = m; M[1] = P0; M[2] = 0; M[3] = 0; M[4] = P1; M[5] = 0; M[6] = P2; M[7] = 0;
+    M[0] = m; M[1] = P[0]; M[2] = P[1]; M[3] = P[2]; M[4] = P[3]; M[5] = P[4]; M[6] = P[5]; M[7] = 0;
     for (int k = 0; k < 3; ++k) hs.qn[12 * b + k] = d->c0[3 * b + k];
     for (int k = 0; k < 9; ++k) hs.qn[12 * b + 3 + k] = d->A0[9 * b + k];
     if (!pinned) {
@@ -98,6 +113,18 @@ inline std::string build_host_scene(const pabd_scene_desc* d, HostScene& hs) {
     }
     for (int k = 0; k < 12; ++k)
       if (!std::isfinite(hs.qn[12 * b + k])) return "non-finite initial state";
+    // A0 must be a rotation: the prediction turns it by R(dQ) and the velocity
+    // recovery inverts it by its transpose
+    const double* A = d->A0 + 9 * (size_t)b;
+    double e2 = 0.0;
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) {
+        const double g = A[r] * A[c] + A[3 + r] * A[3 + c] + A[6 + r] * A[6 + c] - (r == c ? 1.0 : 0.0);
+        e2 += g * g;
+      }
+    const double det = A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
+                       A[2] * (A[3] * A[7] - A[4] * A[6]);
+    if (!(e2 <= 1e-12 && det > 0.0)) return "A0 of body " + std::to_string(b) + " is not a rotation";
   }
   // bond ends, counting sort by owner keeping bond order (i side before j side)
   const int B = d->n_bonds;

@@ -317,13 +317,13 @@ __device__ __forceinline__ void push_end(const View<T>& v, int owner, int sc, in
                                          int feature, int side, const double* xs,
                                          const double* xo, const double* n, double kap,
                                          double mu) {
-  const int cap = v.scenes[sc].ccap;
+  const SceneDev& S = v.scenes[sc];
   const int slot = atomicAdd(v.ccount + owner, 1);
-  if (slot >= cap) {
+  if (slot >= S.ccap) {
     atomicOr(v.health + sc, 2);
     return;
   }
-  const size_t e = (size_t)owner * cap + slot;
+  const size_t e = ce_base(S, owner) + slot;
   T C[CW] = {(T)xs[0], (T)xs[1], (T)xs[2], (T)kap, (T)xo[0], (T)xo[1], (T)xo[2], (T)mu,
              (T)n[0], (T)n[1], (T)n[2], (T)0};
   StageRec<T>& r = v.ce_stage[e];
@@ -806,16 +806,17 @@ __device__ __forceinline__ void move_end(const View<T>& v, size_t base, int from
 }
 
 template <typename T>
-__global__ void __launch_bounds__(64) k_sort_contacts(View<T> v, int cap) {
+__global__ void __launch_bounds__(64) k_sort_contacts(View<T> v) {
   const int i = blockIdx.x;  // the whole wave works on body i
   if (i >= v.n) return;
   const int sc = v.bscene[i];
   if (!contact_body(v, i, sc)) return;
+  const int cap = v.scenes[sc].ccap;
   int cnt = v.ccount[i];
   if (cnt > cap) cnt = cap;
   if (cnt <= 0) return;
   const int lane = threadIdx.x;
-  const size_t base = (size_t)i * cap;
+  const size_t base = ce_base(v.scenes[sc], i);
   const StageRec<T>* st = v.ce_stage + base;
   if (cnt <= 64 * SORT_REG) {
     const int rounds = (cnt + 63) / 64;

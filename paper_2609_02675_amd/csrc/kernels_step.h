@@ -272,7 +272,7 @@ __device__ __forceinline__ void iterate_body(const View<T>& v, int k, double* rh
   if constexpr (CONTACT) {
     int cnt = v.ccount[i];
     if (cnt > S.ccap) cnt = S.ccap;
-    const size_t base = (size_t)i * S.ccap;
+    const size_t base = ce_base(S, i);
     // the lanes of a body take its ends in turn (neighbouring lanes read
     // neighbouring records), two ends per round with both ends' loads (record
     // and partner state) in flight together
@@ -349,7 +349,7 @@ __device__ __forceinline__ void iterate_body(const View<T>& v, int k, double* rh
 #pragma unroll
     for (int c = 0; c < 9; ++c) qo[3 + c] = Ah[c];
   } else {
-    polar_rotation(Ah, qo + 3);
+    polar_rotation(Ah, qo + 3, v.polar + 2 * (size_t)sc);
   }
   store<T, QR>(qd + (size_t)QR * i, qo);
   if (k == K - 1 || rh_num) {

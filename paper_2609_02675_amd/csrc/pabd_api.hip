@@ -61,6 +61,7 @@ struct EngineBase {
   // raw pointers used by the API layer
   virtual SceneDev* scene_table() = 0;
   virtual int* health_ptr() = 0;
+  virtual unsigned long long* polar_ptr() = 0;
   virtual double* rho_ptr() = 0;
   virtual double** history(int* k) = 0;
   virtual pabd_status alloc_history(int K) = 0;
@@ -160,6 +161,7 @@ struct EngineT final : EngineBase {
   int type_size() const override { return (int)sizeof(T); }
   SceneDev* scene_table() override { return e.scenes; }
   int* health_ptr() override { return e.health; }
+  unsigned long long* polar_ptr() override { return e.polar; }
   double* rho_ptr() override { return e.rho; }
   double** history(int* k) override {
     *k = e.rh_k;
@@ -310,7 +312,7 @@ pabd_status pabd_scene_create(const pabd_scene_desc* desc, pabd_scene** out) {
   c.p = std::max(1, (int)s->hs.planes.size() / 4);
   c.dr = std::max(1, (int)s->hs.drv_end_i.size());
   c.contacts = s->hs.contact;
-  c.ccap = s->hs.ccap;
+  c.cslots = (long long)c.n * s->hs.ccap;
   pabd_status st = s->eng->allocate(c);
   if (st != PABD_OK) return fail(st, s->eng->error());
   s->hs.params.steps_total = INT_MAX;
@@ -402,6 +404,23 @@ pabd_status pabd_scene_residuals(pabd_scene* s, double* out, int32_t cap, int32_
   return PABD_OK;
 }
 
+pabd_status pabd_scene_residual(const pabd_scene* s, double* rho_last) {
+  if (!s || !rho_last) return fail(PABD_E_INVALID, "null scene or output");
+  API_HIP(hipDeviceSynchronize());
+  API_HIP(hipMemcpy(rho_last, s->eng->rho_ptr(), sizeof(double), hipMemcpyDeviceToHost));
+  return PABD_OK;
+}
+
+pabd_status pabd_scene_polar_fallbacks(const pabd_scene* s, int64_t* svd, int64_t* det_nonpositive) {
+  if (!s) return fail(PABD_E_INVALID, "null scene");
+  API_HIP(hipDeviceSynchronize());
+  unsigned long long c[2] = {0ull, 0ull};
+  API_HIP(hipMemcpy(c, s->eng->polar_ptr(), sizeof c, hipMemcpyDeviceToHost));
+  if (svd) *svd = (int64_t)c[0];
+  if (det_nonpositive) *det_nonpositive = (int64_t)c[1];
+  return PABD_OK;
+}
+
 pabd_status pabd_scene_set_debug(pabd_scene* s, int32_t flags) {
   if (!s) return fail(PABD_E_INVALID, "null scene");
   API_HIP(hipStreamSynchronize(s->stream));
@@ -423,6 +442,10 @@ pabd_status pabd_scene_poke(pabd_scene* s, int32_t body, int32_t field, double v
   if (body < 0 || body >= s->hs.n || field < 0 || field > 17) return fail(PABD_E_INVALID, "bad poke target");
   API_HIP(hipDeviceSynchronize());
   return s->eng->write_body_field(body, field, value, s->stream);
+}
+
+pabd_status pabd_debug_poke(pabd_scene* s, int32_t body, int32_t field, double value) {
+  return pabd_scene_poke(s, body, field, value);
 }
 
 pabd_status pabd_scene_bond_state(pabd_scene* s, double* kappa, double* lambda) {
@@ -539,6 +562,7 @@ struct Slot {
   bool used = false;
   bool tiled = false;
   int boff = 0, n = 0, eoff = 0, ne = 0, poff = 0, np = 0, doff = 0, nd = 0;
+  int coff = 0, nslot = 0;  // contact slots [coff, coff + nslot): n bodies x the scene's capacity
   int tile = -1;
   int steps_total = 0;
   long long admitted_at = 0;  // batch substep counter at admission
@@ -564,7 +588,7 @@ struct pabd_batch {
   std::unique_ptr<EngineBase> eng;
   hipStream_t stream = nullptr;
   std::vector<Slot> slots;
-  RangeAlloc stream_bodies, tile_space, ends, planes, driven;
+  RangeAlloc stream_bodies, tile_space, ends, planes, driven, cslots;
   std::vector<Tile> tiles;  // index = tile id; used == 0 and no slots: free
   int tile_bodies = 64;
   bool tile_auto = true;
@@ -617,12 +641,13 @@ namespace {
 
 size_t body_cost(int ts) { return (size_t)ts * (4 * (QW + 4) + VW + MW + FW + 4) + 8 * (10 + 8 + 2) + 2 + 4 * 5; }
 size_t end_cost(int ts) { return (size_t)ts * EW + 4 + 8 * 4; }
-// one contact slot: final and staging copies of the record, partner and key
+// one contact slot: final and staging copies of the record, partner and key,
+// and half a candidate pair
 size_t contact_cost(int ts) {
-  return (size_t)ts * CW + 4 + 8 + (ts == 4 ? sizeof(StageRec<float>) : sizeof(StageRec<double>));
+  return (size_t)ts * CW + 4 + 8 + (ts == 4 ? sizeof(StageRec<float>) : sizeof(StageRec<double>)) + 4;
 }
-// per contact body: broad-phase record, reach, large-list entry, candidate pairs
-size_t contact_body_cost(int ccap) { return sizeof(BroadRec) + 8 + 4 + 8 * (size_t)pairs_per_body(ccap); }
+// per flat-path body: broad-phase record, reach, large-list entry, at least 16 candidate pairs
+size_t contact_body_cost() { return sizeof(BroadRec) + 8 + 4 + 8 * 16; }
 
 pabd_status batch_tables(pabd_batch* b) {
   // rebuild the device tile table from the host tiles
@@ -808,20 +833,25 @@ pabd_status batch_place_and_upload(pabd_batch* b, int slot) {
   s.poff = s.np > 0 ? b->planes.take(s.np) : 0;
   s.nd = (int)hs.drv_end_i.size();
   s.doff = s.nd > 0 ? b->driven.take(s.nd) : 0;
+  // contact slots: the scene's own capacity per body, from the batch's pool
+  s.nslot = hs.contact ? hs.n * hs.ccap : 0;
+  s.coff = s.nslot > 0 ? b->cslots.take(s.nslot) : 0;
   auto undo = [&]() {
     if (s.tiled) unplace_tiled(b, slot);
     else if (s.boff >= 0) b->stream_bodies.give(s.boff, std::max(1, hs.n));
     if (s.eoff >= 0) b->ends.give(s.eoff, std::max(1, hs.ne));
     if (s.np > 0 && s.poff >= 0) b->planes.give(s.poff, s.np);
     if (s.nd > 0 && s.doff >= 0) b->driven.give(s.doff, s.nd);
+    if (s.nslot > 0 && s.coff >= 0) b->cslots.give(s.coff, s.nslot);
   };
-  if (s.eoff < 0 || s.poff < 0 || s.doff < 0) {
+  if (s.eoff < 0 || s.poff < 0 || s.doff < 0 || s.coff < 0) {
     undo();
     return PABD_E_BUSY;
   }
   HostScene copy = hs;
   copy.params.steps_total = s.steps_total;
-  copy.params.ccap = b->caps.ccap;
+  copy.params.ccap = hs.ccap;
+  copy.params.ce_off = s.coff;
   copy.params.tiled = tiled ? 1 : 0;
   pabd_status st = b->eng->upload(copy, s.boff, s.eoff, s.poff, s.doff, slot, b->stream);
   if (st != PABD_OK) {
@@ -850,24 +880,25 @@ pabd_status pabd_batch_create(int32_t max_slots, size_t hbm_budget, int32_t prec
   b->max_slots = max_slots;
   b->budget = hbm_budget;
   const int ts = precision == PABD_FP64 ? 8 : 4;
-  // capacity: half the budget for bodies on the flat path (with contact slots),
-  // half for tiled bodies; about three bond ends per body
-  const int ccap = 64;
-  const size_t per_stream =
-      body_cost(ts) + 3 * end_cost(ts) + (size_t)ccap * contact_cost(ts) + contact_body_cost(ccap);
-  const size_t per_tiled = body_cost(ts) + 3 * end_cost(ts);
-  size_t n_stream = std::max<size_t>(1024, hbm_budget / 2 / per_stream);
-  size_t n_tiled = std::max<size_t>(1024, hbm_budget / 2 / per_tiled);
+  // capacity: each pool -- bodies on the flat path, tiled bodies, bond ends,
+  // contact slots -- holds a whole budget's worth of its own item (at most 2^28
+  // items), so that every scene whose pabd_scene_bytes fits the budget fits an
+  // empty batch; the device memory is then at most about four budgets, while
+  // admission keeps the resident scenes' bytes within one
+  const size_t lim = (size_t)1 << 28;
+  const size_t n_stream = std::min(lim, std::max<size_t>(1024, hbm_budget / (body_cost(ts) + contact_body_cost())));
+  size_t n_tiled = std::min(lim, std::max<size_t>(1024, hbm_budget / body_cost(ts)));
   n_tiled = (n_tiled + 255) / 256 * 256;
-  if (n_stream + n_tiled > (size_t)INT_MAX / 64) return fail(PABD_E_INVALID, "budget too large");
+  const size_t n_ends = std::min(lim, std::max<size_t>(4096, hbm_budget / end_cost(ts)));
+  const size_t n_slots = std::min(lim, std::max<size_t>(65536, hbm_budget / contact_cost(ts)));
   b->n_stream = (int)n_stream;
   b->caps.n = (int)(n_stream + n_tiled);
-  b->caps.e = (int)(3 * (n_stream + n_tiled));
+  b->caps.e = (int)n_ends;
   b->caps.s = max_slots;
   b->caps.p = 4 * max_slots + 16;
   b->caps.dr = std::max(64, (int)(n_stream / 4));
   b->caps.contacts = true;
-  b->caps.ccap = ccap;
+  b->caps.cslots = (long long)n_slots;
   b->caps.nc = (int)n_stream;  // contacts only on the flat path
   b->eng = make_engine(precision);
   API_HIP(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
@@ -896,6 +927,7 @@ pabd_status pabd_batch_create(int32_t max_slots, size_t hbm_budget, int32_t prec
   b->ends.init(b->caps.e);
   b->planes.init(b->caps.p);
   b->driven.init(b->caps.dr);
+  b->cslots.init((int)b->caps.cslots);
   *out = b.release();
   return PABD_OK;
 }
@@ -931,8 +963,8 @@ pabd_status pabd_batch_admit(pabd_batch* b, const pabd_scene_desc* desc, int32_t
   auto hs = std::make_shared<HostScene>();
   std::string why = build_host_scene(desc, *hs);
   if (!why.empty()) return fail(PABD_E_INVALID, why);
-  if (hs->contact && hs->ccap > b->caps.ccap)
-    return fail(PABD_E_INVALID, "max_contacts_per_body exceeds the batch capacity (64)");
+  if (hs->contact && (long long)hs->n * hs->ccap > b->caps.cslots)
+    return fail(PABD_E_INVALID, "the scene needs more contact slots (bodies x max_contacts_per_body) than the batch holds");
   const size_t bytes = scene_bytes(*hs, b->precision == PABD_FP64 ? 8 : 4);
   if (b->used_bytes + bytes > b->budget) return fail(PABD_E_BUSY, "HBM budget exhausted");
   int slot = -1;
@@ -983,6 +1015,7 @@ pabd_status pabd_batch_release(pabd_batch* b, int32_t slot) {
   b->ends.give(s.eoff, std::max(1, s.ne));
   if (s.np > 0) b->planes.give(s.poff, s.np);
   if (s.nd > 0) b->driven.give(s.doff, s.nd);
+  if (s.nslot > 0) b->cslots.give(s.coff, s.nslot);
   b->used_bytes -= s.bytes;
   s = Slot{};
   b->dirty = true;
@@ -1066,6 +1099,44 @@ pabd_status pabd_batch_residual(pabd_batch* b, int32_t slot, double* rho_last) {
   return PABD_OK;
 }
 
+pabd_status pabd_batch_faults(pabd_batch* b, int32_t* slots, int32_t* codes, int32_t cap, int32_t* n_out) {
+  if (!b) return fail(PABD_E_INVALID, "null batch");
+  API_HIP(hipDeviceSynchronize());
+  std::vector<int> h(b->max_slots, 0);
+  API_HIP(hipMemcpy(h.data(), b->eng->health_ptr(), h.size() * sizeof(int), hipMemcpyDeviceToHost));
+  int n = 0;
+  for (int k = 0; k < b->max_slots; ++k) {
+    if (!b->slots[k].used || h[k] == 0) continue;
+    if (n < cap) {
+      if (slots) slots[n] = k;
+      if (codes) codes[n] = h[k];
+    }
+    ++n;
+  }
+  if (n_out) *n_out = n;
+  return PABD_OK;
+}
+
+pabd_status pabd_batch_poke(pabd_batch* b, int32_t slot, int32_t body, int32_t field, double value) {
+  if (!b) return fail(PABD_E_INVALID, "null batch");
+  if (slot < 0 || slot >= b->max_slots || !b->slots[slot].used) return fail(PABD_E_NOTFOUND, "slot not in use");
+  const Slot& s = b->slots[slot];
+  if (body < 0 || body >= s.n || field < 0 || field > 17) return fail(PABD_E_INVALID, "bad poke target");
+  API_HIP(hipDeviceSynchronize());
+  return b->eng->write_body_field(s.boff + body, field, value, b->stream);
+}
+
+pabd_status pabd_batch_polar_fallbacks(pabd_batch* b, int32_t slot, int64_t* svd, int64_t* det_nonpositive) {
+  if (!b) return fail(PABD_E_INVALID, "null batch");
+  if (slot < 0 || slot >= b->max_slots || !b->slots[slot].used) return fail(PABD_E_NOTFOUND, "slot not in use");
+  API_HIP(hipDeviceSynchronize());
+  unsigned long long c[2] = {0ull, 0ull};
+  API_HIP(hipMemcpy(c, b->eng->polar_ptr() + 2 * (size_t)slot, sizeof c, hipMemcpyDeviceToHost));
+  if (svd) *svd = (int64_t)c[0];
+  if (det_nonpositive) *det_nonpositive = (int64_t)c[1];
+  return PABD_OK;
+}
+
 static pabd_status batch_repack(pabd_batch* b, int tile_bodies) {
   // read back every resident scene's state, re-place all scenes with the new
   // tile size, and upload again
@@ -1113,6 +1184,7 @@ static pabd_status batch_repack(pabd_batch* b, int tile_bodies) {
     b->ends.give(s.eoff, std::max(1, s.ne));
     if (s.np > 0) b->planes.give(s.poff, s.np);
     if (s.nd > 0) b->driven.give(s.doff, s.nd);
+    if (s.nslot > 0) b->cslots.give(s.coff, s.nslot);
   }
   b->tiles.clear();
   b->tile_bodies = tile_bodies;

@@ -57,6 +57,10 @@ class SceneDesc:
     rest_len: np.ndarray       # [B]
     drive: np.ndarray          # [B,13]
     order: Optional[np.ndarray] = None  # [B] int32 polynomial order (polynomial bonds)
+    # optional generalised mass replacing what density and shape give: mass [N],
+    # Pi0 [N,6] packed symmetric (00, 01, 02, 11, 12, 22) in the material frame
+    mass: Optional[np.ndarray] = None
+    Pi0: Optional[np.ndarray] = None
     gravity: np.ndarray = dataclasses.field(default_factory=lambda: np.array([0.0, -9.81, 0.0]))
     h: float = 1.0 / 60.0
     t0: float = 0.0
@@ -116,6 +120,8 @@ class SceneDesc:
             x_i=f64(self.x_i, (b, 3)), x_j=f64(self.x_j, (b, 3)), kappa=f64(self.kappa, (b,)),
             rest_len=f64(self.rest_len, (b,)), drive=f64(self.drive, (b, 13)),
             order=i32(self.order if self.order is not None else np.full(b, 2)),
+            mass=None if self.mass is None else f64(self.mass, (n,)),
+            Pi0=None if self.Pi0 is None else f64(self.Pi0, (n, 6)),
             gravity=f64(self.gravity, (3,)), planes=f64(self.planes, (-1, 4)))
 
 
@@ -311,7 +317,14 @@ def merge(scenes: List[SceneDesc], name: str = "merged") -> SceneDesc:
     bi = np.concatenate([s.bond_i + off[i] for i, s in enumerate(scenes)])
     bj = np.concatenate([np.where(s.bond_j >= 0, s.bond_j + off[i], -1) for i, s in enumerate(scenes)])
     first = scenes[0]
-    return first.copy(
+    extra = {}
+    for k in ("mass", "Pi0"):
+        given = [getattr(s, k) is not None for s in scenes]
+        if any(given):
+            if not all(given):
+                raise ValueError(f"merge: {k} given for some scenes only")
+            extra[k] = cat(k)
+    return first.copy(**extra,
         shape=cat("shape"), shape_param=cat("shape_param"), density=cat("density"),
         flags=cat("flags"), group=cat("group"), c0=cat("c0"), A0=cat("A0"), v0=cat("v0"),
         w0=cat("w0"), bond_i=bi.astype(np.int32), bond_j=bj.astype(np.int32),
@@ -328,11 +341,17 @@ def merge(scenes: List[SceneDesc], name: str = "merged") -> SceneDesc:
 def box_drop(n_side: int = 10, layers: Optional[int] = None, seed: int = 0, mu: float = 0.5,
              iters: int = 30, h: float = 1.0 / 60.0, spacing: float = 2.7,
              base_height: float = 2.0, precision: int = PREC_FP32, jitter: float = 0.1,
-             name: str = "") -> SceneDesc:
+             max_contacts_per_body: int = 256, name: str = "") -> SceneDesc:
     """Boxes with side lengths U[0.5, 1.5] per axis, density 1000, on an
     n_side x layers x n_side lattice at ``spacing`` with +-jitter, uniformly random
     orientation, at rest, every box's lowest point at least ``base_height``
-    above the ground plane y = 0.  n_side = 10, layers = 10 is the 1,000-box drop."""
+    above the ground plane y = 0.  n_side = 10, layers = 10 is the 1,000-box drop.
+
+    Contact capacity: when such a pile lands, its boxes sink into each other and
+    the speculative margin of the impact step (h |v|, about 0.25 m at 15 m/s)
+    brings many vertices of neighbours into range; measured on the GPU over the
+    landing of piles of 10 to 5,000 boxes, the most contact ends one box held
+    grew with the pile, to 82 at 1,000 boxes and 217 at 4,200, hence 256."""
     layers = n_side if layers is None else layers
     rng = np.random.Generator(np.random.PCG64(seed))
     n = n_side * n_side * layers
@@ -350,7 +369,7 @@ def box_drop(n_side: int = 10, layers: Optional[int] = None, seed: int = 0, mu: 
     return SceneDesc(**bd, **_empty_bonds(0), h=h, iters=iters, contact_enable=1, mu=mu,
                      contact_kappa_scale=0.3, contact_margin=0.01,
                      planes=np.array([[0.0, 1.0, 0.0, 0.0]]), precision=precision,
-                     name=name or f"boxdrop{n}")
+                     max_contacts_per_body=max_contacts_per_body, name=name or f"boxdrop{n}")
 
 
 def box_stack(n: int = 6, mass_ratio: float = 10.0, size: float = 1.0, gap: float = 0.0,
@@ -580,3 +599,56 @@ def granular_bed_quadruped(nx: int = 50, nz: int = 50, ny: int = 20, r: float = 
                      contact_kappa_scale=0.3, contact_margin=0.2 * r, planes=planes,
                      precision=precision, max_contacts_per_body=256,
                      name=name or f"bed{ns}{'_quadruped' if with_robot else ''}")
+
+
+# ---------------------------------------------------------------------------
+# cases of the local step's fallback and of a general generalised mass
+# ---------------------------------------------------------------------------
+
+def polar_fallback_body(kind: str = "flip", kappa: float = 1e7, iters: int = 2,
+                        precision: int = PREC_FP64) -> SceneDesc:
+    """One box (half extents 0.5, 0.4, 0.3; 0.48 kg) at rest, turned 0.7 rad about
+    (0.3, -0.5, 0.8), no gravity, held by four stiff world bonds from the centres
+    of its x and y faces.  "flip": the x anchors sit 2 m beyond the opposite
+    faces and the y anchors 0.8 m beyond their own, so the global step turns A
+    inside out along x and stretches it along y (det A^{k+1/2} < 0, singular
+    values near 4, 3, 1).  "flat": both x anchors sit at the centre and the y
+    anchors 0.1 m out, so A^{k+1/2} is nearly rank two (smallest singular value
+    about 3e-7 at kappa = 1e9)."""
+    bd = _bodies(1)
+    bd["shape_param"][0] = (0.5, 0.4, 0.3)
+    R = rot_axis((0.3, -0.5, 0.8), 0.7)
+    bd["A0"][0] = R
+    if kind == "flip":
+        pairs = [((0.5, 0, 0), (-2.0, 0, 0)), ((-0.5, 0, 0), (2.0, 0, 0)),
+                 ((0, 0.4, 0), (0, 1.2, 0)), ((0, -0.4, 0), (0, -1.2, 0))]
+    elif kind == "flat":
+        pairs = [((0.5, 0, 0), (0.0, 0, 0)), ((-0.5, 0, 0), (0.0, 0, 0)),
+                 ((0, 0.4, 0), (0, 0.5, 0)), ((0, -0.4, 0), (0, -0.5, 0))]
+    else:
+        raise ValueError(kind)
+    bonds = _empty_bonds(len(pairs))
+    for e, (xi, yw) in enumerate(pairs):
+        bonds["bond_i"][e], bonds["bond_j"][e] = 0, -1
+        bonds["x_i"][e] = xi
+        bonds["x_j"][e] = R @ np.asarray(yw, dtype=np.float64)
+        bonds["kappa"][e] = kappa
+    return SceneDesc(**bd, **bonds, gravity=np.zeros(3), iters=iters, precision=precision,
+                     name=f"polar_{kind}")
+
+
+def general_inertia_chain(n: int = 6, seed: int = 5, precision: int = PREC_FP64,
+                          iters: int = 20) -> SceneDesc:
+    """The chain of ``chain`` (top body pinned, 45 degrees) whose bodies carry an
+    explicit mass and an affine moment Pi0 that no box or sphere has: a seeded
+    symmetric positive definite matrix with off-diagonal terms (principal axes
+    turned away from the material frame, moments in [0.02, 0.2] kg m^2) and
+    masses in [0.5, 2] kg."""
+    sc = chain(n, tilt_deg=45.0, kappa=1e5, iters=iters, precision=precision,
+               name=f"geninertia{n}")
+    rng = np.random.Generator(np.random.PCG64(seed))
+    Q = random_rotations(rng, n)
+    lam = rng.uniform(0.02, 0.2, size=(n, 3))
+    P = np.einsum("nij,nj,nkj->nik", Q, lam, Q)
+    pi0 = np.stack([P[:, 0, 0], P[:, 0, 1], P[:, 0, 2], P[:, 1, 1], P[:, 1, 2], P[:, 2, 2]], axis=1)
+    return sc.copy(mass=rng.uniform(0.5, 2.0, size=n), Pi0=pi0)

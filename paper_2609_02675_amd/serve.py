@@ -10,6 +10,13 @@ scenes that have taken all their steps, freeing their slot and memory for the
 next arrivals.  Work of scenes admitted at different times overlaps on the
 device within each replay.
 
+Failures stay with their scene: a request the batch cannot take at all (a
+descriptor it rejects, or one larger than the whole budget) is rejected with
+the reason and the loop goes on; every few replays the batch's fault list is
+read, and a scene that diverged (non-finite state, or contact capacity
+exceeded) is evicted at once.  Such scenes are reported with their status and
+count neither as completed nor in the throughput.
+
 Reported: per-step latency (wall time of the replay that advanced a scene, as
 seen by that scene), aggregate body-iterations per second, queueing delay.
 """
@@ -37,6 +44,8 @@ class Result:
     finished_s: float
     state: tuple
     residual: float
+    status: str = "ok"  # "ok", "diverged" (evicted, state dropped) or "rejected"
+    reason: str = ""
 
 
 @dataclasses.dataclass
@@ -51,6 +60,7 @@ class ServeStats:
     queue_wait_ms_p99: float
     completed: int
     rejected: int
+    diverged: int
     replays: int
     max_resident: int
     peak_bytes: int
@@ -60,7 +70,8 @@ class ServeStats:
                     body_iterations=self.body_iterations, p50_step_ms=self.p50_step_ms,
                     p99_step_ms=self.p99_step_ms, queue_wait_ms_p50=self.queue_wait_ms_p50,
                     queue_wait_ms_p99=self.queue_wait_ms_p99, completed=self.completed,
-                    rejected=self.rejected, replays=self.replays, max_resident=self.max_resident,
+                    rejected=self.rejected, diverged=self.diverged, replays=self.replays,
+                    max_resident=self.max_resident,
                     peak_bytes=self.peak_bytes)
 
 
@@ -70,10 +81,14 @@ class Server:
     methods)."""
 
     def __init__(self, hbm_budget: int, max_slots: int, precision: int,
-                 clock: Callable[[], float] = time.perf_counter, batch=None):
+                 clock: Callable[[], float] = time.perf_counter, batch=None,
+                 fault_check_every: int = 8):
         self.batch = batch if batch is not None else _lib.Batch(max_slots, hbm_budget, precision)
         self.precision = precision
         self.clock = clock
+        # replays between two reads of the batch's fault list (each read waits
+        # for the device and copies one word per slot)
+        self.fault_check_every = max(1, int(fault_check_every))
 
     def close(self):
         self.batch.close()
@@ -96,6 +111,27 @@ class Server:
         peak = 0
         t0 = self.clock()
         order = sorted(range(len(requests)), key=lambda k: requests[k].arrival_s)
+
+        def reject(k, reason):
+            req = requests[k]
+            results[k] = Result(index=k, scene_name=req.scene.name, n_bodies=req.scene.n_bodies,
+                                steps=0, arrival_s=req.arrival_s, admitted_s=-1.0,
+                                finished_s=self.clock() - t0, state=None, residual=float("nan"),
+                                status="rejected", reason=reason)
+
+        def evict(slot, reason):
+            # a diverged scene: its work leaves the throughput, its slot is freed
+            nonlocal body_its
+            r = resident.pop(slot)
+            req = requests[r["k"]]
+            body_its -= r["done"] * r["n"] * r["iters"]
+            results[r["k"]] = Result(index=r["k"], scene_name=req.scene.name, n_bodies=r["n"],
+                                     steps=r["done"], arrival_s=req.arrival_s,
+                                     admitted_s=r["admitted"], finished_s=self.clock() - t0,
+                                     state=None, residual=float("nan"), status="diverged",
+                                     reason=reason)
+            b.release(slot)
+
         while nxt < len(order) or pending or resident:
             now = self.clock() - t0
             if max_wall_s is not None and now > max_wall_s:
@@ -107,17 +143,20 @@ class Server:
             while pending:
                 k = pending[0]
                 req = requests[k]
-                slot = b.admit(req.scene, req.steps)
+                try:
+                    slot = b.admit(req.scene, req.steps)
+                except _lib.PabdError as e:
+                    # the batch can never take this scene (e.g. more contact ends
+                    # per body than it holds): reject it, keep serving the rest
+                    pending.popleft()
+                    reject(k, str(e))
+                    continue
                 if slot is None:
                     if not resident:
                         # nothing resident and still no room: the request can
                         # never fit this server's budget; reject it
                         pending.popleft()
-                        results[k] = Result(index=k, scene_name=req.scene.name,
-                                            n_bodies=req.scene.n_bodies, steps=0,
-                                            arrival_s=req.arrival_s, admitted_s=-1.0,
-                                            finished_s=self.clock() - t0, state=None,
-                                            residual=float("nan"))
+                        reject(k, "larger than the HBM budget")
                         continue
                     break
                 pending.popleft()
@@ -141,10 +180,18 @@ class Server:
                     r["done"] += 1
                     lat.append(1e3 * dt)
                     body_its += r["n"] * r["iters"]
-            for slot in b.poll():
+            finished = b.poll()
+            if finished or replays % self.fault_check_every == 0:
+                for slot, code in b.faults().items():
+                    if slot in resident:
+                        evict(slot, f"health bits {code}: " +
+                              ("non-finite state" if code & 1 else "contact capacity exceeded"))
+            for slot in finished:
+                if slot not in resident:
+                    continue
                 r = resident.pop(slot)
                 req = requests[r["k"]]
-                st = b.state(slot, check=False) if keep_state else None
+                st = b.state(slot) if keep_state else None
                 rho = b.residual(slot)
                 results[r["k"]] = Result(index=r["k"], scene_name=req.scene.name, n_bodies=r["n"],
                                          steps=r["steps"], arrival_s=req.arrival_s,
@@ -159,8 +206,9 @@ class Server:
                            p99_step_ms=float(np.percentile(lat, 99)),
                            queue_wait_ms_p50=float(np.percentile(waits, 50)),
                            queue_wait_ms_p99=float(np.percentile(waits, 99)),
-                           completed=sum(1 for r in results.values() if r.state is not None or r.steps > 0),
-                           rejected=sum(1 for r in results.values() if r.admitted_s < 0),
+                           completed=sum(1 for r in results.values() if r.status == "ok"),
+                           rejected=sum(1 for r in results.values() if r.status == "rejected"),
+                           diverged=sum(1 for r in results.values() if r.status == "diverged"),
                            replays=replays, max_resident=max_res, peak_bytes=peak)
         return results, stats
 

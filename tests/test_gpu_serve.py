@@ -33,8 +33,13 @@ def test_served_results_equal_alone_and_in_the_mix(P, prec):
     budget = max(max(need), sum(need) // 4)
     srv = Server(budget, 32, prec)
     res, st = srv.run(reqs, realtime=False)
-    assert st.rejected == 0 and st.completed == len(reqs)
+    assert st.rejected == 0 and st.diverged == 0 and st.completed == len(reqs)
     assert st.peak_bytes <= budget
+    # every result, piles included, was read back healthy (a non-finite state or
+    # a contact overflow would have evicted it) and is finite
+    for r in res.values():
+        assert r.status == "ok", (r.scene_name, r.reason)
+        assert all(np.isfinite(x).all() for x in r.state), r.scene_name
     assert st.max_resident < len(reqs)
     for k in (0, 5, 11, len(reqs) - 1):
         alone = Server(1 << 28, 4, prec)
@@ -61,8 +66,13 @@ def test_served_mix_full_size_fp32(P):
     budget = 8 << 30
     srv = Server(budget, 512, S.PREC_FP32)
     res, st = srv.run(reqs, realtime=False)
-    assert st.rejected == 0 and st.completed == len(reqs)
+    assert st.rejected == 0 and st.diverged == 0 and st.completed == len(reqs)
     assert st.peak_bytes <= budget
+    # every result, piles included, was read back healthy (a non-finite state or
+    # a contact overflow would have evicted it) and is finite
+    for r in res.values():
+        assert r.status == "ok", (r.scene_name, r.reason)
+        assert all(np.isfinite(x).all() for x in r.state), r.scene_name
     chains = [k for k, r in enumerate(reqs) if "chain" in r.scene.name and r.steps <= 100]
     chains.sort(key=lambda k: reqs[k].scene.n_bodies * reqs[k].steps)
     assert chains

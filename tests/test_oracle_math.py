@@ -154,3 +154,39 @@ def test_polar_of_near_singular_and_rotation():
     best = np.trace(Ro.T @ A)
     for Q in S.random_rotations(rng, 200):
         assert np.trace(Q.T @ A) <= best + 1e-12
+
+
+def test_given_affine_moment_is_frame_invariant():
+    """A body's material frame is a choice: re-expressing a box in a frame turned
+    by Q (x' = Q^T x) gives A' = A Q, Pi0' = Q^T Pi0 Q (off-diagonal in general)
+    and anchors Q^T x, and must leave every world trajectory unchanged
+    (Sec. 4.1.1: M = diag(m I, Pi0, Pi0, Pi0) acts on the rows of A).  The box
+    moments come from density and shape in one run and are given explicitly,
+    turned, in the other."""
+    from paper_2609_02675_amd import scenes as S
+    sc = S.chain(5, tilt_deg=35.0, kappa=1e5, iters=20).copy(
+        w0=np.array([[0, 0, 0], [0.3, -0.2, 0.5], [0, 0.4, 0], [-0.6, 0, 0.1], [0.2, 0.2, 0.2]], float))
+    sc.shape_param[:] = (0.5, 0.3, 0.2)
+    rng = np.random.default_rng(7)
+    Q = S.random_rotations(rng, sc.n_bodies)
+    m = np.zeros(sc.n_bodies)
+    pi = np.zeros((sc.n_bodies, 6))
+    A1 = sc.A0.copy()
+    for b in range(sc.n_bodies):
+        mb, Pb = oracle.body_mass(S.SHAPE_BOX, sc.shape_param[b], sc.density[b])
+        Pq = Q[b].T @ Pb @ Q[b]
+        m[b], pi[b] = mb, (Pq[0, 0], Pq[0, 1], Pq[0, 2], Pq[1, 1], Pq[1, 2], Pq[2, 2])
+        A1[b] = sc.A0[b] @ Q[b]
+    xi = np.einsum("eji,ej->ei", Q[sc.bond_i], sc.x_i)
+    xj = np.einsum("eji,ej->ei", Q[sc.bond_j], sc.x_j)
+    turned = sc.copy(A0=A1, mass=m, Pi0=pi, x_i=xi, x_j=xj)
+    assert np.abs(pi[:, [1, 2, 4]]).max() > 1e-3
+    a, b = oracle.Oracle(sc), oracle.Oracle(turned)
+    a.step(30)
+    b.step(30)
+    ca, Aa, va, wa = a.state()
+    cb, Ab, vb, wb = b.state()
+    np.testing.assert_allclose(cb, ca, atol=1e-12)
+    np.testing.assert_allclose(Ab, Aa @ Q, atol=1e-12)
+    np.testing.assert_allclose(vb, va, atol=1e-10)
+    np.testing.assert_allclose(wb, wa, atol=1e-10)

@@ -35,6 +35,9 @@ MUTANTS = [
     ("mass_block_index",
      "M[12 * (3 + 3 * blk + r) + 3 + 3 * blk + c] = Pi[3 * r + c];",
      "M[12 * (3 + 3 * blk + r) + 3 + 3 * blk + c] = Pi[3 * r + r];"),
+    ("mass_block_diagonal_only",
+     "M[12 * (3 + 3 * blk + r) + 3 + 3 * blk + c] = Pi[3 * r + c];",
+     "M[12 * (3 + 3 * blk + r) + 3 + 3 * blk + c] = r == c ? Pi[3 * r + c] : 0.0;"),
     ("jacobian_transposed",
      "J[12 * r + 3 + 3 * r + k] = x[k];", "J[12 * r + 3 + 3 * k + r] = x[k];"),
     # global step (Sec. 4.2.1: implicit weight and explicit remainder)

@@ -41,6 +41,10 @@ class OracleBatch:
     def poll(self):
         return [k for k, s in self.slots.items() if s["done"] >= s["steps"]]
 
+    def faults(self):
+        # a scene whose oracle state is no longer finite has failed
+        return {k: 1 for k, s in self.slots.items() if not np.isfinite(s["o"].state()[0]).all()}
+
     def state(self, slot, check=True):
         return self.slots[slot]["o"].state()
 
@@ -93,3 +97,57 @@ def test_step_latency_and_throughput_accounting():
     assert st.replays == max(r.steps for r in reqs)
     assert len(st.step_latency_ms) == sum(r.steps for r in reqs)
     assert st.body_iterations == sum(r.scene.n_bodies * r.scene.iters * r.steps for r in reqs)
+
+
+def test_inadmissible_request_is_rejected_and_serving_continues():
+    """A request the batch refuses outright (here: a PabdError for one scene, as
+    the library raises for a scene with more contact ends per body than the batch
+    holds) is rejected with its reason; every other request still completes."""
+    from paper_2609_02675_amd import _lib
+    reqs = small_requests(n=8)
+    bad_name = reqs[3].scene.name
+
+    class Refusing(OracleBatch):
+        def admit(self, scene, steps):
+            if scene.name == bad_name:
+                raise _lib.PabdError(-1, "the scene needs more contact slots than the batch holds (capacity)")
+            return super().admit(scene, steps)
+
+    srv = Server(0, 0, S.PREC_FP64, batch=Refusing(1 << 30, 4))
+    res, st = srv.run(reqs, realtime=False)
+    assert res[3].status == "rejected" and "capacity" in res[3].reason
+    assert st.rejected == 1 and st.completed == len(reqs) - 1 and st.diverged == 0
+    assert all(res[k].status == "ok" and res[k].state is not None for k in range(len(reqs)) if k != 3)
+
+
+def test_diverged_scene_is_evicted_and_left_out_of_the_throughput():
+    """A scene whose state turns non-finite while resident is found by the
+    periodic fault check, evicted with status "diverged", and its iterations are
+    taken out of the throughput; the other scenes complete."""
+    reqs = small_requests(n=6)
+    victim = 2
+
+    class Poisoning(OracleBatch):
+        def step(self):
+            super().step()
+            for s in self.slots.values():
+                if s["o"].n and s["done"] == 2 and s.get("name") == reqs[victim].scene.name:
+                    c = s["o"]
+                    st = list(c.state())
+                    # restart that scene from a non-finite state
+                    st[0] = st[0] * np.nan
+                    s["o"] = oracle.Oracle(reqs[victim].scene.with_state(*st))
+
+        def admit(self, scene, steps):
+            slot = super().admit(scene, steps)
+            if slot is not None:
+                self.slots[slot]["name"] = scene.name
+            return slot
+
+    batch = Poisoning(1 << 30, 8)
+    srv = Server(0, 0, S.PREC_FP64, batch=batch, fault_check_every=1)
+    res, st = srv.run(reqs, realtime=False)
+    assert res[victim].status == "diverged" and res[victim].state is None
+    assert st.diverged == 1 and st.completed == len(reqs) - 1
+    expect = sum(r.scene.n_bodies * r.scene.iters * r.steps for k, r in enumerate(reqs) if k != victim)
+    assert st.body_iterations == expect
