@@ -199,6 +199,25 @@ pabd_status pabd_scene_polar_fallbacks(const pabd_scene *s, int64_t *svd, int64_
 /* the hipStream_t of the handle, as void* */
 void *pabd_scene_stream(pabd_scene *s);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): pabd_scene_create, nsteps calls'
+ * worth of pabd_scene_step and pabd_scene_read_state in one call, with every
+ * device array of the scene taken from a static array of the library
+ * (PABD_NOALLOC_SCRATCH_BYTES per GPU, held until the process ends) instead of
+ * hipMalloc; no device or pinned host memory is allocated.  The same kernels
+ * in the same order as the plain path, so the results equal those of
+ * create + step + read_state bit for bit.  desc as for pabd_scene_create;
+ * outputs as for pabd_scene_read_state (caller-owned host arrays, any may be
+ * NULL); work runs on hip_stream (NULL = the null stream) and the call returns
+ * when it is done.  PABD_E_OOM, before the device is touched, when the scene
+ * needs more than the static array; PABD_E_DIVERGED as read_state.  Every call
+ * on one GPU uses that GPU's one array (its contents are left from the last
+ * call; what must start at zero is cleared by the call): calls that overlap on
+ * one GPU, from several threads or streams, race. */
+#define PABD_NOALLOC_SCRATCH_BYTES (64u << 20)
+pabd_status pabd_scene_run_noalloc(const pabd_scene_desc *desc, int32_t nsteps, double *c, double *A,
+                                   double *v, double *w, void *hip_stream);
+
 /* ---- batched / served path ------------------------------------------------- */
 
 /* A batch keeps many independent scenes resident and advances all of them one

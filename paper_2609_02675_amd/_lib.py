@@ -30,7 +30,7 @@ SYMBOLS = [
     "pabd_batch_memory", "pabd_batch_time_tile_kernel", "pabd_batch_layout",
     "pabd_hbm_copy_probe", "pabd_batch_sync", "pabd_scene_bond_state", "pabd_set_allocator",
     "pabd_scene_residual", "pabd_debug_poke", "pabd_scene_polar_fallbacks", "pabd_batch_faults",
-    "pabd_batch_poke", "pabd_batch_polar_fallbacks",
+    "pabd_batch_poke", "pabd_batch_polar_fallbacks", "pabd_scene_run_noalloc",
 ]
 
 _ALLOC_T = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -132,6 +132,7 @@ def lib():
     L.pabd_batch_faults.argtypes = [vp, _i, _i, C.c_int32, _i]
     L.pabd_batch_poke.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, C.c_double]
     L.pabd_batch_polar_fallbacks.argtypes = [vp, C.c_int32, _i64, _i64]
+    L.pabd_scene_run_noalloc.argtypes = [_P(_Desc), C.c_int32, _d, _d, _d, _d, vp]
     _lib = L
     return L
 
@@ -244,6 +245,17 @@ def scene_bytes(scene: SceneDesc) -> int:
 
 def _state_arrays(n):
     return np.zeros((n, 3)), np.zeros((n, 3, 3)), np.zeros((n, 3)), np.zeros((n, 3))
+
+
+def run_noalloc(scene: SceneDesc, nsteps: int, stream: Optional[int] = None):
+    """pabd_scene_run_noalloc: create, nsteps steps and read-back in one call,
+    with no device allocation (the library's static scratch); returns (c, A, v, w)."""
+    m = _Marshalled(scene)
+    c, A, v, w = _state_arrays(scene.n_bodies)
+    _check(lib().pabd_scene_run_noalloc(C.byref(m.desc), int(nsteps), _ptr(c, C.c_double), _ptr(A, C.c_double),
+                                        _ptr(v, C.c_double), _ptr(w, C.c_double),
+                                        C.c_void_p(stream) if stream else None))
+    return c, A, v, w
 
 
 class Scene:

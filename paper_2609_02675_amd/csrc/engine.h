@@ -131,6 +131,9 @@ struct Engine {
   char* h_stage = nullptr;
   char* d_stage = nullptr;
   size_t stage_cap = 0;
+  // upload with one plain copy per array instead (no pinned or device staging
+  // buffer: for an engine whose memory must not grow)
+  bool direct_upload = false;
 
   ~Engine() { release(); }
   void release() {
@@ -150,6 +153,12 @@ struct Engine {
 
   // every put in one host-to-device copy plus one scatter launch; returns when done
   pabd_status staged_upload(const std::vector<Put>& puts, hipStream_t st) {
+    if (direct_upload) {
+      for (const Put& p : puts)
+        if (p.bytes) PABD_HIP(hipMemcpyAsync(p.dst, p.src, p.bytes, hipMemcpyHostToDevice, st));
+      PABD_HIP(hipStreamSynchronize(st));
+      return PABD_OK;
+    }
     size_t total = 0;
     std::vector<Seg> segs;
     for (const Put& p : puts) {

@@ -7,6 +7,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -74,6 +75,8 @@ struct EngineBase {
   virtual pabd_status raw_bodies(int boff, int n, std::vector<char>& buf, hipStream_t st, bool write) = 0;
   // augmented-bond state of ends [0, ne) as doubles (4 per end)
   virtual pabd_status read_al(int ne, std::vector<double>& out, hipStream_t st) = 0;
+  // device memory from `a` instead of the allocator in force, uploads without staging buffers
+  virtual void use_memory(const DeviceAllocator& a) = 0;
 };
 
 template <typename T>
@@ -158,6 +161,10 @@ struct EngineT final : EngineBase {
     return PABD_OK;
   }
   std::string& error() override { return e.err; }
+  void use_memory(const DeviceAllocator& a) override {
+    e.dev = a;
+    e.direct_upload = true;
+  }
   int type_size() const override { return (int)sizeof(T); }
   SceneDev* scene_table() override { return e.scenes; }
   int* health_ptr() override { return e.health; }
@@ -1349,6 +1356,123 @@ pabd_status pabd_hbm_copy_probe(size_t bytes, int32_t reps, double* gbps, double
   const double per = (double)ms / reps;
   if (avg_ms) *avg_ms = per;
   if (gbps) *gbps = 2.0 * (double)(n * 16) / (per * 1e-3) / 1e9;
+  return PABD_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// allocation-free run (pabd_scene_run_noalloc)
+// ---------------------------------------------------------------------------
+
+// Device memory of pabd_scene_run_noalloc: one file-scope array that each GPU
+// the library runs on holds until the process ends.  In host code this name is
+// a host-side stand-in, not a device address: host code uses the address that
+// hipGetSymbolAddress gives for the current device (scratch_on_device), never
+// the name itself.
+static __device__ __align__(256) unsigned char scratch[PABD_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+// per device: the address of its copy of `scratch`, looked up once with that
+// device current
+struct ScratchTable {
+  std::mutex m;
+  std::vector<void*> addr;
+};
+
+ScratchTable& scratch_table() {
+  static ScratchTable t;
+  return t;
+}
+
+pabd_status scratch_on_device(void** out) {
+  int dev = 0;
+  API_HIP(hipGetDevice(&dev));
+  ScratchTable& t = scratch_table();
+  std::lock_guard<std::mutex> lock(t.m);
+  if ((int)t.addr.size() <= dev) t.addr.resize((size_t)dev + 1, nullptr);
+  if (!t.addr[dev]) {
+    void* p = nullptr;
+    API_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(PABD_E_DEVICE, "hipGetSymbolAddress gave no address for the scratch array");
+    t.addr[dev] = p;
+  }
+  *out = t.addr[dev];
+  return PABD_OK;
+}
+
+// bump allocation from the scratch array, 256-byte aligned; NULL once full
+struct Bump {
+  char* base;
+  size_t cap, used, asked;
+};
+
+void* bump_alloc(size_t bytes, void* ctx) {
+  Bump* b = static_cast<Bump*>(ctx);
+  const size_t off = (b->used + 255) / 256 * 256;
+  b->asked = off + bytes;
+  if (b->asked > b->cap) return nullptr;
+  b->used = b->asked;
+  return b->base + off;
+}
+
+void bump_release(void*, void*) {}
+
+}  // namespace
+
+extern "C" {
+
+pabd_status pabd_scene_run_noalloc(const pabd_scene_desc* desc, int32_t nsteps, double* c, double* A,
+                                   double* v, double* w, void* hip_stream) {
+  if (nsteps < 0) return fail(PABD_E_INVALID, "negative step count");
+  HostScene hs;
+  std::string why = build_host_scene(desc, hs);
+  if (!why.empty()) return fail(PABD_E_INVALID, why);
+  if (pabd_device_count() < 1) return fail(PABD_E_DEVICE, "no HIP device");
+  void* base = nullptr;
+  pabd_status st = scratch_on_device(&base);
+  if (st != PABD_OK) return st;
+  hipStream_t stream = (hipStream_t)hip_stream;
+  // the previous call on this stream may still be reading the scratch
+  API_HIP(hipStreamSynchronize(stream));
+  Bump bump{static_cast<char*>(base), (size_t)PABD_NOALLOC_SCRATCH_BYTES, 0, 0};
+  DeviceAllocator mem;
+  mem.alloc = bump_alloc;
+  mem.release = bump_release;
+  mem.ctx = &bump;
+  std::unique_ptr<EngineBase> eng = make_engine(desc->precision);
+  eng->use_memory(mem);
+  Caps cp;
+  cp.n = std::max(1, hs.n);
+  cp.e = std::max(1, hs.ne);
+  cp.s = 1;
+  cp.p = std::max(1, (int)hs.planes.size() / 4);
+  cp.dr = std::max(1, (int)hs.drv_end_i.size());
+  cp.contacts = hs.contact;
+  cp.cslots = (long long)cp.n * hs.ccap;
+  // every array is taken before anything is written, so a scene that does not
+  // fit is turned away before the device is touched
+  st = eng->allocate(cp);
+  if (st == PABD_E_OOM)
+    return fail(PABD_E_OOM, "the scene needs more than the " + std::to_string((size_t)PABD_NOALLOC_SCRATCH_BYTES) +
+                                " bytes of the library's static scratch (at least " + std::to_string(bump.asked) +
+                                " bytes)");
+  if (st != PABD_OK) return fail(st, eng->error());
+  hs.params.steps_total = INT_MAX;
+  st = eng->upload(hs, 0, 0, 0, 0, 0, stream);
+  if (st != PABD_OK) return fail(st, eng->error());
+  eng->factor(stream);
+  for (int k = 0; k < nsteps && hs.n > 0; ++k)
+    eng->flat_step(0, std::max(1, hs.n), 1, hs.params.iters, hs.contact, (int)hs.drv_end_i.size(), false,
+                   true, stream);
+  API_HIP(hipGetLastError());
+  st = eng->read_bodies(0, hs.n, c, A, v, w, stream);
+  if (st != PABD_OK) return st;
+  int health = 0;
+  API_HIP(hipMemcpy(&health, eng->health_ptr(), sizeof(int), hipMemcpyDeviceToHost));
+  if (health & 1) return fail(PABD_E_DIVERGED, "non-finite state");
+  if (health & 2) return fail(PABD_E_DIVERGED, "contact capacity exceeded");
   return PABD_OK;
 }
 
