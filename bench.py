@@ -30,10 +30,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "affine-body SSM iterations/s (served/batched vs plain); p50/p99 step ms"
 HBM_PEAK = 8.0e12            # B/s, MI355X HBM3E
-FP32_VALU_PEAK = 78.6e12     # flop/s: 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz, unpacked FP32
-# the published vector FP32 figure counts packed two-wide FMAs, which every HIP
-# source here is compiled without; reported beside the unpacked fraction
-FP32_PACKED_PEAK = 157.3e12
+# published MI355X vector FP32 peak: 256 CU x 128 lanes x 2 (FMA) x 2.4 GHz, which
+# counts two-wide packed FMAs; every HIP source here is compiled without packed
+# FP32 instructions, whose issue rate is half of it (78.6 TFLOP/s), reported beside
+FP32_PEAK = 157.3e12
+FP32_UNPACKED_PEAK = 78.6e12
 # algorithmic bytes the tile kernel moves per body: once per launch it reads q
 # (16 floats: c_hi, A, c_lo), v/w (8), mass (8), H^-1 factor (12), two bond ends
 # (8 floats + partner id each), scene id, flags and end range; after every step
@@ -46,13 +47,11 @@ def tile_bytes(n_bodies, steps_per_launch):
     return n_bodies * (TILE_LOAD_BYTES_PER_BODY + steps_per_launch * TILE_STORE_BYTES_PER_BODY_STEP)
 
 
-# flops of one body-iteration of a two-bond chain body: bond terms (2 x 63),
-# inertia term (81), block solve (84), increment (12), two Newton polar steps
-# (2 x 90; FP32 converges in two from a near-rotation)
+# algorithmic flops of one body-iteration of a two-bond chain body, counted by
+# hand from the operations the method needs (an estimate of the work, not a
+# hardware count): bond terms (2 x 63), inertia term M (s - q) (81), closed-form
+# block solve (84), increment (12), two Newton polar steps (2 x 90)
 FLOPS_PER_BODY_ITER = 2 * 63 + 81 + 84 + 12 + 2 * 90
-# bytes per body-iteration a streaming (one launch per iteration) sweep must move:
-# read q^k, s, mass, factor, two bond ends; write q^{k+1}
-STREAM_BYTES_PER_BODY_ITER = 64 + 64 + 32 + 48 + 2 * (32 + 4) + 64
 
 
 def log(*a):
@@ -146,12 +145,19 @@ def cpu_baseline_leg(args, S, scenes, plan):
         o.step(steps)
         return o.state()
 
-    refs = {"batched": {k: run(scenes[k], plan["total_steps"]) for k in plan["batched_sample"]}}
+    refs = {"batched": {k: run(scenes[k], plan["total_steps"]) for k in plan["batched_sample"]},
+            "plain": {k: run(scenes[k], plan["plain_steps"]) for k in plan["plain_sample"]}}
     if plan["big_scenes"] is not None:
         refs["big"] = {k: run(plan["big_scenes"][k], plan["big_steps"]) for k in plan["big_sample"]}
     if plan["requests"]:
         refs["served"] = {k: run(plan["requests"][k].scene, plan["requests"][k].steps)
                           for k in plan["served_sample"]}
+        refs["pile_mid"], refs["pile_next"] = {}, {}
+        for k in plan["pile_sample"]:
+            sc = plan["requests"][k].scene
+            mid = sc.with_state(*run(sc, 60), t0=60 * sc.h)
+            refs["pile_mid"][k] = mid
+            refs["pile_next"][k] = run(mid, 1)
     if not args.no_scenes:
         # the box drop from the oracle's own state after 60 steps (contacts
         # active), and the oracle's next step from there
@@ -160,6 +166,13 @@ def cpu_baseline_leg(args, S, scenes, plan):
         refs["drop_mid"] = mid
         refs["drop_next"] = run(mid, 1)
         refs["mass_ratio"] = {aug: run(S.mass_ratio_chain(augmented=aug), 110) for aug in (True, False)}
+        # the oracle's own spread: the same chain from FP32-rounded inputs
+        f32 = lambda a: np.asarray(a, np.float32).astype(np.float64)
+        refs["mass_ratio_f32_inputs"] = {}
+        for aug in (True, False):
+            mc = S.mass_ratio_chain(augmented=aug)
+            mc = mc.copy(c0=f32(mc.c0), x_i=f32(mc.x_i), x_j=f32(mc.x_j), rest_len=f32(mc.rest_len))
+            refs["mass_ratio_f32_inputs"][aug] = run(mc, 110)
     if cpu is not None and not args.no_oracle_single:
         cpu["single_core_single_scene"] = oracle_single_core(oracle, S, refs.get("drop_mid"))
     return cpu, refs
@@ -217,7 +230,8 @@ def big_batch_leg(P, S, torch, plan, refs):
     out = dict(scenes=n_scenes, bodies=nb, iters=iters, steps_per_launch=spl, ms_per_step=ms,
                body_its_per_s=nb * iters / (ms / 1e3), tile_kernel_ms_per_launch=launch_ms,
                tile_kernel_ms_per_step=tile_ms,
-               alu_frac=flops / (tile_ms / 1e3) / FP32_VALU_PEAK,
+               alu_frac=flops / (tile_ms / 1e3) / FP32_PEAK,
+               alu_frac_of_unpacked_peak=flops / (tile_ms / 1e3) / FP32_UNPACKED_PEAK,
                hbm_GBs_algorithmic=tile_bytes(nb, spl) / (launch_ms / 1e3) / 1e9,
                load_bytes_per_launch=nb * TILE_LOAD_BYTES_PER_BODY,
                max_rel_err_vs_fp64_oracle=acc, tile_bodies=64)
@@ -257,6 +271,8 @@ def oracle_single_core(oracle, S, drop_mid=None):
 # the big batch leg: one warm-up launch, BIG_TIMED_LAUNCHES timed launches, then
 # the tile kernel alone BIG_REPS times (each after a warm launch)
 BIG_TIMED_LAUNCHES, BIG_REPS = 2, 2
+# the plain leg: untimed and timed steps of each scene
+PLAIN_WARM, PLAIN_STEPS = 2, 10
 
 
 def _plan(args, S, scenes):
@@ -270,7 +286,9 @@ def _plan(args, S, scenes):
     plan = dict(spl=spl, launches=args.steps // spl, warm_launches=warm_launches,
                 total_steps=warm_launches * spl + args.steps,
                 batched_sample=[int(k) for k in rng.choice(len(scenes), 4, replace=False)],
-                requests=[], served_sample=[], big_scenes=None, big_sample=(), big_steps=0)
+                requests=[], served_sample=[], pile_sample=[], big_scenes=None, big_sample=(),
+                big_steps=0, plain_steps=PLAIN_WARM + PLAIN_STEPS,
+                plain_sample=list(range(min(3, args.plain_sample))))
     if args.serve_seconds > 0:
         reqs = S.serving_requests(rate_hz=200.0, duration_s=args.serve_seconds, seed=3,
                                   precision=S.PREC_FP32)
@@ -280,6 +298,10 @@ def _plan(args, S, scenes):
         # horizons in the tests
         plan["served_sample"] = [k for k in range(len(reqs))
                                  if "chain" in reqs[k].scene.name and reqs[k].scene.n_bodies <= 80][:3]
+        # piles over one step from the oracle's own state at step 60 (landing,
+        # contacts active), served through the same loop
+        plan["pile_sample"] = [k for k in range(len(reqs))
+                               if "pile" in reqs[k].scene.name and 100 <= reqs[k].scene.n_bodies <= 400][:2]
     if args.big_scenes > 0:
         n = args.big_scenes
         plan["big_scenes"] = S.batched_chains(n, seed=2, precision=S.PREC_FP32)
@@ -305,7 +327,7 @@ def main():
     ap.add_argument("--plain-sample", type=int, default=64)
     ap.add_argument("--cpu-sample", type=int, default=1024)
     ap.add_argument("--cpu-steps", type=int, default=20)
-    ap.add_argument("--serve-seconds", type=float, default=6.0,
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="seconds of Poisson arrivals (200 req/s) in the served leg; 0 = skip")
     ap.add_argument("--serve-budget-gib", type=float, default=8.0)
     ap.add_argument("--only-scene", default="",
@@ -405,14 +427,14 @@ def main():
     common = dict(traffic=traffic, traffic_unit="bytes/launch", kernel="k_tile_step<float>",
                   steps_per_launch=spl, kernel_ms_per_launch=tile_launch_ms, kernel_ms_per_step=tile_ms,
                   flops_per_launch=tile_flops, bytes_per_launch=tbytes)
-    if alu_ach / FP32_VALU_PEAK >= hbm_ach / HBM_PEAK:
-        roof = dict(bound="alu", achieved=alu_ach / 1e12, peak=FP32_VALU_PEAK / 1e12, unit="TFLOP/s",
-                    frac=alu_ach / FP32_VALU_PEAK, frac_of_packed_fp32_peak=alu_ach / FP32_PACKED_PEAK,
+    if alu_ach / FP32_PEAK >= hbm_ach / HBM_PEAK:
+        roof = dict(bound="alu", achieved=alu_ach / 1e12, peak=FP32_PEAK / 1e12, unit="TFLOP/s",
+                    frac=alu_ach / FP32_PEAK, frac_of_unpacked_fp32_peak=alu_ach / FP32_UNPACKED_PEAK,
+                    flops_per_body_iter_estimate=FLOPS_PER_BODY_ITER,
                     hbm_achieved_GBs=hbm_ach / 1e9, **common)
     else:
         roof = dict(bound="hbm", achieved=hbm_ach / 1e9, peak=HBM_PEAK / 1e9, unit="GB/s",
                     frac=hbm_ach / HBM_PEAK, **common)
-    eff_bw = value * STREAM_BYTES_PER_BODY_ITER
     log(f"tile kernel {tile_launch_ms:.4f} ms per launch of {spl} steps ({tile_ms:.4f} ms per step); "
         f"roofline {roof['bound']} frac {roof['frac']:.3f}")
 
@@ -426,19 +448,29 @@ def main():
         sample = scenes[: args.plain_sample]
         objs = [P.Scene(s) for s in sample]
         for o_ in objs:
-            o_.step(2)
+            o_.step(PLAIN_WARM)
         torch.cuda.synchronize()
+        # one scene at a time: each scene's steps run and finish before the next
+        # scene's start
         t = time.perf_counter()
-        nst = 10
         for o_ in objs:
-            o_.step(nst)
-        torch.cuda.synchronize()
+            o_.step(PLAIN_STEPS)
+            torch.cuda.synchronize()
         dt = time.perf_counter() - t
-        its = sum(s.n_bodies for s in sample) * iters * nst
-        plain = dict(value=its / dt, unit="body-iterations/s", ms_per_scene_step=1e3 * dt / (nst * len(sample)),
-                     sample=f"{len(sample)} of the chains, {nst} steps each, one scene at a time")
+        its = sum(s.n_bodies for s in sample) * iters * PLAIN_STEPS
+        acc_p = 0.0
+        for k in plan["plain_sample"]:
+            e = errors(objs[k].state(), refs["plain"][k], scale_of(sample[k]))
+            acc_p = max(acc_p, e["pos"], e["rot"])
+        plain = dict(value=its / dt, unit="body-iterations/s",
+                     ms_per_scene_step=1e3 * dt / (PLAIN_STEPS * len(sample)),
+                     sample=f"{len(sample)} of the chains, {PLAIN_STEPS} steps each, one scene at a time "
+                            f"(each scene's steps synchronised before the next scene starts)",
+                     max_rel_err_vs_fp64_oracle=acc_p,
+                     accuracy_checked=f"first {len(plan['plain_sample'])} scenes after "
+                                      f"{plan['plain_steps']} steps")
         del objs
-        log(f"plain: {plain['value']:.4g} body-it/s")
+        log(f"plain: {plain['value']:.4g} body-it/s, err {acc_p:.2e}")
 
     # served mix: Poisson arrivals of chains and box piles, continuous batching
     served = served_sat = None
@@ -468,6 +500,21 @@ def main():
         served_sat["max_rel_err_vs_fp64_oracle"] = acc_s
         served_sat["checked"] = [reqs[k].scene.name for k in small]
         srv.close()
+        # piles: one served step from the oracle's landing state at step 60
+        from paper_2609_02675_amd.scenes import Request
+        pk = plan["pile_sample"]
+        if pk:
+            preq = [Request(arrival_s=0.0, scene=refs["pile_mid"][k].copy(precision=S.PREC_FP32), steps=1)
+                    for k in pk]
+            srv = Server(budget, 16, S.PREC_FP32)
+            pres, _ = srv.run(preq, realtime=False, keep_state=True)
+            srv.close()
+            acc_pile = 0.0
+            for j, k in enumerate(pk):
+                e = errors(pres[j].state, refs["pile_next"][k], scale_of(refs["pile_mid"][k]))
+                acc_pile = max(acc_pile, e["pos"], e["rot"])
+            served_sat["pile_one_step_err_vs_fp64_oracle"] = acc_pile
+            served_sat["piles_checked"] = [f"{reqs[k].scene.name} from step 60" for k in pk]
         log("served (saturated)", served_sat)
 
     # single-scene legs on the plain path: the 1,000-box drop (contact and
@@ -523,6 +570,12 @@ def main():
                 body_its_per_s=rate, ms_per_step=ms, iters=mc.iters, steps_timed="11..110",
                 max_joint_error_m=float(joint(st[0], st[1])),
                 max_joint_error_oracle_m=float(joint(*refs["mass_ratio"][aug][:2])),
+                # the oracle itself from FP32-rounded inputs: how far rounding the
+                # inputs alone moves this chain after 110 steps
+                max_joint_error_oracle_fp32_inputs_m=float(joint(*refs["mass_ratio_f32_inputs"][aug][:2])),
+                oracle_state_spread_from_fp32_inputs=float(
+                    max(np.abs(refs["mass_ratio_f32_inputs"][aug][0] - refs["mass_ratio"][aug][0]).max(),
+                        np.abs(refs["mass_ratio_f32_inputs"][aug][1] - refs["mass_ratio"][aug][1]).max())),
                 paper_context="Table 2, mass-ratio chain (19 bodies, 10 iterations) on an RTX 3080: "
                               "t_solve 1.28 ms (AL on) / 1.25 ms (off) per frame")
             log(f"mass-ratio chain {tag}: {ms:.3f} ms/step, joint error {joint(st[0], st[1]):.3g} m")
@@ -540,7 +593,7 @@ def main():
             _, rate, ms = time_scene(net, 10, 100)
             scene_legs[f"spring_net_11_p{p_}_fp32"] = dict(
                 body_its_per_s=rate, ms_per_step=ms, bonds=net.n_bonds, iters=net.iters,
-                first_step_rel_error=[float(x) for x in rho[:20]])
+                first_step_residual_rho_k=[float(x) for x in rho[:20]])
             log(f"net p={p_}: {ms:.3f} ms/step, first-step rho {rho[0]:.2e} -> {rho[19]:.2e}")
         # 50^3 stacked cubes in resting contact (the paper's largest scene size)
         if want("block_pile"):
@@ -585,8 +638,6 @@ def main():
         "p50_launch_ms": float(np.percentile(launch_ms, 50)),
         "accuracy": {"max_rel_err_vs_fp64_oracle": acc, "after_steps": total_steps,
                      "tolerance": 1e-3},
-        "effective_stream_bandwidth_GBs": eff_bw / 1e9,
-        "effective_stream_frac_of_hbm": eff_bw / HBM_PEAK,
         "hbm_copy_probe_GBs": probe_gbs,
         "plain": plain,
         "speedup_vs_plain": (value / plain["value"]) if plain else None,

@@ -36,15 +36,21 @@ def test_mass_ratio_chain_fp64(P, steps):
     np.testing.assert_allclose(lg, lo, rtol=1e-8, atol=1e-8 * np.abs(lo).max())
 
 
-def test_mass_ratio_chain_fp32_one_step(P):
+@pytest.mark.parametrize("steps,tol", [(1, 1e-4), (10, 1e-3), (40, 1e-3)])
+def test_mass_ratio_chain_fp32(P, steps, tol):
+    """FP32 against the FP64 oracle over horizons where the chain is not yet
+    sensitive: the oracle itself, started from FP32-rounded inputs, moves by at
+    most 1.2e-7 (positions and rotations, relative) over 1 to 40 steps, while
+    after 110 steps such rounding alone moves its joint errors by per cents."""
     sc = S.mass_ratio_chain(precision=S.PREC_FP32)
+    print(f"[case] augmented chain fp32 steps={steps}", flush=True)
     g = P.Scene(sc)
-    g.step(1)
+    g.step(steps)
     o = oracle.Oracle(sc.copy(precision=S.PREC_FP64))
-    o.step(1)
+    o.step(steps)
     e = errors(g.state(), o.state(), scale_of(sc))
     print(e)
-    assert e["pos"] <= 1e-4 and e["rot"] <= 1e-4
+    assert e["pos"] <= tol and e["rot"] <= tol
 
 
 def test_augmented_chain_in_a_batch_matches_alone(P):

@@ -46,7 +46,7 @@ def test_reduced_bed_with_quadruped_fp64(P):
         np.testing.assert_allclose(cg["x_j"], co["x_j"], atol=1e-9)
         e = errors(g.state(), o.state(), scale_of(sc))
         print("reduced bed after step", step, e)
-        assert fp64_ok(e, vel_tol=1e-5)
+        assert fp64_ok(e)
 
 
 def test_reduced_bed_fp32_one_step(P):
@@ -57,7 +57,7 @@ def test_reduced_bed_fp32_one_step(P):
     o.step(1)
     e = errors(g.state(), o.state(), scale_of(sc))
     print("reduced bed fp32", e)
-    assert e["pos"] <= 1e-4 and e["rot"] <= 1e-3
+    assert e["pos"] <= 1e-4 and e["rot"] <= 1e-4
 
 
 @pytest.mark.parametrize("prec", [S.PREC_FP64, S.PREC_FP32])
@@ -77,9 +77,10 @@ def test_full_bed_one_step(P, prec):
         kg, _ = _table(g.contacts())
         ko, _ = _table(o.contacts())
         np.testing.assert_array_equal(kg, ko)
-        assert fp64_ok(e, vel_tol=1e-5)
+        assert fp64_ok(e)
     else:
-        # positions meet the FP32 bar; the 1 cm spheres' orientations carry more
-        # error (their rotation increment is a small difference of large contact
-        # torques over a tiny affine moment) and do not enter their contact geometry
+        # positions meet the FP32 bar; the orientations of a few 1 cm spheres
+        # carry more: the FP64 oracle itself, from FP32-rounded inputs, moves
+        # them by 2.9e-4 in this step (tests/test_oracle_sensitivity.py), so
+        # their bar is 1e-3
         assert e["pos"] <= 1e-4 and e["rot"] <= 1e-3
