@@ -329,7 +329,7 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=20)
     ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="seconds of Poisson arrivals (200 req/s) in the served leg; 0 = skip")
-    ap.add_argument("--serve-budget-gib", type=float, default=8.0)
+    ap.add_argument("--serve-budget-gib", type=float, default=16.0)
     ap.add_argument("--only-scene", default="",
                     choices=["", "box_drop", "granular_bed", "mass_ratio_chain", "spring_net", "block_pile"],
                     help="run only this one of the single-scene legs (for profiling it alone)")

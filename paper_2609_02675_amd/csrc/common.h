@@ -118,9 +118,9 @@ struct View {
   SceneDev* scenes;
   int* health;  // per scene: bit0 non-finite, bit1 contact overflow
   double* rho;  // per scene: residual of the last iteration of the last step
-  // per scene, 2 each: local steps whose rotation came from the SVD, and those
+  // per body, 2 each: local steps whose rotation came from the SVD, and those
   // whose input had det <= 0
-  unsigned long long* polar;
+  unsigned* polar;
 };
 
 // ---- vector load/store of packed records --------------------------------------

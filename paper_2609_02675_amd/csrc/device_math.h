@@ -302,27 +302,31 @@ __device__ __forceinline__ int polar_finish(T* X, bool ok) {
   return how;
 }
 
-// per-scene counts of the local step's fallback: [0] rotations from the SVD,
-// [1] those whose input had det <= 0
-__device__ __forceinline__ void count_polar(unsigned long long* cnt, int how) {
-  if (!cnt) return;
-  if (how & 1) atomicAdd(cnt, 1ull);
-  if (how & 2) atomicAdd(cnt + 1, 1ull);
+// per-body counts of the local step's fallback, 2 per body from `counts`:
+// [0] rotations from the SVD, [1] those whose input had det <= 0.  Each body
+// is advanced by one lane, which owns its counters, so no atomics; the address
+// is formed here, in the rare path, so that callers keep no pointer live
+// through the common one.
+__device__ __forceinline__ void count_polar(unsigned* counts, int body, int how) {
+  if (!counts || !how) return;
+  unsigned* cnt = counts + 2 * (size_t)body;
+  cnt[0] += (unsigned)(how & 1);
+  cnt[1] += (unsigned)((how >> 1) & 1);
 }
 
 template <typename T>
-__device__ __forceinline__ void polar_rotation_inplace(T* X, unsigned long long* cnt) {
+__device__ __forceinline__ void polar_rotation_inplace(T* X, unsigned* counts, int body) {
   bool ok;
   const bool done = polar_fast(X, &ok);
   if (wave_any(!done))
-    if (!done) count_polar(cnt, polar_finish(X, ok));
+    if (!done) count_polar(counts, body, polar_finish(X, ok));
 }
 
 // The same for a caller short of registers: around the rare continuation X
 // goes through the lane's own 9 words `spill` of LDS, so that the compiler need
 // not keep a second copy of X in registers beside the continuation's own.
 template <typename T>
-__device__ __forceinline__ void polar_rotation_spill(T* X, T* spill, unsigned long long* cnt) {
+__device__ __forceinline__ void polar_rotation_spill(T* X, T* spill, unsigned* counts, int body) {
   bool ok;
   const bool done = polar_fast(X, &ok);
   // spill word w holds X[(w + 1) % 9]: X[1..8] in two 16-byte groups, which
@@ -335,7 +339,7 @@ __device__ __forceinline__ void polar_rotation_spill(T* X, T* spill, unsigned lo
       T Y[9];
 #pragma unroll
       for (int k = 0; k < 9; ++k) Y[k] = spill[(k + 8) % 9];
-      count_polar(cnt, polar_finish(Y, ok));
+      count_polar(counts, body, polar_finish(Y, ok));
 #pragma unroll
       for (int k = 0; k < 9; ++k) spill[(k + 8) % 9] = Y[k];
     }
@@ -346,10 +350,10 @@ __device__ __forceinline__ void polar_rotation_spill(T* X, T* spill, unsigned lo
 }
 
 template <typename T>
-__device__ __forceinline__ void polar_rotation(const T* A, T* R, unsigned long long* cnt) {
+__device__ __forceinline__ void polar_rotation(const T* A, T* R, unsigned* counts, int body) {
 #pragma unroll
   for (int k = 0; k < 9; ++k) R[k] = A[k];
-  polar_rotation_inplace(R, cnt);
+  polar_rotation_inplace(R, counts, body);
 }
 
 // ---- prediction (Algorithm 1, prediction loop) ---------------------------------

@@ -115,7 +115,7 @@ struct Engine {
   SceneDev* scenes = nullptr;
   int* health = nullptr;
   double* rho = nullptr;
-  unsigned long long* polar = nullptr;  // 2 per scene (View::polar)
+  unsigned* polar = nullptr;  // 2 per body (View::polar)
   double* planes = nullptr;
   // driven bonds
   int *drv_scene = nullptr, *drv_end_i = nullptr, *drv_end_j = nullptr;
@@ -246,7 +246,7 @@ struct Engine {
     PABD_TRY(alloc(ccount, n));
     PABD_TRY(alloc(scenes, (size_t)c.s));
     PABD_TRY(alloc(health, (size_t)c.s));
-    PABD_TRY(alloc(polar, 2 * (size_t)c.s));
+    PABD_TRY(alloc(polar, 2 * n));
     PABD_TRY(alloc(rho, (size_t)c.s));
     PABD_TRY(alloc(reach, (size_t)c.s));
     PABD_TRY(alloc(planes, 4 * (size_t)c.p));
@@ -292,8 +292,8 @@ struct Engine {
     PABD_HIP(hipMemcpy(health, zero.data(), (size_t)c.s * sizeof(int), hipMemcpyHostToDevice));
     std::vector<double> rz((size_t)c.s, 0.0);
     PABD_HIP(hipMemcpy(rho, rz.data(), rz.size() * sizeof(double), hipMemcpyHostToDevice));
-    std::vector<unsigned long long> zero64(2 * (size_t)c.s, 0ull);
-    PABD_HIP(hipMemcpy(polar, zero64.data(), zero64.size() * sizeof(unsigned long long), hipMemcpyHostToDevice));
+    std::vector<unsigned> zero2n(2 * n, 0u);
+    PABD_HIP(hipMemcpy(polar, zero2n.data(), zero2n.size() * sizeof(unsigned), hipMemcpyHostToDevice));
     std::vector<int> dneg(std::max(1, c.dr), -1);
     PABD_HIP(hipMemcpy(drv_scene, dneg.data(), dneg.size() * sizeof(int), hipMemcpyHostToDevice));
     std::vector<double> dz(n, 0.0);
@@ -405,8 +405,8 @@ struct Engine {
     add(scenes + sidx, &S, 1);
     int zero = 0;
     add(health + sidx, &zero, 1);
-    const unsigned long long zero2[2] = {0ull, 0ull};
-    add(polar + 2 * (size_t)sidx, zero2, 2);
+    std::vector<unsigned> zero_polar(2 * n, 0u);
+    add(polar + 2 * (size_t)boff, zero_polar.data(), zero_polar.size());
     const double rho0 = 0.0;  // no step taken yet
     add(rho + sidx, &rho0, 1);
     const size_t nd = hs.drv_end_i.size();

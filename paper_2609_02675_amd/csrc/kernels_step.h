@@ -349,7 +349,7 @@ __device__ __forceinline__ void iterate_body(const View<T>& v, int k, double* rh
 #pragma unroll
     for (int c = 0; c < 9; ++c) qo[3 + c] = Ah[c];
   } else {
-    polar_rotation(Ah, qo + 3, v.polar + 2 * (size_t)sc);
+    polar_rotation(Ah, qo + 3, v.polar, i);
   }
   store<T, QR>(qd + (size_t)QR * i, qo);
   if (k == K - 1 || rh_num) {
@@ -366,8 +366,11 @@ __device__ __forceinline__ void iterate_body(const View<T>& v, int k, double* rh
   }
 }
 
+// occupancy: at least four waves per SIMD in FP32 (at most 128 registers), two
+// in FP64; the iteration waits on loads of its partners and contact records,
+// so resident waves matter more than the few registers of its rare paths
 template <typename T, bool CONTACT, int LPB>
-__global__ void __launch_bounds__(256) k_iterate(View<T> v, int k, double* rh_num, double* rh_den) {
+__global__ void __launch_bounds__(256, sizeof(T) == 4 ? 4 : 2) k_iterate(View<T> v, int k, double* rh_num, double* rh_den) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const int i = (int)(t / LPB), sub = (int)(t % LPB);
   if (i >= v.n) return;
@@ -384,7 +387,7 @@ struct FlatWave {
 };
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_iterate_waves(View<T> v, int k, const FlatWave* waves,
+__global__ void __launch_bounds__(256, sizeof(T) == 4 ? 4 : 2) k_iterate_waves(View<T> v, int k, const FlatWave* waves,
                                                        const int* n_waves) {
   const int w = (int)((blockIdx.x * (long long)blockDim.x + threadIdx.x) / 64);
   const int l = (int)(threadIdx.x & 63);

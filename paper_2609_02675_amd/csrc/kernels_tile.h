@@ -255,7 +255,7 @@ __global__ void __launch_bounds__(TB, sizeof(T) == 4 ? 3 : 1) k_tile_step(View<T
           // the rare polar continuation passes X through this lane's words of
           // the other q buffer, which no lane reads before the next iteration
           // has rewritten them
-          polar_rotation_spill(q + 3, lq[(k + 1) & 1] + L::rest(TB, lane), v.polar + 2 * (size_t)scn);
+          polar_rotation_spill(q + 3, lq[(k + 1) & 1] + L::rest(TB, lane), v.polar, i);
           if (last) {
             T dd[QW];
 #pragma unroll

@@ -62,7 +62,7 @@ struct EngineBase {
   // raw pointers used by the API layer
   virtual SceneDev* scene_table() = 0;
   virtual int* health_ptr() = 0;
-  virtual unsigned long long* polar_ptr() = 0;
+  virtual unsigned* polar_ptr() = 0;
   virtual double* rho_ptr() = 0;
   virtual double** history(int* k) = 0;
   virtual pabd_status alloc_history(int K) = 0;
@@ -168,7 +168,7 @@ struct EngineT final : EngineBase {
   int type_size() const override { return (int)sizeof(T); }
   SceneDev* scene_table() override { return e.scenes; }
   int* health_ptr() override { return e.health; }
-  unsigned long long* polar_ptr() override { return e.polar; }
+  unsigned* polar_ptr() override { return e.polar; }
   double* rho_ptr() override { return e.rho; }
   double** history(int* k) override {
     *k = e.rh_k;
@@ -421,10 +421,15 @@ pabd_status pabd_scene_residual(const pabd_scene* s, double* rho_last) {
 pabd_status pabd_scene_polar_fallbacks(const pabd_scene* s, int64_t* svd, int64_t* det_nonpositive) {
   if (!s) return fail(PABD_E_INVALID, "null scene");
   API_HIP(hipDeviceSynchronize());
-  unsigned long long c[2] = {0ull, 0ull};
-  API_HIP(hipMemcpy(c, s->eng->polar_ptr(), sizeof c, hipMemcpyDeviceToHost));
-  if (svd) *svd = (int64_t)c[0];
-  if (det_nonpositive) *det_nonpositive = (int64_t)c[1];
+  std::vector<unsigned> c(2 * (size_t)std::max(1, s->hs.n), 0u);
+  API_HIP(hipMemcpy(c.data(), s->eng->polar_ptr(), c.size() * sizeof(unsigned), hipMemcpyDeviceToHost));
+  int64_t a = 0, d = 0;
+  for (size_t k = 0; k < c.size(); k += 2) {
+    a += c[k];
+    d += c[k + 1];
+  }
+  if (svd) *svd = a;
+  if (det_nonpositive) *det_nonpositive = d;
   return PABD_OK;
 }
 
@@ -892,12 +897,31 @@ pabd_status pabd_batch_create(int32_t max_slots, size_t hbm_budget, int32_t prec
   // items), so that every scene whose pabd_scene_bytes fits the budget fits an
   // empty batch; the device memory is then at most about four budgets, while
   // admission keeps the resident scenes' bytes within one
+  // (scaled down together when that would exceed 85 % of the device's free memory)
   const size_t lim = (size_t)1 << 28;
-  const size_t n_stream = std::min(lim, std::max<size_t>(1024, hbm_budget / (body_cost(ts) + contact_body_cost())));
+  const size_t fb = body_cost(ts) + contact_body_cost();
+  size_t n_stream = std::min(lim, std::max<size_t>(1024, hbm_budget / fb));
   size_t n_tiled = std::min(lim, std::max<size_t>(1024, hbm_budget / body_cost(ts)));
+  size_t n_ends = std::min(lim, std::max<size_t>(4096, hbm_budget / end_cost(ts)));
+  size_t n_slots = std::min(lim, std::max<size_t>(65536, hbm_budget / contact_cost(ts)));
+  {
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && free_b > 0) {
+      const double want = (double)n_stream * fb + (double)n_tiled * body_cost(ts) +
+                          (double)n_ends * end_cost(ts) + (double)n_slots * contact_cost(ts);
+      const double room = 0.85 * (double)free_b;
+      if (want > room) {
+        const double f = room / want;
+        n_stream = std::max<size_t>(1024, (size_t)(n_stream * f));
+        n_tiled = std::max<size_t>(1024, (size_t)(n_tiled * f));
+        n_ends = std::max<size_t>(4096, (size_t)(n_ends * f));
+        n_slots = std::max<size_t>(65536, (size_t)(n_slots * f));
+      }
+    } else {
+      (void)hipGetLastError();
+    }
+  }
   n_tiled = (n_tiled + 255) / 256 * 256;
-  const size_t n_ends = std::min(lim, std::max<size_t>(4096, hbm_budget / end_cost(ts)));
-  const size_t n_slots = std::min(lim, std::max<size_t>(65536, hbm_budget / contact_cost(ts)));
   b->n_stream = (int)n_stream;
   b->caps.n = (int)(n_stream + n_tiled);
   b->caps.e = (int)n_ends;
@@ -1137,10 +1161,17 @@ pabd_status pabd_batch_polar_fallbacks(pabd_batch* b, int32_t slot, int64_t* svd
   if (!b) return fail(PABD_E_INVALID, "null batch");
   if (slot < 0 || slot >= b->max_slots || !b->slots[slot].used) return fail(PABD_E_NOTFOUND, "slot not in use");
   API_HIP(hipDeviceSynchronize());
-  unsigned long long c[2] = {0ull, 0ull};
-  API_HIP(hipMemcpy(c, b->eng->polar_ptr() + 2 * (size_t)slot, sizeof c, hipMemcpyDeviceToHost));
-  if (svd) *svd = (int64_t)c[0];
-  if (det_nonpositive) *det_nonpositive = (int64_t)c[1];
+  const Slot& s = b->slots[slot];
+  std::vector<unsigned> c(2 * (size_t)std::max(1, s.n), 0u);
+  API_HIP(hipMemcpy(c.data(), b->eng->polar_ptr() + 2 * (size_t)s.boff, c.size() * sizeof(unsigned),
+                    hipMemcpyDeviceToHost));
+  int64_t a = 0, d = 0;
+  for (size_t k = 0; k < c.size(); k += 2) {
+    a += c[k];
+    d += c[k + 1];
+  }
+  if (svd) *svd = a;
+  if (det_nonpositive) *det_nonpositive = d;
   return PABD_OK;
 }
 
