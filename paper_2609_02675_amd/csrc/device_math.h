@@ -15,23 +15,24 @@ namespace pabd {
 
 template <typename T>
 struct Eps;
-// polar_tol2: squared Newton step below which the polar iteration ends (the
-// error left is below polar_tol2 / 2); polar_one / polar_two: first-step sizes
-// up to which one / two further unchecked steps leave that same error
-// (2 sqrt(tol) and (64 tol)^(1/4), rounded down)
+// polar_tol2: squared Newton step below which the measured continuation of the
+// polar iteration ends (the error left is below polar_tol2 / 2); polar_e_one /
+// polar_e_two: det X_1 - 1 after the first step up to which one / two further
+// steps leave that same error (sqrt(tol) and (4 tol)^(1/4), rounded down for the
+// rounding of the determinant)
 template <>
 struct Eps<float> {
   static constexpr float polar_tol2 = 1e-7f;
-  static constexpr float polar_one = 6.0e-4f;
-  static constexpr float polar_two = 4.5e-2f;
   static constexpr float det_floor = 1e-6f;
+  static constexpr float polar_e_one = 3.1e-4f;
+  static constexpr float polar_e_two = 2.5e-2f;
 };
 template <>
 struct Eps<double> {
   static constexpr double polar_tol2 = 1e-16;
-  static constexpr double polar_one = 1.9e-8;
-  static constexpr double polar_two = 2.7e-4;
   static constexpr double det_floor = 1e-12;
+  static constexpr double polar_e_one = 0.99e-8;
+  static constexpr double polar_e_two = 1.4e-4;
 };
 
 template <typename T>
@@ -228,44 +229,48 @@ __device__ __forceinline__ bool wave_any(bool p) { return __builtin_amdgcn_ballo
 
 // Rotation factor of the polar decomposition (local step, Sec. 4.2.2), in place:
 // X <- R where X = R S.  Newton's iteration acts on each singular value alone,
-// s <- (s + 1/s) / 2, so with e = s - 1 a step moves s by |s^2 - 1| / (2 s) and
-// leaves e' = (s - 1)^2 / (2 s), at most half the square of that move, and each
-// later move is at most the e it starts from.  Hence for Frobenius norms: the
-// error left after a step of squared size D is at most D / 2, and the next
-// step's squared size is at most D^2 / 4.  The first step is measured: below
-// polar_tol2 the iteration ends; below polar_one (polar_two) one (two) further
-// steps leave an error below polar_tol2 / 2 without being measured; otherwise
-// measured steps continue.  Every Newton iterate has the input's orthogonal
+// s <- (s + 1/s) / 2 (or (zeta s + 1/(zeta s)) / 2 with a scaling zeta), which
+// is at least 1: after the first step every singular value is s_i = 1 + e_i
+// with e_i >= 0, so e = det X_1 - 1 = prod (1 + e_i) - 1 >= sum e_i bounds the
+// Frobenius error |X_1 - R|.  A further step leaves e_i^2 / (2 (1 + e_i)) per
+// singular value, so at most e^2 / 2 in all, and a third e^4 / 8.  The first
+// step is not measured; the second takes det X_1 from the cofactors it needs
+// anyway, and with the error target tau / 2 (tau = polar_tol2) it ends the
+// iteration when e <= polar_e_one (e^2 / 2 < tau / 2), adds a third step when
+// e <= polar_e_two (e^4 / 8 < tau / 2), and otherwise hands the lane to the
+// measured continuation.  Every Newton iterate has the input's orthogonal
 // factor, so if det X is not safely positive or Newton stalls, the nearest
 // proper rotation from the SVD of the current iterate is the answer.
 template <typename T>
 __device__ __forceinline__ bool polar_fast(T* X, bool* ok_out) {
-  // the measured first step, on Y = X (sigma = 1); |X' - X| = |zeta Y' / 2 - Y|
+  // first step, not measured: Y = X + g C(X) and sigma = zeta / 2, so that the
+  // Newton iterate is X_1 = sigma Y
   T C[9];
   const T det = cofactor(X, C);
   const bool ok = det > Eps<T>::det_floor;
   const bool unscaled = det > (T)0.5 && det < (T)1.5;
   const T zeta = unscaled || !ok ? (T)1 : rcp(cbrt(det));
   const T g = ok ? rcp(zeta * zeta * det) : (T)0;
-  const T hz = ok ? (T)0.5 * zeta : (T)1;
-  T d2 = 0;
+  T sigma = ok ? (T)0.5 * zeta : (T)1;
 #pragma unroll
-  for (int k = 0; k < 9; ++k) {
-    const T y = fma(g, C[k], X[k]);
-    const T t = fma(hz, y, -X[k]);
-    d2 = fma(t, t, d2);
-    X[k] = y;
-  }
-  T sigma = hz;
-  const bool conv = ok && d2 < Eps<T>::polar_tol2;
-  const bool one = ok && !conv && unscaled && d2 <= Eps<T>::polar_two;
-  const bool two = one && d2 > Eps<T>::polar_one;
-  polar_newton_plain<T>(X, &sigma, one);
+  for (int k = 0; k < 9; ++k) X[k] = fma(g, C[k], X[k]);
+  // second step, measured by the determinant: a Newton step maps every singular
+  // value s to (s + 1/s) / 2 >= 1, so e = det X_1 - 1 >= sum (s_i - 1) bounds
+  // |X_1 - R|_F, the second step leaves at most e^2 / 2 and a third e^4 / 8
+  T C1[9];
+  const T det1 = cofactor(X, C1);
+  const T e = fma(sigma * sigma * sigma, det1, (T)-1);
+  const bool one = ok && unscaled && e <= Eps<T>::polar_e_one;
+  const bool two = ok && unscaled && !one && e <= Eps<T>::polar_e_two;
+  const T g1 = one || two ? rcp(sigma * sigma * det1) : (T)0;
+  sigma = one || two ? (T)0.5 * sigma : sigma;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) X[k] = fma(g1, C1[k], X[k]);
   if (wave_any(two)) polar_newton_plain<T>(X, &sigma, two);
 #pragma unroll
   for (int k = 0; k < 9; ++k) X[k] *= sigma;
   *ok_out = ok;
-  return conv || one;
+  return one || two;
 }
 
 // The rest for a lane whose first step was too large: measured steps while det X
@@ -441,6 +446,26 @@ __device__ __forceinline__ void block_apply(const F* f, const T* r, T* dq) {
     dq[3 + 3 * k + 0] = -g0 * r[k] + G00 * ra[0] + G01 * ra[1] + G02 * ra[2];
     dq[3 + 3 * k + 1] = -g1 * r[k] + G01 * ra[0] + G11 * ra[1] + G12 * ra[2];
     dq[3 + 3 * k + 2] = -g2 * r[k] + G02 * ra[0] + G12 * ra[1] + G22 * ra[2];
+  }
+}
+
+// q^{k+1/2} = q^k + H^{-1} r in place: each entry one fused chain that starts
+// from its own value (in FP32 the low position word, which carries the
+// displacement within the step), so the increment is never formed apart
+template <typename T, typename F>
+__device__ __forceinline__ void block_apply_add(const F* f, const T* r, T* q) {
+  constexpr int L = sizeof(T) == 4 ? 12 : 0;
+  const T al = (T)f[0], g0 = (T)f[1], g1 = (T)f[2], g2 = (T)f[3];
+  const T G00 = (T)f[4], G01 = (T)f[5], G02 = (T)f[6], G11 = (T)f[7], G12 = (T)f[8],
+          G22 = (T)f[9];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const T* ra = r + 3 + 3 * k;
+    q[L + k] = fma(al, r[k], fma(-g2, ra[2], fma(-g1, ra[1], fma(-g0, ra[0], q[L + k]))));
+    T* a = q + 3 + 3 * k;
+    a[0] = fma(G02, ra[2], fma(G01, ra[1], fma(G00, ra[0], fma(-g0, r[k], a[0]))));
+    a[1] = fma(G12, ra[2], fma(G11, ra[1], fma(G01, ra[0], fma(-g1, r[k], a[1]))));
+    a[2] = fma(G22, ra[2], fma(G12, ra[1], fma(G02, ra[0], fma(-g2, r[k], a[2]))));
   }
 }
 

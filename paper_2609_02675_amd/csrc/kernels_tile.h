@@ -236,22 +236,20 @@ __global__ void __launch_bounds__(TB, sizeof(T) == 4 ? 3 : 1) k_tile_step(View<T
             quad_end_force(Eg, d, f);
             add_JT(r, Eg, f[0], f[1], f[2]);
           }
-          T dq[QW];
-          block_apply(fac, r, dq);
           // q^{k+1} in place; a lane's last iteration keeps what its residual
-          // |q^{k+1} - q^k|_M / |q^k|_M needs (the position part of the
-          // difference is the increment itself)
+          // |q^{k+1} - q^k|_M / |q^k|_M needs
           const bool last = k == K - 1;
-          T Aold[9];
+          constexpr int LO = sizeof(T) == 4 ? 12 : 0;
+          T Aold[9], cold[3];
           if (last) {
             const T cc[3] = {(T)pos_value(q, 0), (T)pos_value(q, 1), (T)pos_value(q, 2)};
             den = m_norm2(m, cc, q);
 #pragma unroll
             for (int c = 0; c < 9; ++c) Aold[c] = q[3 + c];
-          }
-          pos_add_lo(q, dq[0], dq[1], dq[2]);
 #pragma unroll
-          for (int c = 0; c < 9; ++c) q[3 + c] += dq[3 + c];
+            for (int c = 0; c < 3; ++c) cold[c] = q[LO + c];
+          }
+          block_apply_add(fac, r, q);
           // the rare polar continuation passes X through this lane's words of
           // the other q buffer, which no lane reads before the next iteration
           // has rewritten them
@@ -259,7 +257,7 @@ __global__ void __launch_bounds__(TB, sizeof(T) == 4 ? 3 : 1) k_tile_step(View<T
           if (last) {
             T dd[QW];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) dd[c] = dq[c];
+            for (int c = 0; c < 3; ++c) dd[c] = q[LO + c] - cold[c];
 #pragma unroll
             for (int c = 0; c < 9; ++c) dd[3 + c] = q[3 + c] - Aold[c];
             num = m_norm2(m, dd, dd);
