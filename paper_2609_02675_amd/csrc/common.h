@@ -59,6 +59,8 @@ struct SceneDev {
   int tiled;        // advanced by the tile kernel (which also reduces its residual)
   int ce_off;       // first contact slot of the scene: body b of the scene owns
                     // slots ce_off + (b - body_off) * ccap ... + ccap - 1
+  int resident;     // advanced by the resident step kernel (whole steps from LDS)
+  int pad;
 };
 
 // first contact slot of body i of scene S

@@ -14,6 +14,7 @@
 
 #include "host_scene.h"
 #include "kernels_contact.h"
+#include "kernels_resident.h"
 #include "kernels_step.h"
 #include "kernels_tile.h"
 
@@ -123,6 +124,10 @@ struct Engine {
   // residual history (optional)
   double *rh_num = nullptr, *rh_den = nullptr, *rh_rho = nullptr;
   int rh_k = 0;
+  // scenes run by the resident step kernel: [0] contact scenes (four lanes per
+  // body), [1] the others; capacity one entry per scene slot, counts on the device
+  int* res_list[2] = {nullptr, nullptr};
+  int* res_count = nullptr;
 
   std::vector<void*> allocs;
   std::string err;
@@ -254,6 +259,9 @@ struct Engine {
     PABD_TRY(alloc(drv_end_i, (size_t)c.dr));
     PABD_TRY(alloc(drv_end_j, (size_t)c.dr));
     PABD_TRY(alloc(drv_param, 13 * (size_t)c.dr));
+    PABD_TRY(alloc(res_list[0], (size_t)c.s));
+    PABD_TRY(alloc(res_list[1], (size_t)c.s));
+    PABD_TRY(alloc(res_count, 2));
     if (c.contacts) {
       ncb = c.nc < 0 ? c.n : std::min(c.nc, c.n);
       const size_t nb = (size_t)ncb, nc = (size_t)std::max(1LL, c.cslots);
@@ -290,6 +298,8 @@ struct Engine {
     PABD_HIP(hipMemcpy(srow_end, zero.data(), n * sizeof(int), hipMemcpyHostToDevice));
     PABD_HIP(hipMemcpy(ccount, zero.data(), n * sizeof(int), hipMemcpyHostToDevice));
     PABD_HIP(hipMemcpy(health, zero.data(), (size_t)c.s * sizeof(int), hipMemcpyHostToDevice));
+    const int zero_counts[2] = {0, 0};
+    PABD_HIP(hipMemcpy(res_count, zero_counts, sizeof zero_counts, hipMemcpyHostToDevice));
     std::vector<double> rz((size_t)c.s, 0.0);
     PABD_HIP(hipMemcpy(rho, rz.data(), rz.size() * sizeof(double), hipMemcpyHostToDevice));
     std::vector<unsigned> zero2n(2 * n, 0u);
@@ -466,6 +476,28 @@ struct Engine {
     hipLaunchKernelGGL(k_sort_contacts<T>, dim3((unsigned)std::max(1, n)), dim3(64), 0, st, v);
   }
 
+  // the scene slots the resident step kernel runs: [0] contact scenes, [1] others
+  pabd_status set_resident(const std::vector<int>& contact, const std::vector<int>& other, hipStream_t st) {
+    const int counts[2] = {(int)contact.size(), (int)other.size()};
+    if (counts[0]) PABD_HIP(hipMemcpyAsync(res_list[0], contact.data(), counts[0] * sizeof(int), hipMemcpyHostToDevice, st));
+    if (counts[1]) PABD_HIP(hipMemcpyAsync(res_list[1], other.data(), counts[1] * sizeof(int), hipMemcpyHostToDevice, st));
+    PABD_HIP(hipMemcpyAsync(res_count, counts, sizeof counts, hipMemcpyHostToDevice, st));
+    PABD_HIP(hipStreamSynchronize(st));
+    return PABD_OK;
+  }
+
+  // one step of the resident scenes: grid[0] workgroups over the contact list,
+  // grid[1] over the other (extents rounded by the caller; extra workgroups leave)
+  void launch_resident(const int* grid, hipStream_t st) {
+    View<T> v = view();
+    if (grid[0] > 0)
+      hipLaunchKernelGGL((k_resident_step<T, 4, true>), dim3(grid[0]), dim3(Resident<T>::NT), 0, st, v,
+                         (const int*)res_list[0], (const int*)res_count);
+    if (grid[1] > 0)
+      hipLaunchKernelGGL((k_resident_step<T, 1, false>), dim3(grid[1]), dim3(Resident<T>::NT), 0, st, v,
+                         (const int*)res_list[1], (const int*)(res_count + 1));
+  }
+
   // FP64 block factorisation of bodies [first, first + count)
   void launch_factor(hipStream_t st, int first = 0, int count = -1) {
     if (count < 0) count = cap.n;
@@ -477,9 +509,14 @@ struct Engine {
   // One step of Algorithm 1 with flat per-body kernels (one launch per iteration).
   // With a wave table (batches), the iterations run over it instead: four lanes
   // per body of a contact scene, one per body of any other scene.
+  //
+  // resident_grid (optional): the scenes of the resident lists take their whole
+  // step in the resident kernel, after the contact construction; with
+  // flat = false no flat-path kernel is launched (every flat scene is resident).
   void launch_flat_step(int n_scenes, int kmax, bool contacts, int n_driven, bool history,
                         bool finish_scenes, hipStream_t st, const FlatWave* waves = nullptr,
-                        const int* n_waves = nullptr, int wave_grid = 0) {
+                        const int* n_waves = nullptr, int wave_grid = 0,
+                        const int* resident_grid = nullptr, bool flat = true) {
     View<T> v = view();
     const dim3 g = grid_for(cap.n, 256), b(256);
     if (n_driven > 0) {
@@ -489,6 +526,8 @@ struct Engine {
       launch_factor(st);
     }
     if (contacts) launch_contacts(n_scenes, st);
+    if (resident_grid) launch_resident(resident_grid, st);
+    if (!flat) return;
     hipLaunchKernelGGL(k_predict<T>, g, b, 0, st, v);
     double* hn = history ? rh_num : nullptr;
     double* hd = history ? rh_den : nullptr;

@@ -27,7 +27,7 @@ __global__ void __launch_bounds__(256) k_predict(View<T> v) {
   if (sc < 0) return;
   T q[QR];
   load<T, QR>(v.qn + (size_t)QR * i, q);
-  if (v.scenes[sc].step >= v.scenes[sc].steps_total) return;
+  if (v.scenes[sc].step >= v.scenes[sc].steps_total || v.scenes[sc].resident) return;
   if (v.flags[i] & F_PINNED) {
     store<T, QR>(v.q[0] + (size_t)QR * i, q);
     store<T, QR>(v.q[1] + (size_t)QR * i, q);
@@ -225,19 +225,24 @@ __device__ __forceinline__ U lane_sum(U x) {
 // static bond ends and contact ends (lane l takes ends l, l + LPB, ...), sum the
 // force terms and the contact change of the FP64 block across the lanes, and the
 // first lane solves, projects and stores.
-template <typename T, bool CONTACT, int LPB>
+//
+// q^k is read from qs and q^{k+1} written to qd, the record of body b at
+// (b - qoff) QR: the double-buffered global arrays with qoff = 0 for the flat
+// kernels, the scene's LDS buffers with qoff = its first body for the resident
+// step.  A body runs in the kernel family that its scene's `resident` flag
+// names, so the two never both advance it.
+template <typename T, bool CONTACT, int LPB, bool RESIDENT = false>
 __device__ __forceinline__ void iterate_body(const View<T>& v, int k, double* rh_num, double* rh_den,
-                                             int i, int sub) {
+                                             int i, int sub, const T* qs, T* qd, int qoff) {
   constexpr int QR = Rec<T>::Q;
   const int sc = v.bscene[i];
   if (sc < 0 || (v.flags[i] & F_PINNED)) return;
   const SceneDev& S = v.scenes[sc];
+  if ((S.resident != 0) != RESIDENT) return;
   const int K = S.iters;
   if (k >= K || S.step >= S.steps_total) return;
-  const T* qs = v.q[k & 1];
-  T* qd = v.q[(k + 1) & 1];
   T q[QR];
-  load<T, QR>(qs + (size_t)QR * i, q);
+  load<T, QR>(qs + (size_t)QR * (i - qoff), q);
   T rb[QW];
 #pragma unroll
   for (int c = 0; c < QW; ++c) rb[c] = (T)0;
@@ -255,7 +260,7 @@ __device__ __forceinline__ void iterate_body(const View<T>& v, int k, double* rh
       bond_vec<T>(q, E, nullptr, E + 4, d);
     } else {
       T qj[QR];
-      load<T, QR>(qs + (size_t)QR * j, qj);
+      load<T, QR>(qs + (size_t)QR * (j - qoff), qj);
       bond_vec<T>(q, E, qj, E + 4, d);
     }
     T* a = var ? v.al + 4 * (size_t)e : nullptr;
@@ -292,8 +297,8 @@ __device__ __forceinline__ void iterate_body(const View<T>& v, int k, double* rh
       T Ca[CW], Cb[CW], qa[QR], qb[QR];
       load<T, CW>(v.ce + (size_t)CW * (base + c), Ca);
       if (hb) load<T, CW>(v.ce + (size_t)CW * (base + cb), Cb);
-      if (ja >= 0) load<T, QR>(qs + (size_t)QR * ja, qa);
-      if (jb >= 0) load<T, QR>(qs + (size_t)QR * jb, qb);
+      if (ja >= 0) load<T, QR>(qs + (size_t)QR * (ja - qoff), qa);
+      if (jb >= 0) load<T, QR>(qs + (size_t)QR * (jb - qoff), qb);
       contact_end(Ca, ja, qa);
       if (hb) contact_end(Cb, jb, qb);
     }
@@ -351,7 +356,7 @@ __device__ __forceinline__ void iterate_body(const View<T>& v, int k, double* rh
   } else {
     polar_rotation(Ah, qo + 3, v.polar, i);
   }
-  store<T, QR>(qd + (size_t)QR * i, qo);
+  store<T, QR>(qd + (size_t)QR * (i - qoff), qo);
   if (k == K - 1 || rh_num) {
     double num, den;
     residual_terms(m, qo, q, &num, &den);
@@ -374,7 +379,7 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 4 : 2) k_iterate(View<T>
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const int i = (int)(t / LPB), sub = (int)(t % LPB);
   if (i >= v.n) return;
-  iterate_body<T, CONTACT, LPB>(v, k, rh_num, rh_den, i, sub);
+  iterate_body<T, CONTACT, LPB>(v, k, rh_num, rh_den, i, sub, v.q[k & 1], v.q[(k + 1) & 1], 0);
 }
 
 // The same iteration over a table of wavefronts (first body, bodies, lanes per
@@ -395,10 +400,10 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 4 : 2) k_iterate_waves(V
   const FlatWave fw = waves[w];
   if (fw.lpb == 4) {
     if (l / 4 >= fw.count) return;
-    iterate_body<T, true, 4>(v, k, nullptr, nullptr, fw.first + l / 4, l % 4);
+    iterate_body<T, true, 4>(v, k, nullptr, nullptr, fw.first + l / 4, l % 4, v.q[k & 1], v.q[(k + 1) & 1], 0);
   } else {
     if (l >= fw.count) return;
-    iterate_body<T, false, 1>(v, k, nullptr, nullptr, fw.first + l, 0);
+    iterate_body<T, false, 1>(v, k, nullptr, nullptr, fw.first + l, 0, v.q[k & 1], v.q[(k + 1) & 1], 0);
   }
 }
 
@@ -433,7 +438,7 @@ __global__ void __launch_bounds__(256) k_finish(View<T> v) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= v.n) return;
   const int sc = v.bscene[i];
-  if (sc < 0) return;
+  if (sc < 0 || v.scenes[sc].resident) return;
   if (v.flags[i] & F_PINNED) {
     v.r_num[i] = 0.0;
     v.r_den[i] = 0.0;
@@ -467,7 +472,7 @@ __global__ void __launch_bounds__(RED_THREADS) k_reduce_residual(const SceneDev*
   __shared__ double sn[RED_THREADS], sd[RED_THREADS];
   const int sc = blockIdx.x;
   if (sc >= n_scenes) return;
-  if (scenes[sc].tiled) return;  // the tile kernel reduces its own scenes
+  if (scenes[sc].tiled || scenes[sc].resident) return;  // those kernels reduce their own scenes
   const int off = scenes[sc].body_off, nb = scenes[sc].n_bodies;
   // each thread sums a fixed stride of the scene's bodies in order; the unrolled
   // loop keeps several loads in flight
@@ -565,7 +570,7 @@ __global__ void k_update_driven(View<T> v, int n_driven, const int* d_scene, con
 
 __global__ void k_end_step(SceneDev* scenes, int n_scenes) {
   const int sc = blockIdx.x * blockDim.x + threadIdx.x;
-  if (sc < n_scenes && !scenes[sc].tiled && scenes[sc].step < scenes[sc].steps_total)
+  if (sc < n_scenes && !scenes[sc].tiled && !scenes[sc].resident && scenes[sc].step < scenes[sc].steps_total)
     scenes[sc].step += 1;
 }
 

@@ -50,7 +50,14 @@ struct EngineBase {
   virtual void flat_step(int first, int n, int n_scenes, int kmax, bool contacts, int n_driven,
                          bool history, bool finish_scenes, hipStream_t st,
                          const FlatWave* waves = nullptr, const int* n_waves = nullptr,
-                         int wave_grid = 0) = 0;
+                         int wave_grid = 0, const int* resident_grid = nullptr, bool flat = true) = 0;
+  virtual pabd_status set_resident(const std::vector<int>& contact, const std::vector<int>& other,
+                                   hipStream_t st) = 0;
+  // the most bodies a scene run by the resident step kernel may have: those
+  // that one pass of the workgroup covers (a contact scene's bodies take four
+  // lanes each); larger scenes wait on their partners' loads pass after pass
+  // there, and run faster on the flat path, spread over many compute units
+  virtual int resident_max(bool contact) const = 0;
   virtual void tile_step(int tile_bodies, const TileTable& tt, int grid, int nsteps,
                          hipStream_t st) = 0;
   virtual void finish_scenes(int n_scenes, hipStream_t st) = 0;
@@ -93,13 +100,19 @@ struct EngineT final : EngineBase {
   void factor(hipStream_t st, int first, int count) override { e.launch_factor(st, first, count); }
   void flat_step(int first, int n, int n_scenes, int kmax, bool contacts, int n_driven, bool history,
                  bool fin, hipStream_t st, const FlatWave* waves, const int* n_waves,
-                 int wave_grid) override {
+                 int wave_grid, const int* resident_grid, bool flat) override {
     (void)first;
     const int saved = e.cap.n;
     e.cap.n = n;  // flat kernels cover bodies [0, n)
-    e.launch_flat_step(n_scenes, kmax, contacts, n_driven, history, fin, st, waves, n_waves, wave_grid);
+    e.launch_flat_step(n_scenes, kmax, contacts, n_driven, history, fin, st, waves, n_waves, wave_grid,
+                       resident_grid, flat);
     e.cap.n = saved;
   }
+  pabd_status set_resident(const std::vector<int>& contact, const std::vector<int>& other,
+                           hipStream_t st) override {
+    return e.set_resident(contact, other, st);
+  }
+  int resident_max(bool contact) const override { return contact ? Resident<T>::NT / 4 : Resident<T>::NT; }
   void tile_step(int tb, const TileTable& tt, int grid, int nsteps, hipStream_t st) override {
     View<T> v = e.view();
     switch (tb) {
@@ -272,6 +285,9 @@ struct pabd_scene {
   int precision = PABD_FP32;
   int debug = 0;
   bool history = false;
+  // the whole step in the resident kernel (bodies fit its LDS; not while the
+  // residual of every iteration is recorded, which the flat kernels do)
+  bool resident = false;
   Graph graph;
   // releases what the handle holds, also after a create that failed part-way
   // (its own stream is drained first; work on callers' streams is the caller's)
@@ -323,8 +339,14 @@ pabd_status pabd_scene_create(const pabd_scene_desc* desc, pabd_scene** out) {
   pabd_status st = s->eng->allocate(c);
   if (st != PABD_OK) return fail(st, s->eng->error());
   s->hs.params.steps_total = INT_MAX;
+  s->resident = s->hs.n > 0 && s->hs.n <= s->eng->resident_max(s->hs.contact);
+  s->hs.params.resident = s->resident ? 1 : 0;
   st = s->eng->upload(s->hs, 0, 0, 0, 0, 0, s->stream);
   if (st != PABD_OK) return fail(st, s->eng->error());
+  if (s->resident) {
+    st = s->hs.contact ? s->eng->set_resident({0}, {}, s->stream) : s->eng->set_resident({}, {0}, s->stream);
+    if (st != PABD_OK) return fail(st, s->eng->error());
+  }
   s->eng->factor(s->stream);
   API_HIP(hipGetLastError());
   API_HIP(hipStreamSynchronize(s->stream));
@@ -353,6 +375,12 @@ pabd_status pabd_set_allocator(void* (*alloc)(size_t bytes, void* ctx), void (*r
 
 static void scene_enqueue_step(pabd_scene* s, hipStream_t st) {
   const HostScene& hs = s->hs;
+  if (s->resident && !s->history) {
+    const int grid[2] = {hs.contact ? 1 : 0, hs.contact ? 0 : 1};
+    s->eng->flat_step(0, std::max(1, hs.n), 1, hs.params.iters, hs.contact, (int)hs.drv_end_i.size(), false,
+                      true, st, nullptr, nullptr, 0, grid, false);
+    return;
+  }
   s->eng->flat_step(0, std::max(1, hs.n), 1, hs.params.iters, hs.contact,
                     (int)hs.drv_end_i.size(), s->history, true, st);
 }
@@ -444,6 +472,10 @@ pabd_status pabd_scene_set_debug(pabd_scene* s, int32_t flags) {
   }
   int dbg = flags & 1;
   API_HIP(hipMemcpy((char*)s->eng->scene_table() + offsetof(SceneDev, debug), &dbg, sizeof(int),
+                    hipMemcpyHostToDevice));
+  // recording every iteration's residual is the flat kernels' work
+  const int res = s->resident && !s->history ? 1 : 0;
+  API_HIP(hipMemcpy((char*)s->eng->scene_table() + offsetof(SceneDev, resident), &res, sizeof(int),
                     hipMemcpyHostToDevice));
   s->graph.reset();
   return PABD_OK;
@@ -573,6 +605,7 @@ struct RangeAlloc {
 struct Slot {
   bool used = false;
   bool tiled = false;
+  bool resident = false;  // not tiled, and its whole step runs in the resident kernel
   int boff = 0, n = 0, eoff = 0, ne = 0, poff = 0, np = 0, doff = 0, nd = 0;
   int coff = 0, nslot = 0;  // contact slots [coff, coff + nslot): n bodies x the scene's capacity
   int tile = -1;
@@ -624,13 +657,15 @@ struct pabd_batch {
   // (and so the captured step graph) unchanged; kernels skip unused slots
   struct Launch {
     int stream_n = 0, driven_n = 0, grid = 0, kmax = 0, tile = 0, wave_grid = 0;
-    bool stream = false, contact = false;
+    int res_grid[2] = {0, 0};  // workgroups over the resident lists (contact, other)
+    bool stream = false, contact = false, flat = false;
     const int* table = nullptr;
     const FlatWave* waves = nullptr;
     bool operator==(const Launch& o) const {
       return stream_n == o.stream_n && driven_n == o.driven_n && grid == o.grid && kmax == o.kmax &&
              tile == o.tile && stream == o.stream && contact == o.contact && table == o.table &&
-             wave_grid == o.wave_grid && waves == o.waves;
+             wave_grid == o.wave_grid && waves == o.waves && res_grid[0] == o.res_grid[0] &&
+             res_grid[1] == o.res_grid[1] && flat == o.flat;
     }
   } launch;
   // releases what the handle holds, also after a create that failed part-way
@@ -700,13 +735,25 @@ pabd_status batch_tables(pabd_batch* b) {
   b->stream_kmax = 0;
   b->n_driven_hi = 0;
   b->stream_hi = 0;
-  for (const Slot& s : b->slots) {
+  bool any_flat = false;  // some scene on the flat path iterates in the flat kernels
+  std::vector<int> res_contact, res_other;
+  for (int k = 0; k < b->max_slots; ++k) {
+    const Slot& s = b->slots[k];
     if (!s.used || s.tiled) continue;
     b->any_stream = true;
     b->any_contact = b->any_contact || s.contact;
-    b->stream_kmax = std::max(b->stream_kmax, s.iters);
     if (s.nd > 0) b->n_driven_hi = std::max(b->n_driven_hi, s.doff + s.nd);
     b->stream_hi = std::max(b->stream_hi, s.boff + std::max(1, s.n));
+    if (s.resident) {
+      (s.contact ? res_contact : res_other).push_back(k);
+    } else {
+      any_flat = true;
+      b->stream_kmax = std::max(b->stream_kmax, s.iters);
+    }
+  }
+  {
+    pabd_status st = b->eng->set_resident(res_contact, res_other, b->stream);
+    if (st != PABD_OK) return fail(st, b->eng->error());
   }
   auto round_up = [](int x, int q, int cap) { return std::min(cap, (x + q - 1) / q * q); };
   // flat-path waves, when contact scenes share the flat path with others: a
@@ -716,7 +763,7 @@ pabd_status batch_tables(pabd_batch* b) {
   if (b->any_contact) {
     std::vector<const Slot*> flat;
     for (const Slot& s : b->slots)
-      if (s.used && !s.tiled && s.n > 0) flat.push_back(&s);
+      if (s.used && !s.tiled && !s.resident && s.n > 0) flat.push_back(&s);
     std::sort(flat.begin(), flat.end(), [](const Slot* x, const Slot* y) { return x->boff < y->boff; });
     for (const Slot* s : flat) {
       const int lpb = s->contact ? 4 : 1, per = 64 / lpb;
@@ -742,7 +789,11 @@ pabd_status batch_tables(pabd_batch* b) {
   pabd_batch::Launch L;
   L.stream = b->any_stream;
   L.contact = b->any_contact;
+  L.flat = any_flat;
   L.kmax = b->stream_kmax;
+  // rounded like the other extents, so that most admissions reuse the graph
+  L.res_grid[0] = res_contact.empty() ? 0 : round_up((int)res_contact.size(), 64, b->max_slots);
+  L.res_grid[1] = res_other.empty() ? 0 : round_up((int)res_other.size(), 64, b->max_slots);
   L.stream_n = b->any_stream ? round_up(b->stream_hi, 16384, b->n_stream) : 0;
   L.driven_n = b->n_driven_hi > 0 ? round_up(b->n_driven_hi, 256, b->caps.dr) : 0;
   L.grid = b->grid_tiles > 0 ? round_up(b->grid_tiles, 256, INT_MAX) : 0;
@@ -770,10 +821,10 @@ void batch_enqueue(pabd_batch* b, int nsteps, hipStream_t st) {
   if (L.stream) {
     for (int k = 0; k < nsteps; ++k) {
       b->eng->flat_step(0, L.stream_n, b->max_slots, L.kmax, L.contact, L.driven_n, false, false, st,
-                        L.wave_grid > 0 ? b->d_waves : nullptr, b->d_nwaves, L.wave_grid);
+                        L.wave_grid > 0 ? b->d_waves : nullptr, b->d_nwaves, L.wave_grid, L.res_grid, L.flat);
       // scenes on the flat path: residual reduction and step counters (tiled
-      // scenes do both inside the tile kernel)
-      b->eng->finish_scenes(b->max_slots, st);
+      // and resident scenes do both inside their kernels)
+      if (L.flat) b->eng->finish_scenes(b->max_slots, st);
     }
   }
 }
@@ -832,6 +883,12 @@ pabd_status batch_place_and_upload(pabd_batch* b, int slot) {
   const HostScene& hs = *s.hs;
   const bool tiled = !hs.contact && !hs.driven && !hs.variable && hs.n > 0 && hs.n <= b->tile_bodies;
   s.tiled = tiled;
+  // In a batch the flat path's scenes stay in the flat kernels: a resident
+  // workgroup holds a whole compute unit for one scene's step, which beside
+  // the flat kernels' other scenes costs more than it saves (served mix, all
+  // requests queued: 2.96e9 body-iterations/s with resident scenes against
+  // 3.22e9 without); a single scene alone gains from it (pabd_scene_step).
+  s.resident = false;
   if (tiled) {
     pabd_status st = place_tiled(b, slot, hs.n);
     if (st != PABD_OK) return st;
@@ -865,6 +922,7 @@ pabd_status batch_place_and_upload(pabd_batch* b, int slot) {
   copy.params.ccap = hs.ccap;
   copy.params.ce_off = s.coff;
   copy.params.tiled = tiled ? 1 : 0;
+  copy.params.resident = s.resident ? 1 : 0;
   pabd_status st = b->eng->upload(copy, s.boff, s.eoff, s.poff, s.doff, slot, b->stream);
   if (st != PABD_OK) {
     undo();
@@ -1491,12 +1549,20 @@ pabd_status pabd_scene_run_noalloc(const pabd_scene_desc* desc, int32_t nsteps, 
                                 " bytes)");
   if (st != PABD_OK) return fail(st, eng->error());
   hs.params.steps_total = INT_MAX;
+  // the same path as the plain scene's (pabd_scene_step)
+  const bool resident = hs.n > 0 && hs.n <= eng->resident_max(hs.contact);
+  hs.params.resident = resident ? 1 : 0;
   st = eng->upload(hs, 0, 0, 0, 0, 0, stream);
   if (st != PABD_OK) return fail(st, eng->error());
+  if (resident) {
+    st = hs.contact ? eng->set_resident({0}, {}, stream) : eng->set_resident({}, {0}, stream);
+    if (st != PABD_OK) return fail(st, eng->error());
+  }
   eng->factor(stream);
+  const int grid[2] = {hs.contact ? 1 : 0, hs.contact ? 0 : 1};
   for (int k = 0; k < nsteps && hs.n > 0; ++k)
     eng->flat_step(0, std::max(1, hs.n), 1, hs.params.iters, hs.contact, (int)hs.drv_end_i.size(), false,
-                   true, stream);
+                   true, stream, nullptr, nullptr, 0, resident ? grid : nullptr, !resident);
   API_HIP(hipGetLastError());
   st = eng->read_bodies(0, hs.n, c, A, v, w, stream);
   if (st != PABD_OK) return st;
