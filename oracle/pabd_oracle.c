@@ -372,6 +372,7 @@ typedef struct {
   int32_t feature;
   double al_kappa, al_lambda; /* augmented bonds: kappa_j^k, lambda_j^k */
   int32_t order;              /* polynomial bonds: p */
+  double axis[3];             /* slider bonds: unit axis u of the line (j's frame) */
 } bond_t;
 
 struct pabd_oracle {
@@ -493,7 +494,8 @@ pabd_oracle *pabd_oracle_create(const pabd_oracle_desc *d) {
     bd->type = d->bond_type ? d->bond_type[e] : ORACLE_BOND_QUADRATIC;
     if (bd->i < 0 || bd->i >= n || bd->j < -1 || bd->j >= n || bd->i == bd->j) goto bad;
     if (bd->type != ORACLE_BOND_QUADRATIC && bd->type != ORACLE_BOND_DRIVEN &&
-        bd->type != ORACLE_BOND_AUGMENTED && bd->type != ORACLE_BOND_POLYNOMIAL)
+        bd->type != ORACLE_BOND_AUGMENTED && bd->type != ORACLE_BOND_POLYNOMIAL &&
+        bd->type != ORACLE_BOND_SLIDER)
       goto bad;
     if (bd->type == ORACLE_BOND_POLYNOMIAL) {
       bd->order = d->order ? d->order[e] : 0;
@@ -513,6 +515,12 @@ pabd_oracle *pabd_oracle_create(const pabd_oracle_desc *d) {
     if (bd->type == ORACLE_BOND_DRIVEN) {
       if (!d->drive) goto bad;
       memcpy(o->drive + 13 * e, d->drive + 13 * e, 13 * sizeof(double));
+    }
+    if (bd->type == ORACLE_BOND_SLIDER) {
+      if (!d->drive || bd->rest != 0.0) goto bad;
+      const double un = v3_norm(d->drive + 13 * e);
+      if (!(un > 0.0) || !isfinite(un)) goto bad;
+      for (int k = 0; k < 3; ++k) bd->axis[k] = d->drive[13 * e + k] / un;
     }
   }
   memcpy(o->gravity, d->gravity, sizeof o->gravity);
@@ -898,6 +906,24 @@ static void end_point(const double *q, int body, const double *x, double *y) {
   apply_J(x, q + 12 * body, y);
 }
 
+/* slider bond at iterate q: the material point xf = x_j + t u of j (world
+ * coordinates if j = -1) whose world image yf is the foot of the perpendicular
+ * from y_i onto the line, t = (y_i - y_j(x_j)).g / g.g with g the line's world
+ * direction (A_j u, or u) */
+static void slider_foot(const double *q, const bond_t *b, double *xf, double *yf) {
+  double yi[3], y0[3], g[3];
+  end_point(q, b->i, b->xi, yi);
+  end_point(q, b->j, b->xj, y0);
+  if (b->j < 0)
+    memcpy(g, b->axis, sizeof g);
+  else
+    m3_vec(q + 12 * b->j + 3, b->axis, g);
+  const double dv[3] = {yi[0] - y0[0], yi[1] - y0[1], yi[2] - y0[2]};
+  const double t = v3_dot(dv, g) / v3_dot(g, g);
+  for (int k = 0; k < 3; ++k) xf[k] = b->xj[k] + t * b->axis[k];
+  end_point(q, b->j, xf, yf);
+}
+
 /* contact force on the i side at iterate q (reading above) */
 static void contact_force(const bond_t *b, const double *yi, const double *yj, double *f) {
   double d[3] = {yj[0] - yi[0], yj[1] - yi[1], yj[2] - yi[2]};
@@ -1047,6 +1073,22 @@ static int one_step(pabd_oracle *o) {
           contact_force(bd, yi, yj, f);
           for (int q = 0; q < 3; ++q) fe[q] = f[q] - bd->kappa * (yj[q] - yi[q]);
           add_JT(xs, fe, side ? -h2 : h2, r);
+          continue;
+        }
+        if (bd->type == ORACLE_BOND_SLIDER) {
+          /* ball joint between x_i and the foot point of j at iterate k: the i
+           * end is drawn to the foot, the foot point of j to y_i */
+          double xf[3], yf[3];
+          slider_foot(qk, bd, xf, yf);
+          if (side == 0) {
+            add_JTJ(bd->xi, h2 * bd->kappa, H);
+            add_JT(bd->xi, yf, h2 * bd->kappa, r);
+          } else {
+            double yi[3];
+            end_point(qk, bd->i, bd->xi, yi);
+            add_JTJ(xf, h2 * bd->kappa, H);
+            add_JT(xf, yi, h2 * bd->kappa, r);
+          }
           continue;
         }
         if (bd->type == ORACLE_BOND_POLYNOMIAL) {

@@ -48,6 +48,13 @@ extern "C" {
 /* polynomial bond: Psi = kappa / p (d - l)^p, p even >= 2 (order[] of the bond);
  * phi = kappa (d - l)^{p-1} split by the sign of its binomial terms */
 #define ORACLE_BOND_POLYNOMIAL 4
+/* slider (point-on-line) bond, a reading: Sec. 5.1 names slider joints but gives
+ * no energy.  Psi = 1/2 kappa dist(y_i, L_j)^2, where L_j is the line through
+ * x_j along the unit axis u (both in j's material frame, world if j = -1; u is
+ * drive[0..2] of the bond, rest_len must be 0).  Every iteration the line-side
+ * anchor is the foot of the perpendicular from y_i^k onto L_j at q^k, and the
+ * bond then acts as a ball joint between x_i and that material point of j */
+#define ORACLE_BOND_SLIDER 5
 
 typedef struct {
   int32_t n_bodies;
@@ -60,10 +67,11 @@ typedef struct {
   const double *v0, *w0;       /* [N*3], [N*3] */
   int32_t n_bonds;
   const int32_t *bond_i, *bond_j; /* [B]; j = -1: world anchor */
-  const int32_t *bond_type;       /* [B] QUADRATIC, DRIVEN or AUGMENTED */
+  const int32_t *bond_type;       /* [B] ORACLE_BOND_*, or NULL (all quadratic) */
   const double *x_i, *x_j;        /* [B*3] material anchors (world coords if j = -1) */
   const double *kappa, *rest_len; /* [B] */
-  const double *drive;            /* [B*13]: axis(3) pivot(3) base(3) theta0 amp freq phase */
+  const double *drive;            /* [B*13]: axis(3) pivot(3) base(3) theta0 amp freq phase;
+                                   * SLIDER bonds use axis(3) only */
   double gravity[3];
   double h;
   double t0; /* simulation time at the start of the first step */

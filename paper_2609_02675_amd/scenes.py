@@ -12,7 +12,9 @@ explicit seed.
 Shapes: 0 = box (shape_param = half extents), 1 = sphere (shape_param[0] = radius).
 Body flags: bit0 = pinned (kinematic, infinite mass), bit1 = no contact.
 Bond types: 0 = quadratic (rest length l; l = 0 is a ball joint),
-            1 = driven ball joint (j-side anchor follows a target angle).
+            1 = driven ball joint (j-side anchor follows a target angle),
+            3 = augmented Lagrangian, 4 = polynomial,
+            5 = slider (point of i on a line of j; drive[0:3] is the line's axis).
 """
 from __future__ import annotations
 
@@ -30,6 +32,9 @@ BOND_QUADRATIC = 0
 BOND_DRIVEN = 1
 BOND_AUGMENTED = 3  # augmented Lagrangian (Sec. 5.2.2); kappa is kappa_start
 BOND_POLYNOMIAL = 4  # Psi = kappa / p (d - l)^p, p = order (even >= 2)
+# point-on-line bond: x_i of body i held on the line through x_j along the axis
+# drive[0:3] (both in j's material frame, world if j = -1); rest length 0
+BOND_SLIDER = 5
 
 PREC_FP32 = 0
 PREC_FP64 = 1
@@ -419,6 +424,78 @@ def world_pendulum(ell: float = 0.5, theta0_deg: float = 0.0, kappa: float = 1e5
     bonds["x_i"][0] = x
     bonds["kappa"][0] = kappa
     return SceneDesc(**bd, **bonds, h=h, iters=iters, precision=precision, name="pendulum")
+
+
+def linkage(kind: str = "slider", *, kappa: float = 1e5, crank: float = 0.2, rod: float = 0.6,
+            theta0_deg: float = 60.0, rocker: float = 1.0, drive_amp_deg: Optional[float] = None,
+            drive_freq: float = 0.5, iters: int = 20, h: float = 1.0 / 60.0,
+            precision: int = PREC_FP64) -> SceneDesc:
+    """The four-body linkage of Sec. 5.1 (Table 2): a pinned ground (body 0), a
+    crank (1) hinged to the ground at the origin, a connecting rod (2) hinged to
+    the crank's tip, and a 1 kg block (3) hinged to the rod's far end, all in the
+    x-y plane with hinge axes along z and gravity along -y.  Each hinge is two
+    ball bonds 5 cm either side of the axis point.
+
+    kind "slider": the block slides on the ground's x axis (a slider crank),
+    held by three slider bonds from its points (+-5 cm, 0, 0) and (0, 0, 5 cm)
+    to lines along x.  kind "four_bar": the block is replaced by a rocker of
+    the same mass hinged to the ground `rocker` below the rod's end (the slider
+    crank is the four-bar linkage whose rocker is infinitely long).
+
+    Crank and rod are boxes 4 cm thick of density 1000 (0.32 kg and 0.96 kg at
+    the default lengths); the crank starts at theta0 from the x axis, every body
+    at rest.  With drive_amp_deg, a driven bond turns the crank's tip about the
+    pivot by amp sin(2 pi f t) from its start (stiffness kappa)."""
+    th = math.radians(theta0_deg)
+    p1 = crank * np.array([math.cos(th), math.sin(th), 0.0])
+    p2 = np.array([crank * math.cos(th) + math.sqrt(rod * rod - (crank * math.sin(th)) ** 2), 0.0, 0.0])
+    bd = _bodies(4)
+    bd["flags"][:] = FLAG_NO_CONTACT
+    bd["flags"][0] |= FLAG_PINNED
+    bd["shape_param"][0] = 0.1
+    bd["density"][:] = 1000.0
+
+    def link(b, a, z, half):
+        d = z - a
+        bd["c0"][b] = 0.5 * (a + z)
+        bd["A0"][b] = rot_z(math.atan2(d[1], d[0]))
+        bd["shape_param"][b] = (half, 0.02, 0.02)
+
+    link(1, np.zeros(3), p1, crank / 2)
+    link(2, p1, p2, rod / 2)
+    rows = []
+
+    def hinge(i, j, xi, xj):
+        for dz in (-0.05, 0.05):
+            rows.append((i, j, BOND_QUADRATIC, np.add(xi, (0, 0, dz)), np.add(xj, (0, 0, dz)), np.zeros(13)))
+
+    hinge(1, 0, (-crank / 2, 0, 0), (0, 0, 0))
+    hinge(2, 1, (-rod / 2, 0, 0), (crank / 2, 0, 0))
+    if kind == "slider":
+        bd["c0"][3] = p2
+        bd["shape_param"][3] = 0.05
+        hinge(3, 2, (0, 0, 0), (rod / 2, 0, 0))
+        axis = np.r_[1.0, 0.0, 0.0, np.zeros(10)]
+        for xi, xj in (((0.05, 0, 0), (0, 0, 0)), ((-0.05, 0, 0), (0, 0, 0)),
+                       ((0, 0, 0.05), (0, 0, 0.05))):
+            rows.append((3, 0, BOND_SLIDER, np.asarray(xi, float), np.asarray(xj, float), axis))
+    elif kind == "four_bar":
+        pg = p2 - np.array([0.0, rocker, 0.0])
+        link(3, pg, p2, rocker / 2)
+        bd["density"][3] = 1.0 / (rocker * 0.04 * 0.04)  # 1 kg, as the block
+        hinge(3, 2, (rocker / 2, 0, 0), (rod / 2, 0, 0))
+        hinge(3, 0, (-rocker / 2, 0, 0), pg)
+    else:
+        raise ValueError(kind)
+    if drive_amp_deg is not None:
+        drive = np.r_[0.0, 0.0, 1.0, 0.0, 0.0, 0.0, p1, 0.0, math.radians(drive_amp_deg), drive_freq, 0.0]
+        rows.append((1, 0, BOND_DRIVEN, np.array([crank / 2, 0.0, 0.0]), p1, drive))
+    bonds = _empty_bonds(len(rows))
+    for e, (i, j, t, xi, xj, dr) in enumerate(rows):
+        bonds["bond_i"][e], bonds["bond_j"][e], bonds["bond_type"][e] = i, j, t
+        bonds["x_i"][e], bonds["x_j"][e], bonds["drive"][e] = xi, xj, dr
+    bonds["kappa"][:] = kappa
+    return SceneDesc(**bd, **bonds, h=h, iters=iters, precision=precision, name=f"linkage_{kind}")
 
 
 # ---------------------------------------------------------------------------

@@ -14,7 +14,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "pabd_oracle.c")
 HDR = os.path.join(ROOT, "oracle", "pabd_oracle.h")
 PINS = ["tests/test_oracle_math.py", "tests/test_oracle_dynamics.py", "tests/test_oracle_contact.py",
-        "tests/test_oracle_polynomial.py", "tests/test_oracle_augmented.py", "tests/test_oracle_driven.py"]
+        "tests/test_oracle_polynomial.py", "tests/test_oracle_augmented.py", "tests/test_oracle_driven.py",
+        "tests/test_oracle_slider.py"]
 
 # (name, text in the oracle, planted replacement); each text occurs once.
 MUTANTS = [
@@ -100,6 +101,18 @@ MUTANTS = [
      "double th = dr[9] + dr[10] * sin(2.0 * M_PI * dr[11] * t + dr[12]);",
      "double th = dr[9] - dr[10] * sin(2.0 * M_PI * dr[11] * t + dr[12]);"),
     ("driven_turn_sense", "rotate_about(dr, th, rel, rot);", "rotate_about(dr, -th, rel, rot);"),
+    # slider bond (reading of Sec. 5.1's slider joints)
+    ("slider_foot_at_the_anchor",
+     "const double t = v3_dot(dv, g) / v3_dot(g, g);", "const double t = 0.0 * v3_dot(dv, g);"),
+    ("slider_foot_direction_sign",
+     "xf[k] = b->xj[k] + t * b->axis[k];", "xf[k] = b->xj[k] - t * b->axis[k];"),
+    ("slider_axis_in_world_frame",
+     "    m3_vec(q + 12 * b->j + 3, b->axis, g);", "    memcpy(g, b->axis, sizeof g);"),
+    ("slider_line_side_arm_at_the_anchor",
+     "add_JTJ(xf, h2 * bd->kappa, H);\n            add_JT(xf, yi, h2 * bd->kappa, r);",
+     "add_JTJ(bd->xj, h2 * bd->kappa, H);\n            add_JT(bd->xj, yi, h2 * bd->kappa, r);"),
+    ("slider_line_side_drawn_to_its_foot",
+     "add_JT(xf, yi, h2 * bd->kappa, r);", "add_JT(xf, yf, h2 * bd->kappa, r);"),
     ("driven_time_at_step_start",
      "const double t = o->t0 + (double)(o->steps_done + 1) * h;",
      "const double t = o->t0 + (double)o->steps_done * h;"),
