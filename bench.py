@@ -166,6 +166,7 @@ def cpu_baseline_leg(args, S, scenes, plan):
         refs["drop_mid"] = mid
         refs["drop_next"] = run(mid, 1)
         refs["mass_ratio"] = {aug: run(S.mass_ratio_chain(augmented=aug), 110) for aug in (True, False)}
+        refs["linkage"] = run(S.linkage("slider", drive_amp_deg=60.0), 120)
         # the oracle's own spread: the same chain from FP32-rounded inputs
         f32 = lambda a: np.asarray(a, np.float32).astype(np.float64)
         refs["mass_ratio_f32_inputs"] = {}
@@ -331,7 +332,8 @@ def main():
                     help="seconds of Poisson arrivals (200 req/s) in the served leg; 0 = skip")
     ap.add_argument("--serve-budget-gib", type=float, default=16.0)
     ap.add_argument("--only-scene", default="",
-                    choices=["", "box_drop", "granular_bed", "mass_ratio_chain", "spring_net", "block_pile"],
+                    choices=["", "box_drop", "granular_bed", "mass_ratio_chain", "linkage", "spring_net",
+                             "block_pile"],
                     help="run only this one of the single-scene legs (for profiling it alone)")
     ap.add_argument("--no-scenes", action="store_true",
                     help="skip the single-scene legs (1,000-box drop, granular bed)")
@@ -579,6 +581,17 @@ def main():
                 paper_context="Table 2, mass-ratio chain (19 bodies, 10 iterations) on an RTX 3080: "
                               "t_solve 1.28 ms (AL on) / 1.25 ms (off) per frame")
             log(f"mass-ratio chain {tag}: {ms:.3f} ms/step, joint error {joint(st[0], st[1]):.3g} m")
+        # the paper's four-body linkage (three hinges and a slider), crank driven
+        if want("linkage"):
+            lk = S.linkage("slider", drive_amp_deg=60.0, precision=S.PREC_FP32)
+            g, rate, ms = time_scene(lk, 10, 110)
+            e = errors(g.state(check=False), refs["linkage"], scale_of(lk))
+            scene_legs["linkage_slider_crank_fp32"] = dict(
+                body_its_per_s=rate, ms_per_step=ms, bodies=lk.n_bodies, bonds=lk.n_bonds, iters=lk.iters,
+                steps_timed="11..120", err_vs_fp64_oracle_after_120_steps=max(e["pos"], e["rot"]),
+                paper_context="Table 2, linkage (a) (4 bodies, 4 joints, 20 iterations) on an RTX 3080: "
+                              "t_solve 2.37 ms per frame")
+            log(f"linkage: {ms:.4f} ms/step, err {max(e['pos'], e['rot']):.2e}")
         # the paper's 11 x 11 net of 220 springs, quadratic and quartic bonds:
         # convergence of the first step (relative error per iteration) and step time
         for p_ in (2, 4) if want("spring_net") else ():

@@ -59,6 +59,15 @@ typedef enum {
  * phi = kappa (d - l)^{p-1} split by the signs of its binomial terms (non-negative terms
  * implicit, the rest explicit); p = 2 is the quadratic bond.  Flat path. */
 #define PABD_BOND_POLYNOMIAL 4
+/* slider bond (the slider joint of Sec. 5.1, whose energy the paper does not print;
+ * read as a point-on-line bond): Psi = 1/2 kappa dist(y_i, L_j)^2 with L_j the line
+ * through x_j along the axis drive[0..2] (both in j's material frame, world if
+ * j = -1; the axis need not be unit; rest_len must be 0 or NULL).  Every iteration
+ * the line-side anchor is the foot of the perpendicular from y_i^k onto L_j at q^k,
+ * and the bond acts as a ball joint between x_i and that point of j: the point
+ * side's weight stays at x_i, the line side's moves with the foot.  A prismatic
+ * joint is three such bonds from non-collinear points to parallel lines.  Flat path. */
+#define PABD_BOND_SLIDER 5
 /* precision of bond and body arithmetic; the block factorisation and the
  * convergence-residual reductions are always FP64 */
 #define PABD_FP32 0
@@ -96,7 +105,8 @@ typedef struct {
   const double *x_i, *x_j;    /* [B*3] material anchors */
   const double *kappa;        /* [B] stiffness > 0 */
   const double *rest_len;     /* [B] rest length >= 0, or NULL */
-  const double *drive;        /* [B*13] driven bonds: axis3 pivot3 base3 theta0 amp freq phase */
+  const double *drive;        /* [B*13] driven bonds: axis3 pivot3 base3 theta0 amp freq phase;
+                               * slider bonds: the line axis in [0..2] */
   double gravity[3];
   double h;                   /* time step > 0 */
   double t0;                  /* time at the start of the first step */

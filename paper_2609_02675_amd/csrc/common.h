@@ -40,6 +40,11 @@ struct Rec<float> {
 };
 constexpr uint8_t F_PINNED = 1, F_NOCONTACT = 2;
 constexpr uint8_t F_VARIABLE = 4;  // set by the library: the body owns ends whose weight changes every iteration
+// kind of a variable end, held in the last of its four per-end values: > 0 an
+// augmented end (that value is kappa_start), -p a polynomial end of even order p,
+// and the two odd codes below the two ends of a slider bond (never an order)
+constexpr int AL_SLIDER_POINT = -1;  // the point side: drawn to the foot on the partner's line
+constexpr int AL_SLIDER_LINE = -3;   // the line side: its foot point drawn to the partner's point
 
 // per-scene parameters (device scene table)
 struct SceneDev {

@@ -135,8 +135,15 @@ inline std::string build_host_scene(const pabd_scene_desc* d, HostScene& hs) {
     const int ty = d->bond_type ? d->bond_type[e] : PABD_BOND_QUADRATIC;
     if (i < 0 || i >= n || j < -1 || j >= n || i == j) return "bond " + std::to_string(e) + " has bad endpoints";
     if (ty != PABD_BOND_QUADRATIC && ty != PABD_BOND_DRIVEN && ty != PABD_BOND_AUGMENTED &&
-        ty != PABD_BOND_POLYNOMIAL)
+        ty != PABD_BOND_POLYNOMIAL && ty != PABD_BOND_SLIDER)
       return "unknown bond type";
+    if (ty == PABD_BOND_SLIDER) {
+      if (!d->drive) return "slider bond without its axis (drive[0..2])";
+      const double* u = d->drive + 13 * (size_t)e;
+      const double un = std::sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+      if (!(un > 0.0) || !std::isfinite(un)) return "slider axis must be finite and nonzero";
+      if (d->rest_len && d->rest_len[e] != 0.0) return "slider bond needs rest length 0";
+    }
     if (ty == PABD_BOND_POLYNOMIAL) {
       const int p = d->order ? d->order[e] : 0;
       if (p < 2 || p > 12 || p % 2 != 0) return "polynomial bond order must be even in [2, 12]";
@@ -212,6 +219,25 @@ inline std::string build_host_scene(const pabd_scene_desc* d, HostScene& hs) {
       if (j >= 0) hs.flags[j] |= F_VARIABLE;
       // a pinned body never iterates, so its copy of the state is not advanced
       if ((hs.flags[i] & PABD_FLAG_PINNED) && ej >= 0) hs.bond_end[e] = ej;
+    }
+    if (ty == PABD_BOND_SLIDER) {
+      // per-end axis u (unit, line body's frame) and side code; the point side's
+      // weight sits at its fixed anchor (static block), the line side's at the
+      // foot, which moves every iteration (se64 kappa 0)
+      hs.variable = true;
+      const double* u = d->drive + 13 * (size_t)e;
+      const double un = std::sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+      for (int ee : {ei, ej}) {
+        if (ee < 0) continue;
+        double* a = &hs.al[4 * (size_t)ee];
+        a[0] = u[0] / un;
+        a[1] = u[1] / un;
+        a[2] = u[2] / un;
+        a[3] = ee == ei ? AL_SLIDER_POINT : AL_SLIDER_LINE;
+      }
+      if (ej >= 0) hs.se64[4 * (size_t)ej + 3] = 0.0;
+      hs.flags[i] |= F_VARIABLE;
+      if (j >= 0) hs.flags[j] |= F_VARIABLE;
     }
     if (ty == PABD_BOND_DRIVEN) {
       hs.drv_end_i.push_back(ei);

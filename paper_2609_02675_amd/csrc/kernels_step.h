@@ -120,6 +120,26 @@ __device__ __forceinline__ T polynomial_end(const T* a, const T* d, T h2, T* f) 
   return h2 * w;
 }
 
+// one slider end (the point-on-line reading of the slider joint of Sec. 5.1).
+// d0 = y_o - y_s is the record's bond vector (point side: from the point to the
+// line's anchor on the partner; line side: from the own line anchor to the
+// partner's point); g = A u is the line's world direction (u the unit axis in
+// the line body's frame, A that body's iterate, or u itself for a world line).
+// Sets d to the part of d0 across g -- on either side the vector from this end's
+// point to the other, with the line-side point at the foot of the
+// perpendicular -- and returns t = d0.g / g.g, the foot's distance along u from
+// the line anchor as seen from the line side.
+template <typename T>
+__device__ __forceinline__ T slider_end(const T* d0, const T* A, const T* u, T* d) {
+  T g[3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) g[r] = A ? A[3 * r] * u[0] + A[3 * r + 1] * u[1] + A[3 * r + 2] * u[2] : u[r];
+  const T t = (d0[0] * g[0] + d0[1] * g[1] + d0[2] * g[2]) / (g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+#pragma unroll
+  for (int r = 0; r < 3; ++r) d[r] = d0[r] - t * g[r];
+  return t;
+}
+
 // mass64: 8 doubles per body (m, Pi sym 6, -)
 template <typename T>
 __global__ void __launch_bounds__(256) k_factor(View<T> v, const double* mass64, int first, int count) {
@@ -255,24 +275,56 @@ __device__ __forceinline__ void iterate_body(const View<T>& v, int k, double* rh
     const int j = v.se_partner[e];
     T E[EW];
     load<T, EW>(v.se + (size_t)EW * e, E);
-    T d[3], f[3];
-    if (j < 0) {
-      bond_vec<T>(q, E, nullptr, E + 4, d);
-    } else {
-      T qj[QR];
-      load<T, QR>(qs + (size_t)QR * (j - qoff), qj);
-      bond_vec<T>(q, E, qj, E + 4, d);
-    }
     T* a = var ? v.al + 4 * (size_t)e : nullptr;
-    if (a && a[3] != (T)0) {
-      const T w = a[3] > (T)0 ? augmented_end(a, d, (T)(S.h * S.h), (T)S.al_beta, f)
+    const T kind = a ? a[3] : (T)0;
+    // a slider end's line anchor sits t0 = E[7] along the axis from the given
+    // one (a slider's rest length is 0, so E[7] holds no phi^-): the same line,
+    // re-anchored near the point every step so that the bond vector, whose
+    // across-axis part is the force, stays short (in FP32 a long one would lose
+    // that part to rounding)
+    T xs[3] = {E[0], E[1], E[2]}, xo[3] = {E[4], E[5], E[6]};
+    if (kind == (T)AL_SLIDER_POINT) {
+#pragma unroll
+      for (int r = 0; r < 3; ++r) xo[r] = fma(E[7], a[r], xo[r]);
+    } else if (kind == (T)AL_SLIDER_LINE) {
+#pragma unroll
+      for (int r = 0; r < 3; ++r) xs[r] = fma(E[7], a[r], xs[r]);
+    }
+    T d[3], f[3];
+    T qj[QR];
+    if (j < 0) {
+      bond_vec<T>(q, xs, nullptr, xo, d);
+    } else {
+      load<T, QR>(qs + (size_t)QR * (j - qoff), qj);
+      bond_vec<T>(q, xs, qj, xo, d);
+    }
+    if (kind == (T)AL_SLIDER_POINT) {
+      // fixed weight at the own point (in the static block), drawn to the foot
+      T dp[3];
+      const T t = slider_end(d, j < 0 ? (const T*)nullptr : qj + 3, a, dp);
+      end_force(E[3], (T)0, dp, f);
+      add_JT(rb, E, f[0], f[1], f[2]);
+      if (k == K - 1) v.se[(size_t)EW * e + 7] = E[7] - t;  // the foot is -t from the anchor
+    } else if (kind == (T)AL_SLIDER_LINE) {
+      // the own point is the foot xf = x_s + t u, so its weight moves every iteration
+      T dp[3];
+      const T t = slider_end(d, q + 3, a, dp);
+      const T xf[3] = {fma(t, a[0], xs[0]), fma(t, a[1], xs[1]), fma(t, a[2], xs[2])};
+      end_force(E[3], (T)0, dp, f);
+      add_JT(rb, xf, f[0], f[1], f[2]);
+      block_add_end(dB, (double)E[3], (double)xf[0], (double)xf[1], (double)xf[2]);
+      refactor = true;
+      if (k == K - 1) v.se[(size_t)EW * e + 7] = E[7] + t;
+    } else if (kind != (T)0) {
+      const T w = kind > (T)0 ? augmented_end(a, d, (T)(S.h * S.h), (T)S.al_beta, f)
                               : polynomial_end(a, d, (T)(S.h * S.h), f);
       block_add_end(dB, (double)w, (double)E[0], (double)E[1], (double)E[2]);
       refactor = true;
+      add_JT(rb, E, f[0], f[1], f[2]);
     } else {
       quad_end_force(E, d, f);
+      add_JT(rb, E, f[0], f[1], f[2]);
     }
-    add_JT(rb, E, f[0], f[1], f[2]);
   }
   if constexpr (CONTACT) {
     int cnt = v.ccount[i];
@@ -323,7 +375,7 @@ __device__ __forceinline__ void iterate_body(const View<T>& v, int k, double* rh
     }
     if (sub != 0) return;
   }
-  if (refactor) {  // H^k changed: some contact penetrates at this iterate
+  if (refactor) {  // H^k changed: a contact penetrates, or a variable end's weight or point moved
     const double* bb = v.blk + 10 * (size_t)i;
     const Block B{bb[0] + dB.a,   bb[1] + dB.b0,  bb[2] + dB.b1,  bb[3] + dB.b2,  bb[4] + dB.d00,
                   bb[5] + dB.d01, bb[6] + dB.d02, bb[7] + dB.d11, bb[8] + dB.d12, bb[9] + dB.d22};

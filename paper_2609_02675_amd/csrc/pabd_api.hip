@@ -501,7 +501,8 @@ pabd_status pabd_scene_bond_state(pabd_scene* s, double* kappa, double* lambda) 
   for (int e = 0; e < B; ++e) {
     const double* a = &al[4 * (size_t)s->hs.bond_end[e]];
     const bool aug = a[3] > 0.0;
-    if (kappa) kappa[e] = aug || a[3] < 0.0 ? a[0] : s->hs.se[8 * (size_t)s->hs.bond_end[e] + 3];
+    const bool poly = a[3] < 0.0 && a[3] != AL_SLIDER_POINT && a[3] != AL_SLIDER_LINE;
+    if (kappa) kappa[e] = aug || poly ? a[0] : s->hs.se[8 * (size_t)s->hs.bond_end[e] + 3];
     if (lambda) lambda[e] = aug ? a[1] : 0.0;
   }
   return PABD_OK;

@@ -426,6 +426,80 @@ def world_pendulum(ell: float = 0.5, theta0_deg: float = 0.0, kappa: float = 1e5
     return SceneDesc(**bd, **bonds, h=h, iters=iters, precision=precision, name="pendulum")
 
 
+def _slider_scene(bd, rows, gravity, iters, precision, name):
+    bonds = _empty_bonds(len(rows))
+    for e, (i, j, xi, xj, axis, kappa) in enumerate(rows):
+        bonds["bond_i"][e], bonds["bond_j"][e], bonds["bond_type"][e] = i, j, BOND_SLIDER
+        bonds["x_i"][e], bonds["x_j"][e], bonds["kappa"][e] = xi, xj, kappa
+        bonds["drive"][e][:3] = axis
+    return SceneDesc(**bd, **bonds, gravity=np.asarray(gravity, float), iters=iters,
+                     precision=precision, name=name)
+
+
+def slider_rail(kappa: float = 1e5, deg: float = 30.0, iters: int = 20,
+                precision: int = PREC_FP64) -> SceneDesc:
+    """A 1 kg cube (half extent 5 cm) on a world rail down a `deg` incline in
+    the x-y plane (gravity -y): its points +-5 cm along the rail held on the
+    rail's line through the origin, its point 5 cm along z on the parallel line
+    through (0, 0, 5 cm).  Returns the scene; the rail's direction is
+    (cos deg, -sin deg, 0)."""
+    u = np.array([math.cos(math.radians(deg)), -math.sin(math.radians(deg)), 0.0])
+    bd = _bodies(1)
+    bd["shape_param"][0] = 0.05
+    bd["density"][0] = 1000.0
+    rows = [(0, -1, 0.05 * u, (0, 0, 0), u, kappa), (0, -1, -0.05 * u, (0, 0, 0), u, kappa),
+            (0, -1, (0, 0, 0.05), (0, 0, 0.05), u, kappa)]
+    return _slider_scene(bd, rows, (0.0, -9.81, 0.0), iters, precision, "slider_rail")
+
+
+def slider_rod(kappa: float = 1e7, turn=None, iters: int = 100,
+               precision: int = PREC_FP64) -> SceneDesc:
+    """A 20 kg rod (2 m x 10 cm x 10 cm, centre at 0.25 m on x) threaded over
+    two fixed points of a pinned body at x = -0.25 m and x = 1 m: slider bonds
+    whose line is the rod's axis (material x through its centre), so the line
+    side is the free body.  `turn` = (axis, angle) turns the whole scene (both
+    frames and gravity) by one rotation."""
+    R = np.eye(3) if turn is None else rot_axis(turn[0], turn[1])
+    bd = _bodies(2)
+    bd["flags"][0] = FLAG_PINNED
+    bd["shape_param"][0] = 0.05
+    bd["shape_param"][1] = (1.0, 0.05, 0.05)
+    bd["density"][1] = 1000.0
+    bd["c0"][1] = R @ np.array([0.25, 0.0, 0.0])
+    bd["A0"][:] = R
+    ex = (1.0, 0.0, 0.0)
+    rows = [(0, 1, (-0.25, 0, 0), (0, 0, 0), ex, kappa), (0, 1, (1.0, 0, 0), (0, 0, 0), ex, kappa)]
+    return _slider_scene(bd, rows, R @ np.array([0.0, -9.81, 0.0]), iters, precision, "slider_rod")
+
+
+def slider_pair(kappa: float = 1e5, moving_along: bool = False, iters: int = 20,
+                precision: int = PREC_FP64) -> SceneDesc:
+    """Two free bodies and no gravity: a 1 kg cube whose point (2, 1, 0) cm is
+    held on the axis (1, 0.2, 0) through the centre of a 10 kg rod (1 m x 10 cm x
+    10 cm) turned by 0.4 rad about (0.2, 0.3, 1), starting on that axis 0.3 m
+    from the rod's centre; both move and spin.  With
+    `moving_along`, the cube instead sits on the unturned rod's axis at -0.6 m,
+    sliding along it at 2 m/s with the rod at rest."""
+    bd = _bodies(2)
+    bd["shape_param"][0] = 0.05
+    bd["shape_param"][1] = (0.5, 0.05, 0.05)
+    bd["density"][:] = 1000.0
+    if moving_along:
+        bd["c0"][0] = (-0.6, 0.0, 0.0)
+        bd["v0"][0] = (2.0, 0.0, 0.0)
+        rows = [(0, 1, (0, 0, 0), (0, 0, 0), (1.0, 0.0, 0.0), kappa)]
+    else:
+        bd["A0"][1] = rot_axis((0.2, 0.3, 1.0), 0.4)
+        u = np.array([1.0, 0.2, 0.0]) / math.hypot(1.0, 0.2)
+        bd["c0"][0] = 0.3 * (bd["A0"][1] @ u) - np.array([0.02, 0.01, 0.0])
+        bd["v0"][0] = (0.5, 1.0, -0.3)
+        bd["w0"][0] = (0.2, -0.1, 0.4)
+        bd["v0"][1] = (0.0, -0.1, 0.05)
+        bd["w0"][1] = (0.0, 0.1, 0.3)
+        rows = [(0, 1, (0.02, 0.01, 0), (0, 0, 0), (1.0, 0.2, 0.0), kappa)]
+    return _slider_scene(bd, rows, (0.0, 0.0, 0.0), iters, precision, "slider_pair")
+
+
 def linkage(kind: str = "slider", *, kappa: float = 1e5, crank: float = 0.2, rod: float = 0.6,
             theta0_deg: float = 60.0, rocker: float = 1.0, drive_amp_deg: Optional[float] = None,
             drive_freq: float = 0.5, iters: int = 20, h: float = 1.0 / 60.0,

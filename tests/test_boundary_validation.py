@@ -62,3 +62,12 @@ def test_free_bodies_need_positive_mass_and_definite_pi0(bad):
 def test_polar_fallback_scenes_are_valid():
     for kind in ("flip", "flat"):
         assert _both_accept(S.polar_fallback_body(kind))
+
+
+def test_slider_bonds_need_an_axis_and_no_rest_length():
+    for sc in (S.slider_rail(), S.slider_rod(), S.slider_pair(), S.linkage("slider", drive_amp_deg=60.0)):
+        assert _both_accept(sc)
+    sc = S.slider_rail()
+    assert not _both_accept(sc.copy(drive=np.zeros_like(sc.drive)))
+    assert not _both_accept(sc.copy(rest_len=np.full(sc.n_bonds, 0.1)))
+    assert _both_accept(sc.copy(drive=3.0 * sc.drive))  # the axis need not be unit

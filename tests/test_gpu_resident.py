@@ -25,7 +25,9 @@ def _cases(prec):
     return [S.chain(150, tilt_deg=25.0, precision=prec, name="chain150"),     # one lane per body
             S.pile(120, seed=7, precision=prec),                             # contacts, four lanes per body
             S.mass_ratio_chain(augmented=True, precision=prec),              # augmented bonds
-            S.spring_net(order=4, precision=prec)]                           # polynomial bonds
+            S.spring_net(order=4, precision=prec),                           # polynomial bonds
+            S.linkage("slider", drive_amp_deg=60.0, precision=prec),         # slider and driven bonds
+            S.slider_pair(precision=prec)]                                   # slider line side on a free body
 
 
 @pytest.mark.parametrize("prec", [S.PREC_FP32, S.PREC_FP64], ids=["fp32", "fp64"])

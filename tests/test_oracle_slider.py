@@ -19,35 +19,13 @@ import oracle
 from paper_2609_02675_amd import scenes as S
 
 
-def _scene(bodies, rows, gravity=(0.0, -9.81, 0.0), iters=20):
-    bonds = S._empty_bonds(len(rows))
-    for e, (i, j, t, xi, xj, axis, kappa) in enumerate(rows):
-        bonds["bond_i"][e], bonds["bond_j"][e], bonds["bond_type"][e] = i, j, t
-        bonds["x_i"][e], bonds["x_j"][e], bonds["kappa"][e] = xi, xj, kappa
-        bonds["drive"][e][:3] = axis
-    return S.SceneDesc(**bodies, **bonds, gravity=np.asarray(gravity, float), iters=iters)
-
-
-def _rail_block(kappa, iters, deg=30.0):
-    """1 kg cube (half extent 5 cm) on a world rail down a 30 degree incline in
-    the x-y plane: its points (+-5 cm along the rail) on the rail's line through
-    the origin, its point 5 cm along z on the parallel line 5 cm along z."""
-    u = np.array([math.cos(math.radians(deg)), -math.sin(math.radians(deg)), 0.0])
-    bd = S._bodies(1)
-    bd["shape_param"][0] = 0.05
-    bd["density"][0] = 1000.0
-    rows = [(0, -1, S.BOND_SLIDER, 0.05 * u, (0, 0, 0), u, kappa),
-            (0, -1, S.BOND_SLIDER, -0.05 * u, (0, 0, 0), u, kappa),
-            (0, -1, S.BOND_SLIDER, (0, 0, 0.05), (0, 0, 0.05), u, kappa)]
-    return _scene(bd, rows, iters=iters), u
-
-
 @pytest.mark.parametrize("iters", [1, 20])
 def test_block_on_an_incline_rail_falls_along_it_as_a_free_body(iters):
     # along the rail only g.u acts, and the prediction already has it, so each
     # step's axial position is that of a free fall along u (symplectic Euler from
     # rest: c_n.u = h^2 (g.u) n (n + 1) / 2) after any number of iterations
-    sc, u = _rail_block(1e5, iters)
+    sc = S.slider_rail(iters=iters)
+    u = sc.drive[0, :3]
     o = oracle.Oracle(sc)
     g_ax = float(np.dot(sc.gravity, u))
     for n in range(1, 61):
@@ -63,7 +41,8 @@ def test_block_on_an_incline_rail_settles_at_the_static_sag():
     # the centre leaves it unloaded), each sagging by delta = m |g_perp| / (2 kappa);
     # the block turns about the rail until the third point is back on its line
     kappa = 1e5
-    sc, u = _rail_block(kappa, 60)
+    sc = S.slider_rail(kappa=kappa, iters=60)
+    u = sc.drive[0, :3]
     o = oracle.Oracle(sc)
     o.step(120)
     c, A, v, w = o.state()
@@ -96,18 +75,9 @@ def test_rod_on_two_fixed_points_takes_the_lever_rule_sag(turned):
     # bodies' frames and gravity) turned by one rotation, whose result is the
     # same one turned (the axis lives in the rod's material frame)
     kappa = 1e7
-    R = S.rot_axis((0.3, -0.8, 0.5), 1.1) if turned else np.eye(3)
-    bd = S._bodies(2)
-    bd["flags"][0] = S.FLAG_PINNED
-    bd["shape_param"][0] = 0.05
-    bd["shape_param"][1] = (1.0, 0.05, 0.05)
-    bd["density"][1] = 1000.0
-    bd["c0"][1] = R @ (0.25, 0.0, 0.0)
-    bd["A0"][:] = R
-    ex = (1.0, 0.0, 0.0)
-    rows = [(0, 1, S.BOND_SLIDER, (-0.25, 0, 0), (0, 0, 0), ex, kappa),
-            (0, 1, S.BOND_SLIDER, (1.0, 0, 0), (0, 0, 0), ex, kappa)]
-    sc = _scene(bd, rows, gravity=R @ (0.0, -9.81, 0.0), iters=100)
+    turn = ((0.3, -0.8, 0.5), 1.1) if turned else None
+    R = S.rot_axis(*turn) if turned else np.eye(3)
+    sc = S.slider_rod(kappa=kappa, turn=turn)
     o = oracle.Oracle(sc)
     o.step(60)
     c, A, v, w = o.state()
@@ -128,14 +98,7 @@ def test_point_slides_freely_along_a_free_bodys_line():
     # no gravity, rod at rest, a block on the rod's axis moving along it: the
     # bond exerts nothing, the block keeps its speed and the rod stays put (a
     # ball joint in its place would drag the two together)
-    bd = S._bodies(2)
-    bd["shape_param"][0] = 0.05
-    bd["shape_param"][1] = (1.0, 0.05, 0.05)
-    bd["density"][:] = 1000.0
-    bd["c0"][0] = (-0.6, 0.0, 0.0)
-    bd["v0"][0] = (2.0, 0.0, 0.0)
-    rows = [(0, 1, S.BOND_SLIDER, (0, 0, 0), (0, 0, 0), (1.0, 0.0, 0.0), 1e5)]
-    sc = _scene(bd, rows, gravity=(0.0, 0.0, 0.0))
+    sc = S.slider_pair(moving_along=True)
     o = oracle.Oracle(sc)
     o.step(30)
     c, A, v, w = o.state()
