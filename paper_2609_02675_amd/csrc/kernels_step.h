@@ -271,59 +271,92 @@ __device__ __forceinline__ void iterate_body(const View<T>& v, int k, double* rh
   Block dB{};  // contact and augmented part of H^k - H (this lane's ends)
   const bool var = (v.flags[i] & F_VARIABLE) != 0;
   const int e1 = v.srow_end[i];
-  for (int e = v.srow[i] + sub; e < e1; e += LPB) {
-    const int j = v.se_partner[e];
-    T E[EW];
-    load<T, EW>(v.se + (size_t)EW * e, E);
-    T* a = var ? v.al + 4 * (size_t)e : nullptr;
-    const T kind = a ? a[3] : (T)0;
-    // a slider end's line anchor sits t0 = E[7] along the axis from the given
-    // one (a slider's rest length is 0, so E[7] holds no phi^-): the same line,
-    // re-anchored near the point every step so that the bond vector, whose
-    // across-axis part is the force, stays short (in FP32 a long one would lose
-    // that part to rounding)
-    T xs[3] = {E[0], E[1], E[2]}, xo[3] = {E[4], E[5], E[6]};
-    if (kind == (T)AL_SLIDER_POINT) {
-#pragma unroll
-      for (int r = 0; r < 3; ++r) xo[r] = fma(E[7], a[r], xo[r]);
-    } else if (kind == (T)AL_SLIDER_LINE) {
-#pragma unroll
-      for (int r = 0; r < 3; ++r) xs[r] = fma(E[7], a[r], xs[r]);
+  // a wave none of whose bodies has variable ends takes the quadratic loop
+  // below; otherwise the whole wave takes the general one (a divergent wave
+  // would run both loops one after the other).  Both form every end's terms
+  // with the same operations in the same order, so the choice does not change
+  // the bits.
+  if (!wave_any(var)) {
+    // quadratic ends only: the lanes of a body take its ends in turn, two ends
+    // per round with both ends' loads (record and partner state) in flight
+    // together; each end's terms are still added in end order
+    for (int e = v.srow[i] + sub; e < e1; e += 2 * LPB) {
+      const int eb = e + LPB;
+      const bool hb = eb < e1;
+      const int ja = v.se_partner[e];
+      const int jb = hb ? v.se_partner[eb] : -1;
+      T Ea[EW], Eb[EW], qa[QR], qb[QR];
+      load<T, EW>(v.se + (size_t)EW * e, Ea);
+      if (hb) load<T, EW>(v.se + (size_t)EW * eb, Eb);
+      if (ja >= 0) load<T, QR>(qs + (size_t)QR * (ja - qoff), qa);
+      if (jb >= 0) load<T, QR>(qs + (size_t)QR * (jb - qoff), qb);
+      T d[3], f[3];
+      bond_vec<T>(q, Ea, ja < 0 ? (const T*)nullptr : qa, Ea + 4, d);
+      quad_end_force(Ea, d, f);
+      add_JT(rb, Ea, f[0], f[1], f[2]);
+      if (hb) {
+        bond_vec<T>(q, Eb, jb < 0 ? (const T*)nullptr : qb, Eb + 4, d);
+        quad_end_force(Eb, d, f);
+        add_JT(rb, Eb, f[0], f[1], f[2]);
+      }
     }
-    T d[3], f[3];
-    T qj[QR];
-    if (j < 0) {
-      bond_vec<T>(q, xs, nullptr, xo, d);
-    } else {
-      load<T, QR>(qs + (size_t)QR * (j - qoff), qj);
-      bond_vec<T>(q, xs, qj, xo, d);
-    }
-    if (kind == (T)AL_SLIDER_POINT) {
-      // fixed weight at the own point (in the static block), drawn to the foot
-      T dp[3];
-      const T t = slider_end(d, j < 0 ? (const T*)nullptr : qj + 3, a, dp);
-      end_force(E[3], (T)0, dp, f);
-      add_JT(rb, E, f[0], f[1], f[2]);
-      if (k == K - 1) v.se[(size_t)EW * e + 7] = E[7] - t;  // the foot is -t from the anchor
-    } else if (kind == (T)AL_SLIDER_LINE) {
-      // the own point is the foot xf = x_s + t u, so its weight moves every iteration
-      T dp[3];
-      const T t = slider_end(d, q + 3, a, dp);
-      const T xf[3] = {fma(t, a[0], xs[0]), fma(t, a[1], xs[1]), fma(t, a[2], xs[2])};
-      end_force(E[3], (T)0, dp, f);
-      add_JT(rb, xf, f[0], f[1], f[2]);
-      block_add_end(dB, (double)E[3], (double)xf[0], (double)xf[1], (double)xf[2]);
-      refactor = true;
-      if (k == K - 1) v.se[(size_t)EW * e + 7] = E[7] + t;
-    } else if (kind != (T)0) {
-      const T w = kind > (T)0 ? augmented_end(a, d, (T)(S.h * S.h), (T)S.al_beta, f)
-                              : polynomial_end(a, d, (T)(S.h * S.h), f);
-      block_add_end(dB, (double)w, (double)E[0], (double)E[1], (double)E[2]);
-      refactor = true;
-      add_JT(rb, E, f[0], f[1], f[2]);
-    } else {
-      quad_end_force(E, d, f);
-      add_JT(rb, E, f[0], f[1], f[2]);
+  } else {
+    // the general loop (augmented, polynomial and slider ends among others),
+    // one end at a time
+    for (int e = v.srow[i] + sub; e < e1; e += LPB) {
+      const int j = v.se_partner[e];
+      T E[EW];
+      load<T, EW>(v.se + (size_t)EW * e, E);
+      T* a = var ? v.al + 4 * (size_t)e : nullptr;
+      const T kind = a ? a[3] : (T)0;
+      // a slider end's line anchor sits t0 = E[7] along the axis from the given
+      // one (a slider's rest length is 0, so E[7] holds no phi^-): the same line,
+      // re-anchored near the point every step so that the bond vector, whose
+      // across-axis part is the force, stays short (in FP32 a long one would lose
+      // that part to rounding)
+      T xs[3] = {E[0], E[1], E[2]}, xo[3] = {E[4], E[5], E[6]};
+      if (kind == (T)AL_SLIDER_POINT) {
+#pragma unroll
+        for (int r = 0; r < 3; ++r) xo[r] = fma(E[7], a[r], xo[r]);
+      } else if (kind == (T)AL_SLIDER_LINE) {
+#pragma unroll
+        for (int r = 0; r < 3; ++r) xs[r] = fma(E[7], a[r], xs[r]);
+      }
+      T d[3], f[3];
+      T qj[QR];
+      if (j < 0) {
+        bond_vec<T>(q, xs, nullptr, xo, d);
+      } else {
+        load<T, QR>(qs + (size_t)QR * (j - qoff), qj);
+        bond_vec<T>(q, xs, qj, xo, d);
+      }
+      if (kind == (T)AL_SLIDER_POINT) {
+        // fixed weight at the own point (in the static block), drawn to the foot
+        T dp[3];
+        const T t = slider_end(d, j < 0 ? (const T*)nullptr : qj + 3, a, dp);
+        end_force(E[3], (T)0, dp, f);
+        add_JT(rb, E, f[0], f[1], f[2]);
+        if (k == K - 1) v.se[(size_t)EW * e + 7] = E[7] - t;  // the foot is -t from the anchor
+      } else if (kind == (T)AL_SLIDER_LINE) {
+        // the own point is the foot xf = x_s + t u, so its weight moves every iteration
+        T dp[3];
+        const T t = slider_end(d, q + 3, a, dp);
+        const T xf[3] = {fma(t, a[0], xs[0]), fma(t, a[1], xs[1]), fma(t, a[2], xs[2])};
+        end_force(E[3], (T)0, dp, f);
+        add_JT(rb, xf, f[0], f[1], f[2]);
+        block_add_end(dB, (double)E[3], (double)xf[0], (double)xf[1], (double)xf[2]);
+        refactor = true;
+        if (k == K - 1) v.se[(size_t)EW * e + 7] = E[7] + t;
+      } else if (kind != (T)0) {
+        const T w = kind > (T)0 ? augmented_end(a, d, (T)(S.h * S.h), (T)S.al_beta, f)
+                                : polynomial_end(a, d, (T)(S.h * S.h), f);
+        block_add_end(dB, (double)w, (double)E[0], (double)E[1], (double)E[2]);
+        refactor = true;
+        add_JT(rb, E, f[0], f[1], f[2]);
+      } else {
+        quad_end_force(E, d, f);
+        add_JT(rb, E, f[0], f[1], f[2]);
+      }
     }
   }
   if constexpr (CONTACT) {
