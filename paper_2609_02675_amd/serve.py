@@ -111,6 +111,10 @@ class Server:
         peak = 0
         t0 = self.clock()
         order = sorted(range(len(requests)), key=lambda k: requests[k].arrival_s)
+        # set when the head of the queue found no room: room appears only when a
+        # scene leaves, so admission is not tried again until one does (a failed
+        # admission costs a host-side scene build)
+        blocked = False
 
         def reject(k, reason):
             req = requests[k]
@@ -121,7 +125,7 @@ class Server:
 
         def evict(slot, reason):
             # a diverged scene: its work leaves the throughput, its slot is freed
-            nonlocal body_its
+            nonlocal body_its, blocked
             r = resident.pop(slot)
             req = requests[r["k"]]
             body_its -= r["done"] * r["n"] * r["iters"]
@@ -131,6 +135,7 @@ class Server:
                                      state=None, residual=float("nan"), status="diverged",
                                      reason=reason)
             b.release(slot)
+            blocked = False
 
         while nxt < len(order) or pending or resident:
             now = self.clock() - t0
@@ -140,7 +145,7 @@ class Server:
                 pending.append(order[nxt])
                 nxt += 1
             # admit in arrival order while room is free
-            while pending:
+            while pending and not (blocked and resident):
                 k = pending[0]
                 req = requests[k]
                 try:
@@ -158,6 +163,7 @@ class Server:
                         pending.popleft()
                         reject(k, "larger than the HBM budget")
                         continue
+                    blocked = True
                     break
                 pending.popleft()
                 t_adm = self.clock() - t0
@@ -198,6 +204,7 @@ class Server:
                                          admitted_s=r["admitted"], finished_s=self.clock() - t0,
                                          state=st, residual=rho)
                 b.release(slot)
+                blocked = False
         wall = self.clock() - t0
         lat = np.asarray(lat) if lat else np.zeros(1)
         waits = np.asarray(waits) if waits else np.zeros(1)

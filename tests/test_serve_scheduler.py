@@ -18,8 +18,11 @@ class OracleBatch:
         self.budget, self.max_slots, self.used = budget, max_slots, 0
         self.slots = {}
         self.admitted = []
+        self.admit_calls = 0
+        self.releases = 0
 
     def admit(self, scene, steps):
+        self.admit_calls += 1
         need = fake_bytes(scene)
         if self.used + need > self.budget or len(self.slots) >= self.max_slots:
             return None
@@ -52,6 +55,7 @@ class OracleBatch:
         return float(self.slots[slot]["o"].residuals()[-1])
 
     def release(self, slot):
+        self.releases += 1
         self.used -= self.slots.pop(slot)["bytes"]
 
     def memory(self):
@@ -78,6 +82,9 @@ def test_scheduler_admits_in_order_within_budget_and_completes_all():
     assert fb.admitted == [reqs[k].scene.name for k in fits]  # FIFO
     assert st.peak_bytes <= budget
     assert st.max_resident < len(reqs)  # requests had to wait for room
+    # a request that found no room is tried again only after a scene left: at
+    # most one failed admission per release (plus the ones that were admitted)
+    assert fb.admit_calls <= len(fits) + fb.releases
     for k in fits:
         assert results[k].steps == reqs[k].steps
         o = oracle.Oracle(reqs[k].scene)
