@@ -488,14 +488,17 @@ struct Engine {
 
   // one step of the resident scenes: grid[0] workgroups over the contact list,
   // grid[1] over the other (extents rounded by the caller; extra workgroups leave)
-  void launch_resident(const int* grid, hipStream_t st) {
+  // n_driven > 0: the resident scenes' driven anchors and refactor run inside
+  // the resident kernel (no flat-path scene shares the step)
+  void launch_resident(const int* grid, int n_driven, hipStream_t st) {
     View<T> v = view();
+    const DrivenTable dt{n_driven, drv_scene, drv_end_i, drv_end_j, drv_param, mass64};
     if (grid[0] > 0)
       hipLaunchKernelGGL((k_resident_step<T, 4, true>), dim3(grid[0]), dim3(Resident<T>::NT), 0, st, v,
-                         (const int*)res_list[0], (const int*)res_count);
+                         (const int*)res_list[0], (const int*)res_count, dt);
     if (grid[1] > 0)
       hipLaunchKernelGGL((k_resident_step<T, 1, false>), dim3(grid[1]), dim3(Resident<T>::NT), 0, st, v,
-                         (const int*)res_list[1], (const int*)(res_count + 1));
+                         (const int*)res_list[1], (const int*)(res_count + 1), dt);
   }
 
   // FP64 block factorisation of bodies [first, first + count)
@@ -519,14 +522,17 @@ struct Engine {
                         const int* resident_grid = nullptr, bool flat = true) {
     View<T> v = view();
     const dim3 g = grid_for(cap.n, 256), b(256);
-    if (n_driven > 0) {
+    // with every scene resident the driven update and refactor run in the
+    // resident kernel, after the contact construction, which reads neither
+    const bool drive_inside = resident_grid && !flat;
+    if (n_driven > 0 && !drive_inside) {
       hipLaunchKernelGGL(k_update_driven<T>, grid_for(n_driven, 64), dim3(64), 0, st, v, n_driven,
                          (const int*)drv_scene, (const int*)drv_end_i, (const int*)drv_end_j,
                          (const double*)drv_param);
       launch_factor(st);
     }
     if (contacts) launch_contacts(n_scenes, st);
-    if (resident_grid) launch_resident(resident_grid, st);
+    if (resident_grid) launch_resident(resident_grid, drive_inside ? n_driven : 0, st);
     if (!flat) return;
     hipLaunchKernelGGL(k_predict<T>, g, b, 0, st, v);
     double* hn = history ? rh_num : nullptr;

@@ -30,13 +30,24 @@ struct Resident<double> {
   static constexpr int NT = 512, RMAX = 512;
 };
 
+// the driven bonds of the scenes in the lists (Sec. 5.3.3, read as in
+// k_update_driven) and the FP64 masses the refactor needs: a resident scene
+// with driven bonds turns their anchors and refactors its bodies' blocks at
+// the start of its step, as the flat path's k_update_driven and k_factor do
+struct DrivenTable {
+  int n;
+  const int *scene, *end_i, *end_j;
+  const double *param, *mass64;
+};
+
 // list: scene slots, one workgroup each (entries past *n_list leave at once, so
 // the grid can stay fixed while scenes come and go); CONTACT: the list holds
 // the contact scenes.  LPB lanes per body as in the flat iteration: four for
 // contact scenes (their ends split among them), one otherwise; a scene larger
 // than NT / LPB bodies takes several passes per iteration.
 template <typename T, int LPB, bool CONTACT>
-__global__ void __launch_bounds__(Resident<T>::NT) k_resident_step(View<T> v, const int* list, const int* n_list) {
+__global__ void __launch_bounds__(Resident<T>::NT) k_resident_step(View<T> v, const int* list, const int* n_list,
+                                                                   DrivenTable dt) {
   constexpr int QR = Rec<T>::Q, NT = Resident<T>::NT, RMAX = Resident<T>::RMAX, BPP = NT / LPB;
   __shared__ __align__(16) T lq[2][RMAX * QR];
   __shared__ double rn[NT], rd[NT];
@@ -46,6 +57,20 @@ __global__ void __launch_bounds__(Resident<T>::NT) k_resident_step(View<T> v, co
   const SceneDev& S = v.scenes[sc];
   if (S.step >= S.steps_total || S.n_bodies > RMAX) return;
   const int off = S.body_off, n = S.n_bodies, K = S.iters;
+  if (dt.n > 0) {
+    // driven anchors at this step's time, then every block of the scene
+    // refactored (the same functions as the flat path's kernels)
+    bool any = false;
+    for (int b = t; b < dt.n; b += NT)
+      if (dt.scene[b] == sc) {
+        update_driven_entry(v, b, sc, dt.end_i, dt.end_j, dt.param);
+        any = true;
+      }
+    if (__syncthreads_or(any)) {
+      for (int b = t; b < n; b += NT) factor_body(v, dt.mass64, off + b);
+      __syncthreads();
+    }
+  }
   // prediction (Algorithm 1), as k_predict: s in global memory, q^0 = s in LDS;
   // a pinned body keeps q^n, in both buffers
   for (int b = t; b < n; b += NT) {

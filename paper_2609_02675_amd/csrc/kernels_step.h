@@ -142,11 +142,7 @@ __device__ __forceinline__ T slider_end(const T* d0, const T* A, const T* u, T* 
 
 // mass64: 8 doubles per body (m, Pi sym 6, -)
 template <typename T>
-__global__ void __launch_bounds__(256) k_factor(View<T> v, const double* mass64, int first, int count) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= count) return;
-  const int i = first + t;
-  if (i >= v.n) return;
+__device__ __forceinline__ void factor_body(const View<T>& v, const double* mass64, int i) {
   const int sc = v.bscene[i];
   if (sc < 0 || (v.flags[i] & F_PINNED)) return;
   const double h2 = v.scenes[sc].h * v.scenes[sc].h;
@@ -166,6 +162,14 @@ __global__ void __launch_bounds__(256) k_factor(View<T> v, const double* mass64,
   for (int k = 0; k < 10; ++k) ft[k] = (T)f[k];
   ft[10] = ft[11] = (T)0;
   store<T, FW>(v.fac + (size_t)FW * i, ft);
+}
+template <typename T>
+__global__ void __launch_bounds__(256) k_factor(View<T> v, const double* mass64, int first, int count) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= count) return;
+  const int i = first + t;
+  if (i >= v.n) return;
+  factor_body(v, mass64, i);
 }
 
 // contribution of one quadratic bond end with bond vector d = y_o - y_s, scaled
@@ -271,36 +275,11 @@ __device__ __forceinline__ void iterate_body(const View<T>& v, int k, double* rh
   Block dB{};  // contact and augmented part of H^k - H (this lane's ends)
   const bool var = (v.flags[i] & F_VARIABLE) != 0;
   const int e1 = v.srow_end[i];
-  // a wave none of whose bodies has variable ends takes the quadratic loop
-  // below; otherwise the whole wave takes the general one (a divergent wave
-  // would run both loops one after the other).  Both form every end's terms
-  // with the same operations in the same order, so the choice does not change
-  // the bits.
-  if (!wave_any(var)) {
-    // quadratic ends only: the lanes of a body take its ends in turn, two ends
-    // per round with both ends' loads (record and partner state) in flight
-    // together; each end's terms are still added in end order
-    for (int e = v.srow[i] + sub; e < e1; e += 2 * LPB) {
-      const int eb = e + LPB;
-      const bool hb = eb < e1;
-      const int ja = v.se_partner[e];
-      const int jb = hb ? v.se_partner[eb] : -1;
-      T Ea[EW], Eb[EW], qa[QR], qb[QR];
-      load<T, EW>(v.se + (size_t)EW * e, Ea);
-      if (hb) load<T, EW>(v.se + (size_t)EW * eb, Eb);
-      if (ja >= 0) load<T, QR>(qs + (size_t)QR * (ja - qoff), qa);
-      if (jb >= 0) load<T, QR>(qs + (size_t)QR * (jb - qoff), qb);
-      T d[3], f[3];
-      bond_vec<T>(q, Ea, ja < 0 ? (const T*)nullptr : qa, Ea + 4, d);
-      quad_end_force(Ea, d, f);
-      add_JT(rb, Ea, f[0], f[1], f[2]);
-      if (hb) {
-        bond_vec<T>(q, Eb, jb < 0 ? (const T*)nullptr : qb, Eb + 4, d);
-        quad_end_force(Eb, d, f);
-        add_JT(rb, Eb, f[0], f[1], f[2]);
-      }
-    }
-  } else {
+  // a wave with a body that has variable ends takes the general loop, any
+  // other wave the quadratic loop below (a divergent wave would run both loops
+  // one after the other).  Both form every end's terms with the same
+  // operations in the same order, so the choice does not change the bits.
+  if (wave_any(var)) {
     // the general loop (augmented, polynomial and slider ends among others),
     // one end at a time
     for (int e = v.srow[i] + sub; e < e1; e += LPB) {
@@ -356,6 +335,30 @@ __device__ __forceinline__ void iterate_body(const View<T>& v, int k, double* rh
       } else {
         quad_end_force(E, d, f);
         add_JT(rb, E, f[0], f[1], f[2]);
+      }
+    }
+  } else {
+    // quadratic ends only: the lanes of a body take its ends in turn, two ends
+    // per round with both ends' loads (record and partner state) in flight
+    // together; each end's terms are still added in end order
+    for (int e = v.srow[i] + sub; e < e1; e += 2 * LPB) {
+      const int eb = e + LPB;
+      const bool hb = eb < e1;
+      const int ja = v.se_partner[e];
+      const int jb = hb ? v.se_partner[eb] : -1;
+      T Ea[EW], Eb[EW], qa[QR], qb[QR];
+      load<T, EW>(v.se + (size_t)EW * e, Ea);
+      if (hb) load<T, EW>(v.se + (size_t)EW * eb, Eb);
+      if (ja >= 0) load<T, QR>(qs + (size_t)QR * (ja - qoff), qa);
+      if (jb >= 0) load<T, QR>(qs + (size_t)QR * (jb - qoff), qb);
+      T d[3], f[3];
+      bond_vec<T>(q, Ea, ja < 0 ? (const T*)nullptr : qa, Ea + 4, d);
+      quad_end_force(Ea, d, f);
+      add_JT(rb, Ea, f[0], f[1], f[2]);
+      if (hb) {
+        bond_vec<T>(q, Eb, jb < 0 ? (const T*)nullptr : qb, Eb + 4, d);
+        quad_end_force(Eb, d, f);
+        add_JT(rb, Eb, f[0], f[1], f[2]);
       }
     }
   }
@@ -617,12 +620,8 @@ __global__ void __launch_bounds__(256) k_reduce_history(int n, int K, const doub
 // the step being taken.  Updates the i-side end's partner anchor and the j-side
 // end's own anchor (T and FP64 copies).
 template <typename T>
-__global__ void k_update_driven(View<T> v, int n_driven, const int* d_scene, const int* d_end_i,
-                                const int* d_end_j, const double* d_param) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= n_driven) return;
-  const int sc = d_scene[b];
-  if (sc < 0) return;  // unused table entry
+__device__ __forceinline__ void update_driven_entry(const View<T>& v, int b, int sc, const int* d_end_i,
+                                                    const int* d_end_j, const double* d_param) {
   const SceneDev& S = v.scenes[sc];
   if (S.step >= S.steps_total) return;
   const double t = S.t0 + (double)(S.step + 1) * S.h;
@@ -651,6 +650,15 @@ __global__ void k_update_driven(View<T> v, int n_driven, const int* d_scene, con
     e64[1] = x1;
     e64[2] = x2;
   }
+}
+template <typename T>
+__global__ void k_update_driven(View<T> v, int n_driven, const int* d_scene, const int* d_end_i,
+                                const int* d_end_j, const double* d_param) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= n_driven) return;
+  const int sc = d_scene[b];
+  if (sc < 0) return;  // unused table entry
+  update_driven_entry(v, b, sc, d_end_i, d_end_j, d_param);
 }
 
 __global__ void k_end_step(SceneDev* scenes, int n_scenes) {

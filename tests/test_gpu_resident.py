@@ -27,7 +27,8 @@ def _cases(prec):
             S.mass_ratio_chain(augmented=True, precision=prec),              # augmented bonds
             S.spring_net(order=4, precision=prec),                           # polynomial bonds
             S.linkage("slider", drive_amp_deg=60.0, precision=prec),         # slider and driven bonds
-            S.slider_pair(precision=prec)]                                   # slider line side on a free body
+            S.slider_pair(precision=prec),                                   # slider line side on a free body
+            S.granular_bed_quadruped(nx=6, nz=6, ny=2, precision=prec)]      # contacts and driven bonds
 
 
 @pytest.mark.parametrize("prec", [S.PREC_FP32, S.PREC_FP64], ids=["fp32", "fp64"])
