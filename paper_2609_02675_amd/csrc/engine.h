@@ -543,16 +543,20 @@ struct Engine {
       hipLaunchKernelGGL(k_zero_double, gz, dim3(256), 0, st, rh_num, nh);
       hipLaunchKernelGGL(k_zero_double, gz, dim3(256), 0, st, rh_den, nh);
     }
+    // the iterations launch one wave per workgroup, so that a small scene's
+    // waves spread over as many CUs (and L1 caches) as there are waves
     constexpr int LPB = 4;  // lanes per body when contacts are present
-    const dim3 gc = grid_for((int)std::min<long long>((long long)cap.n * LPB, INT_MAX), 256);
-    const dim3 gw((unsigned)std::max(1, (wave_grid + 3) / 4));
+    const dim3 w1(64);
+    const dim3 gc = grid_for((int)std::min<long long>((long long)cap.n * LPB, INT_MAX), 64);
+    const dim3 g1 = grid_for(cap.n, 64);
+    const dim3 gw((unsigned)std::max(1, wave_grid));
     for (int k = 0; k < kmax; ++k) {
       if (waves && !history)
-        hipLaunchKernelGGL(k_iterate_waves<T>, gw, b, 0, st, v, k, waves, n_waves);
+        hipLaunchKernelGGL(k_iterate_waves<T>, gw, w1, 0, st, v, k, waves, n_waves);
       else if (contacts)
-        hipLaunchKernelGGL((k_iterate<T, true, LPB>), gc, b, 0, st, v, k, hn, hd);
+        hipLaunchKernelGGL((k_iterate<T, true, LPB>), gc, w1, 0, st, v, k, hn, hd);
       else
-        hipLaunchKernelGGL((k_iterate<T, false, 1>), g, b, 0, st, v, k, hn, hd);
+        hipLaunchKernelGGL((k_iterate<T, false, 1>), g1, w1, 0, st, v, k, hn, hd);
     }
     hipLaunchKernelGGL(k_finish<T>, g, b, 0, st, v);
     if (!finish_scenes) return;
