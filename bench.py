@@ -67,6 +67,16 @@ def tile_traffic(steps_per_launch, tile_bodies, workload):
     """HBM bytes per tile-kernel launch from the committed counter profile, if the
     kernel sources still hash to what was profiled and the profile ran the same
     workload, tile size and steps per launch; else None."""
+    return tile_profile_value("traffic_bytes_per_launch", steps_per_launch, tile_bodies, workload)
+
+
+def tile_valu(steps_per_launch, tile_bodies, workload):
+    """VALU instructions (wave64) per tile-kernel launch, SQ_INSTS_VALU from the
+    committed counter profile, under the same conditions as tile_traffic."""
+    return tile_profile_value("valu_insts_per_launch", steps_per_launch, tile_bodies, workload)
+
+
+def tile_profile_value(key, steps_per_launch, tile_bodies, workload):
     import hashlib
     h = hashlib.sha256()
     for f in TILE_SOURCES:
@@ -78,7 +88,7 @@ def tile_traffic(steps_per_launch, tile_bodies, workload):
         return None
     import re
     m = re.search(r"kernel-source-sha256-16:\s*([0-9a-f]{16})", text)
-    t = re.search(r"traffic_bytes_per_launch:\s*(\d+)", text)
+    t = re.search(key + r":\s*(\d+)", text)
     n = re.search(r"steps_per_launch:\s*(\d+)", text)
     tb = re.search(r"tile_bodies:\s*(\d+)", text)
     w = re.search(r"workload:\s*(\S+)", text)
@@ -426,7 +436,13 @@ def main():
     hbm_ach = tbytes / (tile_launch_ms / 1e3)
     alu_ach = tile_flops / (tile_launch_ms / 1e3)
     traffic = tile_traffic(spl, lay["tile_bodies"], f"batched_chains_{len(scenes)}")
-    common = dict(traffic=traffic, traffic_unit="bytes/launch", kernel="k_tile_step<float>",
+    # counter figure beside the flop estimate: wave64 VALU instructions of the
+    # profiled launch (SQ_INSTS_VALU) and the flops the estimate gives each of
+    # their lane-operations
+    valu = tile_valu(spl, lay["tile_bodies"], f"batched_chains_{len(scenes)}")
+    common = dict(traffic=traffic, traffic_unit="bytes/launch", valu_insts_per_launch=valu,
+                  est_flops_per_valu_lane_op=None if valu is None else tile_flops / (64.0 * valu),
+                  kernel="k_tile_step<float>",
                   steps_per_launch=spl, kernel_ms_per_launch=tile_launch_ms, kernel_ms_per_step=tile_ms,
                   flops_per_launch=tile_flops, bytes_per_launch=tbytes)
     if alu_ach / FP32_PEAK >= hbm_ach / HBM_PEAK:
