@@ -447,6 +447,9 @@ struct Engine {
 
   // contact-bond construction for every contact scene among the bodies
   // [0, min(cap.n, contact bodies))
+  // a single contact scene of at most this many bodies takes the all-pairs broad
+  // phase (at most 2.1M pair threads)
+  static constexpr int BRUTE_MAX = 2048;
   void launch_contacts(int n_scenes, hipStream_t st) {
     View<T> v = view();
     v.n = std::min(cap.n, ncb);
@@ -456,21 +459,28 @@ struct Engine {
     hipLaunchKernelGGL(k_contact_prep<T>, grid_for(std::max(n, REACH_BINS * n_scenes), 256), dim3(256), 0,
                        st, v, cb, n_scenes);
     hipLaunchKernelGGL(k_contact_reach<T>, grid_for(n, 256), dim3(256), 0, st, v, cb);
-    hipLaunchKernelGGL(k_contact_cells, grid_for(n_scenes, 64), dim3(64), 0, st, scenes, n_scenes,
-                       (const unsigned long long*)reach, (const int*)hist);
-    hipLaunchKernelGGL(k_zero_int, grid_for(tb, 256), dim3(256), 0, st, bucket_count, tb);
-    hipLaunchKernelGGL(k_zero_int, grid_for(tb, 256), dim3(256), 0, st, bucket_fill, tb);
-    hipLaunchKernelGGL(k_hash_count<T>, grid_for(n, 256), dim3(256), 0, st, v, cb);
-    const int nb = (tb + 1023) / 1024;
-    hipLaunchKernelGGL(k_scan_block, dim3(nb), dim3(1024), 0, st, (const int*)bucket_count,
-                       bucket_start, tb, scan_tmp);
-    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, st, scan_tmp, nb, bucket_start + tb);
-    hipLaunchKernelGGL(k_scan_add, grid_for(tb, 256), dim3(256), 0, st, bucket_start, tb,
-                       (const int*)scan_tmp);
-    hipLaunchKernelGGL(k_hash_fill<T>, grid_for(n, 256), dim3(256), 0, st, v, cb);
-    hipLaunchKernelGGL(k_broad_small<T>, grid_for((int)std::min<long long>((long long)n * BLPB, INT_MAX), 256),
-                       dim3(256), 0, st, v, cb);
-    hipLaunchKernelGGL(k_broad_large<T>, dim3(256), dim3(256), 0, st, v, cb);
+    if (n_scenes == 1 && n <= BRUTE_MAX) {
+      // one scene of few bodies: all pairs directly, no spatial hash
+      const long long threads = (long long)n + (long long)n * (n - 1) / 2;
+      hipLaunchKernelGGL(k_broad_brute<T>, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, v, cb,
+                         0, n);
+    } else {
+      hipLaunchKernelGGL(k_contact_cells, grid_for(n_scenes, 64), dim3(64), 0, st, scenes, n_scenes,
+                         (const unsigned long long*)reach, (const int*)hist);
+      hipLaunchKernelGGL(k_zero_int, grid_for(tb, 256), dim3(256), 0, st, bucket_count, tb);
+      hipLaunchKernelGGL(k_zero_int, grid_for(tb, 256), dim3(256), 0, st, bucket_fill, tb);
+      hipLaunchKernelGGL(k_hash_count<T>, grid_for(n, 256), dim3(256), 0, st, v, cb);
+      const int nb = (tb + 1023) / 1024;
+      hipLaunchKernelGGL(k_scan_block, dim3(nb), dim3(1024), 0, st, (const int*)bucket_count,
+                         bucket_start, tb, scan_tmp);
+      hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, st, scan_tmp, nb, bucket_start + tb);
+      hipLaunchKernelGGL(k_scan_add, grid_for(tb, 256), dim3(256), 0, st, bucket_start, tb,
+                         (const int*)scan_tmp);
+      hipLaunchKernelGGL(k_hash_fill<T>, grid_for(n, 256), dim3(256), 0, st, v, cb);
+      hipLaunchKernelGGL(k_broad_small<T>, grid_for((int)std::min<long long>((long long)n * BLPB, INT_MAX), 256),
+                         dim3(256), 0, st, v, cb);
+      hipLaunchKernelGGL(k_broad_large<T>, dim3(256), dim3(256), 0, st, v, cb);
+    }
     const int ng = std::min(8192, std::max(1, (pcap + 255) / 256));
     hipLaunchKernelGGL(k_narrow_pairs<T>, dim3(ng), dim3(256), 0, st, v, cb);
     hipLaunchKernelGGL(k_sort_contacts<T>, dim3((unsigned)std::max(1, n)), dim3(64), 0, st, v);

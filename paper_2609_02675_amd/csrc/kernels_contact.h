@@ -27,6 +27,8 @@
 //   k_broad_large    one workgroup per large body: small partners over the cells
 //                    its reach spans (or over the scene's bodies when that is
 //                    fewer), large partners of higher index over the scene
+//   k_broad_brute    instead of the hash and both broad kernels, for a single
+//                    scene of few bodies: one thread per pair
 //   k_narrow_pairs   one thread per candidate pair: narrow phase, bond ends into
 //                    the owners' staging slots
 //   k_sort_contacts  one wave per body, ends copied in canonical key order to
@@ -767,6 +769,49 @@ __global__ void __launch_bounds__(256) k_broad_large(View<T> v, ContactBuf cb) {
 }
 
 // one thread per candidate pair (grid-stride)
+// A single scene of few bodies, [first, first + n): every pair tested directly,
+// one thread per pair, and one thread per body for its plane contacts.  The
+// candidate rule is the broad kernels' (bounding spheres of reach R + pm, the
+// same filters), so the pairs proposed are the same; only the spatial hash and
+// its eight launches are gone.  The narrow phase repeats the exact test and the
+// sort fixes the order, so the contact set and its order do not depend on which
+// broad phase found the pairs.
+template <typename T>
+__global__ void __launch_bounds__(256) k_broad_brute(View<T> v, ContactBuf cb, int first, int n) {
+  __shared__ int2 lbuf[PAIR_LDS];
+  __shared__ int lcount, lbase;
+  if (threadIdx.x == 0) lcount = 0;
+  __syncthreads();
+  const PairBuf pb{lbuf, &lcount, &lbase};
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long npairs = (long long)n * (n - 1) / 2;
+  if (t < n) {
+    const int i = first + (int)t;
+    const int sc = v.bscene[i];
+    if (contact_body(v, i, sc) && !(v.flags[i] & F_PINNED) && v.scenes[sc].n_planes > 0) {
+      BodyGeo<T> gi;
+      body_geo(v, i, gi);
+      plane_contacts(v, cb, sc, i, gi, own_pm(v, i, sc, gi));
+    }
+  } else if (t < n + npairs) {
+    // pair p = b (b - 1) / 2 + a with 0 <= a < b < n
+    const long long p = t - n;
+    long long b = (long long)((1.0 + sqrt(1.0 + 8.0 * (double)p)) * 0.5);
+    while (b * (b - 1) / 2 > p) --b;
+    while ((b + 1) * b / 2 <= p) ++b;
+    const int i = first + (int)(p - b * (b - 1) / 2), j = first + (int)b;
+    const int sc = v.bscene[i];
+    if (sc == v.bscene[j] && contact_body(v, i, sc) && contact_body(v, j, sc) &&
+        pair_allowed((v.flags[i] & F_PINNED) != 0, v.group[i], v.flags[j], v.group[j])) {
+      double ci[3], cj[3];
+      centre_of(v, i, ci);
+      centre_of(v, j, cj);
+      if (spheres_near(ci, cb.breach[i], cj, cb.breach[j])) append_pair(pb, cb, v.health, sc, i, j);
+    }
+  }
+  flush_pairs(pb, v, cb);
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_narrow_pairs(View<T> v, ContactBuf cb) {
   const int np = min(cb.counters[1], cb.pcap);
