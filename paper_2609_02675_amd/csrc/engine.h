@@ -14,6 +14,7 @@
 
 #include "host_scene.h"
 #include "kernels_contact.h"
+#include "kernels_flat.h"
 #include "kernels_resident.h"
 #include "kernels_step.h"
 #include "kernels_tile.h"
@@ -128,6 +129,7 @@ struct Engine {
   // body), [1] the others; capacity one entry per scene slot, counts on the device
   int* res_list[2] = {nullptr, nullptr};
   int* res_count = nullptr;
+  bool res_variable = true;  // some resident scene has variable ends
 
   std::vector<void*> allocs;
   std::string err;
@@ -487,7 +489,10 @@ struct Engine {
   }
 
   // the scene slots the resident step kernel runs: [0] contact scenes, [1] others
-  pabd_status set_resident(const std::vector<int>& contact, const std::vector<int>& other, hipStream_t st) {
+  // variable: some listed scene has variable ends (augmented, polynomial, slider)
+  pabd_status set_resident(const std::vector<int>& contact, const std::vector<int>& other, bool variable,
+                           hipStream_t st) {
+    res_variable = variable;
     const int counts[2] = {(int)contact.size(), (int)other.size()};
     if (counts[0]) PABD_HIP(hipMemcpyAsync(res_list[0], contact.data(), counts[0] * sizeof(int), hipMemcpyHostToDevice, st));
     if (counts[1]) PABD_HIP(hipMemcpyAsync(res_list[1], other.data(), counts[1] * sizeof(int), hipMemcpyHostToDevice, st));
@@ -503,12 +508,19 @@ struct Engine {
   void launch_resident(const int* grid, int n_driven, hipStream_t st) {
     View<T> v = view();
     const DrivenTable dt{n_driven, drv_scene, drv_end_i, drv_end_j, drv_param, mass64};
+    if (res_variable)
+      n_driven > 0 ? launch_resident_as<2, true>(v, grid, dt, st) : launch_resident_as<2, false>(v, grid, dt, st);
+    else
+      n_driven > 0 ? launch_resident_as<1, true>(v, grid, dt, st) : launch_resident_as<1, false>(v, grid, dt, st);
+  }
+  template <int ENDS, bool DRIVEN>
+  void launch_resident_as(const View<T>& v, const int* grid, const DrivenTable& dt, hipStream_t st) {
     if (grid[0] > 0)
-      hipLaunchKernelGGL((k_resident_step<T, 4, true>), dim3(grid[0]), dim3(Resident<T>::NT), 0, st, v,
-                         (const int*)res_list[0], (const int*)res_count, dt);
+      hipLaunchKernelGGL((k_resident_step<T, 4, true, ENDS, DRIVEN>), dim3(grid[0]), dim3(Resident<T>::NT), 0,
+                         st, v, (const int*)res_list[0], (const int*)res_count, dt);
     if (grid[1] > 0)
-      hipLaunchKernelGGL((k_resident_step<T, 1, false>), dim3(grid[1]), dim3(Resident<T>::NT), 0, st, v,
-                         (const int*)res_list[1], (const int*)(res_count + 1), dt);
+      hipLaunchKernelGGL((k_resident_step<T, 1, false, ENDS, DRIVEN>), dim3(grid[1]), dim3(Resident<T>::NT), 0,
+                         st, v, (const int*)res_list[1], (const int*)(res_count + 1), dt);
   }
 
   // FP64 block factorisation of bodies [first, first + count)

@@ -12,6 +12,7 @@
 
 #include "common.h"
 #include "device_math.h"
+#include "kernels_flat.h"
 #include "kernels_step.h"
 
 namespace pabd {
@@ -45,7 +46,10 @@ struct DrivenTable {
 // the contact scenes.  LPB lanes per body as in the flat iteration: four for
 // contact scenes (their ends split among them), one otherwise; a scene larger
 // than NT / LPB bodies takes several passes per iteration.
-template <typename T, int LPB, bool CONTACT>
+// ENDS as for iterate_body: 1 when no listed scene has variable ends, 2 otherwise,
+// so that each variant carries one loop over the static ends; DRIVEN when the
+// scenes have driven bonds (the variants without carry no refactor code)
+template <typename T, int LPB, bool CONTACT, int ENDS, bool DRIVEN>
 __global__ void __launch_bounds__(Resident<T>::NT) k_resident_step(View<T> v, const int* list, const int* n_list,
                                                                    DrivenTable dt) {
   constexpr int QR = Rec<T>::Q, NT = Resident<T>::NT, RMAX = Resident<T>::RMAX, BPP = NT / LPB;
@@ -57,7 +61,7 @@ __global__ void __launch_bounds__(Resident<T>::NT) k_resident_step(View<T> v, co
   const SceneDev& S = v.scenes[sc];
   if (S.step >= S.steps_total || S.n_bodies > RMAX) return;
   const int off = S.body_off, n = S.n_bodies, K = S.iters;
-  if (dt.n > 0) {
+  if (DRIVEN && dt.n > 0) {
     // driven anchors at this step's time, then every block of the scene
     // refactored (the same functions as the flat path's kernels)
     bool any = false;
@@ -111,7 +115,7 @@ __global__ void __launch_bounds__(Resident<T>::NT) k_resident_step(View<T> v, co
     T* dst = lq[(k + 1) & 1];
     for (int b0 = 0; b0 < n; b0 += BPP) {
       const int b = b0 + t / LPB;  // the same for the LPB lanes of a body
-      if (b < n) iterate_body<T, CONTACT, LPB, true>(v, k, nullptr, nullptr, off + b, t % LPB, src, dst, off);
+      if (b < n) iterate_body<T, CONTACT, LPB, true, ENDS>(v, k, nullptr, nullptr, off + b, t % LPB, src, dst, off);
     }
     __syncthreads();
   }

@@ -52,7 +52,7 @@ struct EngineBase {
                          const FlatWave* waves = nullptr, const int* n_waves = nullptr,
                          int wave_grid = 0, const int* resident_grid = nullptr, bool flat = true) = 0;
   virtual pabd_status set_resident(const std::vector<int>& contact, const std::vector<int>& other,
-                                   hipStream_t st) = 0;
+                                   bool variable, hipStream_t st) = 0;
   // the most bodies a scene run by the resident step kernel may have: those
   // that one pass of the workgroup covers (a contact scene's bodies take four
   // lanes each); larger scenes wait on their partners' loads pass after pass
@@ -108,9 +108,9 @@ struct EngineT final : EngineBase {
                        resident_grid, flat);
     e.cap.n = saved;
   }
-  pabd_status set_resident(const std::vector<int>& contact, const std::vector<int>& other,
+  pabd_status set_resident(const std::vector<int>& contact, const std::vector<int>& other, bool variable,
                            hipStream_t st) override {
-    return e.set_resident(contact, other, st);
+    return e.set_resident(contact, other, variable, st);
   }
   int resident_max(bool contact) const override { return contact ? Resident<T>::NT / 4 : Resident<T>::NT; }
   void tile_step(int tb, const TileTable& tt, int grid, int nsteps, hipStream_t st) override {
@@ -344,7 +344,8 @@ pabd_status pabd_scene_create(const pabd_scene_desc* desc, pabd_scene** out) {
   st = s->eng->upload(s->hs, 0, 0, 0, 0, 0, s->stream);
   if (st != PABD_OK) return fail(st, s->eng->error());
   if (s->resident) {
-    st = s->hs.contact ? s->eng->set_resident({0}, {}, s->stream) : s->eng->set_resident({}, {0}, s->stream);
+    st = s->hs.contact ? s->eng->set_resident({0}, {}, s->hs.variable, s->stream)
+                       : s->eng->set_resident({}, {0}, s->hs.variable, s->stream);
     if (st != PABD_OK) return fail(st, s->eng->error());
   }
   s->eng->factor(s->stream);
@@ -753,7 +754,7 @@ pabd_status batch_tables(pabd_batch* b) {
     }
   }
   {
-    pabd_status st = b->eng->set_resident(res_contact, res_other, b->stream);
+    pabd_status st = b->eng->set_resident(res_contact, res_other, true, b->stream);
     if (st != PABD_OK) return fail(st, b->eng->error());
   }
   auto round_up = [](int x, int q, int cap) { return std::min(cap, (x + q - 1) / q * q); };
@@ -1556,7 +1557,8 @@ pabd_status pabd_scene_run_noalloc(const pabd_scene_desc* desc, int32_t nsteps, 
   st = eng->upload(hs, 0, 0, 0, 0, 0, stream);
   if (st != PABD_OK) return fail(st, eng->error());
   if (resident) {
-    st = hs.contact ? eng->set_resident({0}, {}, stream) : eng->set_resident({}, {0}, stream);
+    st = hs.contact ? eng->set_resident({0}, {}, hs.variable, stream)
+                    : eng->set_resident({}, {0}, hs.variable, stream);
     if (st != PABD_OK) return fail(st, eng->error());
   }
   eng->factor(stream);
