@@ -108,7 +108,7 @@ struct Engine {
   T* ce = nullptr;
   StageRec<T>* ce_stage = nullptr;
   int *bucket_count = nullptr, *bucket_start = nullptr, *bucket_fill = nullptr, *scan_tmp = nullptr;
-  int *hist = nullptr, *large = nullptr, *counters = nullptr;
+  int *hist = nullptr, *large = nullptr, *counters = nullptr, *ltask = nullptr;
   double* breach = nullptr;
   BroadRec* brec = nullptr;
   int2* pairs = nullptr;
@@ -281,7 +281,8 @@ struct Engine {
       PABD_TRY(alloc(brec, nb));
       PABD_TRY(alloc(breach, nb));
       PABD_TRY(alloc(large, nb));
-      PABD_TRY(alloc(counters, 2));
+      PABD_TRY(alloc(ltask, nb + 1));
+      PABD_TRY(alloc(counters, 3));
       PABD_TRY(alloc(hist, (size_t)REACH_BINS * c.s));
       // candidate pairs: half a pair per slot, at least 16 per body
       const size_t pc = std::max(nb * 16, nc / 2);
@@ -456,7 +457,7 @@ struct Engine {
     View<T> v = view();
     v.n = std::min(cap.n, ncb);
     ContactBuf cb{tb,    bucket_count, bucket_start, bucket_fill, brec,  reach,   hist,
-                  breach, large,       counters,     pairs,       pcap,  mass64,  scan_tmp};
+                  breach, large,       counters,     pairs,       pcap,  mass64,  scan_tmp, ltask};
     const int n = v.n;
     hipLaunchKernelGGL(k_contact_prep<T>, grid_for(std::max(n, REACH_BINS * n_scenes), 256), dim3(256), 0,
                        st, v, cb, n_scenes);
@@ -481,7 +482,8 @@ struct Engine {
       hipLaunchKernelGGL(k_hash_fill<T>, grid_for(n, 256), dim3(256), 0, st, v, cb);
       hipLaunchKernelGGL(k_broad_small<T>, grid_for((int)std::min<long long>((long long)n * BLPB, INT_MAX), 256),
                          dim3(256), 0, st, v, cb);
-      hipLaunchKernelGGL(k_broad_large<T>, dim3(256), dim3(256), 0, st, v, cb);
+      hipLaunchKernelGGL(k_large_tasks<T>, dim3(1), dim3(1024), 0, st, v, cb);
+      hipLaunchKernelGGL(k_broad_large<T>, dim3(1024), dim3(BL_CHUNK), 0, st, v, cb);
     }
     const int ng = std::min(8192, std::max(1, (pcap + 255) / 256));
     hipLaunchKernelGGL(k_narrow_pairs<T>, dim3(ng), dim3(256), 0, st, v, cb);

@@ -283,10 +283,10 @@ inline size_t scene_bytes(const HostScene& hs, int ts) {
   const size_t per_body = (size_t)ts * (4 * (QW + 4) + VW + MW + FW + 4) + 8 * (10 + 8 + 2) + 2 + 4 * 4;
   const size_t per_end = (size_t)ts * (EW + 4) + 4 + 8 * 4;
   // contact slots (final and staging) and the broad phase: record, reach,
-  // large-list entry and max(16, ccap / 2) candidate pairs per body
+  // large-list entry and task offset, and max(16, ccap / 2) candidate pairs per body
   // final record, partner and key, then the staged copy
   const size_t per_contact = (size_t)ts * CW + 4 + 8 + (ts == 4 ? sizeof(StageRec<float>) : sizeof(StageRec<double>));
-  const size_t per_contact_body = hs.ccap > 0 ? 64 + 8 + 4 + 8 * (size_t)std::max(16, hs.ccap / 2) : 0;
+  const size_t per_contact_body = hs.ccap > 0 ? 64 + 8 + 4 + 4 + 8 * (size_t)std::max(16, hs.ccap / 2) : 0;
   return per_body * hs.n + per_end * hs.ne + per_contact * (size_t)hs.n * hs.ccap +
          per_contact_body * hs.n +
          hs.drv_param.size() * 8 + hs.planes.size() * 8 + sizeof(SceneDev) + 64;

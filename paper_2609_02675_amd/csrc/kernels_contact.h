@@ -24,9 +24,10 @@
 //   k_broad_small    14 lanes per body: planes; then own cell and the 13 cells
 //                    of the forward half-neighbourhood of a small body, one per
 //                    lane, pairs with small bodies
-//   k_broad_large    one workgroup per large body: small partners over the cells
-//                    its reach spans (or over the scene's bodies when that is
-//                    fewer), large partners of higher index over the scene
+//   k_large_tasks / k_broad_large   the large bodies' work in tasks of 256
+//                    threads spread over the grid: small partners over the
+//                    cells a body's reach spans (or over the scene's bodies when
+//                    that is fewer), large partners of higher index
 //   k_broad_brute    instead of the hash and both broad kernels, for a single
 //                    scene of few bodies: one thread per pair
 //   k_narrow_pairs   one thread per candidate pair: narrow phase, bond ends into
@@ -75,11 +76,12 @@ struct ContactBuf {
   int* hist;             // per scene: REACH_BINS counts
   double* breach;        // per body: R + pm
   int* large;            // [nc] large bodies
-  int* counters;         // [0] large bodies, [1] candidate pairs
+  int* counters;         // [0] large bodies, [1] candidate pairs, [2] large-body tasks
   int2* pairs;           // [pcap]
   int pcap;
   const double* mass64;  // 8 per body
   int* scan_tmp;         // block sums
+  int* ltask;            // [nc + 1] first task of each large body (exclusive prefix)
 };
 
 // speculative margin: the body's surface moves by about h (|v| + |w| R) in a
@@ -101,7 +103,7 @@ __global__ void k_contact_prep(View<T> v, ContactBuf cb, int n_scenes) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n_scenes) cb.reach[i] = 0ull;
   if (i < n_scenes * REACH_BINS) cb.hist[i] = 0;
-  if (i < 2) cb.counters[i] = 0;
+  if (i < 3) cb.counters[i] = 0;
   if (i >= v.n) return;
   v.ccount[i] = 0;
   v.r_num[i] = 0.0;
@@ -710,36 +712,99 @@ __global__ void __launch_bounds__(256) k_broad_small(View<T> v, ContactBuf cb) {
   flush_pairs(pb, v, cb);
 }
 
-// one workgroup per large body (grid-stride over the large list)
+// A large body's share of the broad phase, split into tasks of BL_CHUNK
+// threads: its cells (those within its reach plus the cut of its centre's
+// cell), one per thread, then one pass over the large list for large partners
+// of higher index; or, when its cells would outnumber the scene's bodies, the
+// scene's bodies, one per thread.  The tasks of all large bodies are spread over
+// the grid, so one body with a long reach (a robot's torso over a bed of small
+// spheres: tens of thousands of cells) no longer keeps one workgroup busy while
+// the others idle.
+constexpr int BL_CHUNK = 256;  // threads of k_broad_large
+
+struct LargeWork {
+  double c[3], rL, cell;
+  int m, w, ncell, tasks;
+  bool by_cells;
+};
+
 template <typename T>
-__global__ void __launch_bounds__(256) k_broad_large(View<T> v, ContactBuf cb) {
+__device__ __forceinline__ LargeWork large_work(const View<T>& v, const ContactBuf& cb, int L) {
+  LargeWork lw;
+  const SceneDev& S = v.scenes[v.bscene[L]];
+  lw.cell = S.cell;
+  const double cut = 0.5 * lw.cell;
+  centre_of(v, L, lw.c);
+  lw.rL = cb.breach[L];
+  // small partners lie within rL + cut of the centre: cells within m of its own
+  const double md = ceil((lw.rL + cut) / lw.cell);
+  const double span = 2.0 * md + 1.0;
+  lw.by_cells = span * span * span <= (double)S.n_bodies;
+  lw.m = lw.by_cells ? (int)md : 0;
+  lw.w = 2 * lw.m + 1;
+  lw.ncell = lw.by_cells ? lw.w * lw.w * lw.w : 0;
+  lw.tasks = lw.by_cells ? (lw.ncell + BL_CHUNK - 1) / BL_CHUNK + 1 : (S.n_bodies + BL_CHUNK - 1) / BL_CHUNK;
+  return lw;
+}
+
+// the first task of every large body (exclusive prefix) and their total; one
+// workgroup of 1024 threads
+template <typename T>
+__global__ void __launch_bounds__(1024) k_large_tasks(View<T> v, ContactBuf cb) {
+  __shared__ int part[1024];
+  const int nl = cb.counters[0];
+  int carry = 0;
+  for (int base = 0; base < nl; base += 1024) {
+    const int l = base + (int)threadIdx.x;
+    const int t = l < nl ? large_work(v, cb, cb.large[l]).tasks : 0;
+    part[threadIdx.x] = t;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {  // inclusive scan
+      const int x = (int)threadIdx.x >= o ? part[threadIdx.x - o] : 0;
+      __syncthreads();
+      part[threadIdx.x] += x;
+      __syncthreads();
+    }
+    if (l < nl) cb.ltask[l] = carry + part[threadIdx.x] - t;
+    carry += part[1023];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    cb.ltask[nl] = carry;
+    cb.counters[2] = carry;
+  }
+}
+
+// grid-stride over the large bodies' tasks
+template <typename T>
+__global__ void __launch_bounds__(BL_CHUNK) k_broad_large(View<T> v, ContactBuf cb) {
   __shared__ int2 lbuf[PAIR_LDS];
   __shared__ int lcount, lbase;
   if (threadIdx.x == 0) lcount = 0;
   __syncthreads();
   const PairBuf pb{lbuf, &lcount, &lbase};
-  const int nl = cb.counters[0];
-  for (int l = blockIdx.x; l < nl; l += gridDim.x) {
-    const int L = cb.large[l];
+  const int nl = cb.counters[0], total = cb.counters[2];
+  for (int task = blockIdx.x; task < total; task += gridDim.x) {
+    // the large body holding this task: the last l with ltask[l] <= task
+    int lo = 0, hi = nl - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) / 2;
+      if (cb.ltask[mid] <= task) lo = mid;
+      else hi = mid - 1;
+    }
+    const int L = cb.large[lo];
+    const int part = task - cb.ltask[lo];
+    const LargeWork lw = large_work(v, cb, L);
     const int sc = v.bscene[L];
     const SceneDev& S = v.scenes[sc];
-    const double cell = S.cell, cut = 0.5 * cell;
-    double c[3];
-    centre_of(v, L, c);
-    const double rL = cb.breach[L];
     const bool pin_L = (v.flags[L] & F_PINNED) != 0;
     const int group_L = v.group[L];
-    const int off = S.body_off, ns = S.n_bodies;
-    // small partners lie within rL + cut of the centre: cells within m of its own
-    const double md = ceil((rL + cut) / cell);
-    const double span = 2.0 * md + 1.0;
-    const bool by_cells = span * span * span <= (double)ns;
-    if (by_cells) {
-      const int m = (int)md, w = 2 * m + 1;
-      int cc[3];
-      cell_of_pos(c, cell, cc);
-      const int ncell = w * w * w;
-      for (int t = threadIdx.x; t < ncell; t += blockDim.x) {
+    if (lw.by_cells && part < lw.tasks - 1) {
+      const int t = part * BL_CHUNK + (int)threadIdx.x;
+      if (t < lw.ncell) {
+        const int m = lw.m, w = lw.w;
+        int cc[3];
+        cell_of_pos(lw.c, lw.cell, cc);
         const int tx = cc[0] + t % w - m, ty = cc[1] + (t / w) % w - m, tz = cc[2] + t / (w * w) - m;
         const unsigned long long key = pack_cell(tx, ty, tz);
         const unsigned b = bucket_of(sc, tx, ty, tz, cb.tb);
@@ -747,28 +812,36 @@ __global__ void __launch_bounds__(256) k_broad_large(View<T> v, ContactBuf cb) {
         for (int e = cb.bucket_start[b]; e < e1; ++e) {
           const BroadRec r = cb.rec[e];
           if (r.cell != key || r.scene != sc) continue;
-          if (!near_rec(c, rL, r)) continue;
+          if (!near_rec(lw.c, lw.rL, r)) continue;
           if (!pair_allowed(pin_L, group_L, v.flags[r.body], v.group[r.body])) continue;
           append_pair(pb, cb, v.health, sc, min(L, r.body), max(L, r.body));
         }
       }
-    }
-    // over the scene's bodies: large partners of higher index, and small ones
-    // when the cells were not used
-    for (int j = off + threadIdx.x; j < off + ns; j += blockDim.x) {
-      if (j == L || !contact_body(v, j, sc)) continue;
-      const bool lj = is_large(v, cb, j, sc);
-      if (lj ? j < L : by_cells) continue;
-      if (!pair_allowed(pin_L, group_L, v.flags[j], v.group[j])) continue;
-      double cj[3];
-      centre_of(v, j, cj);
-      if (spheres_near(c, rL, cj, cb.breach[j])) append_pair(pb, cb, v.health, sc, min(L, j), max(L, j));
+    } else if (lw.by_cells) {
+      // large partners of higher index in the same scene
+      for (int q = (int)threadIdx.x; q < nl; q += BL_CHUNK) {
+        const int j = cb.large[q];
+        if (j <= L || v.bscene[j] != sc) continue;
+        if (!pair_allowed(pin_L, group_L, v.flags[j], v.group[j])) continue;
+        double cj[3];
+        centre_of(v, j, cj);
+        if (spheres_near(lw.c, lw.rL, cj, cb.breach[j])) append_pair(pb, cb, v.health, sc, L, j);
+      }
+    } else {
+      // the scene's bodies: every small one, and large ones of higher index
+      const int j = S.body_off + part * BL_CHUNK + (int)threadIdx.x;
+      if (j < S.body_off + S.n_bodies && j != L && contact_body(v, j, sc) &&
+          !(is_large(v, cb, j, sc) && j < L) &&
+          pair_allowed(pin_L, group_L, v.flags[j], v.group[j])) {
+        double cj[3];
+        centre_of(v, j, cj);
+        if (spheres_near(lw.c, lw.rL, cj, cb.breach[j])) append_pair(pb, cb, v.health, sc, min(L, j), max(L, j));
+      }
     }
   }
   flush_pairs(pb, v, cb);
 }
 
-// one thread per candidate pair (grid-stride)
 // A single scene of few bodies, [first, first + n): every pair tested directly,
 // one thread per pair, and one thread per body for its plane contacts.  The
 // candidate rule is the broad kernels' (bounding spheres of reach R + pm, the
@@ -812,6 +885,7 @@ __global__ void __launch_bounds__(256) k_broad_brute(View<T> v, ContactBuf cb, i
   flush_pairs(pb, v, cb);
 }
 
+// one thread per candidate pair (grid-stride)
 template <typename T>
 __global__ void __launch_bounds__(256) k_narrow_pairs(View<T> v, ContactBuf cb) {
   const int np = min(cb.counters[1], cb.pcap);
