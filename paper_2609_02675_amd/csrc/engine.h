@@ -465,8 +465,8 @@ struct Engine {
     if (n_scenes == 1 && n <= BRUTE_MAX) {
       // one scene of few bodies: all pairs directly, no spatial hash
       const long long threads = (long long)n + (long long)n * (n - 1) / 2;
-      hipLaunchKernelGGL(k_broad_brute<T>, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, v, cb,
-                         0, n);
+      hipLaunchKernelGGL(k_broad_brute<T>, dim3((unsigned)std::max(1LL, (threads + 255) / 256)), dim3(256), 0, st,
+                         v, cb, 0, n);
     } else {
       hipLaunchKernelGGL(k_contact_cells, grid_for(n_scenes, 64), dim3(64), 0, st, scenes, n_scenes,
                          (const unsigned long long*)reach, (const int*)hist);

@@ -225,3 +225,28 @@ def test_box_drop_1000_full_size_from_a_landing_state(P):
     e = errors(g32.state(), ref.state(), scale_of(st))
     print("box drop fp32 one step", e)
     assert e["pos"] <= 1e-4 and e["rot"] <= 1e-4
+
+
+def test_empty_and_single_body_contact_scenes(P):
+    """The all-pairs broad phase at its smallest: a contact scene with no body,
+    and one box (no pair at all) coming to rest on the plane, against the oracle."""
+    drop = S.box_drop(n_side=2, layers=1, precision=S.PREC_FP64)
+    empty = drop.copy(shape=np.zeros(0, np.int32), shape_param=np.zeros((0, 3)), density=np.zeros(0),
+                      flags=np.zeros(0, np.uint8), group=np.zeros(0, np.int32), c0=np.zeros((0, 3)),
+                      A0=np.zeros((0, 3, 3)), v0=np.zeros((0, 3)), w0=np.zeros((0, 3)))
+    print("[case] empty contact scene", flush=True)
+    g = P.Scene(empty)
+    g.step(3)
+    assert g.state()[0].shape == (0, 3)
+    keep = [0]
+    one = drop.copy(shape=drop.shape[keep], shape_param=drop.shape_param[keep], density=drop.density[keep],
+                    flags=drop.flags[keep], group=drop.group[keep], A0=drop.A0[keep], v0=drop.v0[keep],
+                    w0=drop.w0[keep], c0=np.array([[0.0, 0.9, 0.0]]))
+    print("[case] one box on the plane", flush=True)
+    g = P.Scene(one)
+    o = oracle.Oracle(one)
+    for _ in range(3):
+        g.step(10)
+        o.step(10)
+    _compare_contacts(g, o)
+    assert fp64_ok(errors(g.state(), o.state(), scale_of(one)))
