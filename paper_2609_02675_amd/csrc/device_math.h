@@ -226,6 +226,7 @@ __device__ __forceinline__ void polar_newton_plain(T* Y, T* sigma, bool on) {
 }
 
 __device__ __forceinline__ bool wave_any(bool p) { return __builtin_amdgcn_ballot_w64(p) != 0; }
+__device__ __forceinline__ bool wave_all(bool p) { return __builtin_amdgcn_ballot_w64(!p) == 0; }
 
 // Rotation factor of the polar decomposition (local step, Sec. 4.2.2), in place:
 // X <- R where X = R S.  Newton's iteration acts on each singular value alone,
@@ -615,9 +616,13 @@ __device__ __forceinline__ void mass_times(const T* mass, const T* s, T* ms) {
   }
 }
 
-// r = ms - M q (the inertia term M (s - q) with ms = M s from mass_times)
+// r = ms - M q (the inertia term M (s - q) with ms = M s from mass_times): the
+// diagonal of Pi first, then, with offdiag, its off-diagonal entries.  A caller
+// whose bodies all have a diagonal Pi (boxes and spheres in their own frames)
+// passes offdiag = false: the terms it skips are products with zero, so the
+// result is the same.
 template <typename T>
-__device__ __forceinline__ void inertia_from(T* r, const T* mass, const T* ms, const T* q) {
+__device__ __forceinline__ void inertia_from(T* r, const T* mass, const T* ms, const T* q, bool offdiag) {
   constexpr int L = sizeof(T) == 4 ? 12 : 0;
   const T m = mass[0], p00 = mass[1], p01 = mass[2], p02 = mass[3], p11 = mass[4],
           p12 = mass[5], p22 = mass[6];
@@ -625,10 +630,18 @@ __device__ __forceinline__ void inertia_from(T* r, const T* mass, const T* ms, c
   for (int c = 0; c < 3; ++c) r[c] = fma(-m, q[L + c], ms[c]);
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    const T a0 = q[3 + 3 * k], a1 = q[4 + 3 * k], a2 = q[5 + 3 * k];
-    r[3 + 3 * k] = fma(-p02, a2, fma(-p01, a1, fma(-p00, a0, ms[3 + 3 * k])));
-    r[4 + 3 * k] = fma(-p12, a2, fma(-p11, a1, fma(-p01, a0, ms[4 + 3 * k])));
-    r[5 + 3 * k] = fma(-p22, a2, fma(-p12, a1, fma(-p02, a0, ms[5 + 3 * k])));
+    r[3 + 3 * k] = fma(-p00, q[3 + 3 * k], ms[3 + 3 * k]);
+    r[4 + 3 * k] = fma(-p11, q[4 + 3 * k], ms[4 + 3 * k]);
+    r[5 + 3 * k] = fma(-p22, q[5 + 3 * k], ms[5 + 3 * k]);
+  }
+  if (offdiag) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const T a0 = q[3 + 3 * k], a1 = q[4 + 3 * k], a2 = q[5 + 3 * k];
+      r[3 + 3 * k] = fma(-p02, a2, fma(-p01, a1, r[3 + 3 * k]));
+      r[4 + 3 * k] = fma(-p12, a2, fma(-p01, a0, r[4 + 3 * k]));
+      r[5 + 3 * k] = fma(-p12, a1, fma(-p02, a0, r[5 + 3 * k]));
+    }
   }
 }
 

@@ -140,6 +140,10 @@ __global__ void __launch_bounds__(TB, sizeof(T) == 4 ? 3 : 1) k_tile_step(View<T
         ne = min(ne, MAXE);  // a pinned body only publishes its register ends
       }
     }
+    // whether every body of the wave has a diagonal Pi (boxes and spheres in
+    // their own frames): the inertia term then takes the diagonal alone
+    // (wave-uniform, fixed for the launch)
+    const bool diag_pi = wave_all(scn < 0 || pinned || (m[2] == (T)0 && m[3] == (T)0 && m[5] == (T)0));
     // per register end, whether some lane of the wave takes it the long way
     // (wave-uniform, fixed for the launch)
 #pragma unroll
@@ -191,7 +195,7 @@ __global__ void __launch_bounds__(TB, sizeof(T) == 4 ? 3 : 1) k_tile_step(View<T
           // r = M (s - q^k) + sum of the ends' J^T f (the forces carry h^2);
           // starting from the inertia term leaves no accumulator to clear
           T r[QW];
-          inertia_from(r, m, ms, q);
+          inertia_from(r, m, ms, q, !diag_pi);
 #pragma unroll
           for (int u = 0; u < MAXE; ++u)
             if (u < ne) {
