@@ -156,6 +156,9 @@ __global__ void __launch_bounds__(TB, sizeof(T) == 4 ? 3 : 1) k_tile_step(View<T
       // scene constants are re-read every step rather than held in registers
       // through the iterations
       const int K = present ? v.scenes[scn].iters : 0;
+      // the residual is formed on the launch's last step and on a scene's own
+      // last step (the only ones whose residual can be read afterwards)
+      const bool want_rho = present && (step == nsteps - 1 || v.scenes[scn].step + 1 >= v.scenes[scn].steps_total);
       // M s of the prediction s: the inertia term's part that no iteration
       // changes (q's high position words stay those of s through the step)
       T ms[QW];
@@ -242,7 +245,7 @@ __global__ void __launch_bounds__(TB, sizeof(T) == 4 ? 3 : 1) k_tile_step(View<T
           }
           // q^{k+1} in place; a lane's last iteration keeps what its residual
           // |q^{k+1} - q^k|_M / |q^k|_M needs
-          const bool last = k == K - 1;
+          const bool last = k == K - 1 && want_rho;
           constexpr int LO = sizeof(T) == 4 ? 12 : 0;
           T Aold[9], cold[3];
           if (last) {
@@ -288,22 +291,26 @@ __global__ void __launch_bounds__(TB, sizeof(T) == 4 ? 3 : 1) k_tile_step(View<T
         store<T, QR>(v.qn + (size_t)QR * i, q);
         store<T, VW>(v.vel + (size_t)VW * i, vw);
       }
-      __syncthreads();
       // pairwise sums over the scene's bodies by their index within the scene:
-      // the same order wherever the scene sits in the tile
+      // the same order wherever the scene sits in the tile (skipped on the
+      // steps where no scene of the tile forms its residual)
       const int loc = present ? i - v.scenes[scn].body_off : 1;
       const int nbs = present ? v.scenes[scn].n_bodies : 0;
+      if (__syncthreads_or(want_rho)) {
 #pragma unroll
-      for (int w = 1; w < TB; w <<= 1) {
-        if ((loc & (2 * w - 1)) == 0 && loc + w < nbs) {
-          red[lane] += red[lane + w];
-          red[TB + lane] += red[TB + lane + w];
+        for (int w = 1; w < TB; w <<= 1) {
+          if ((loc & (2 * w - 1)) == 0 && loc + w < nbs) {
+            red[lane] += red[lane + w];
+            red[TB + lane] += red[TB + lane + w];
+          }
+          __syncthreads();
         }
-        __syncthreads();
       }
       if (present && loc == 0) {
-        const double a = red[lane], b = red[TB + lane];
-        v.rho[scn] = b > 0.0 ? sqrt(a / b) : 0.0;
+        if (want_rho) {
+          const double a = red[lane], b = red[TB + lane];
+          v.rho[scn] = b > 0.0 ? sqrt(a / b) : 0.0;
+        }
         v.scenes[scn].step += 1;
       }
       __syncthreads();  // LDS and step counters settled for the next step or tile
