@@ -510,10 +510,15 @@ struct Engine {
   void launch_resident(const int* grid, int n_driven, hipStream_t st) {
     View<T> v = view();
     const DrivenTable dt{n_driven, drv_scene, drv_end_i, drv_end_j, drv_param, mass64};
-    if (res_variable)
-      n_driven > 0 ? launch_resident_as<2, true>(v, grid, dt, st) : launch_resident_as<2, false>(v, grid, dt, st);
+    const bool driven = n_driven > 0;
+    if (res_variable && driven)
+      launch_resident_as<2, true>(v, grid, dt, st);
+    else if (res_variable)
+      launch_resident_as<2, false>(v, grid, dt, st);
+    else if (driven)
+      launch_resident_as<1, true>(v, grid, dt, st);
     else
-      n_driven > 0 ? launch_resident_as<1, true>(v, grid, dt, st) : launch_resident_as<1, false>(v, grid, dt, st);
+      launch_resident_as<1, false>(v, grid, dt, st);
   }
   template <int ENDS, bool DRIVEN>
   void launch_resident_as(const View<T>& v, const int* grid, const DrivenTable& dt, hipStream_t st) {
