@@ -302,6 +302,61 @@ pabd_status pabd_batch_layout(pabd_batch *b, int32_t *n_bodies, int32_t *n_tiles
 /* Bytes of HBM budget in use / free. */
 pabd_status pabd_batch_memory(pabd_batch *b, size_t *used, size_t *budget);
 
+/* ---- launch schedules and the tuner --------------------------------------- */
+
+/* How the work of Algorithm 1's iterations is laid out on the device.  The
+ * body-wise update of Sec. 4.2.1 sums one term per bond end of a body; the
+ * schedule says how many lanes share those ends and how many bodies share a
+ * workgroup.  Results under any schedule agree with the oracle to the same
+ * bounds; different schedules add a body's terms in different orders, so their
+ * bits may differ (the same schedule repeats the same bits). */
+typedef struct pabd_schedule {
+  int32_t tile_bodies;   /* batches: bodies per workgroup of the tile kernel, 32, 64, 128
+                            or 256 (0 for a plain scene, which has no tiles) */
+  int32_t contact_lanes; /* lanes that share a contact body's ends on the flat path:
+                            1, 2, 4, 8 or 16 (other bodies take one lane each) */
+  int32_t group_waves;   /* wavefronts per workgroup of the flat-path iteration: 1, 2
+                            or 4 */
+  int32_t from_cache;    /* output of the tuners: 1 when the schedule came from the
+                            tuning cache instead of timing */
+} pabd_schedule;
+
+/* flags of the tuners: time the candidates even when the cache holds the key */
+#define PABD_TUNE_FORCE 1
+
+/* Pick a batch's schedule by timing, on the scenes resident now (their state,
+ * bond states, health bits and residuals are saved first and restored after
+ * every candidate, so the scenes continue as if the call had not been made): the tile sizes that hold the largest tiled scene, timed on the
+ * tile kernel alone (as pabd_batch_autotune); then, when contact scenes run on
+ * the flat path, contact_lanes from {1, 2, 4, 8, 16}; then, when any scene runs
+ * on the flat path, group_waves from {1, 2, 4}: each timed as whole batch steps
+ * (one graph replay per step, HIP events, best of three rounds from the saved
+ * state).  The result is kept in a per-process cache under (device
+ * architecture, precision, size bucket): the bit lengths of the body counts of
+ * the scenes the tile kernel can take (joint scenes without contacts, driven
+ * or variable bonds), of the contact scenes and of the other scenes, the bit
+ * length of the largest contact capacity, and the smallest tile size that
+ * holds the largest scene the tile kernel can take.  A later call with the same key applies the cached schedule without
+ * timing (unless flags has PABD_TUNE_FORCE).  Writes the schedule in force. */
+pabd_status pabd_batch_tune(pabd_batch *b, int32_t flags, pabd_schedule *out);
+/* Apply a schedule to a batch (tile_bodies 0 leaves the tile size as it is;
+ * from_cache is ignored).  PABD_E_INVALID for a value outside the sets above. */
+pabd_status pabd_batch_set_schedule(pabd_batch *b, const pabd_schedule *s);
+pabd_status pabd_batch_get_schedule(const pabd_batch *b, pabd_schedule *out);
+/* The same for a plain scene: contact_lanes, then group_waves, each timed over
+ * whole steps from the saved state.  A scene whose whole step runs in the
+ * resident kernel (small scenes) has no flat-path launch to tune: the call
+ * writes the schedule in force and times nothing.  Cache key: (device
+ * architecture, precision, bit length of the body count, contact flag, bit
+ * length of the contact capacity). */
+pabd_status pabd_scene_tune(pabd_scene *s, int32_t flags, pabd_schedule *out);
+/* (tile_bodies and from_cache are ignored; a scene reads back tile_bodies 0) */
+pabd_status pabd_scene_set_schedule(pabd_scene *s, const pabd_schedule *sch);
+pabd_status pabd_scene_get_schedule(const pabd_scene *s, pabd_schedule *out);
+/* Empty the tuning cache / number of entries in it. */
+void pabd_tune_cache_clear(void);
+int32_t pabd_tune_cache_size(void);
+
 /* ---- measurement ------------------------------------------------------------ */
 
 /* Device-wide streaming copy of `bytes` (rounded down to 16-byte units) between

@@ -6,4 +6,5 @@ and the build script.
 """
 from . import scenes  # noqa: F401
 from ._lib import (Batch, Busy, Diverged, PabdError, Scene, device_count,  # noqa: F401
-                   hbm_copy_probe, lib, scene_bytes, use_torch_allocator)
+                   hbm_copy_probe, lib, scene_bytes, tune_cache_clear, tune_cache_size,
+                   use_torch_allocator)

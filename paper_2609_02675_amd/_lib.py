@@ -31,7 +31,12 @@ SYMBOLS = [
     "pabd_hbm_copy_probe", "pabd_batch_sync", "pabd_scene_bond_state", "pabd_set_allocator",
     "pabd_scene_residual", "pabd_debug_poke", "pabd_scene_polar_fallbacks", "pabd_batch_faults",
     "pabd_batch_poke", "pabd_batch_polar_fallbacks", "pabd_scene_run_noalloc",
+    "pabd_batch_tune", "pabd_batch_set_schedule", "pabd_batch_get_schedule", "pabd_scene_tune",
+    "pabd_scene_set_schedule", "pabd_scene_get_schedule", "pabd_tune_cache_clear",
+    "pabd_tune_cache_size",
 ]
+
+TUNE_FORCE = 1
 
 _ALLOC_T = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 _FREE_T = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
@@ -54,6 +59,18 @@ class Diverged(PabdError):
 _P = C.POINTER
 _d = _P(C.c_double)
 _i = _P(C.c_int32)
+
+
+class _Schedule(C.Structure):
+    _fields_ = [("tile_bodies", C.c_int32), ("contact_lanes", C.c_int32),
+                ("group_waves", C.c_int32), ("from_cache", C.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
+def _schedule(tile_bodies: int = 0, contact_lanes: int = 4, group_waves: int = 1) -> _Schedule:
+    return _Schedule(int(tile_bodies), int(contact_lanes), int(group_waves), 0)
 
 
 class _Desc(C.Structure):
@@ -133,6 +150,13 @@ def lib():
     L.pabd_batch_poke.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, C.c_double]
     L.pabd_batch_polar_fallbacks.argtypes = [vp, C.c_int32, _i64, _i64]
     L.pabd_scene_run_noalloc.argtypes = [_P(_Desc), C.c_int32, _d, _d, _d, _d, vp]
+    for name in ("pabd_batch_tune", "pabd_scene_tune"):
+        getattr(L, name).argtypes = [vp, C.c_int32, _P(_Schedule)]
+    for name in ("pabd_batch_set_schedule", "pabd_batch_get_schedule", "pabd_scene_set_schedule",
+                 "pabd_scene_get_schedule"):
+        getattr(L, name).argtypes = [vp, _P(_Schedule)]
+    L.pabd_tune_cache_clear.restype = None
+    L.pabd_tune_cache_size.restype = C.c_int32
     _lib = L
     return L
 
@@ -229,6 +253,14 @@ def use_torch_allocator(enable: bool = True):
 
 def device_count() -> int:
     return int(lib().pabd_device_count())
+
+
+def tune_cache_clear():
+    lib().pabd_tune_cache_clear()
+
+
+def tune_cache_size() -> int:
+    return int(lib().pabd_tune_cache_size())
 
 
 def hbm_copy_probe(nbytes: int, reps: int = 20):
@@ -338,6 +370,22 @@ class Scene:
                                              _ptr(kk, C.c_double), C.byref(n)))
         return dict(i=ci, j=cj, feature=ft, x_i=xi, x_j=xj, normal=nn, kappa=kk)
 
+    def schedule(self) -> dict:
+        """Flat-path schedule in force (contact_lanes, group_waves; tile_bodies 0)."""
+        sc = _Schedule()
+        _check(lib().pabd_scene_get_schedule(self._h, C.byref(sc)))
+        return sc.as_dict()
+
+    def set_schedule(self, contact_lanes: int = 4, group_waves: int = 1):
+        sc = _schedule(0, contact_lanes, group_waves)
+        _check(lib().pabd_scene_set_schedule(self._h, C.byref(sc)))
+
+    def tune(self, force: bool = False) -> dict:
+        """Time the flat-path schedules from the saved state and keep the fastest."""
+        sc = _Schedule()
+        _check(lib().pabd_scene_tune(self._h, TUNE_FORCE if force else 0, C.byref(sc)))
+        return sc.as_dict()
+
 
 class Batch:
     """Many resident scenes advanced together, one graph replay per step."""
@@ -437,6 +485,24 @@ class Batch:
 
     def set_tile(self, tile_bodies: int):
         _check(lib().pabd_batch_set_tile(self._h, int(tile_bodies)))
+
+    def schedule(self) -> dict:
+        """Schedule in force: tile_bodies, contact_lanes, group_waves."""
+        sc = _Schedule()
+        _check(lib().pabd_batch_get_schedule(self._h, C.byref(sc)))
+        return sc.as_dict()
+
+    def set_schedule(self, tile_bodies: int = 0, contact_lanes: int = 4, group_waves: int = 1):
+        sc = _schedule(tile_bodies, contact_lanes, group_waves)
+        _check(lib().pabd_batch_set_schedule(self._h, C.byref(sc)))
+
+    def tune(self, force: bool = False) -> dict:
+        """Time tile sizes, then flat-path lanes and workgroup shapes, from the
+        saved state; keep the fastest (cached per architecture, precision and
+        size bucket)."""
+        sc = _Schedule()
+        _check(lib().pabd_batch_tune(self._h, TUNE_FORCE if force else 0, C.byref(sc)))
+        return sc.as_dict()
 
     def time_tile_kernel(self, reps: int, nsteps: int = 1) -> float:
         """Average ms of one tile-kernel launch running nsteps steps."""

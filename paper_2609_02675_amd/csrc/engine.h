@@ -130,6 +130,9 @@ struct Engine {
   int* res_list[2] = {nullptr, nullptr};
   int* res_count = nullptr;
   bool res_variable = true;  // some resident scene has variable ends
+  // flat-path schedule: lanes that share a contact body's ends (1, 2, 4, 8 or
+  // 16) and wavefronts per workgroup of the iteration launches (1, 2 or 4)
+  int contact_lanes = 4, group_waves = 1;
 
   std::vector<void*> allocs;
   std::string err;
@@ -538,9 +541,32 @@ struct Engine {
                        (const double*)mass64, first, count);
   }
 
+  // the K iteration launches of a flat step, CL lanes per contact body; by
+  // default one wavefront per workgroup, so that a small scene's waves spread
+  // over as many CUs (and L1 caches) as there are waves
+  template <int CL>
+  void launch_iterations(int kmax, bool contacts, bool history, hipStream_t st, const FlatWave* waves,
+                         const int* n_waves, int wave_grid, double* hn, double* hd) {
+    View<T> v = view();
+    const int gw = group_waves;
+    const dim3 wg(64 * gw);
+    const dim3 gc = grid_for((int)std::min<long long>((long long)cap.n * CL, INT_MAX), 64 * gw);
+    const dim3 g1 = grid_for(cap.n, 64 * gw);
+    const dim3 gwv((unsigned)std::max(1, (wave_grid + gw - 1) / gw));
+    for (int k = 0; k < kmax; ++k) {
+      if (waves && !history)
+        hipLaunchKernelGGL((k_iterate_waves<T, CL>), gwv, wg, 0, st, v, k, waves, n_waves);
+      else if (contacts)
+        hipLaunchKernelGGL((k_iterate<T, true, CL>), gc, wg, 0, st, v, k, hn, hd);
+      else
+        hipLaunchKernelGGL((k_iterate<T, false, 1>), g1, wg, 0, st, v, k, hn, hd);
+    }
+  }
+
   // One step of Algorithm 1 with flat per-body kernels (one launch per iteration).
-  // With a wave table (batches), the iterations run over it instead: four lanes
-  // per body of a contact scene, one per body of any other scene.
+  // With a wave table (batches), the iterations run over it instead:
+  // contact_lanes lanes per body of a contact scene, one per body of any other
+  // scene.
   //
   // resident_grid (optional): the scenes of the resident lists take their whole
   // step in the resident kernel, after the contact construction; with
@@ -572,20 +598,12 @@ struct Engine {
       hipLaunchKernelGGL(k_zero_double, gz, dim3(256), 0, st, rh_num, nh);
       hipLaunchKernelGGL(k_zero_double, gz, dim3(256), 0, st, rh_den, nh);
     }
-    // the iterations launch one wave per workgroup, so that a small scene's
-    // waves spread over as many CUs (and L1 caches) as there are waves
-    constexpr int LPB = 4;  // lanes per body when contacts are present
-    const dim3 w1(64);
-    const dim3 gc = grid_for((int)std::min<long long>((long long)cap.n * LPB, INT_MAX), 64);
-    const dim3 g1 = grid_for(cap.n, 64);
-    const dim3 gw((unsigned)std::max(1, wave_grid));
-    for (int k = 0; k < kmax; ++k) {
-      if (waves && !history)
-        hipLaunchKernelGGL(k_iterate_waves<T>, gw, w1, 0, st, v, k, waves, n_waves);
-      else if (contacts)
-        hipLaunchKernelGGL((k_iterate<T, true, LPB>), gc, w1, 0, st, v, k, hn, hd);
-      else
-        hipLaunchKernelGGL((k_iterate<T, false, 1>), g1, w1, 0, st, v, k, hn, hd);
+    switch (contact_lanes) {
+      case 1: launch_iterations<1>(kmax, contacts, history, st, waves, n_waves, wave_grid, hn, hd); break;
+      case 2: launch_iterations<2>(kmax, contacts, history, st, waves, n_waves, wave_grid, hn, hd); break;
+      case 8: launch_iterations<8>(kmax, contacts, history, st, waves, n_waves, wave_grid, hn, hd); break;
+      case 16: launch_iterations<16>(kmax, contacts, history, st, waves, n_waves, wave_grid, hn, hd); break;
+      default: launch_iterations<4>(kmax, contacts, history, st, waves, n_waves, wave_grid, hn, hd); break;
     }
     hipLaunchKernelGGL(k_finish<T>, g, b, 0, st, v);
     if (!finish_scenes) return;

@@ -5,7 +5,7 @@
 //               q^k, writes q^{k+1} to the other buffer), increment form:
 //               dq = H^{-1} (M (s - q^k) + h^2 sum [w J^T (y_o - y_s) + phi^- J^T n
 //                    + J^T f_contact]),  then A <- polar rotation (Sec. 4.2.2)
-//   k_iterate_waves  the same over a batch's table of wavefronts (four lanes per
+//   k_iterate_waves  the same over a batch's table of wavefronts (CL lanes per
 //               body of a contact scene, one per body of any other scene)
 // with the force terms of the variable ends (augmented, polynomial, slider) and
 // of the contact ends.  The resident step kernel runs the same body iteration.
@@ -390,19 +390,19 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 4 : 2) k_iterate(View<T>
 // scenes.  Waves past the table's count leave at once, so the grid can stay
 // fixed while scenes come and go.
 struct FlatWave {
-  int first, count, lpb, pad;
+  int first, count, lpb, contact;  // lpb: lanes per body (CL for a contact wave, else 1)
 };
 
-template <typename T>
+template <typename T, int CL>
 __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 4 : 2) k_iterate_waves(View<T> v, int k, const FlatWave* waves,
                                                        const int* n_waves) {
   const int w = (int)((blockIdx.x * (long long)blockDim.x + threadIdx.x) / 64);
   const int l = (int)(threadIdx.x & 63);
   if (w >= *n_waves) return;
   const FlatWave fw = waves[w];
-  if (fw.lpb == 4) {
-    if (l / 4 >= fw.count) return;
-    iterate_body<T, true, 4>(v, k, nullptr, nullptr, fw.first + l / 4, l % 4, v.q[k & 1], v.q[(k + 1) & 1], 0);
+  if (fw.contact) {
+    if (l / CL >= fw.count) return;
+    iterate_body<T, true, CL>(v, k, nullptr, nullptr, fw.first + l / CL, l % CL, v.q[k & 1], v.q[(k + 1) & 1], 0);
   } else {
     if (l >= fw.count) return;
     iterate_body<T, false, 1>(v, k, nullptr, nullptr, fw.first + l, 0, v.q[k & 1], v.q[(k + 1) & 1], 0);

@@ -77,11 +77,19 @@ struct EngineBase {
                                     std::vector<int>& partner,
                                     std::vector<unsigned long long>& key,
                                     std::vector<double>& rec, hipStream_t st) = 0;
+  // q^n, velocities and the scene table of bodies [0, n), the bond-end states,
+  // health bits, last residuals and recorded residual history (saved, or
+  // written back)
   virtual pabd_status snapshot(int n, std::vector<char>& buf, hipStream_t st, bool restore) = 0;
+  // flat-path schedule: lanes per contact body, wavefronts per workgroup
+  virtual void set_schedule(int contact_lanes, int group_waves) = 0;
+  virtual void get_schedule(int* contact_lanes, int* group_waves) const = 0;
   // raw q^n and velocity records of bodies [boff, boff + n) (read, or write back)
   virtual pabd_status raw_bodies(int boff, int n, std::vector<char>& buf, hipStream_t st, bool write) = 0;
   // augmented-bond state of ends [0, ne) as doubles (4 per end)
   virtual pabd_status read_al(int ne, std::vector<double>& out, hipStream_t st) = 0;
+  // raw bond-end state records of ends [eoff, eoff + ne) (read, or write back)
+  virtual pabd_status raw_al(int eoff, int ne, std::vector<char>& buf, hipStream_t st, bool write) = 0;
   // device memory from `a` instead of the allocator in force, uploads without staging buffers
   virtual void use_memory(const DeviceAllocator& a) = 0;
 };
@@ -224,6 +232,18 @@ struct EngineT final : EngineBase {
     out.assign(a.begin(), a.end());
     return PABD_OK;
   }
+  pabd_status raw_al(int eoff, int ne, std::vector<char>& buf, hipStream_t st, bool write) override {
+    const size_t bytes = (size_t)4 * std::max(ne, 0) * sizeof(T);
+    if (!write) buf.resize(bytes);
+    if (bytes == 0) return PABD_OK;
+    if (buf.size() < bytes) return fail(PABD_E_INVALID, "bond state buffer too small");
+    T* d = e.al + (size_t)4 * eoff;
+    hipError_t r = write ? hipMemcpyAsync(d, buf.data(), bytes, hipMemcpyHostToDevice, st)
+                         : hipMemcpyAsync(buf.data(), d, bytes, hipMemcpyDeviceToHost, st);
+    if (r != hipSuccess || hipStreamSynchronize(st) != hipSuccess)
+      return fail(PABD_E_DEVICE, "bond state copy failed");
+    return PABD_OK;
+  }
   pabd_status raw_bodies(int boff, int n, std::vector<char>& buf, hipStream_t st, bool write) override {
     const size_t bq = (size_t)Rec<T>::Q * n * sizeof(T), bv = (size_t)VW * n * sizeof(T);
     T* dq = e.qn + (size_t)Rec<T>::Q * boff;
@@ -239,19 +259,40 @@ struct EngineT final : EngineBase {
     return PABD_OK;
   }
   pabd_status snapshot(int n, std::vector<char>& buf, hipStream_t st, bool restore) override {
-    const size_t bq = (size_t)Rec<T>::Q * n * sizeof(T), bv = (size_t)VW * n * sizeof(T);
-    const size_t bs = (size_t)e.cap.s * sizeof(SceneDev);
-    if (!restore) buf.resize(bq + bv + bs);
-    hipMemcpyKind kind = restore ? hipMemcpyHostToDevice : hipMemcpyDeviceToHost;
+    struct Part {
+      void* dev;
+      size_t bytes;
+    };
+    const Part parts[] = {{e.qn, (size_t)Rec<T>::Q * n * sizeof(T)},
+                          {e.vel, (size_t)VW * n * sizeof(T)},
+                          {e.scenes, (size_t)e.cap.s * sizeof(SceneDev)},
+                          {e.al, (size_t)4 * e.cap.e * sizeof(T)},
+                          {e.health, (size_t)e.cap.s * sizeof(int)},
+                          {e.rho, (size_t)e.cap.s * sizeof(double)},
+                          {e.rh_rho, (size_t)e.rh_k * sizeof(double)}};
+    size_t total = 0;
+    for (const Part& p : parts) total += p.bytes;
+    if (!restore) buf.resize(total);
+    if (buf.size() < total) return fail(PABD_E_INVALID, "snapshot buffer too small");
     char* h = buf.data();
-    hipError_t r1 = restore ? hipMemcpyAsync(e.qn, h, bq, kind, st) : hipMemcpyAsync(h, e.qn, bq, kind, st);
-    hipError_t r2 = restore ? hipMemcpyAsync(e.vel, h + bq, bv, kind, st)
-                            : hipMemcpyAsync(h + bq, e.vel, bv, kind, st);
-    hipError_t r3 = restore ? hipMemcpyAsync(e.scenes, h + bq + bv, bs, kind, st)
-                            : hipMemcpyAsync(h + bq + bv, e.scenes, bs, kind, st);
-    if (r1 != hipSuccess || r2 != hipSuccess || r3 != hipSuccess || hipStreamSynchronize(st) != hipSuccess)
-      return fail(PABD_E_DEVICE, "snapshot copy failed");
+    for (const Part& p : parts) {
+      if (p.bytes > 0 && p.dev) {
+        hipError_t r = restore ? hipMemcpyAsync(p.dev, h, p.bytes, hipMemcpyHostToDevice, st)
+                               : hipMemcpyAsync(h, p.dev, p.bytes, hipMemcpyDeviceToHost, st);
+        if (r != hipSuccess) return fail(PABD_E_DEVICE, "snapshot copy failed");
+      }
+      h += p.bytes;
+    }
+    if (hipStreamSynchronize(st) != hipSuccess) return fail(PABD_E_DEVICE, "snapshot copy failed");
     return PABD_OK;
+  }
+  void set_schedule(int contact_lanes, int group_waves) override {
+    e.contact_lanes = contact_lanes;
+    e.group_waves = group_waves;
+  }
+  void get_schedule(int* contact_lanes, int* group_waves) const override {
+    *contact_lanes = e.contact_lanes;
+    *group_waves = e.group_waves;
   }
 };
 
@@ -639,6 +680,8 @@ struct pabd_batch {
   std::vector<Tile> tiles;  // index = tile id; used == 0 and no slots: free
   int tile_bodies = 64;
   bool tile_auto = true;
+  // flat-path schedule (lanes per contact body, wavefronts per workgroup)
+  int contact_lanes = 4, group_waves = 1;
   long long substeps = 0;
   // device tile table
   int *d_first = nullptr, *d_count = nullptr, *d_kmax = nullptr, *d_ntiles = nullptr;
@@ -660,6 +703,7 @@ struct pabd_batch {
   struct Launch {
     int stream_n = 0, driven_n = 0, grid = 0, kmax = 0, tile = 0, wave_grid = 0;
     int res_grid[2] = {0, 0};  // workgroups over the resident lists (contact, other)
+    int contact_lanes = 0, group_waves = 0;
     bool stream = false, contact = false, flat = false;
     const int* table = nullptr;
     const FlatWave* waves = nullptr;
@@ -667,7 +711,8 @@ struct pabd_batch {
       return stream_n == o.stream_n && driven_n == o.driven_n && grid == o.grid && kmax == o.kmax &&
              tile == o.tile && stream == o.stream && contact == o.contact && table == o.table &&
              wave_grid == o.wave_grid && waves == o.waves && res_grid[0] == o.res_grid[0] &&
-             res_grid[1] == o.res_grid[1] && flat == o.flat;
+             res_grid[1] == o.res_grid[1] && flat == o.flat && contact_lanes == o.contact_lanes &&
+             group_waves == o.group_waves;
     }
   } launch;
   // releases what the handle holds, also after a create that failed part-way
@@ -759,8 +804,10 @@ pabd_status batch_tables(pabd_batch* b) {
   }
   auto round_up = [](int x, int q, int cap) { return std::min(cap, (x + q - 1) / q * q); };
   // flat-path waves, when contact scenes share the flat path with others: a
-  // contact scene's bodies take four lanes each (16 per wave), any other
-  // scene's one lane each (64 per wave); a wave stays within one scene
+  // contact scene's bodies take contact_lanes lanes each (64 / contact_lanes
+  // per wave), any other scene's one lane each (64 per wave); a wave stays
+  // within one scene
+  b->eng->set_schedule(b->contact_lanes, b->group_waves);
   std::vector<FlatWave> waves;
   if (b->any_contact) {
     std::vector<const Slot*> flat;
@@ -768,8 +815,9 @@ pabd_status batch_tables(pabd_batch* b) {
       if (s.used && !s.tiled && !s.resident && s.n > 0) flat.push_back(&s);
     std::sort(flat.begin(), flat.end(), [](const Slot* x, const Slot* y) { return x->boff < y->boff; });
     for (const Slot* s : flat) {
-      const int lpb = s->contact ? 4 : 1, per = 64 / lpb;
-      for (int f = 0; f < s->n; f += per) waves.push_back(FlatWave{s->boff + f, std::min(per, s->n - f), lpb, 0});
+      const int lpb = s->contact ? b->contact_lanes : 1, per = 64 / lpb;
+      for (int f = 0; f < s->n; f += per)
+        waves.push_back(FlatWave{s->boff + f, std::min(per, s->n - f), lpb, s->contact ? 1 : 0});
     }
   }
   const int nw = (int)waves.size();
@@ -805,6 +853,8 @@ pabd_status batch_tables(pabd_batch* b) {
   // releases reuse the captured graph
   L.wave_grid = b->any_contact ? round_up(std::max(1, nw), 256, INT_MAX) : 0;
   L.waves = b->any_contact ? b->d_waves : nullptr;
+  L.contact_lanes = b->contact_lanes;
+  L.group_waves = b->group_waves;
   if (!(L == b->launch)) {
     b->launch = L;
     b->graph.reset();
@@ -1250,11 +1300,14 @@ static pabd_status batch_repack(pabd_batch* b, int tile_bodies) {
   }
   // the device records move bit for bit (an FP32 position is a (hi, lo) pair that
   // a round trip through FP64 need not reproduce)
-  std::vector<std::vector<char>> raw(b->max_slots);
+  // The bond-end states (augmented multipliers and stiffnesses) move the same
+  // way: an upload would restart them from the descriptor.
+  std::vector<std::vector<char>> raw(b->max_slots), raw_ends(b->max_slots);
   for (int k : live) {
     Slot& s = b->slots[k];
     pabd_status st = b->eng->raw_bodies(s.boff, s.n, raw[k], b->stream, false);
     if (st != PABD_OK) return st;
+    if ((st = b->eng->raw_al(s.eoff, s.ne, raw_ends[k], b->stream, false)) != PABD_OK) return st;
   }
   for (int k : live) {
     Slot& s = b->slots[k];
@@ -1290,9 +1343,10 @@ static pabd_status batch_repack(pabd_batch* b, int tile_bodies) {
     Slot& s = b->slots[k];
     pabd_status st = batch_place_and_upload(b, k);
     if (st != PABD_OK) return fail(PABD_E_OOM, "repack did not fit");
-    // restore the scene's records and step counter
+    // restore the scene's records, bond-end states and step counter
     st = b->eng->raw_bodies(s.boff, s.n, raw[k], b->stream, true);
     if (st != PABD_OK) return st;
+    if ((st = b->eng->raw_al(s.eoff, s.ne, raw_ends[k], b->stream, true)) != PABD_OK) return st;
     SceneDev* d = b->eng->scene_table() + k;
     API_HIP(hipMemcpy((char*)d + offsetof(SceneDev, step), &sc_steps[k], sizeof(int), hipMemcpyHostToDevice));
   }
@@ -1364,7 +1418,7 @@ pabd_status pabd_batch_autotune(pabd_batch* b, int32_t* tile_out) {
   // candidates: tile sizes that hold the largest tiled scene
   int largest = 0;
   for (const Slot& s : b->slots)
-    if (s.used && !s.hs->contact && !s.hs->driven) largest = std::max(largest, s.n);
+    if (s.used && !s.hs->contact && !s.hs->driven && !s.hs->variable) largest = std::max(largest, s.n);
   std::vector<int> cand;
   for (int t : {32, 64, 128, 256})
     if (t >= largest) cand.push_back(t);
@@ -1400,6 +1454,361 @@ pabd_status pabd_batch_autotune(pabd_batch* b, int32_t* tile_out) {
   if ((st = batch_repack(b, best)) != PABD_OK) return st;
   b->tile_auto = false;
   if (tile_out) *tile_out = best;
+  return PABD_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// launch schedules and the tuner
+// ---------------------------------------------------------------------------
+
+namespace {
+
+// cache key of a tuned schedule: device architecture, precision, kind (0 batch,
+// 1 plain scene) and size buckets (bit lengths of counts)
+struct TuneKey {
+  std::string arch;
+  int precision = 0, kind = 0;
+  int bucket[5] = {0, 0, 0, 0, 0};
+  bool operator<(const TuneKey& o) const {
+    if (arch != o.arch) return arch < o.arch;
+    if (precision != o.precision) return precision < o.precision;
+    if (kind != o.kind) return kind < o.kind;
+    return std::lexicographical_compare(bucket, bucket + 5, o.bucket, o.bucket + 5);
+  }
+};
+
+std::mutex g_tune_mu;
+std::map<TuneKey, pabd_schedule>& tune_cache() {
+  static std::map<TuneKey, pabd_schedule> m;
+  return m;
+}
+
+int bit_length(long long x) {
+  int b = 0;
+  for (; x > 0; x >>= 1) ++b;
+  return b;
+}
+
+std::string device_arch() {
+  int d = 0;
+  hipDeviceProp_t p;
+  if (hipGetDevice(&d) != hipSuccess || hipGetDeviceProperties(&p, d) != hipSuccess) {
+    (void)hipGetLastError();
+    return "unknown";
+  }
+  return p.gcnArchName;
+}
+
+bool valid_lanes(int l) { return l == 1 || l == 2 || l == 4 || l == 8 || l == 16; }
+bool valid_waves(int g) { return g == 1 || g == 2 || g == 4; }
+
+const int kLaneCandidates[] = {1, 2, 4, 8, 16};
+const int kWaveCandidates[] = {1, 2, 4};
+
+struct EventPair {  // released on every path, failures included
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  ~EventPair() {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+  }
+};
+
+// Average duration in ms of one step, timed with HIP events on `st` over
+// `reps` calls of step() after one untimed call (which may capture a graph).
+template <typename Step>
+pabd_status time_steps(hipStream_t st, int reps, Step step, double* ms_out) {
+  EventPair ev;
+  API_HIP(hipEventCreate(&ev.e0));
+  API_HIP(hipEventCreate(&ev.e1));
+  pabd_status s = step();
+  if (s != PABD_OK) return s;
+  API_HIP(hipEventRecord(ev.e0, st));
+  for (int r = 0; r < reps; ++r)
+    if ((s = step()) != PABD_OK) return s;
+  API_HIP(hipEventRecord(ev.e1, st));
+  API_HIP(hipEventSynchronize(ev.e1));
+  float ms = 0.f;
+  API_HIP(hipEventElapsedTime(&ms, ev.e0, ev.e1));
+  *ms_out = (double)ms / reps;
+  return PABD_OK;
+}
+
+// Coordinate search over the flat-path schedule: contact lanes (when `lanes`),
+// then wavefronts per workgroup, each candidate applied by apply(cl, gw) and
+// timed by timed(&ms) (best of three rounds, each from the saved state, which
+// restore() writes back).  Leaves the best schedule in *cl, *gw.
+template <typename Apply, typename Timed, typename Restore>
+pabd_status search_flat(bool lanes, int* cl, int* gw, Apply apply, Timed timed, Restore restore) {
+  auto best_of = [&](int c, int g, double* out) -> pabd_status {
+    apply(c, g);
+    double best = 1e300;
+    for (int round = 0; round < 3; ++round) {
+      double ms = 0.0;
+      pabd_status s = timed(&ms);
+      if (s != PABD_OK) return s;
+      if ((s = restore()) != PABD_OK) return s;
+      best = std::min(best, ms);
+    }
+    *out = best;
+    return PABD_OK;
+  };
+  pabd_status s;
+  if (lanes) {
+    double best_t = 1e300;
+    int best = *cl;
+    for (int c : kLaneCandidates) {
+      double t = 0.0;
+      if ((s = best_of(c, *gw, &t)) != PABD_OK) return s;
+      if (t < best_t) {
+        best_t = t;
+        best = c;
+      }
+    }
+    *cl = best;
+  }
+  double best_t = 1e300;
+  int best = *gw;
+  for (int g : kWaveCandidates) {
+    double t = 0.0;
+    if ((s = best_of(*cl, g, &t)) != PABD_OK) return s;
+    if (t < best_t) {
+      best_t = t;
+      best = g;
+    }
+  }
+  *gw = best;
+  apply(*cl, *gw);
+  return PABD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void pabd_tune_cache_clear(void) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  tune_cache().clear();
+}
+
+int32_t pabd_tune_cache_size(void) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  return (int32_t)tune_cache().size();
+}
+
+pabd_status pabd_batch_get_schedule(const pabd_batch* b, pabd_schedule* out) {
+  if (!b || !out) return fail(PABD_E_INVALID, "null argument");
+  out->tile_bodies = b->tile_bodies;
+  out->contact_lanes = b->contact_lanes;
+  out->group_waves = b->group_waves;
+  out->from_cache = 0;
+  return PABD_OK;
+}
+
+pabd_status pabd_batch_set_schedule(pabd_batch* b, const pabd_schedule* sch) {
+  if (!b || !sch) return fail(PABD_E_INVALID, "null argument");
+  if (sch->tile_bodies != 0 && sch->tile_bodies != 32 && sch->tile_bodies != 64 && sch->tile_bodies != 128 &&
+      sch->tile_bodies != 256)
+    return fail(PABD_E_INVALID, "tile size must be 0, 32, 64, 128 or 256");
+  if (!valid_lanes(sch->contact_lanes)) return fail(PABD_E_INVALID, "contact lanes must be 1, 2, 4, 8 or 16");
+  if (!valid_waves(sch->group_waves)) return fail(PABD_E_INVALID, "wavefronts per workgroup must be 1, 2 or 4");
+  if (sch->tile_bodies != 0) {
+    pabd_status st = pabd_batch_set_tile(b, sch->tile_bodies);
+    if (st != PABD_OK) return st;
+  }
+  if (sch->contact_lanes != b->contact_lanes || sch->group_waves != b->group_waves) {
+    API_HIP(hipStreamSynchronize(b->stream));
+    b->contact_lanes = sch->contact_lanes;
+    b->group_waves = sch->group_waves;
+    b->dirty = true;  // new wave table; the changed launch recaptures the graph
+  }
+  return PABD_OK;
+}
+
+pabd_status pabd_batch_tune(pabd_batch* b, int32_t flags, pabd_schedule* out) {
+  if (!b) return fail(PABD_E_INVALID, "null batch");
+  // the workload's shape, whatever the current placement: scenes the tile
+  // kernel can take, contact scenes and other scenes (both always on the flat
+  // path), and the largest contact capacity
+  long long tileable = 0, contact = 0, other = 0;
+  int largest = 0, ccap = 0;
+  for (const Slot& s : b->slots) {
+    if (!s.used) continue;
+    if (s.hs->contact) {
+      contact += s.n;
+      ccap = std::max(ccap, s.hs->ccap);
+    } else if (!s.hs->driven && !s.hs->variable) {
+      tileable += s.n;
+      largest = std::max(largest, s.n);
+    } else {
+      other += s.n;
+    }
+  }
+  int tile_class = 0;
+  if (largest > 0) {
+    tile_class = 512;
+    for (int t : {32, 64, 128, 256})
+      if (t >= largest) {
+        tile_class = t;
+        break;
+      }
+  }
+  TuneKey key;
+  key.arch = device_arch();
+  key.precision = b->precision;
+  key.kind = 0;
+  key.bucket[0] = bit_length(tileable);
+  key.bucket[1] = tile_class;
+  key.bucket[2] = bit_length(contact);
+  key.bucket[3] = bit_length(other);
+  key.bucket[4] = bit_length(ccap);
+  pabd_status st;
+  if (!(flags & PABD_TUNE_FORCE)) {
+    pabd_schedule hit;
+    bool found = false;
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      auto it = tune_cache().find(key);
+      if (it != tune_cache().end()) {
+        hit = it->second;
+        found = true;
+      }
+    }
+    if (found) {
+      hit.from_cache = 0;
+      if ((st = pabd_batch_set_schedule(b, &hit)) != PABD_OK) return st;
+      if ((st = pabd_batch_get_schedule(b, out ? out : &hit)) != PABD_OK) return st;
+      if (out) out->from_cache = 1;
+      return PABD_OK;
+    }
+  }
+  // 1. tile size, on the tile kernel alone
+  if (tileable > 0) {
+    int t = 0;
+    if ((st = pabd_batch_autotune(b, &t)) != PABD_OK) return st;
+  }
+  // 2. the flat path (its scenes depend on the tile size just chosen), on
+  // whole steps from the saved state
+  if (b->dirty) {
+    if ((st = batch_tables(b)) != PABD_OK) return st;
+    b->dirty = false;
+  }
+  long long flat_contact = 0, flat_other = 0;
+  for (const Slot& s : b->slots)
+    if (s.used && !s.tiled && !s.resident) (s.contact ? flat_contact : flat_other) += s.n;
+  if (flat_contact + flat_other > 0) {
+    API_HIP(hipDeviceSynchronize());
+    std::vector<char> snap;
+    const int n = b->caps.n;
+    if ((st = b->eng->snapshot(n, snap, b->stream, false)) != PABD_OK) return st;
+    const long long substeps0 = b->substeps;
+    int cl = b->contact_lanes, gw = b->group_waves;
+    auto apply = [&](int c, int g) {
+      pabd_schedule sc{0, c, g, 0};
+      (void)pabd_batch_set_schedule(b, &sc);
+    };
+    auto timed = [&](double* ms) {
+      return time_steps(b->stream, 2, [&]() { return pabd_batch_steps(b, 1, nullptr); }, ms);
+    };
+    auto restore = [&]() {
+      b->substeps = substeps0;
+      return b->eng->snapshot(n, snap, b->stream, true);
+    };
+    if ((st = search_flat(flat_contact > 0, &cl, &gw, apply, timed, restore)) != PABD_OK) return st;
+  }
+  pabd_schedule best;
+  if ((st = pabd_batch_get_schedule(b, &best)) != PABD_OK) return st;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_cache()[key] = best;
+  }
+  if (out) *out = best;
+  return PABD_OK;
+}
+
+pabd_status pabd_scene_get_schedule(const pabd_scene* s, pabd_schedule* out) {
+  if (!s || !out) return fail(PABD_E_INVALID, "null argument");
+  out->tile_bodies = 0;
+  s->eng->get_schedule(&out->contact_lanes, &out->group_waves);
+  out->from_cache = 0;
+  return PABD_OK;
+}
+
+pabd_status pabd_scene_set_schedule(pabd_scene* s, const pabd_schedule* sch) {
+  if (!s || !sch) return fail(PABD_E_INVALID, "null argument");
+  if (!valid_lanes(sch->contact_lanes)) return fail(PABD_E_INVALID, "contact lanes must be 1, 2, 4, 8 or 16");
+  if (!valid_waves(sch->group_waves)) return fail(PABD_E_INVALID, "wavefronts per workgroup must be 1, 2 or 4");
+  int cl = 0, gw = 0;
+  s->eng->get_schedule(&cl, &gw);
+  if (cl != sch->contact_lanes || gw != sch->group_waves) {
+    API_HIP(hipStreamSynchronize(s->stream));
+    s->eng->set_schedule(sch->contact_lanes, sch->group_waves);
+    s->graph.reset();  // the captured step launches the old schedule
+  }
+  return PABD_OK;
+}
+
+pabd_status pabd_scene_tune(pabd_scene* s, int32_t flags, pabd_schedule* out) {
+  if (!s) return fail(PABD_E_INVALID, "null scene");
+  pabd_status st;
+  // a scene whose whole step runs in the resident kernel has no flat-path
+  // launch to tune
+  if ((s->resident && !s->history) || s->hs.n == 0) {
+    pabd_schedule cur;
+    if ((st = pabd_scene_get_schedule(s, &cur)) != PABD_OK) return st;
+    if (out) *out = cur;
+    return PABD_OK;
+  }
+  TuneKey key;
+  key.arch = device_arch();
+  key.precision = s->precision;
+  key.kind = 1;
+  key.bucket[0] = bit_length(s->hs.n);
+  key.bucket[1] = s->hs.contact ? 1 : 0;
+  key.bucket[2] = bit_length(s->hs.contact ? s->hs.ccap : 0);
+  if (!(flags & PABD_TUNE_FORCE)) {
+    pabd_schedule hit;
+    bool found = false;
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      auto it = tune_cache().find(key);
+      if (it != tune_cache().end()) {
+        hit = it->second;
+        found = true;
+      }
+    }
+    if (found) {
+      if ((st = pabd_scene_set_schedule(s, &hit)) != PABD_OK) return st;
+      if (out) {
+        if ((st = pabd_scene_get_schedule(s, out)) != PABD_OK) return st;
+        out->from_cache = 1;
+      }
+      return PABD_OK;
+    }
+  }
+  API_HIP(hipDeviceSynchronize());
+  std::vector<char> snap;
+  const int n = std::max(1, s->hs.n);
+  if ((st = s->eng->snapshot(n, snap, s->stream, false)) != PABD_OK) return st;
+  int cl = 0, gw = 0;
+  s->eng->get_schedule(&cl, &gw);
+  auto apply = [&](int c, int g) {
+    pabd_schedule sc{0, c, g, 0};
+    (void)pabd_scene_set_schedule(s, &sc);
+  };
+  auto timed = [&](double* ms) {
+    return time_steps(s->stream, 2, [&]() { return pabd_scene_step(s, 1, nullptr); }, ms);
+  };
+  auto restore = [&]() { return s->eng->snapshot(n, snap, s->stream, true); };
+  if ((st = search_flat(s->hs.contact, &cl, &gw, apply, timed, restore)) != PABD_OK) return st;
+  pabd_schedule best;
+  if ((st = pabd_scene_get_schedule(s, &best)) != PABD_OK) return st;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_cache()[key] = best;
+  }
+  if (out) *out = best;
   return PABD_OK;
 }
 
