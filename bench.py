@@ -391,8 +391,8 @@ def main():
         b.set_tile(args.tile)
     elif not args.no_autotune:
         t = time.perf_counter()
-        tb = b.autotune()
-        log(f"autotune picked tile {tb} in {time.perf_counter() - t:.1f}s")
+        sch = b.tune()
+        log(f"tuner picked {sch} in {time.perf_counter() - t:.1f}s")
     lay = b.layout()
 
     # timed: `launches` graph replays of spl steps each (one tile-kernel launch
@@ -497,11 +497,16 @@ def main():
         reqs = plan["requests"]
         log(f"{len(reqs)} requests")
         budget = int(args.serve_budget_gib * (1 << 30))
+        # the served batch keeps the default schedule (tile 64, four lanes per
+        # contact body, one wavefront per workgroup): the tuner's pick on a
+        # sample of the load (the first 80 requests, 50 steps in) measured
+        # slower on the whole served run, saturated and in real time
         srv = Server(budget, 512, S.PREC_FP32)
         res, st = srv.run(reqs, realtime=True, keep_state=False)
         served = st.summary()
         served.update(requests=len(reqs), rate_hz=200.0, arrivals_s=args.serve_seconds,
-                      budget_bytes=budget, mode="Poisson arrivals in real time")
+                      budget_bytes=budget, mode="Poisson arrivals in real time",
+                      schedule=srv.batch.schedule())
         srv.close()
         log("served", served)
         srv = Server(budget, 512, S.PREC_FP32)
@@ -541,9 +546,22 @@ def main():
     if not args.no_scenes:
         scene_legs = {}
 
-        def time_scene(sc, warm, steps):
+        schedules = {}
+
+        def time_scene(sc, warm, steps, tune_on=None):
+            """ms per step over `steps` steps after `warm`, under the schedule the
+            tuner picks on the state after the warm-up (or on `tune_on`, a state of
+            the same scene with its contacts formed, whose pick the cache then
+            hands to the timed scene)."""
+            if tune_on is not None and not args.no_autotune:
+                gt = P.Scene(tune_on)
+                gt.step(1)
+                gt.tune(force=True)
+                del gt
             g = P.Scene(sc)
             g.step(warm)
+            if not args.no_autotune:
+                schedules[sc.name] = g.tune()
             torch.cuda.synchronize()
             t = time.perf_counter()
             g.step(steps)
@@ -556,15 +574,16 @@ def main():
 
         for prec, tag in ((S.PREC_FP32, "fp32"), (S.PREC_FP64, "fp64")) if want("box_drop") else ():
             sc = S.box_drop(precision=prec)
-            g, rate, ms = time_scene(sc, 40, 60)
             # accuracy: one step from the oracle's state after 60 steps (contacts active)
             mid = refs["drop_mid"].copy(precision=prec)
+            g, rate, ms = time_scene(sc, 40, 60, tune_on=mid)
             gm = P.Scene(mid)
             gm.step(1)
             e = errors(gm.state(check=False), refs["drop_next"], scale_of(mid))
             scene_legs[f"box_drop_1000_{tag}"] = dict(
                 body_its_per_s=rate, ms_per_step=ms, steps_timed="40..100 (falling, then landing)",
-                one_step_err_vs_oracle=max(e["pos"], e["rot"]), iters=sc.iters)
+                one_step_err_vs_oracle=max(e["pos"], e["rot"]), iters=sc.iters,
+                schedule=schedules.get(sc.name))
             log(f"box drop {tag}: {rate:.3g} body-it/s, {ms:.3f} ms/step, 1-step err {max(e['pos'], e['rot']):.2e}")
         if want("granular_bed"):
             bed = S.granular_bed_quadruped(precision=S.PREC_FP32)
@@ -574,7 +593,7 @@ def main():
             ct = g.contacts()
             scene_legs["granular_bed_quadruped_fp32"] = dict(
                 body_its_per_s=rate, ms_per_step=ms, bodies=bed.n_bodies, iters=bed.iters,
-                steps_timed="2..6", contacts_after=int(len(ct["i"])))
+                steps_timed="2..6", contacts_after=int(len(ct["i"])), schedule=schedules.get(bed.name))
             log(f"granular bed: {rate:.3g} body-it/s, {ms:.3f} ms/step")
         # the paper's mass-ratio chain, augmented-Lagrangian joints on and off
         for aug, tag in ((True, "al"), (False, "quadratic")) if want("mass_ratio_chain") else ():
@@ -631,7 +650,7 @@ def main():
             ct = g.contacts()
             scene_legs["block_pile_125k_fp32"] = dict(
                 body_its_per_s=rate, ms_per_step=ms, bodies=pile.n_bodies, iters=pile.iters,
-                steps_timed="2..11", contacts_after=int(len(ct["i"])),
+                steps_timed="2..11", contacts_after=int(len(ct["i"])), schedule=schedules.get(pile.name),
                 paper_context="Table 2, 50^3 block pile on an RTX 3080: 72.56 ms collision + 87.55 ms "
                               "solve per frame at 20 iterations (2.9e7 body-iterations/s for the solve)")
             del g

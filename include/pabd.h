@@ -326,17 +326,22 @@ typedef struct pabd_schedule {
 
 /* Pick a batch's schedule by timing, on the scenes resident now (their state,
  * bond states, health bits and residuals are saved first and restored after
- * every candidate, so the scenes continue as if the call had not been made): the tile sizes that hold the largest tiled scene, timed on the
- * tile kernel alone (as pabd_batch_autotune); then, when contact scenes run on
- * the flat path, contact_lanes from {1, 2, 4, 8, 16}; then, when any scene runs
- * on the flat path, group_waves from {1, 2, 4}: each timed as whole batch steps
- * (one graph replay per step, HIP events, best of three rounds from the saved
- * state).  The result is kept in a per-process cache under (device
- * architecture, precision, size bucket): the bit lengths of the body counts of
- * the scenes the tile kernel can take (joint scenes without contacts, driven
- * or variable bonds), of the contact scenes and of the other scenes, the bit
- * length of the largest contact capacity, and the smallest tile size that
- * holds the largest scene the tile kernel can take.  A later call with the same key applies the cached schedule without
+ * every candidate, so the scenes continue as if the call had not been made).
+ * First the tile size: when every scene is one the tile kernel can take, the
+ * sizes that hold the largest, timed on the tile kernel alone (as
+ * pabd_batch_autotune); otherwise every size whose placement fits, timed as
+ * whole batch steps (a smaller tile moves the larger chains to the flat path).
+ * Then, when contact scenes run on the flat path, contact_lanes from {1, 2, 4,
+ * 8, 16}; then, when any scene runs on the flat path, group_waves from {1, 2,
+ * 4}.  Whole batch steps are one graph replay each, timed with HIP events,
+ * best of three rounds of four steps from the saved state; a candidate
+ * replaces the schedule in force only when it is more than 3 % faster.  The result is kept in a
+ * per-process cache under (device architecture, precision, size bucket): the
+ * bit lengths of the body counts of the scenes the tile kernel can take (joint
+ * scenes without contacts, driven or variable bonds), of the contact scenes
+ * and of the other scenes, the bit length of the largest contact capacity, and
+ * the smallest tile size that holds the largest scene the tile kernel can
+ * take.  A later call with the same key applies the cached schedule without
  * timing (unless flags has PABD_TUNE_FORCE).  Writes the schedule in force. */
 pabd_status pabd_batch_tune(pabd_batch *b, int32_t flags, pabd_schedule *out);
 /* Apply a schedule to a batch (tile_bodies 0 leaves the tile size as it is;
@@ -344,7 +349,7 @@ pabd_status pabd_batch_tune(pabd_batch *b, int32_t flags, pabd_schedule *out);
 pabd_status pabd_batch_set_schedule(pabd_batch *b, const pabd_schedule *s);
 pabd_status pabd_batch_get_schedule(const pabd_batch *b, pabd_schedule *out);
 /* The same for a plain scene: contact_lanes, then group_waves, each timed over
- * whole steps from the saved state.  A scene whose whole step runs in the
+ * whole steps from the saved state (with the same 3 % margin).  A scene whose whole step runs in the
  * resident kernel (small scenes) has no flat-path launch to tune: the call
  * writes the schedule in force and times nothing.  Cache key: (device
  * architecture, precision, bit length of the body count, contact flag, bit

@@ -1535,6 +1535,10 @@ pabd_status time_steps(hipStream_t st, int reps, Step step, double* ms_out) {
   return PABD_OK;
 }
 
+// A candidate replaces the schedule in force only when it is faster by more
+// than this fraction (timing noise between candidates is a few per cent).
+constexpr double kTuneMargin = 0.03;
+
 // Coordinate search over the flat-path schedule: contact lanes (when `lanes`),
 // then wavefronts per workgroup, each candidate applied by apply(cl, gw) and
 // timed by timed(&ms) (best of three rounds, each from the saved state, which
@@ -1556,24 +1560,28 @@ pabd_status search_flat(bool lanes, int* cl, int* gw, Apply apply, Timed timed, 
   };
   pabd_status s;
   if (lanes) {
-    double best_t = 1e300;
+    double best_t = 0.0;
+    if ((s = best_of(*cl, *gw, &best_t)) != PABD_OK) return s;
     int best = *cl;
     for (int c : kLaneCandidates) {
+      if (c == *cl) continue;
       double t = 0.0;
       if ((s = best_of(c, *gw, &t)) != PABD_OK) return s;
-      if (t < best_t) {
+      if (t < (1.0 - kTuneMargin) * best_t) {
         best_t = t;
         best = c;
       }
     }
     *cl = best;
   }
-  double best_t = 1e300;
+  double best_t = 0.0;
+  if ((s = best_of(*cl, *gw, &best_t)) != PABD_OK) return s;
   int best = *gw;
   for (int g : kWaveCandidates) {
+    if (g == *gw) continue;
     double t = 0.0;
     if ((s = best_of(*cl, g, &t)) != PABD_OK) return s;
-    if (t < best_t) {
+    if (t < (1.0 - kTuneMargin) * best_t) {
       best_t = t;
       best = g;
     }
@@ -1683,13 +1691,61 @@ pabd_status pabd_batch_tune(pabd_batch* b, int32_t flags, pabd_schedule* out) {
       return PABD_OK;
     }
   }
-  // 1. tile size, on the tile kernel alone
-  if (tileable > 0) {
+  const int n = b->caps.n;
+  const long long substeps0 = b->substeps;
+  std::vector<char> snap;
+  // whole steps (one graph replay each), timed from the saved state
+  auto timed = [&](double* ms) {
+    return time_steps(b->stream, 4, [&]() { return pabd_batch_steps(b, 1, nullptr); }, ms);
+  };
+  auto restore = [&]() {
+    b->substeps = substeps0;
+    return b->eng->snapshot(n, snap, b->stream, true);
+  };
+  // 1. tile size.  With only scenes the tile kernel takes, the sizes that hold
+  // them all, on the tile kernel alone; with other scenes beside them, every
+  // size on whole steps (a smaller tile moves the larger chains to the flat
+  // path, whose time then counts too).  A repack keeps every record bit for
+  // bit, so each candidate starts from the same state.
+  if (tileable > 0 && contact + other == 0) {
     int t = 0;
     if ((st = pabd_batch_autotune(b, &t)) != PABD_OK) return st;
+  } else if (tileable > 0) {
+    double best_t = 1e300;
+    const int start = b->tile_bodies;
+    int best = start;
+    int order[4] = {start, 0, 0, 0}, no = 1;
+    for (int t : {32, 64, 128, 256})
+      if (t != start) order[no++] = t;
+    for (int t : order) {
+      // only sizes whose placement surely fits: the flat-path bodies within the
+      // flat pool, the tiled ones within half the tile pool
+      long long flat_n = 0, tiled_n = 0;
+      for (const Slot& sl : b->slots) {
+        if (!sl.used) continue;
+        const bool tl = !sl.hs->contact && !sl.hs->driven && !sl.hs->variable && sl.n > 0 && sl.n <= t;
+        (tl ? tiled_n : flat_n) += std::max(1, sl.n);
+      }
+      if (flat_n > b->n_stream || 2 * tiled_n > (long long)b->caps.n - b->n_stream) continue;
+      if (t != b->tile_bodies && (st = batch_repack(b, t)) != PABD_OK) return st;
+      API_HIP(hipDeviceSynchronize());
+      if ((st = b->eng->snapshot(n, snap, b->stream, false)) != PABD_OK) return st;
+      double dt = 1e300;
+      for (int round = 0; round < 3; ++round) {
+        double ms = 0.0;
+        if ((st = timed(&ms)) != PABD_OK) return st;
+        if ((st = restore()) != PABD_OK) return st;
+        dt = std::min(dt, ms);
+      }
+      if (t == start ? dt < best_t : dt < (1.0 - kTuneMargin) * best_t) {
+        best_t = dt;
+        best = t;
+      }
+    }
+    if (best != b->tile_bodies && (st = batch_repack(b, best)) != PABD_OK) return st;
+    b->tile_auto = false;
   }
-  // 2. the flat path (its scenes depend on the tile size just chosen), on
-  // whole steps from the saved state
+  // 2. the flat path (its scenes depend on the tile size just chosen)
   if (b->dirty) {
     if ((st = batch_tables(b)) != PABD_OK) return st;
     b->dirty = false;
@@ -1699,21 +1755,11 @@ pabd_status pabd_batch_tune(pabd_batch* b, int32_t flags, pabd_schedule* out) {
     if (s.used && !s.tiled && !s.resident) (s.contact ? flat_contact : flat_other) += s.n;
   if (flat_contact + flat_other > 0) {
     API_HIP(hipDeviceSynchronize());
-    std::vector<char> snap;
-    const int n = b->caps.n;
     if ((st = b->eng->snapshot(n, snap, b->stream, false)) != PABD_OK) return st;
-    const long long substeps0 = b->substeps;
     int cl = b->contact_lanes, gw = b->group_waves;
     auto apply = [&](int c, int g) {
       pabd_schedule sc{0, c, g, 0};
       (void)pabd_batch_set_schedule(b, &sc);
-    };
-    auto timed = [&](double* ms) {
-      return time_steps(b->stream, 2, [&]() { return pabd_batch_steps(b, 1, nullptr); }, ms);
-    };
-    auto restore = [&]() {
-      b->substeps = substeps0;
-      return b->eng->snapshot(n, snap, b->stream, true);
     };
     if ((st = search_flat(flat_contact > 0, &cl, &gw, apply, timed, restore)) != PABD_OK) return st;
   }
@@ -1798,7 +1844,7 @@ pabd_status pabd_scene_tune(pabd_scene* s, int32_t flags, pabd_schedule* out) {
     (void)pabd_scene_set_schedule(s, &sc);
   };
   auto timed = [&](double* ms) {
-    return time_steps(s->stream, 2, [&]() { return pabd_scene_step(s, 1, nullptr); }, ms);
+    return time_steps(s->stream, 4, [&]() { return pabd_scene_step(s, 1, nullptr); }, ms);
   };
   auto restore = [&]() { return s->eng->snapshot(n, snap, s->stream, true); };
   if ((st = search_flat(s->hs.contact, &cl, &gw, apply, timed, restore)) != PABD_OK) return st;

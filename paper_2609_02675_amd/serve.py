@@ -82,8 +82,11 @@ class Server:
 
     def __init__(self, hbm_budget: int, max_slots: int, precision: int,
                  clock: Callable[[], float] = time.perf_counter, batch=None,
-                 fault_check_every: int = 8):
+                 fault_check_every: int = 8, schedule: Optional[dict] = None):
         self.batch = batch if batch is not None else _lib.Batch(max_slots, hbm_budget, precision)
+        if schedule:  # a launch schedule picked beforehand (Batch.tune on a sample of the load)
+            self.batch.set_schedule(**{k: int(schedule[k]) for k in
+                                       ("tile_bodies", "contact_lanes", "group_waves")})
         self.precision = precision
         self.clock = clock
         # replays between two reads of the batch's fault list (each read waits

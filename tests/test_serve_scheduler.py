@@ -158,3 +158,17 @@ def test_diverged_scene_is_evicted_and_left_out_of_the_throughput():
     assert st.diverged == 1 and st.completed == len(reqs) - 1
     expect = sum(r.scene.n_bodies * r.scene.iters * r.steps for k, r in enumerate(reqs) if k != victim)
     assert st.body_iterations == expect
+
+
+def test_server_applies_a_given_schedule_to_its_batch():
+    calls = []
+
+    class Scheduled(OracleBatch):
+        def set_schedule(self, **kw):
+            calls.append(kw)
+
+    sch = dict(tile_bodies=128, contact_lanes=8, group_waves=2, from_cache=1)
+    Server(1 << 30, 4, S.PREC_FP64, batch=Scheduled(1 << 30, 4), schedule=sch)
+    assert calls == [dict(tile_bodies=128, contact_lanes=8, group_waves=2)]
+    Server(1 << 30, 4, S.PREC_FP64, batch=Scheduled(1 << 30, 4))
+    assert len(calls) == 1
