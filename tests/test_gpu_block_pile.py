@@ -1,13 +1,16 @@
-"""Contact construction at the paper's largest scale: 50^3 = 125,000 stacked
-cubes, every cube in resting contact with its neighbours.  The full contact set
-is too large for the oracle's all-pairs detection, so sampled bodies are checked:
-for each, the oracle's O(N) per-body query must return exactly the contacts the
-GPU built for that body (FP64, bit-exact keys and anchors)."""
+"""Contact construction and dynamics at the paper's largest scale: 50^3 = 125,000
+stacked cubes, every cube in resting contact with its neighbours.  The full
+scene is too large for the oracle's all-pairs detection, so sampled bodies are
+checked: for each, the oracle's O(N) per-body query must return exactly the
+contacts the GPU built for that body (FP64, bit-exact keys and anchors), and the
+oracle's step of the sub-pile a sampled cube depends on must reproduce its
+state."""
 import numpy as np
 import pytest
 
 import oracle
 from paper_2609_02675_amd import scenes as S
+from parity import errors, fp64_ok, scale_of
 
 pytestmark = pytest.mark.gpu
 
@@ -59,3 +62,60 @@ def test_block_pile_125k_fp32_steps(P):
     assert np.all(np.isfinite(c)) and np.all(np.isfinite(v))
     # the stack settles under gravity: nothing rises far above its start or leaves the floor
     assert c[:, 1].max() < sc.c0[:, 1].max() + 0.5 and c[:, 1].min() > 0.0
+
+
+def _lattice(sc, n_side=50, layers=50, size=1.0, gap=1e-3):
+    """Lattice coordinates (ix, iy, iz) of the pile's cubes, from their centres."""
+    sp = size + gap
+    g = np.rint(np.stack([sc.c0[:, 0] / sp + (n_side - 1) / 2, (sc.c0[:, 1] - size / 2 - gap) / sp,
+                          sc.c0[:, 2] / sp + (n_side - 1) / 2], axis=1)).astype(np.int64)
+    assert np.array_equal((g[:, 0] * layers + g[:, 1]) * n_side + g[:, 2], np.arange(sc.n_bodies))
+    return g
+
+
+def _sub_pile(sc, sel):
+    return sc.copy(shape=sc.shape[sel], shape_param=sc.shape_param[sel], density=sc.density[sel],
+                   flags=sc.flags[sel], group=sc.group[sel], c0=sc.c0[sel], A0=sc.A0[sel],
+                   v0=sc.v0[sel], w0=sc.w0[sel])
+
+
+def test_block_pile_125k_sampled_dynamics(P):
+    """One full step of the 125,000-cube pile (K = 20, as timed) against the
+    oracle, on sampled cubes.  A Jacobi iteration moves a cube from its contact
+    partners' previous iterates only, so after K iterations a cube depends on
+    the cubes within K contact hops, and in this lattice (checked below on the
+    GPU's own contact set) every contact joins cubes at most one lattice step
+    apart.  The oracle therefore steps the sub-pile of cubes within K + 1
+    lattice steps of a sampled cube and must reproduce that cube's state: FP64
+    to 1e-9, FP32 to 1e-4 (the one-step bars)."""
+    sc64 = S.block_pile(precision=S.PREC_FP64)
+    g = _lattice(sc64)
+    L = scale_of(sc64)
+    states = {}
+    for prec in (S.PREC_FP64, S.PREC_FP32):
+        print(f"[case] block pile dynamics n={sc64.n_bodies} prec {prec}", flush=True)
+        gp = P.Scene(sc64.copy(precision=prec))
+        gp.step(1)
+        states[prec] = gp.state()
+        if prec == S.PREC_FP64:
+            ct = gp.contacts()
+            j = ct["j"]
+            body = j >= 0
+            hop = np.abs(g[ct["i"][body]] - g[j[body]]).max(axis=1)
+            assert hop.max() <= 1
+        del gp
+    corner_top_edge = (25 * 50 + 49) * 50 + 0
+    for b in (0, sc64.n_bodies - 1, corner_top_edge):
+        sel = np.nonzero(np.abs(g - g[b]).max(axis=1) <= sc64.iters + 1)[0]
+        o = oracle.Oracle(_sub_pile(sc64, sel))
+        o.step(1)
+        k = int(np.searchsorted(sel, b))
+        ref = tuple(x[k:k + 1] for x in o.state())
+        for prec, st in states.items():
+            got = tuple(x[b:b + 1] for x in st)
+            e = errors(got, ref, L)
+            print(f"cube {b} (sub-pile of {len(sel)}) prec {prec}: {e}", flush=True)
+            if prec == S.PREC_FP64:
+                assert fp64_ok(e), (b, e)
+            else:
+                assert e["pos"] <= 1e-4 and e["rot"] <= 1e-4, (b, e)
