@@ -3,7 +3,8 @@
 // Per-body records are packed arrays of structures so one body is a few 16-byte
 // vector loads (a bond partner's coordinates are gathered by its neighbours):
 //   Q    12 T : c0 c1 c2 | a1 (3) | a2 (3) | a3 (3)      (A rows)
-//        (FP32: 16 floats, c_lo0 c_lo1 c_lo2 - appended, see Rec)
+//        (FP32: 16 floats, c_lo0 c_lo1 c_lo2 kc appended, see Rec; kc =
+//        round(scale * free mass), the body's share of a contact's h^2 kappa)
 //   VEL   8 T : v0 v1 v2 w0 w1 w2 - -
 //   MASS  8 T : m  Pi00 Pi01 Pi02 Pi11 Pi12 Pi22 -
 //   FAC  12 T : alpha g0 g1 g2 G00 G01 G02 G11 G12 G22 - -   (H^{-1}, FP64-computed)
@@ -13,7 +14,9 @@
 //   END   8 T : xs0 xs1 xs2 kappa xo0 xo1 xo2 phim   (phim = phi^- = -kappa l)
 //   plus the partner body (int, -1 = world; xo then in world coordinates).
 // Contact ends live in fixed per-body slots (capacity C per body, ELL by body):
-//   CEND 12 T : xs0 xs1 xs2 kappa xo0 xo1 xo2 mu n0 n1 n2 -
+//   CEND FP64 12 T : xs0 xs1 xs2 kappa xo0 xo1 xo2 mu n0 n1 n2 -
+//   CEND FP32  8 T : xs0 xs1 xs2 nu xo0 xo1 xo2 nv   (n in octahedral form;
+//        kappa is the larger kc of the two q records, mu the scene's)
 //   plus partner (int) and a 64-bit sort key; n is oriented for the owning side
 //   (it points from the partner's surface towards the owner).
 #pragma once
@@ -24,6 +27,12 @@
 namespace pabd {
 
 constexpr int QW = 12, VW = 8, MW = 8, FW = 12, EW = 8, CW = 12;
+
+// Stored width of a contact end record: CW values in FP64, 8 in FP32.
+template <typename T>
+struct ContactRec {
+  static constexpr int W = sizeof(T) == 4 ? 8 : CW;
+};
 
 // Stored width of a Q record.  In FP32 the body position is kept as an
 // unevaluated sum c_hi + c_lo of two floats (c_lo at 12..14) so that bond
@@ -75,16 +84,16 @@ __device__ __forceinline__ size_t ce_base(const SceneDev& S, int i) {
 
 // A contact end as the narrow phase stages it, in the order its atomics give:
 // the end's record, its partner and its sort key (partner + 1, feature, side)
-// side by side, so that staging an end writes one run of bytes (64 in FP32)
+// side by side, so that staging an end writes one run of bytes (48 in FP32)
 // and the sort reads one.
 template <typename T>
 struct alignas(16) StageRec {
-  T C[CW];
+  T C[ContactRec<T>::W];
   int partner;
   int pad;
   unsigned long long key;
 };
-static_assert(sizeof(StageRec<float>) == 64, "an FP32 staged end is one 64-byte run");
+static_assert(sizeof(StageRec<float>) == 48, "an FP32 staged end is one 48-byte run");
 
 template <typename T>
 struct View {

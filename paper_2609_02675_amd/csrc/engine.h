@@ -270,7 +270,7 @@ struct Engine {
     if (c.contacts) {
       ncb = c.nc < 0 ? c.n : std::min(c.nc, c.n);
       const size_t nb = (size_t)ncb, nc = (size_t)std::max(1LL, c.cslots);
-      PABD_TRY(alloc(ce, CW * nc));
+      PABD_TRY(alloc(ce, ContactRec<T>::W * nc));
       PABD_TRY(alloc(ce_partner, nc));
       PABD_TRY(alloc(ce_key, nc));
       PABD_TRY(alloc(ce_stage, nc));
@@ -371,9 +371,13 @@ struct Engine {
     std::vector<T> tq(QR * n, (T)0), tv(VW * n), tm(MW * n), th(4 * n), te(EW * ne);
     for (size_t b = 0; b < n; ++b) {
       for (int k = 0; k < QW; ++k) tq[QR * b + k] = (T)hs.qn[QW * b + k];
-      if (QR > QW)  // compensated position: c = c_hi + c_lo
+      if (QR > QW) {  // compensated position: c = c_hi + c_lo
         for (int k = 0; k < 3; ++k)
           tq[QR * b + 12 + k] = (T)(hs.qn[QW * b + k] - (double)tq[QR * b + k]);
+        // the body's share of a contact's h^2 kappa, round(scale * free mass)
+        const double mfree = (hs.flags[b] & F_PINNED) ? 0.0 : hs.mass64[8 * b];
+        tq[QR * b + Q_KAPPA] = (T)(hs.params.kscale * mfree);
+      }
     }
     for (size_t k = 0; k < VW * n; ++k) tv[k] = (T)hs.vel[k];
     for (size_t b = 0; b < n; ++b) {

@@ -285,7 +285,8 @@ inline size_t scene_bytes(const HostScene& hs, int ts) {
   // contact slots (final and staging) and the broad phase: record, reach,
   // large-list entry and task offset, and max(16, ccap / 2) candidate pairs per body
   // final record, partner and key, then the staged copy
-  const size_t per_contact = (size_t)ts * CW + 4 + 8 + (ts == 4 ? sizeof(StageRec<float>) : sizeof(StageRec<double>));
+  const size_t per_contact = (size_t)ts * (ts == 4 ? ContactRec<float>::W : ContactRec<double>::W) + 4 + 8 +
+                             (ts == 4 ? sizeof(StageRec<float>) : sizeof(StageRec<double>));
   const size_t per_contact_body = hs.ccap > 0 ? 64 + 8 + 4 + 4 + 8 * (size_t)std::max(16, hs.ccap / 2) : 0;
   return per_body * hs.n + per_end * hs.ne + per_contact * (size_t)hs.n * hs.ccap +
          per_contact_body * hs.n +

@@ -41,6 +41,7 @@
 #pragma once
 
 #include "common.h"
+#include "contact_record.h"
 #include "device_math.h"
 
 namespace pabd {
@@ -328,10 +329,18 @@ __device__ __forceinline__ void push_end(const View<T>& v, int owner, int sc, in
     return;
   }
   const size_t e = ce_base(S, owner) + slot;
-  T C[CW] = {(T)xs[0], (T)xs[1], (T)xs[2], (T)kap, (T)xo[0], (T)xo[1], (T)xo[2], (T)mu,
-             (T)n[0], (T)n[1], (T)n[2], (T)0};
   StageRec<T>& r = v.ce_stage[e];
-  store<T, CW>(r.C, C);
+  if constexpr (sizeof(T) == 4) {
+    // stiffness and friction coefficient come from the q records and the scene
+    double uv[2];
+    oct_encode(n, uv);
+    const T C[8] = {(T)xs[0], (T)xs[1], (T)xs[2], (T)uv[0], (T)xo[0], (T)xo[1], (T)xo[2], (T)uv[1]};
+    store<T, 8>(r.C, C);
+  } else {
+    const T C[CW] = {(T)xs[0], (T)xs[1], (T)xs[2], (T)kap, (T)xo[0], (T)xo[1], (T)xo[2], (T)mu,
+                     (T)n[0], (T)n[1], (T)n[2], (T)0};
+    store<T, CW>(r.C, C);
+  }
   r.partner = partner;
   r.pad = 0;
   r.key = ((unsigned long long)(unsigned)(partner + 1) << 32) |
@@ -916,10 +925,11 @@ __device__ __forceinline__ unsigned long long lane_key(unsigned long long k, int
 template <typename T>
 __device__ __forceinline__ void move_end(const View<T>& v, size_t base, int from, int to,
                                          unsigned long long key) {
+  constexpr int W = ContactRec<T>::W;
   const StageRec<T>& r = v.ce_stage[base + from];
-  T C[CW];
-  load<T, CW>(r.C, C);
-  store<T, CW>(v.ce + CW * (base + to), C);
+  T C[W];
+  load<T, W>(r.C, C);
+  store<T, W>(v.ce + W * (base + to), C);
   v.ce_partner[base + to] = r.partner;
   v.ce_key[base + to] = key;
 }

@@ -12,6 +12,7 @@
 #pragma once
 
 #include "common.h"
+#include "contact_record.h"
 #include "device_math.h"
 #include "kernels_step.h"
 
@@ -101,16 +102,15 @@ __device__ __forceinline__ T slider_end(const T* d0, const T* A, const T* u, T* 
 
 // contact end (reading of the paper's contact bond), d = y_o - y_s: stick force
 // kappa d acting only while penetrating along n (n from the partner's surface
-// towards the owner), tangential part clamped to mu times the normal part; the
-// record holds h^2 kappa, so the force comes out scaled by h^2 like the bonds'.
+// towards the owner), tangential part clamped to mu times the normal part; kap
+// is h^2 kappa, so the force comes out scaled by h^2 like the bonds'.
 // Returns false when separated (no contribution, no implicit weight).
 template <typename T>
-__device__ __forceinline__ bool contact_end_force(const T* C, const T* d, T* f) {
+__device__ __forceinline__ bool contact_end_force(T kap, T mu, const T* n, const T* d, T* f) {
   const T d0 = d[0], d1 = d[1], d2 = d[2];
-  const T n0 = C[8], n1 = C[9], n2 = C[10];
+  const T n0 = n[0], n1 = n[1], n2 = n[2];
   T dn = n0 * d0 + n1 * d1 + n2 * d2;  // = -gap
   if (!(dn > (T)0)) return false;
-  const T kap = C[3], mu = C[7];
   T fn = kap * dn;
   T t0 = kap * (d0 - dn * n0), t1 = kap * (d1 - dn * n1), t2 = kap * (d2 - dn * n2);
   T tn2 = t0 * t0 + t1 * t1 + t2 * t2;
@@ -283,12 +283,24 @@ __device__ __forceinline__ void iterate_body(const View<T>& v, int k, double* rh
     // the lanes of a body take its ends in turn (neighbouring lanes read
     // neighbouring records), two ends per round with both ends' loads (record
     // and partner state) in flight together
+    constexpr int W = ContactRec<T>::W;
+    const T mu = (T)S.mu;
     auto contact_end = [&](const T* C, int j, const T* qj) {
-      T d[3], f[3];
+      T d[3], f[3], n[3], kap;
       bond_vec<T>(q, C, j < 0 ? nullptr : qj, C + 4, d);
-      if (!contact_end_force(C, d, f)) return;
+      if constexpr (sizeof(T) == 4) {
+        // h^2 kappa from the two q records, the normal from its octahedral form
+        kap = fmax(q[Q_KAPPA], j < 0 ? (T)0 : qj[Q_KAPPA]);
+        oct_decode(C[3], C[7], n);
+      } else {
+        kap = C[3];
+        n[0] = C[8];
+        n[1] = C[9];
+        n[2] = C[10];
+      }
+      if (!contact_end_force(kap, mu, n, d, f)) return;
       add_JT(rb, C, f[0], f[1], f[2]);
-      block_add_end(dB, (double)C[3], (double)C[0], (double)C[1], (double)C[2]);
+      block_add_end(dB, (double)kap, (double)C[0], (double)C[1], (double)C[2]);
       refactor = true;
     };
     for (int c = sub; c < cnt; c += 2 * LPB) {
@@ -296,9 +308,9 @@ __device__ __forceinline__ void iterate_body(const View<T>& v, int k, double* rh
       const bool hb = cb < cnt;
       const int ja = v.ce_partner[base + c];
       const int jb = hb ? v.ce_partner[base + cb] : -1;
-      T Ca[CW], Cb[CW], qa[QR], qb[QR];
-      load<T, CW>(v.ce + (size_t)CW * (base + c), Ca);
-      if (hb) load<T, CW>(v.ce + (size_t)CW * (base + cb), Cb);
+      T Ca[W], Cb[W], qa[QR], qb[QR];
+      load<T, W>(v.ce + (size_t)W * (base + c), Ca);
+      if (hb) load<T, W>(v.ce + (size_t)W * (base + cb), Cb);
       if (ja >= 0) load<T, QR>(qs + (size_t)QR * (ja - qoff), qa);
       if (jb >= 0) load<T, QR>(qs + (size_t)QR * (jb - qoff), qb);
       contact_end(Ca, ja, qa);

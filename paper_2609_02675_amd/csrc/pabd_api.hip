@@ -204,24 +204,49 @@ struct EngineT final : EngineBase {
     e.rh_k = K;
     return PABD_OK;
   }
+  // contact records of bodies [0, n), each returned as the CW values of the FP64
+  // layout (an FP32 record's stiffness is rebuilt from the two bodies' q
+  // records and its normal decoded; its friction coefficient reads 0)
   pabd_status read_contacts(int n, int ccap, std::vector<int>& count, std::vector<int>& partner,
                             std::vector<unsigned long long>& key, std::vector<double>& rec,
                             hipStream_t st) override {
+    constexpr int W = ContactRec<T>::W, QR = Rec<T>::Q;
     count.assign(n, 0);
     const size_t ns = (size_t)n * ccap;
     partner.assign(ns, 0);
     key.assign(ns, 0);
-    std::vector<T> r(CW * ns);
+    std::vector<T> r(W * ns), q;
     if (n > 0 && ccap > 0) {
       if (hipMemcpyAsync(count.data(), e.ccount, n * sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
           hipMemcpyAsync(partner.data(), e.ce_partner, ns * sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
           hipMemcpyAsync(key.data(), e.ce_key, ns * sizeof(unsigned long long), hipMemcpyDeviceToHost, st) != hipSuccess ||
           hipMemcpyAsync(r.data(), e.ce, r.size() * sizeof(T), hipMemcpyDeviceToHost, st) != hipSuccess)
         return fail(PABD_E_DEVICE, "contact copy failed");
+      if constexpr (W != CW) {
+        q.resize((size_t)QR * n);
+        if (hipMemcpyAsync(q.data(), e.qn, q.size() * sizeof(T), hipMemcpyDeviceToHost, st) != hipSuccess)
+          return fail(PABD_E_DEVICE, "contact copy failed");
+      }
     }
     if (hipStreamSynchronize(st) != hipSuccess) return fail(PABD_E_DEVICE, "stream sync failed");
-    rec.resize(r.size());
-    for (size_t k = 0; k < r.size(); ++k) rec[k] = (double)r[k];
+    rec.assign(CW * ns, 0.0);
+    for (size_t k = 0; k < ns; ++k) {
+      const T* c = &r[W * k];
+      double* o = &rec[CW * k];
+      if constexpr (W == CW) {
+        for (int d = 0; d < CW; ++d) o[d] = (double)c[d];
+      } else {
+        const int owner = (int)(k / (size_t)ccap), j = partner[k];
+        const T ko = q[(size_t)QR * owner + Q_KAPPA];
+        const T kj = j >= 0 && j < n ? q[(size_t)QR * j + Q_KAPPA] : (T)0;
+        for (int d = 0; d < 3; ++d) {
+          o[d] = (double)c[d];
+          o[4 + d] = (double)c[4 + d];
+        }
+        o[3] = (double)(ko > kj ? ko : kj);
+        oct_decode_host((double)c[3], (double)c[7], o + 8);
+      }
+    }
     return PABD_OK;
   }
   pabd_status read_al(int ne, std::vector<double>& out, hipStream_t st) override {
@@ -738,7 +763,8 @@ size_t end_cost(int ts) { return (size_t)ts * EW + 4 + 8 * 4; }
 // one contact slot: final and staging copies of the record, partner and key,
 // and half a candidate pair
 size_t contact_cost(int ts) {
-  return (size_t)ts * CW + 4 + 8 + (ts == 4 ? sizeof(StageRec<float>) : sizeof(StageRec<double>)) + 4;
+  return (size_t)ts * (ts == 4 ? ContactRec<float>::W : ContactRec<double>::W) + 4 + 8 +
+         (ts == 4 ? sizeof(StageRec<float>) : sizeof(StageRec<double>)) + 4;
 }
 // per flat-path body: broad-phase record, reach, large-list entry, at least 16 candidate pairs
 size_t contact_body_cost() { return sizeof(BroadRec) + 8 + 4 + 8 * 16; }
