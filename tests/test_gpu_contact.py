@@ -250,3 +250,33 @@ def test_empty_and_single_body_contact_scenes(P):
         o.step(10)
     _compare_contacts(g, o)
     assert fp64_ok(errors(g.state(), o.state(), scale_of(one)))
+
+
+def test_fp32_contact_records_decode_to_the_fp64_ones(P):
+    """The FP32 contact record keeps the normal in octahedral form and takes the
+    stiffness from the two bodies' q records.  On the same settled state, every
+    contact the FP32 and FP64 scenes both find must read back the FP64 record's
+    points and normal to float rounding, and its stiffness as the FP64 one
+    rounded to float (the larger of the two rounded body shares is the rounded
+    larger share)."""
+    sc = settled_drop(seed=4)
+    print(f"[case] fp32 contact records n={sc.n_bodies}", flush=True)
+    g64 = P.Scene(sc)
+    g64.step(1)
+    g32 = P.Scene(sc.copy(precision=S.PREC_FP32))
+    g32.step(1)
+    k64, c64 = _contact_table(g64.contacts())
+    k32, c32 = _contact_table(g32.contacts())
+    pos = {tuple(k): n for n, k in enumerate(map(tuple, k64))}
+    both = [(pos[tuple(k)], n) for n, k in enumerate(map(tuple, k32)) if tuple(k) in pos]
+    assert len(both) >= 0.9 * max(len(k64), len(k32)) and len(both) > 50
+    a = np.array([x for x, _ in both])
+    b = np.array([y for _, y in both])
+    n64, n32 = c64["normal"][a], c32["normal"][b]
+    assert np.abs(np.linalg.norm(n32, axis=1) - 1.0).max() < 1e-6
+    assert np.abs(n32 - n64).max() < 1e-6
+    for f in ("x_i", "x_j"):
+        assert np.abs(c32[f][b] - c64[f][a]).max() < 1e-5
+    h2 = sc.h * sc.h
+    want = (np.float32(c64["kappa"][a] * h2)).astype(np.float64) / h2
+    np.testing.assert_allclose(c32["kappa"][b], want, rtol=1e-12)
