@@ -303,18 +303,42 @@ __device__ __forceinline__ void iterate_body(const View<T>& v, int k, double* rh
       block_add_end(dB, (double)kap, (double)C[0], (double)C[1], (double)C[2]);
       refactor = true;
     };
+    // In the flat kernels the next round's partner ids are loaded during this
+    // round, so that a round's records and partner states all go out at once
+    // instead of the states waiting for the ids.  The resident kernel, whose
+    // partner states come from LDS, loads each round's ids at its start (it has
+    // no registers to spare for the ids ahead).
+    int ja = -1, jb = -1;
+    if constexpr (!RESIDENT) {
+      if (sub < cnt) {
+        ja = v.ce_partner[base + sub];
+        jb = sub + LPB < cnt ? v.ce_partner[base + sub + LPB] : -1;
+      }
+    }
     for (int c = sub; c < cnt; c += 2 * LPB) {
       const int cb = c + LPB;
       const bool hb = cb < cnt;
-      const int ja = v.ce_partner[base + c];
-      const int jb = hb ? v.ce_partner[base + cb] : -1;
+      if constexpr (RESIDENT) {
+        ja = v.ce_partner[base + c];
+        jb = hb ? v.ce_partner[base + cb] : -1;
+      }
       T Ca[W], Cb[W], qa[QR], qb[QR];
       load<T, W>(v.ce + (size_t)W * (base + c), Ca);
       if (hb) load<T, W>(v.ce + (size_t)W * (base + cb), Cb);
       if (ja >= 0) load<T, QR>(qs + (size_t)QR * (ja - qoff), qa);
       if (jb >= 0) load<T, QR>(qs + (size_t)QR * (jb - qoff), qb);
+      int jan = -1, jbn = -1;
+      if constexpr (!RESIDENT) {
+        const int cn = c + 2 * LPB;
+        jan = cn < cnt ? v.ce_partner[base + cn] : -1;
+        jbn = cn + LPB < cnt ? v.ce_partner[base + cn + LPB] : -1;
+      }
       contact_end(Ca, ja, qa);
       if (hb) contact_end(Cb, jb, qb);
+      if constexpr (!RESIDENT) {
+        ja = jan;
+        jb = jbn;
+      }
     }
   }
   if constexpr (LPB > 1) {
