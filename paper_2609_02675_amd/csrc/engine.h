@@ -466,10 +466,12 @@ struct Engine {
     ContactBuf cb{tb,    bucket_count, bucket_start, bucket_fill, brec,  reach,   hist,
                   breach, large,       counters,     pairs,       pcap,  mass64,  scan_tmp, ltask};
     const int n = v.n;
-    hipLaunchKernelGGL(k_contact_prep<T>, grid_for(std::max(n, REACH_BINS * n_scenes), 256), dim3(256), 0,
-                       st, v, cb, n_scenes);
+    const bool brute = n_scenes == 1 && n <= BRUTE_MAX;
+    const int nbk = brute ? 0 : tb;  // bucket counts cleared by the prep kernel
+    hipLaunchKernelGGL(k_contact_prep<T>, grid_for(std::max({n, REACH_BINS * n_scenes, nbk}), 256), dim3(256), 0,
+                       st, v, cb, n_scenes, nbk);
     hipLaunchKernelGGL(k_contact_reach<T>, grid_for(n, 256), dim3(256), 0, st, v, cb);
-    if (n_scenes == 1 && n <= BRUTE_MAX) {
+    if (brute) {
       // one scene of few bodies: all pairs directly, no spatial hash
       const long long threads = (long long)n + (long long)n * (n - 1) / 2;
       hipLaunchKernelGGL(k_broad_brute<T>, dim3((unsigned)std::max(1LL, (threads + 255) / 256)), dim3(256), 0, st,
@@ -477,8 +479,6 @@ struct Engine {
     } else {
       hipLaunchKernelGGL(k_contact_cells, grid_for(n_scenes, 64), dim3(64), 0, st, scenes, n_scenes,
                          (const unsigned long long*)reach, (const int*)hist);
-      hipLaunchKernelGGL(k_zero_int, grid_for(tb, 256), dim3(256), 0, st, bucket_count, tb);
-      hipLaunchKernelGGL(k_zero_int, grid_for(tb, 256), dim3(256), 0, st, bucket_fill, tb);
       hipLaunchKernelGGL(k_hash_count<T>, grid_for(n, 256), dim3(256), 0, st, v, cb);
       const int nb = (tb + 1023) / 1024;
       hipLaunchKernelGGL(k_scan_block, dim3(nb), dim3(1024), 0, st, (const int*)bucket_count,
@@ -611,13 +611,12 @@ struct Engine {
     }
     hipLaunchKernelGGL(k_finish<T>, g, b, 0, st, v);
     if (!finish_scenes) return;
-    hipLaunchKernelGGL(k_reduce_residual, dim3(std::max(1, n_scenes)), dim3(RED_THREADS), 0, st,
-                       (const SceneDev*)scenes, n_scenes, (const double*)r_num,
-                       (const double*)r_den, rho);
+    // the residual and the end of the step (step counters) of the flat-path scenes
+    hipLaunchKernelGGL(k_reduce_residual, dim3(std::max(1, n_scenes)), dim3(RED_THREADS), 0, st, scenes,
+                       n_scenes, (const double*)r_num, (const double*)r_den, rho);
     if (history)
       hipLaunchKernelGGL(k_reduce_history, dim3(std::max(1, kmax)), dim3(256), 0, st, cap.n, kmax,
                          (const double*)rh_num, (const double*)rh_den, rh_rho);
-    hipLaunchKernelGGL(k_end_step, grid_for(n_scenes, 64), dim3(64), 0, st, scenes, n_scenes);
   }
 };
 

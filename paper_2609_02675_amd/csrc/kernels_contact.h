@@ -11,7 +11,8 @@
 // the spin term).
 //
 // Pipeline (one launch each):
-//   k_contact_prep   clear per-body and per-scene counters
+//   k_contact_prep   clear per-body and per-scene counters (and the hash's
+//                    bucket counts, when the step builds the hash)
 //   k_contact_reach  reach = R + pm per body; per-scene maximum and a log-scale
 //                    histogram of reach (four bins per octave)
 //   k_contact_cells  per scene: cell = 2 cut, cut = the smaller of the maximum
@@ -100,8 +101,12 @@ __device__ __forceinline__ bool contact_body(const View<T>& v, int i, int sc) {
 }
 
 template <typename T>
-__global__ void k_contact_prep(View<T> v, ContactBuf cb, int n_scenes) {
+__global__ void k_contact_prep(View<T> v, ContactBuf cb, int n_scenes, int n_buckets) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_buckets) {  // the spatial hash's counts, when this step builds it
+    cb.bucket_count[i] = 0;
+    cb.bucket_fill[i] = 0;
+  }
   if (i < n_scenes) cb.reach[i] = 0ull;
   if (i < n_scenes * REACH_BINS) cb.hist[i] = 0;
   if (i < 3) cb.counters[i] = 0;
@@ -211,11 +216,6 @@ __device__ __forceinline__ void centre_of(const View<T>& v, int i, double* c) {
   c[0] = pos_value(q, 0);
   c[1] = pos_value(q, 1);
   c[2] = pos_value(q, 2);
-}
-
-__global__ void k_zero_int(int* p, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = 0;
 }
 
 template <typename T>

@@ -421,10 +421,10 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 4 : 2) k_iterate(View<T>
 }
 
 // The same iteration over a table of wavefronts (first body, bodies, lanes per
-// body): a wave covers 16 bodies of a contact scene with four lanes each, or 64
-// bodies of a contact-free scene with one lane each, and never spans two
-// scenes.  Waves past the table's count leave at once, so the grid can stay
-// fixed while scenes come and go.
+// body): a wave covers 64 / CL bodies of a contact scene with CL lanes each (16
+// with the default four), or 64 bodies of a contact-free scene with one lane
+// each, and never spans two scenes.  Waves past the table's count leave at
+// once, so the grid can stay fixed while scenes come and go.
 struct FlatWave {
   int first, count, lpb, contact;  // lpb: lanes per body (CL for a contact wave, else 1)
 };

@@ -5,7 +5,8 @@
 //               inverse (Sec. 4.3), stored as the FP64 block and a T factor
 //   (the iterations themselves are in kernels_flat.h)
 //   k_finish    velocity recovery (Sec. 4.4) and health flags
-//   k_reduce_residual  per-scene FP64 residual, fixed summation order
+//   k_reduce_residual  per-scene FP64 residual, fixed summation order, and the
+//               end of the scene's step
 #pragma once
 
 #include "common.h"
@@ -167,7 +168,9 @@ __global__ void __launch_bounds__(256) k_finish(View<T> v) {
 // fixed order (strided partial sums, then a tree), so results are reproducible
 constexpr int RED_THREADS = 1024;
 
-__global__ void __launch_bounds__(RED_THREADS) k_reduce_residual(const SceneDev* scenes, int n_scenes,
+// per flat-path scene: the FP64 residual of its last iteration, then the end of
+// its step (the step counter advances unless the scene has taken all its steps)
+__global__ void __launch_bounds__(RED_THREADS) k_reduce_residual(SceneDev* scenes, int n_scenes,
                                                                 const double* num, const double* den,
                                                                 double* rho) {
   __shared__ double sn[RED_THREADS], sd[RED_THREADS];
@@ -193,7 +196,10 @@ __global__ void __launch_bounds__(RED_THREADS) k_reduce_residual(const SceneDev*
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) rho[sc] = sd[0] > 0.0 ? sqrt(sn[0] / sd[0]) : 0.0;
+  if (threadIdx.x == 0) {
+    rho[sc] = sd[0] > 0.0 ? sqrt(sn[0] / sd[0]) : 0.0;
+    if (scenes[sc].step < scenes[sc].steps_total) scenes[sc].step += 1;
+  }
 }
 
 // zero n doubles (a kernel, so that it can sit in a captured graph)
@@ -272,12 +278,6 @@ __global__ void k_update_driven(View<T> v, int n_driven, const int* d_scene, con
   const int sc = d_scene[b];
   if (sc < 0) return;  // unused table entry
   update_driven_entry(v, b, sc, d_end_i, d_end_j, d_param);
-}
-
-__global__ void k_end_step(SceneDev* scenes, int n_scenes) {
-  const int sc = blockIdx.x * blockDim.x + threadIdx.x;
-  if (sc < n_scenes && !scenes[sc].tiled && !scenes[sc].resident && scenes[sc].step < scenes[sc].steps_total)
-    scenes[sc].step += 1;
 }
 
 }  // namespace pabd

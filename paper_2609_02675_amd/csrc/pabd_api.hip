@@ -139,11 +139,8 @@ struct EngineT final : EngineBase {
     }
   }
   void finish_scenes(int n_scenes, hipStream_t st) override {
-    hipLaunchKernelGGL(k_reduce_residual, dim3(std::max(1, n_scenes)), dim3(RED_THREADS), 0, st,
-                       (const SceneDev*)e.scenes, n_scenes, (const double*)e.r_num,
-                       (const double*)e.r_den, e.rho);
-    hipLaunchKernelGGL(k_end_step, Engine<T>::grid_for(n_scenes, 64), dim3(64), 0, st, e.scenes,
-                       n_scenes);
+    hipLaunchKernelGGL(k_reduce_residual, dim3(std::max(1, n_scenes)), dim3(RED_THREADS), 0, st, e.scenes,
+                       n_scenes, (const double*)e.r_num, (const double*)e.r_den, e.rho);
   }
   pabd_status read_bodies(int boff, int n, double* c, double* A, double* v, double* w,
                           hipStream_t st) override {
