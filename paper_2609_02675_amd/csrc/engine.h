@@ -609,7 +609,7 @@ struct Engine {
       case 16: launch_iterations<16>(kmax, contacts, history, st, waves, n_waves, wave_grid, hn, hd); break;
       default: launch_iterations<4>(kmax, contacts, history, st, waves, n_waves, wave_grid, hn, hd); break;
     }
-    hipLaunchKernelGGL(k_finish<T>, g, b, 0, st, v);
+    // (each body's step ends in its last iteration: velocities, health, q^{n+1})
     if (!finish_scenes) return;
     // the residual and the end of the step (step counters) of the flat-path scenes
     hipLaunchKernelGGL(k_reduce_residual, dim3(std::max(1, n_scenes)), dim3(RED_THREADS), 0, st, scenes,

@@ -167,7 +167,16 @@ __device__ __forceinline__ void iterate_body(const View<T>& v, int k, double* rh
                                              int i, int sub, const T* qs, T* qd, int qoff) {
   constexpr int QR = Rec<T>::Q;
   const int sc = v.bscene[i];
-  if (sc < 0 || (v.flags[i] & F_PINNED)) return;
+  if (sc < 0) return;
+  if (v.flags[i] & F_PINNED) {
+    // a pinned body's residual shares stay zero (it never moves); written in
+    // the first iteration, before the step's residual reduction reads them
+    if (!RESIDENT && k == 0 && sub == 0) {
+      v.r_num[i] = 0.0;
+      v.r_den[i] = 0.0;
+    }
+    return;
+  }
   const SceneDev& S = v.scenes[sc];
   if ((S.resident != 0) != RESIDENT) return;
   const int K = S.iters;
@@ -394,7 +403,9 @@ __device__ __forceinline__ void iterate_body(const View<T>& v, int k, double* rh
   } else {
     polar_rotation(Ah, qo + 3, v.polar, i);
   }
-  store<T, QR>(qd + (size_t)QR * (i - qoff), qo);
+  // q^{k+1} for the partners' next iteration; after the flat path's last
+  // iteration nothing reads it (the body's step ends below)
+  if (RESIDENT || k < K - 1) store<T, QR>(qd + (size_t)QR * (i - qoff), qo);
   if (k == K - 1 || rh_num) {
     double num, den;
     residual_terms(m, qo, q, &num, &den);
@@ -405,6 +416,30 @@ __device__ __forceinline__ void iterate_body(const View<T>& v, int k, double* rh
     if (rh_num) {
       rh_num[(size_t)k * v.n + i] = num;
       rh_den[(size_t)k * v.n + i] = den;
+    }
+  }
+  if constexpr (!RESIDENT) {
+    if (k == K - 1) {
+      // the end of the body's step on the flat path: velocity recovery (Sec. 4.4)
+      // from q^K and q^n, the health bit, and q^{n+1} = q^K with its position
+      // folded back to (hi, lo) (the resident kernel ends its scenes' steps itself)
+      T q0[QR], vw[VW];
+      load<T, QR>(v.qn + (size_t)QR * i, q0);
+      // q^K as a value of its own, as if read back from memory: the recovery's
+      // subtractions must not fuse with the local step's last products, so
+      // that the flat path rounds as the resident kernel does
+#pragma unroll
+      for (int c = 0; c < QR; ++c) asm volatile("" : "+v"(qo[c]));
+      recover_velocity(qo, q0, (T)(1.0 / S.h), vw);
+      bool finite = true;
+#pragma unroll
+      for (int c = 0; c < QR; ++c) finite = finite && isfinite(qo[c]);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) finite = finite && isfinite(vw[c]);
+      if (!finite) atomicOr(v.health + sc, 1);
+      pos_renorm(qo);
+      store<T, QR>(v.qn + (size_t)QR * i, qo);
+      store<T, VW>(v.vel + (size_t)VW * i, vw);
     }
   }
 }

@@ -119,7 +119,7 @@ __global__ void __launch_bounds__(Resident<T>::NT) k_resident_step(View<T> v, co
     }
     __syncthreads();
   }
-  // velocity recovery and health, as k_finish
+  // velocity recovery and health, as the flat path's last iteration does
   const T* qK = lq[K & 1];
   for (int b = t; b < n; b += NT) {
     const int i = off + b;

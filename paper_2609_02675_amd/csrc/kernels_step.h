@@ -4,7 +4,6 @@
 //   k_factor    FP64 block H_i = M_i + h^2 sum w J^T J (Sec. 4.2.1) and its sparse
 //               inverse (Sec. 4.3), stored as the FP64 block and a T factor
 //   (the iterations themselves are in kernels_flat.h)
-//   k_finish    velocity recovery (Sec. 4.4) and health flags
 //   k_reduce_residual  per-scene FP64 residual, fixed summation order, and the
 //               end of the scene's step
 #pragma once
@@ -132,36 +131,6 @@ __device__ __forceinline__ void recover_velocity(const T* qf, const T* q0, T ih,
   vw[4] = (T)0.5 * (W[2] - W[6]) * ih;
   vw[5] = (T)0.5 * (W[3] - W[1]) * ih;
   vw[6] = vw[7] = (T)0;
-}
-
-template <typename T>
-__global__ void __launch_bounds__(256) k_finish(View<T> v) {
-  constexpr int QR = Rec<T>::Q;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= v.n) return;
-  const int sc = v.bscene[i];
-  if (sc < 0 || v.scenes[sc].resident) return;
-  if (v.flags[i] & F_PINNED) {
-    v.r_num[i] = 0.0;
-    v.r_den[i] = 0.0;
-    return;
-  }
-  const SceneDev& S = v.scenes[sc];
-  if (S.step >= S.steps_total) return;
-  T qf[QR], q0[QR];
-  load<T, QR>(v.q[S.iters & 1] + (size_t)QR * i, qf);
-  load<T, QR>(v.qn + (size_t)QR * i, q0);
-  T vw[VW];
-  recover_velocity(qf, q0, (T)(1.0 / S.h), vw);
-  bool finite = true;
-#pragma unroll
-  for (int c = 0; c < QR; ++c) finite = finite && isfinite(qf[c]);
-#pragma unroll
-  for (int c = 0; c < 6; ++c) finite = finite && isfinite(vw[c]);
-  if (!finite) atomicOr(v.health + sc, 1);
-  pos_renorm(qf);
-  store<T, QR>(v.qn + (size_t)QR * i, qf);
-  store<T, VW>(v.vel + (size_t)VW * i, vw);
 }
 
 // one block per scene; rho = sqrt(sum num / sum den) over the scene's bodies in a
