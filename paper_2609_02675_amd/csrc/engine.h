@@ -460,7 +460,9 @@ struct Engine {
   // a single contact scene of at most this many bodies takes the all-pairs broad
   // phase (at most 2.1M pair threads)
   static constexpr int BRUTE_MAX = 2048;
-  void launch_contacts(int n_scenes, hipStream_t st) {
+  // predict: the prep kernel also runs the step's prediction for the bodies
+  // [0, min(cap.n, contact bodies))
+  void launch_contacts(int n_scenes, hipStream_t st, bool predict = false) {
     View<T> v = view();
     v.n = std::min(cap.n, ncb);
     ContactBuf cb{tb,    bucket_count, bucket_start, bucket_fill, brec,  reach,   hist,
@@ -469,7 +471,7 @@ struct Engine {
     const bool brute = n_scenes == 1 && n <= BRUTE_MAX;
     const int nbk = brute ? 0 : tb;  // bucket counts cleared by the prep kernel
     hipLaunchKernelGGL(k_contact_prep<T>, grid_for(std::max({n, REACH_BINS * n_scenes, nbk}), 256), dim3(256), 0,
-                       st, v, cb, n_scenes, nbk);
+                       st, v, cb, n_scenes, nbk, predict);
     hipLaunchKernelGGL(k_contact_reach<T>, grid_for(n, 256), dim3(256), 0, st, v, cb);
     if (brute) {
       // one scene of few bodies: all pairs directly, no spatial hash
@@ -590,10 +592,13 @@ struct Engine {
                          (const double*)drv_param);
       launch_factor(st);
     }
-    if (contacts) launch_contacts(n_scenes, st);
+    // with contacts, the contact construction's first kernel also predicts
+    // (when its body range covers the flat path's)
+    const bool predict_in_prep = contacts && flat && ncb >= cap.n;
+    if (contacts) launch_contacts(n_scenes, st, predict_in_prep);
     if (resident_grid) launch_resident(resident_grid, drive_inside ? n_driven : 0, st);
     if (!flat) return;
-    hipLaunchKernelGGL(k_predict<T>, g, b, 0, st, v);
+    if (!predict_in_prep) hipLaunchKernelGGL(k_predict<T>, g, b, 0, st, v);
     double* hn = history ? rh_num : nullptr;
     double* hd = history ? rh_den : nullptr;
     if (history) {

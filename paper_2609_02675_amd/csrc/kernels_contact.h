@@ -12,7 +12,8 @@
 //
 // Pipeline (one launch each):
 //   k_contact_prep   clear per-body and per-scene counters (and the hash's
-//                    bucket counts, when the step builds the hash)
+//                    bucket counts, when the step builds the hash); in the
+//                    flat path also the step's prediction
 //   k_contact_reach  reach = R + pm per body; per-scene maximum and a log-scale
 //                    histogram of reach (four bins per octave)
 //   k_contact_cells  per scene: cell = 2 cut, cut = the smaller of the maximum
@@ -44,6 +45,7 @@
 #include "common.h"
 #include "contact_record.h"
 #include "device_math.h"
+#include "kernels_step.h"
 
 namespace pabd {
 
@@ -101,7 +103,7 @@ __device__ __forceinline__ bool contact_body(const View<T>& v, int i, int sc) {
 }
 
 template <typename T>
-__global__ void k_contact_prep(View<T> v, ContactBuf cb, int n_scenes, int n_buckets) {
+__global__ void k_contact_prep(View<T> v, ContactBuf cb, int n_scenes, int n_buckets, bool predict) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n_buckets) {  // the spatial hash's counts, when this step builds it
     cb.bucket_count[i] = 0;
@@ -114,6 +116,9 @@ __global__ void k_contact_prep(View<T> v, ContactBuf cb, int n_scenes, int n_buc
   v.ccount[i] = 0;
   v.r_num[i] = 0.0;
   v.r_den[i] = 0.0;
+  // the step's prediction, which the contact construction neither reads nor
+  // changes (it reads q^n and the velocities)
+  if (predict) predict_body(v, i);
 }
 
 __device__ __forceinline__ int reach_bin(double r) {

@@ -13,11 +13,12 @@
 
 namespace pabd {
 
+// the prediction of body i (Algorithm 1): s = q^0 from q^n and the velocities,
+// and the augmented ends' warm start; scenes of the resident kernel, finished
+// scenes and unused slots are left alone
 template <typename T>
-__global__ void __launch_bounds__(256) k_predict(View<T> v) {
+__device__ __forceinline__ void predict_body(const View<T>& v, int i) {
   constexpr int QR = Rec<T>::Q;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= v.n) return;
   const int sc = v.bscene[i];
   if (sc < 0) return;
   T q[QR];
@@ -51,6 +52,12 @@ __global__ void __launch_bounds__(256) k_predict(View<T> v) {
       a[1] = ag * a[1];
     }
   }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_predict(View<T> v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < v.n) predict_body(v, i);
 }
 
 // mass64: 8 doubles per body (m, Pi sym 6, -)
