@@ -497,10 +497,8 @@ def main():
         reqs = plan["requests"]
         log(f"{len(reqs)} requests")
         budget = int(args.serve_budget_gib * (1 << 30))
-        # the served batch keeps the default schedule (tile 64, four lanes per
-        # contact body, one wavefront per workgroup): the tuner's pick on a
-        # sample of the load (the first 80 requests, 50 steps in) measured
-        # slower on the whole served run, saturated and in real time
+        # the server's own schedule (serve.SERVE_SCHEDULE: eight lanes per
+        # contact body), the same for the real-time and the saturated run
         srv = Server(budget, 512, S.PREC_FP32)
         res, st = srv.run(reqs, realtime=True, keep_state=False)
         served = st.summary()
@@ -513,7 +511,8 @@ def main():
         res, st = srv.run(reqs, realtime=False, keep_state=True)
         served_sat = st.summary()
         served_sat.update(requests=len(reqs), budget_bytes=budget,
-                          mode="same requests all queued at t=0 (capacity)")
+                          mode="same requests all queued at t=0 (capacity)",
+                          schedule=srv.batch.schedule())
         # accuracy of served results against the oracle, on sampled chains
         acc_s = 0.0
         small = plan["served_sample"]
