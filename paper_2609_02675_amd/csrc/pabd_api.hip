@@ -77,10 +77,10 @@ struct EngineBase {
                                     std::vector<int>& partner,
                                     std::vector<unsigned long long>& key,
                                     std::vector<double>& rec, hipStream_t st) = 0;
-  // q^n, velocities and the scene table of bodies [0, n), the bond-end states,
-  // health bits, last residuals and recorded residual history (saved, or
-  // written back)
-  virtual pabd_status snapshot(int n, std::vector<char>& buf, hipStream_t st, bool restore) = 0;
+  // q^n and velocities of bodies [0, n), the bond-end states of ends [0, ne),
+  // the scene table, health bits, last residuals and recorded residual history
+  // (saved, or written back)
+  virtual pabd_status snapshot(int n, int ne, std::vector<char>& buf, hipStream_t st, bool restore) = 0;
   // flat-path schedule: lanes per contact body, wavefronts per workgroup
   virtual void set_schedule(int contact_lanes, int group_waves) = 0;
   virtual void get_schedule(int* contact_lanes, int* group_waves) const = 0;
@@ -280,7 +280,7 @@ struct EngineT final : EngineBase {
       return fail(PABD_E_DEVICE, "body record copy failed");
     return PABD_OK;
   }
-  pabd_status snapshot(int n, std::vector<char>& buf, hipStream_t st, bool restore) override {
+  pabd_status snapshot(int n, int ne, std::vector<char>& buf, hipStream_t st, bool restore) override {
     struct Part {
       void* dev;
       size_t bytes;
@@ -288,7 +288,7 @@ struct EngineT final : EngineBase {
     const Part parts[] = {{e.qn, (size_t)Rec<T>::Q * n * sizeof(T)},
                           {e.vel, (size_t)VW * n * sizeof(T)},
                           {e.scenes, (size_t)e.cap.s * sizeof(SceneDev)},
-                          {e.al, (size_t)4 * e.cap.e * sizeof(T)},
+                          {e.al, (size_t)4 * std::min(ne, e.cap.e) * sizeof(T)},
                           {e.health, (size_t)e.cap.s * sizeof(int)},
                           {e.rho, (size_t)e.cap.s * sizeof(double)},
                           {e.rh_rho, (size_t)e.rh_k * sizeof(double)}};
@@ -1308,6 +1308,19 @@ pabd_status pabd_batch_polar_fallbacks(pabd_batch* b, int32_t slot, int64_t* svd
   return PABD_OK;
 }
 
+// one past the highest body and the highest bond end any resident scene uses:
+// the extent of a snapshot of the batch's state
+static void batch_extent(const pabd_batch* b, int* n, int* ne) {
+  int hn = 0, he = 0;
+  for (const Slot& s : b->slots) {
+    if (!s.used) continue;
+    hn = std::max(hn, s.boff + std::max(1, s.n));
+    he = std::max(he, s.eoff + std::max(1, s.ne));
+  }
+  *n = std::min(hn, b->caps.n);
+  *ne = std::min(he, b->caps.e);
+}
+
 static pabd_status batch_repack(pabd_batch* b, int tile_bodies) {
   // read back every resident scene's state, re-place all scenes with the new
   // tile size, and upload again
@@ -1448,7 +1461,6 @@ pabd_status pabd_batch_autotune(pabd_batch* b, int32_t* tile_out) {
   if (cand.empty()) cand.push_back(256);
   API_HIP(hipDeviceSynchronize());
   std::vector<char> snap;
-  const int n = b->caps.n;
   pabd_status st;
   double best_t = 1e300;
   int best = b->tile_bodies;
@@ -1459,13 +1471,15 @@ pabd_status pabd_batch_autotune(pabd_batch* b, int32_t* tile_out) {
   // each from the saved state so that no scene's step budget runs out midway.
   const int ns = b->graph_steps > 0 ? b->graph_steps : 10;
   for (int t : cand) {
-    if ((st = batch_repack(b, t)) != PABD_OK) return st;
-    if ((st = b->eng->snapshot(n, snap, b->stream, false)) != PABD_OK) return st;
+    if (t != b->tile_bodies && (st = batch_repack(b, t)) != PABD_OK) return st;
+    int n = 0, ne = 0;  // the state of the scenes as now placed
+    batch_extent(b, &n, &ne);
+    if ((st = b->eng->snapshot(n, ne, snap, b->stream, false)) != PABD_OK) return st;
     double dt = 1e300;
     for (int round = 0; round < 3; ++round) {
       double ms = 0.0;
       if ((st = pabd_batch_time_tile_kernel(b, 1, ns, &ms)) != PABD_OK) return st;
-      if ((st = b->eng->snapshot(n, snap, b->stream, true)) != PABD_OK) return st;
+      if ((st = b->eng->snapshot(n, ne, snap, b->stream, true)) != PABD_OK) return st;
       dt = std::min(dt, ms);
     }
     b->substeps = substeps0;
@@ -1474,7 +1488,7 @@ pabd_status pabd_batch_autotune(pabd_batch* b, int32_t* tile_out) {
       best = t;
     }
   }
-  if ((st = batch_repack(b, best)) != PABD_OK) return st;
+  if (best != b->tile_bodies && (st = batch_repack(b, best)) != PABD_OK) return st;
   b->tile_auto = false;
   if (tile_out) *tile_out = best;
   return PABD_OK;
@@ -1714,16 +1728,20 @@ pabd_status pabd_batch_tune(pabd_batch* b, int32_t flags, pabd_schedule* out) {
       return PABD_OK;
     }
   }
-  const int n = b->caps.n;
   const long long substeps0 = b->substeps;
   std::vector<char> snap;
+  int n = 0, ne = 0;  // extent of the saved state (the scenes as placed when it was saved)
+  auto save = [&]() {
+    batch_extent(b, &n, &ne);
+    return b->eng->snapshot(n, ne, snap, b->stream, false);
+  };
   // whole steps (one graph replay each), timed from the saved state
   auto timed = [&](double* ms) {
     return time_steps(b->stream, 4, [&]() { return pabd_batch_steps(b, 1, nullptr); }, ms);
   };
   auto restore = [&]() {
     b->substeps = substeps0;
-    return b->eng->snapshot(n, snap, b->stream, true);
+    return b->eng->snapshot(n, ne, snap, b->stream, true);
   };
   // 1. tile size.  With only scenes the tile kernel takes, the sizes that hold
   // them all, on the tile kernel alone; with other scenes beside them, every
@@ -1752,7 +1770,7 @@ pabd_status pabd_batch_tune(pabd_batch* b, int32_t flags, pabd_schedule* out) {
       if (flat_n > b->n_stream || 2 * tiled_n > (long long)b->caps.n - b->n_stream) continue;
       if (t != b->tile_bodies && (st = batch_repack(b, t)) != PABD_OK) return st;
       API_HIP(hipDeviceSynchronize());
-      if ((st = b->eng->snapshot(n, snap, b->stream, false)) != PABD_OK) return st;
+      if ((st = save()) != PABD_OK) return st;
       double dt = 1e300;
       for (int round = 0; round < 3; ++round) {
         double ms = 0.0;
@@ -1778,7 +1796,7 @@ pabd_status pabd_batch_tune(pabd_batch* b, int32_t flags, pabd_schedule* out) {
     if (s.used && !s.tiled && !s.resident) (s.contact ? flat_contact : flat_other) += s.n;
   if (flat_contact + flat_other > 0) {
     API_HIP(hipDeviceSynchronize());
-    if ((st = b->eng->snapshot(n, snap, b->stream, false)) != PABD_OK) return st;
+    if ((st = save()) != PABD_OK) return st;
     int cl = b->contact_lanes, gw = b->group_waves;
     auto apply = [&](int c, int g) {
       pabd_schedule sc{0, c, g, 0};
@@ -1858,8 +1876,8 @@ pabd_status pabd_scene_tune(pabd_scene* s, int32_t flags, pabd_schedule* out) {
   }
   API_HIP(hipDeviceSynchronize());
   std::vector<char> snap;
-  const int n = std::max(1, s->hs.n);
-  if ((st = s->eng->snapshot(n, snap, s->stream, false)) != PABD_OK) return st;
+  const int n = std::max(1, s->hs.n), ne = std::max(1, s->hs.ne);
+  if ((st = s->eng->snapshot(n, ne, snap, s->stream, false)) != PABD_OK) return st;
   int cl = 0, gw = 0;
   s->eng->get_schedule(&cl, &gw);
   auto apply = [&](int c, int g) {
@@ -1869,7 +1887,7 @@ pabd_status pabd_scene_tune(pabd_scene* s, int32_t flags, pabd_schedule* out) {
   auto timed = [&](double* ms) {
     return time_steps(s->stream, 4, [&]() { return pabd_scene_step(s, 1, nullptr); }, ms);
   };
-  auto restore = [&]() { return s->eng->snapshot(n, snap, s->stream, true); };
+  auto restore = [&]() { return s->eng->snapshot(n, ne, snap, s->stream, true); };
   if ((st = search_flat(s->hs.contact, &cl, &gw, apply, timed, restore)) != PABD_OK) return st;
   pabd_schedule best;
   if ((st = pabd_scene_get_schedule(s, &best)) != PABD_OK) return st;
