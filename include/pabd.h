@@ -335,27 +335,35 @@ typedef struct pabd_schedule {
  * 8, 16}; then, when any scene runs on the flat path, group_waves from {1, 2,
  * 4}.  Whole batch steps are one graph replay each, timed with HIP events,
  * best of three rounds of four steps from the saved state; a candidate
- * replaces the schedule in force only when it is more than 3 % faster.  The result is kept in a
- * per-process cache under (device architecture, precision, size bucket): the
+ * replaces the schedule in force only when it is more than 3 % faster.  The
+ * result is kept in a per-process cache under (device architecture, precision, size bucket): the
  * bit lengths of the body counts of the scenes the tile kernel can take (joint
  * scenes without contacts, driven or variable bonds), of the contact scenes
  * and of the other scenes, the bit length of the largest contact capacity, and
  * the smallest tile size that holds the largest scene the tile kernel can
  * take.  A later call with the same key applies the cached schedule without
- * timing (unless flags has PABD_TUNE_FORCE).  Writes the schedule in force. */
+ * timing (unless flags has PABD_TUNE_FORCE).  Writes the schedule in force to
+ * *out (may be NULL).  Blocks until the device is idle, and steps the scenes
+ * only inside the saved-and-restored timing rounds.  PABD_E_INVALID for a null
+ * batch; PABD_E_DEVICE when a device call fails and PABD_E_OOM when a re-placed
+ * layout does not fit (then the batch's state is undefined: release its
+ * scenes). */
 pabd_status pabd_batch_tune(pabd_batch *b, int32_t flags, pabd_schedule *out);
 /* Apply a schedule to a batch (tile_bodies 0 leaves the tile size as it is;
- * from_cache is ignored).  PABD_E_INVALID for a value outside the sets above. */
+ * from_cache is ignored): a new tile size re-places every scene, keeping its
+ * state and bond states; the next step recaptures its graph.  PABD_E_INVALID
+ * for a value outside the sets above or a null argument. */
 pabd_status pabd_batch_set_schedule(pabd_batch *b, const pabd_schedule *s);
 pabd_status pabd_batch_get_schedule(const pabd_batch *b, pabd_schedule *out);
 /* The same for a plain scene: contact_lanes, then group_waves, each timed over
- * whole steps from the saved state (with the same 3 % margin).  A scene whose whole step runs in the
- * resident kernel (small scenes) has no flat-path launch to tune: the call
+ * whole steps from the saved state (with the same 3 % margin).  A scene whose
+ * whole step runs in the resident kernel (small scenes) has no flat-path launch to tune: the call
  * writes the schedule in force and times nothing.  Cache key: (device
  * architecture, precision, bit length of the body count, contact flag, bit
  * length of the contact capacity). */
 pabd_status pabd_scene_tune(pabd_scene *s, int32_t flags, pabd_schedule *out);
-/* (tile_bodies and from_cache are ignored; a scene reads back tile_bodies 0) */
+/* (tile_bodies and from_cache are ignored; a scene reads back tile_bodies 0;
+ * errors as for the batch) */
 pabd_status pabd_scene_set_schedule(pabd_scene *s, const pabd_schedule *sch);
 pabd_status pabd_scene_get_schedule(const pabd_scene *s, pabd_schedule *out);
 /* Empty the tuning cache / number of entries in it. */
