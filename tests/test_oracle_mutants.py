@@ -160,3 +160,20 @@ def test_planted_mistake_fails_a_pin(tmp_path, name, old, new):
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     # 0: every pin passed (the mistake went unnoticed); 5: nothing collected
     assert r.returncode not in (0, 5), f"{name} passed every pin:\n{r.stdout[-1500:]}"
+
+
+@pytest.mark.skipif(shutil.which("gcc") is None, reason="gcc is needed to build the copy")
+def test_pins_pass_on_an_oracle_built_with_undefined_behaviour_checks(tmp_path):
+    """The oracle's host code under the undefined-behaviour sanitizer (signed
+    overflow, invalid shifts, misaligned or null access, out-of-range array
+    indices where the bound is known), in trap mode, so that no sanitizer runtime
+    is needed: any such event ends the process, and every pin must still pass."""
+    lib = tmp_path / "libpabd_oracle_ubsan.so"
+    subprocess.check_call(["gcc", "-O1", "-g", "-std=c11", "-fPIC", "-shared", "-fno-omit-frame-pointer",
+                           "-fsanitize=undefined", "-fsanitize=bounds-strict",
+                           "-fsanitize-undefined-trap-on-error", "-o", str(lib), SRC, "-lm"])
+    env = dict(os.environ, PABD_ORACLE_LIB=str(lib))
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-m", "not gpu",
+                        "-p", "no:cacheprovider", *PINS, "tests/test_oracle_checkpoint.py"],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=900)
+    assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-1000:]
