@@ -323,6 +323,35 @@ def _plan(args, S, scenes):
 
 # ---------------------------------------------------------------------------
 
+def tile_occupancy_sweep(steps_per_launch=10):
+    """The tile kernel alone on n identical tiles (one FP32 chain of 64 bodies
+    each, K = 20, joints turned by -20..20 degrees), n = 1 to 6 tiles per SIMD,
+    one 64-lane wave per tile: launch time against waves per SIMD.  Each point
+    is the best of three means over five launches (HIP events)."""
+    import torch
+    import paper_2609_02675_amd as P
+    from paper_2609_02675_amd import scenes as S
+    if P.device_count() < 1:
+        raise SystemExit("no HIP device visible")
+    simds = 4 * torch.cuda.get_device_properties(0).multi_processor_count
+    base = S.chain(64, tilt_deg=0.0, joint_angles_deg=np.linspace(-20, 20, 63), kappa=1e5, iters=20,
+                   precision=S.PREC_FP32, name="chain64")
+    for per in (1.0, 2.0, 2.18, 3.0, 3.5, 4.5, 6.0):
+        nt = int(round(per * simds))
+        b = P.Batch(nt + 2, 4 << 30, S.PREC_FP32)
+        b.set_tile(64)
+        for _ in range(nt):
+            assert b.admit(base, 1 << 30) is not None
+        assert b.layout()["tiles"] == nt
+        b.step(nsteps=steps_per_launch)
+        b.sync()
+        ms = min(b.time_tile_kernel(5, nsteps=steps_per_launch) for _ in range(3))
+        print(json.dumps({"tiles_per_simd": per, "tiles": nt, "simds": simds,
+                          "steps_per_launch": steps_per_launch, "ms_per_launch": ms,
+                          "us_per_step": 1e3 * ms / steps_per_launch}), flush=True)
+        b.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -353,6 +382,10 @@ def main():
                     help="skip the single-core oracle timings of the single-scene workloads")
     ap.add_argument("--probe-only", action="store_true",
                     help="run only the 1 GiB HBM copy probe (counter calibration)")
+    ap.add_argument("--tile-occupancy-sweep", action="store_true",
+                    help="run only the tile kernel on identical 64-body tiles at 1 to 6 tiles per "
+                         "SIMD (one JSON line per point), to separate a wave's step latency from "
+                         "the SIMDs' issue rate")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "the library runs on one GPU; --gpus must be 1"}))
@@ -362,6 +395,9 @@ def main():
         import paper_2609_02675_amd as P
         gbs, ms = P.hbm_copy_probe(1 << 30, 10)
         print(json.dumps({"probe": "hbm_copy", "bytes_per_direction": 1 << 30, "GBs": gbs, "ms": ms}))
+        return
+    if args.tile_occupancy_sweep:
+        tile_occupancy_sweep()
         return
 
     from paper_2609_02675_amd import scenes as S
