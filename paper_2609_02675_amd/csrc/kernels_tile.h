@@ -148,6 +148,15 @@ __global__ void __launch_bounds__(TB, sizeof(T) == 4 ? 3 : 1) k_tile_step(View<T
     // (wave-uniform, fixed for the launch)
 #pragma unroll
     for (int u = 0; u < MAXE; ++u) some_unmirrored[u] = wave_any(!pinned && u < ne && !mirrored[u]);
+    // whether some lane of the tile reads a partner's q^k from LDS after the
+    // first iteration (an end taken the long way, or ends beyond the register
+    // ones); when none does, q^k is published only for the first iteration,
+    // where the partners' high position words are read (uniform over the
+    // workgroup, whose waves read each other's slots)
+    bool long_way = scn >= 0 && !pinned && ne > MAXE;
+#pragma unroll
+    for (int u = 0; u < MAXE; ++u) long_way = long_way || (scn >= 0 && !pinned && u < ne && !mirrored[u]);
+    const bool need_q = __syncthreads_or(long_way);
     for (int step = 0; step < nsteps; ++step) {
       // the scene's step counter was advanced by its first lane before the
       // previous step's last barrier
@@ -183,7 +192,7 @@ __global__ void __launch_bounds__(TB, sizeof(T) == 4 ? 3 : 1) k_tile_step(View<T
         T* buf = lq[k & 1];
         T* ybuf = ly[k & 1];
         if (present) {
-          L::put(buf, TB, lane, q);
+          if (k == 0 || need_q) L::put(buf, TB, lane, q);
 #pragma unroll
           for (int u = 0; u < MAXE; ++u)
             if (u < ne) {
