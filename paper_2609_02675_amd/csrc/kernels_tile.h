@@ -157,17 +157,19 @@ __global__ void __launch_bounds__(TB, sizeof(T) == 4 ? 3 : 1) k_tile_step(View<T
 #pragma unroll
     for (int u = 0; u < MAXE; ++u) long_way = long_way || (scn >= 0 && !pinned && u < ne && !mirrored[u]);
     const bool need_q = __syncthreads_or(long_way);
+    // the scene's step count, read once per launch and advanced in registers
+    // beside the scene table's counter (which the scene's first lane advances
+    // for the host), so that no step waits for the previous one's store
+    int sstep = scn >= 0 ? v.scenes[scn].step : 0;
     for (int step = 0; step < nsteps; ++step) {
-      // the scene's step counter was advanced by its first lane before the
-      // previous step's last barrier
-      const bool present = scn >= 0 && v.scenes[scn].step < v.scenes[scn].steps_total;
+      const bool present = scn >= 0 && sstep < v.scenes[scn].steps_total;
       const bool moving = present && !pinned;
       // scene constants are re-read every step rather than held in registers
       // through the iterations
       const int K = present ? v.scenes[scn].iters : 0;
       // the residual is formed on the launch's last step and on a scene's own
       // last step (the only ones whose residual can be read afterwards)
-      const bool want_rho = present && (step == nsteps - 1 || v.scenes[scn].step + 1 >= v.scenes[scn].steps_total);
+      const bool want_rho = present && (step == nsteps - 1 || sstep + 1 >= v.scenes[scn].steps_total);
       // M s of the prediction s: the inertia term's part that no iteration
       // changes (q's high position words stay those of s through the step)
       T ms[QW];
@@ -320,9 +322,10 @@ __global__ void __launch_bounds__(TB, sizeof(T) == 4 ? 3 : 1) k_tile_step(View<T
           const double a = red[lane], b = red[TB + lane];
           v.rho[scn] = b > 0.0 ? sqrt(a / b) : 0.0;
         }
-        v.scenes[scn].step += 1;
+        v.scenes[scn].step = sstep + 1;
       }
-      __syncthreads();  // LDS and step counters settled for the next step or tile
+      if (present) ++sstep;
+      __syncthreads();  // LDS settled for the next step or tile
     }
   }
 }
