@@ -132,14 +132,14 @@ def test_spring_net_in_a_tile(P, prec, steps, tol, tile):
         assert e["pos"] <= tol and e["rot"] <= tol, e
 
 
-def test_mixed_tiles_same_bits_in_every_grouping(P):
+@pytest.mark.parametrize("prec", [S.PREC_FP32, S.PREC_FP64])
+def test_mixed_tiles_same_bits_in_every_grouping(P, prec):
     """Chains whose every end pairs with a mirror end beside hinge chains (more
     ends per body than a lane keeps in registers) and a chain hung from the
     world (an end taken the long way): a workgroup holding any of the latter
     publishes q^k in every iteration, one of chains alone only in a step's
     first.  Every tile size (so every grouping of scenes into workgroups) and
     each scene alone give the same bits, over three launches of five steps."""
-    prec = S.PREC_FP32
     scs = (S.batched_chains(6, seed=8, precision=prec, hi=30) +
            [_hinge_chain(9, prec, True, seed=3), _world_chain(6, prec)] +
            S.batched_chains(5, seed=9, precision=prec, hi=30))
@@ -156,12 +156,12 @@ def test_mixed_tiles_same_bits_in_every_grouping(P):
 
     ref = run(scs, 64)
     for tile in (32, 128, 256):
-        print(f"[case] mixed tiles, tile {tile}", flush=True)
+        print(f"[case] mixed tiles, prec {prec}, tile {tile}", flush=True)
         for x, y in zip(ref, run(scs, tile)):
             for a, c in zip(x, y):
                 np.testing.assert_array_equal(a, c)
     for k in (0, 6, 7, 12):
-        print(f"[case] mixed tiles, {scs[k].name} alone", flush=True)
+        print(f"[case] mixed tiles, prec {prec}, {scs[k].name} alone", flush=True)
         (alone,) = run([scs[k]], 64)
         for a, c in zip(ref[k], alone):
             np.testing.assert_array_equal(a, c)
